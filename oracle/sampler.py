@@ -1,0 +1,104 @@
+"""Informative random line sampling in FP64 (oracle; test infrastructure only).
+
+Algorithm 4 normalises the columns of the factors, scores every entry by the
+energy of its factor rows (eq. 13) and draws K trials from that distribution.
+Sec. VI-C samples whole phase-encode rows, marginalising eq. 13 over the columns:
+s_t(n1) = (N2 ||abar_{n1}||^2 + R) / (R (N1 + N2)), rows drawn with replacement,
+so at most K distinct rows.
+
+Readings:
+* the factor scored is the k-space row factor F_l A (the rows being sampled are
+  k-space rows; the section's experiment runs the k-space algorithm), taken at
+  the precision the step stores it in (its complex64 values, widened exactly);
+* a column of zero norm is left out of the normalised row energy;
+* draw k of the mask for frame t uses u_k = (w0 >> 11) 2^-53 where w0 is the
+  first word of Philox4x64-10 at counter (t, k, 0, 0) and key (seed, stream id);
+* the row drawn is the first i whose inclusive weight prefix exceeds u_k W,
+  W being the computed weight total (clamped to the last row);
+* every sum runs sequentially in index order in float64 with no fused
+  multiply-add, so identical inputs give identical rows on any IEEE machine.
+"""
+
+import numpy as np
+
+from .philox import philox4x64_10
+
+
+def line_weights_prefix(Ahat, n2):
+    """Unnormalised row weights w_i = N2 ||abar_i||^2 + R and their inclusive prefix.
+
+    ``Ahat`` is the [N1, R] k-space row factor.  Returns (w, prefix), float64.
+    """
+    Ahat = np.asarray(Ahat)
+    re = Ahat.real.astype(np.float64)
+    im = Ahat.imag.astype(np.float64)
+    E = re * re + im * im                      # |Ahat_ir|^2
+    n1, R = E.shape
+    c = np.zeros(R)
+    for i in range(n1):                        # column energies ||ahat_r||^2
+        c = c + E[i]
+    q = np.zeros(n1)
+    for r in range(R):                         # ||abar_i||^2 after normalisation
+        if c[r] > 0.0:
+            q = q + E[:, r] / c[r]
+    w = float(n2) * q
+    w = w + float(R)
+    prefix = np.empty(n1)
+    acc = 0.0
+    for i in range(n1):
+        acc = acc + w[i]
+        prefix[i] = acc
+    return w, prefix
+
+
+def line_scores(Ahat, n2):
+    """The row probabilities s_t(n1) of Sec. VI-C, normalised by the computed
+    weight total (which is R (N1 + N2) when no column is zero)."""
+    w, prefix = line_weights_prefix(Ahat, n2)
+    return w / prefix[-1]
+
+
+def point_scores(Ahat, Bhat):
+    """The entry probabilities s_t(n1, n2) of eq. (13) from both normalised factors."""
+    def row_energy(F):
+        E = np.abs(np.asarray(F, dtype=np.complex128)) ** 2
+        c = E.sum(axis=0)
+        keep = c > 0
+        return (E[:, keep] / c[keep]).sum(axis=1)
+    qa, qb = row_energy(Ahat), row_energy(Bhat)
+    n1, R = np.asarray(Ahat).shape
+    n2 = np.asarray(Bhat).shape[0]
+    return (qa[:, None] + qb[None, :]) / (R * (n1 + n2))
+
+
+def uniform_draws(seed, stream, t, K):
+    """u_k in [0, 1) for the K trials of the mask of frame t."""
+    out = np.empty(K)
+    for k in range(K):
+        w0 = philox4x64_10((t, k, 0, 0), (seed, stream))[0]
+        out[k] = float(w0 >> 11) * 2.0 ** -53
+    return out
+
+
+def draw_lines(Ahat, n2, K, seed, stream, t):
+    """Algorithm 4 on rows: K draws with replacement; returns (rows, draws).
+
+    ``rows`` is the ascending set of distinct rows (int32), ``draws`` the K
+    row indices in trial order.
+    """
+    _, prefix = line_weights_prefix(Ahat, n2)
+    n1 = prefix.size
+    W = prefix[-1]
+    u = uniform_draws(seed, stream, t, K)
+    draws = np.empty(K, dtype=np.int32)
+    for k in range(K):
+        target = u[k] * W
+        i = int(np.searchsorted(prefix, target, side="right"))
+        draws[k] = min(i, n1 - 1)
+    return np.unique(draws).astype(np.int32), draws
+
+
+def expected_count(scores, K):
+    """E|Omega_t| = sum over candidates of 1 - (1 - s)^K (Sec. V-B)."""
+    s = np.asarray(scores, dtype=np.float64)
+    return float(np.sum(1.0 - (1.0 - s) ** K))

@@ -1,0 +1,412 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these checks retypes the oracle's own formula: each compares it with an
+independent route (a library transform, an explicit sketch-matrix sum, a finite
+difference, a brute-force eigenvalue, a closed form, a published known-answer
+table, a second formulation of the algorithm, or a statistical law).
+"""
+
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from oracle import tsl as otsl
+from oracle.sampler import expected_count, point_scores
+from paper_1609_04104_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rng(s):
+    return np.random.default_rng(1000 + s)
+
+
+def _cn(rng, shape):
+    return rng.normal(size=shape) + 1j * rng.normal(size=shape)
+
+
+def _nr(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+# ----------------------------------------------------------------- DFT (Sec. IV)
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 12, 15, 64, 120, 200, 256])
+def test_dft_matches_library_fft_unitary_symmetric(n):
+    F = oracle.dft_matrix(n)
+    x = _cn(_rng(n), n)
+    assert np.allclose(F @ x, np.fft.fft(x, norm="ortho"), atol=1e-12, rtol=0)
+    assert np.allclose(F, F.T, atol=0, rtol=0)                                    # symmetric
+    assert np.allclose(F.conj().T @ F, np.eye(n), atol=1e-12)                     # unitary
+    assert abs(np.linalg.norm(F @ x) - np.linalg.norm(x)) < 1e-12 * np.linalg.norm(x)  # Parseval
+
+
+def test_dft_closed_forms():
+    n = 12
+    F = oracle.dft_matrix(n)
+    d = np.zeros(n); d[0] = 1.0
+    assert np.allclose(F @ d, np.full(n, 1.0 / np.sqrt(n)), atol=1e-15)           # delta -> flat
+    m0 = 5
+    tone = np.exp(2j * np.pi * m0 * np.arange(n) / n)
+    expect = np.zeros(n, complex); expect[m0] = np.sqrt(n)
+    assert np.allclose(F @ tone, expect, atol=1e-12)                               # tone -> spike
+
+
+def test_fft2_matches_library_and_inverts():
+    rng = _rng(1)
+    X = _cn(rng, (24, 40))
+    K = oracle.fft2_unitary(X)
+    assert np.allclose(K, np.fft.fft2(X, norm="ortho"), atol=1e-12)
+    assert np.allclose(oracle.ifft2_unitary(K), X, atol=1e-12)
+    a, b = _cn(rng, 24), _cn(rng, 40)
+    # separability F(a b^T) = (F_l a)(F_r b)^T, which needs F_r symmetric
+    assert np.allclose(oracle.fft2_unitary(np.outer(a, b)),
+                       np.outer(oracle.dft_matrix(24) @ a, oracle.dft_matrix(40) @ b), atol=1e-12)
+
+
+# ----------------------------------------------------------------- S1 (Sec. III-A)
+def test_regression_matrix_columns_are_sampled_fft_of_rank_one():
+    rng = _rng(2)
+    n1, n2, R = 10, 9, 4
+    A, B = _cn(rng, (n1, R)), _cn(rng, (n2, R))
+    mask = rng.random((n1, n2)) < 0.4
+    oi, oj = np.nonzero(mask)
+    Phi = oracle.regression_matrix(A, B, oi, oj, oracle.dft_matrix(n1), oracle.dft_matrix(n2))
+    for r in range(R):
+        col = np.fft.fft2(np.outer(A[:, r], B[:, r]), norm="ortho")[oi, oj]
+        assert np.allclose(Phi[:, r], col, atol=1e-12)
+
+
+def test_ridge_closed_form_equals_svd_form_and_augmented_lstsq():
+    rng = _rng(3)
+    for L, R, lam in [(50, 8, 0.3), (6, 10, 0.7), (200, 32, 0.05)]:
+        Phi, y = _cn(rng, (L, R)), _cn(rng, L)
+        g, G, h = oracle.ridge_gamma(Phi, y, lam)
+        g_svd = oracle.ridge_gamma_svd(Phi, y, lam)
+        aug = np.vstack([Phi, np.sqrt(lam) * np.eye(R)])
+        g_ls = scipy.linalg.lstsq(aug, np.concatenate([y, np.zeros(R)]))[0]
+        assert _nr(g, g_svd) < 1e-10
+        assert _nr(g, g_ls) < 1e-10
+
+
+def test_ridge_scalar_case_and_limits():
+    rng = _rng(4)
+    phi, y = _cn(rng, (30, 1)), _cn(rng, 30)
+    lam = 0.9
+    g, _, _ = oracle.ridge_gamma(phi, y, lam)
+    assert np.allclose(g[0], np.vdot(phi[:, 0], y) / (np.vdot(phi[:, 0], phi[:, 0]).real + lam))
+    Phi = _cn(rng, (40, 6))
+    g_big, _, _ = oracle.ridge_gamma(Phi, _cn(rng, 40), 1e12)
+    assert np.linalg.norm(g_big) < 1e-9
+    # rank-deficient Phi with lambda = 0 is an error, not an arbitrary choice
+    Phi_def = np.hstack([Phi[:, :3], Phi[:, :3]])
+    with pytest.raises(otsl.NotPositiveDefinite):
+        oracle.ridge_gamma(Phi_def, _cn(rng, 40), 0.0)
+
+
+# ----------------------------------------------------------------- residual and back-projection
+def _tiny_state(seed=5, n1=6, n2=5, R=3):
+    rng = _rng(seed)
+    return rng, n1, n2, R, 0.2 * _cn(rng, (n1, R)), 0.2 * _cn(rng, (n2, R))
+
+
+def test_residual_equals_y_minus_fft_of_synthesis():
+    rng, n1, n2, R, A, B = _tiny_state()
+    o = oracle.TslOracle(n1, n2, R, 0.1, A, B)
+    mask = rng.random((n1, n2)) < 0.5
+    Y = _cn(rng, (n1, n2))
+    s = o.push_points(mask, Y)
+    K = np.fft.fft2((A * s.gamma[None, :]) @ B.T, norm="ortho")
+    assert np.allclose(s.e, Y[mask] - K[mask], atol=1e-12)
+
+
+def test_back_projection_equals_explicit_sketch_sum():
+    rng, n1, n2, R, A, B = _tiny_state(6)
+    Fl, Fr = oracle.dft_matrix(n1), oracle.dft_matrix(n2)
+    Xi = np.zeros((n1, n2), complex)
+    mask = rng.random((n1, n2)) < 0.5
+    Xi[mask] = _cn(rng, mask.sum())
+    Theta = np.zeros((n1, n2), complex)
+    for i, j in zip(*np.nonzero(mask)):
+        E = np.zeros((n1, n2)); E[i, j] = 1.0
+        W = Fl @ E @ Fr                          # sketch of entry (i, j)
+        Theta += Xi[i, j] * np.conj(W)           # sum_l e_l W_l^*
+    assert np.allclose(oracle.back_projection(Xi, Fl, Fr), Theta, atol=1e-12)
+
+
+# ----------------------------------------------------------------- gradient, Hessian bound, MM
+def _explicit_gradient(A, B, gamma, oi, oj, y, lam, t, Fl, Fr, wrt="A"):
+    """eq. (7) with explicit sketch matrices W_l = F_l e_i e_j^T F_r."""
+    n1, n2 = Fl.shape[0], Fr.shape[0]
+    R = A.shape[1]
+    Ws = []
+    for i, j in zip(oi, oj):
+        E = np.zeros((n1, n2)); E[i, j] = 1.0
+        Ws.append(Fl @ E @ Fr)
+    # <a b^T, W> = sum_mn a_m b_n W_mn (bilinear)
+    e = np.array([y[l] - sum(gamma[r] * (A[:, r] @ Ws[l] @ B[:, r]) for r in range(R))
+                  for l in range(len(Ws))])
+    if wrt == "A":
+        g = (lam / t) * A.astype(complex)
+        for r in range(R):
+            for l, W in enumerate(Ws):
+                g[:, r] -= np.conj(gamma[r]) * e[l] * np.conj(W @ B[:, r])
+    else:
+        g = (lam / t) * B.astype(complex)
+        for r in range(R):
+            for l, W in enumerate(Ws):
+                g[:, r] -= np.conj(gamma[r]) * e[l] * np.conj(W.T @ A[:, r])
+    return g
+
+
+def test_update_direction_is_eq7_gradient_and_matches_finite_differences():
+    rng, n1, n2, R, A, B = _tiny_state(7)
+    lam = 0.3
+    o = oracle.TslOracle(n1, n2, R, lam, A, B)
+    o.push_points(rng.random((n1, n2)) < 0.6, _cn(rng, (n1, n2)))   # t = 1, move away from init
+    A1, B1 = o.A.copy(), o.B.copy()
+    mask = rng.random((n1, n2)) < 0.6
+    Y = _cn(rng, (n1, n2))
+    s = o.push_points(mask, Y)
+    t, Fl, Fr = s.t, o.Fl, o.Fr
+    gA = (A1 - s.A) / s.mu
+    gB = (B1 - s.B) / s.mu
+    assert np.allclose(gA, _explicit_gradient(A1, B1, s.gamma, s.oi, s.oj, s.y, lam, t, Fl, Fr, "A"), atol=1e-10)
+    assert np.allclose(gB, _explicit_gradient(A1, B1, s.gamma, s.oi, s.oj, s.y, lam, t, Fl, Fr, "B"), atol=1e-10)
+    # directional derivatives by central differences: df = Re <grad, E>
+    f = lambda a, b: oracle.instantaneous_cost(a, b, s.gamma, s.oi, s.oj, s.y, lam, t, Fl, Fr)
+    for _ in range(3):
+        E = _cn(rng, A1.shape)
+        h = 1e-6
+        fd = (f(A1 + h * E, B1) - f(A1 - h * E, B1)) / (2 * h)
+        assert abs(fd - np.vdot(gA, E).real) < 1e-6 * max(1.0, abs(fd))
+        E = _cn(rng, B1.shape)
+        fd = (f(A1, B1 + h * E) - f(A1, B1 - h * E)) / (2 * h)
+        assert abs(fd - np.vdot(gB, E).real) < 1e-6 * max(1.0, abs(fd))
+
+
+def _block_operator(A, B, gamma, oi, oj, Fl, Fr, wrt):
+    """Matrix of the complex-linear map (factor) -> sampled F(A diag(g) B^T)."""
+    n = A.shape[0] if wrt == "A" else B.shape[0]
+    R = A.shape[1]
+    cols = []
+    for r in range(R):
+        for m in range(n):
+            D = np.zeros((n, R), complex); D[m, r] = 1.0
+            X = (D * gamma) @ B.T if wrt == "A" else (A * gamma) @ D.T
+            cols.append((Fl @ X @ Fr)[oi, oj])
+    return np.array(cols).T
+
+
+@pytest.mark.parametrize("seed", [8, 9, 10])
+def test_step_alpha_bounds_the_block_hessian(seed):
+    rng, n1, n2, R, A, B = _tiny_state(seed, n1=7, n2=6, R=3)
+    Fl, Fr = oracle.dft_matrix(n1), oracle.dft_matrix(n2)
+    gamma = _cn(rng, R)
+    lam, t = 0.4, 3
+    mask = rng.random((n1, n2)) < 0.5
+    oi, oj = np.nonzero(mask)
+    alpha = oracle.step_alpha(A, B, gamma, lam, t)
+    for wrt in ("A", "B"):
+        Lop = _block_operator(A, B, gamma, oi, oj, Fl, Fr, wrt)
+        H = Lop.conj().T @ Lop + (lam / t) * np.eye(Lop.shape[1])   # Hessian of f_t in this factor
+        assert np.linalg.eigvalsh(H).max() <= alpha * (1 + 1e-12)
+    # with every entry sampled, the bound is attained up to the Gershgorin slack
+    full = np.ones((n1, n2), bool)
+    Lop = _block_operator(A, B, gamma, *np.nonzero(full), Fl, Fr, "A")
+    top = np.linalg.eigvalsh(Lop.conj().T @ Lop).max() + lam / t
+    assert top <= alpha * (1 + 1e-12)
+
+
+def test_mm_majorized_cost_never_increases():
+    c = I.config1(T=8)
+    o = oracle.TslOracle(c["n1"], c["n2"], c["r"], 0.1, c["A0"], c["B0"])
+    for fr in c["frames"]:
+        A0, B0 = o.A.copy(), o.B.copy()
+        s = o.push_points(fr.mask, fr.y)
+        f = lambda a, b: oracle.instantaneous_cost(a, b, s.gamma, s.oi, s.oj, s.y, 0.1, s.t, o.Fl, o.Fr)
+        f0 = f(A0, B0)
+        for new, grad_at in (("A", (s.A, B0)), ("B", (A0, s.B))):
+            delta = (s.A - A0) if new == "A" else (s.B - B0)
+            grad = -delta / s.mu
+            surrogate = f0 + np.vdot(grad, delta).real + 0.5 * s.alpha * np.vdot(delta, delta).real
+            f_new = f(*grad_at)
+            assert f_new <= surrogate * (1 + 1e-12) + 1e-12
+            assert surrogate <= f0 * (1 + 1e-12) + 1e-12
+
+
+def test_recursion_equals_weighted_sum_of_mm_minimisers():
+    rng, n1, n2, R, A, B = _tiny_state(11)
+    lam = 0.25
+    o = oracle.TslOracle(n1, n2, R, lam, A, B)
+    Fl, Fr = o.Fl, o.Fr
+    acc, abar = np.zeros_like(o.A), 0.0
+    for _ in range(4):
+        A_prev, B_prev = o.A.copy(), o.B.copy()
+        mask = rng.random((n1, n2)) < 0.6
+        s = o.push_points(mask, _cn(rng, (n1, n2)))
+        g = _explicit_gradient(A_prev, B_prev, s.gamma, s.oi, s.oj, s.y, lam, s.t, Fl, Fr, "A")
+        acc += s.alpha * (A_prev - g / s.alpha)
+        abar += s.alpha
+        assert np.allclose(o.A, acc / abar, atol=1e-12)        # A[t] = (1/abar_t) sum alpha_tau {...}
+
+
+# ----------------------------------------------------------------- whole-step special cases
+def test_exact_recovery_noiseless_full_sampling_lambda0():
+    c = I.config1(T=4, exact=True)
+    A, B, G = c["truth"]
+    o = oracle.TslOracle(c["n1"], c["n2"], c["r"], 0.0, A, B)
+    for t, fr in enumerate(c["frames"]):
+        # the stored frames are complex64; take the FP64 k-space of the truth here
+        s = o.push_points(fr.mask, np.fft.fft2(fr.truth, norm="ortho"))
+        assert _nr(s.gamma, G[t]) < 1e-11
+        assert np.max(np.abs(s.e)) < 1e-10
+        assert _nr(s.A, A) < 1e-12 and _nr(s.B, B) < 1e-12
+        assert _nr(s.X, fr.truth) < 1e-11
+
+
+def test_exact_data_with_lambda_gives_shrunk_closed_form():
+    c = I.config1(T=1, exact=True)
+    A, B, G = c["truth"]
+    lam = 3.0
+    o = oracle.TslOracle(c["n1"], c["n2"], c["r"], lam, A, B)
+    s = o.push_points(c["frames"][0].mask, np.fft.fft2(c["frames"][0].truth, norm="ortho"))
+    P = (A.conj().T @ A) * (B.conj().T @ B)          # Phi^H Phi for the full mask (Schur product)
+    assert _nr(s.gamma, np.linalg.solve(P + lam * np.eye(c["r"]), P @ G[0])) < 1e-10
+
+
+def test_empty_mask_is_pure_shrink():
+    rng, n1, n2, R, A, B = _tiny_state(12)
+    o = oracle.TslOracle(n1, n2, R, 0.5, A, B)
+    s = o.push_lines(np.zeros(0, np.int32), np.zeros((0, n2)))
+    assert np.all(s.gamma == 0) and np.allclose(s.A, s.shrink * A) and np.allclose(s.B, s.shrink * B)
+    assert s.alpha == pytest.approx(0.5)
+
+
+def test_lines_equal_points_on_full_rows():
+    rng, n1, n2, R, A, B = _tiny_state(13, n1=16, n2=12, R=4)
+    rows = np.array([0, 3, 4, 9, 15], np.int32)
+    Y = _cn(rng, (n1, n2))
+    mask = np.zeros((n1, n2), bool); mask[rows] = True
+    a = oracle.TslOracle(n1, n2, R, 0.2, A, B).push_lines(rows, Y[rows])
+    b = oracle.TslOracle(n1, n2, R, 0.2, A, B).push_points(mask, Y)
+    assert np.allclose(a.X, b.X, atol=1e-13) and np.allclose(a.gamma, b.gamma, atol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["lines", "points"])
+def test_image_domain_step_equals_kspace_interpolation_step(kind):
+    rng = _rng(14)
+    n1, n2, R, lam = 20, 16, 5, 0.15
+    A0, B0 = 0.3 * _cn(rng, (n1, R)), 0.3 * _cn(rng, (n2, R))
+    Fl, Fr = oracle.dft_matrix(n1), oracle.dft_matrix(n2)
+    img = oracle.TslOracle(n1, n2, R, lam, A0, B0)
+    ksp = oracle.KspaceOracle(n1, n2, R, lam, Fl @ A0, Fr @ B0)
+    for t in range(6):
+        Y = _cn(rng, (n1, n2))
+        if kind == "lines":
+            rows = np.sort(rng.choice(n1, 7, replace=False)).astype(np.int32)
+            a, b = img.push_lines(rows, Y[rows]), ksp.push_lines(rows, Y[rows])
+        else:
+            mask = rng.random((n1, n2)) < 0.3
+            a, b = img.push_points(mask, Y), ksp.push_points(mask, Y)
+        assert _nr(a.gamma, b.gamma) < 1e-11
+        assert _nr(Fl @ a.A, b.alpha_f) < 1e-11
+        assert _nr(Fr @ a.B, b.beta_f) < 1e-11
+        assert _nr(a.X, oracle.ifft2_unitary(b.Xk)) < 1e-11
+
+
+# ----------------------------------------------------------------- sampler (Sec. V, Sec. VI-C)
+def test_philox_known_answer_vectors():
+    with open(os.path.join(GOLDEN, "philox4x64_10_kat.txt")) as fh:
+        rows = [ln.split() for ln in fh if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for w in rows:
+        v = [int(x, 16) for x in w]
+        assert oracle.philox4x64_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_philox_matches_numpy_bit_generator():
+    # numpy's Philox advances its counter before the first block: block c+1 first.
+    key = [0x1234567890ABCDEF, 42]
+    for ctr in ([0, 0, 0, 0], [7, 3, 0, 0], [2**64 - 1, 5, 0, 0]):
+        bg = np.random.Philox(key=np.array(key, np.uint64), counter=np.array(ctr, np.uint64))
+        raw = [int(x) for x in bg.random_raw(4)]
+        nxt = list(ctr)
+        nxt[0] = (nxt[0] + 1) % 2**64
+        if nxt[0] == 0:
+            nxt[1] += 1
+        assert oracle.philox4x64_10(nxt, key) == raw
+
+
+def test_scores_sum_to_one_and_line_score_is_the_marginal():
+    rng = _rng(15)
+    n1, n2, R = 24, 18, 5
+    Ah, Bh = _cn(rng, (n1, R)), _cn(rng, (n2, R))
+    s2 = point_scores(Ah, Bh)
+    s1 = oracle.line_scores(Ah, n2)
+    assert abs(s2.sum() - 1.0) < 1e-13 and abs(s1.sum() - 1.0) < 1e-13
+    assert np.all(s2 > 0)
+    assert np.allclose(s2.sum(axis=1), s1, atol=1e-15)      # Sec. VI-C marginal of eq. 13
+    _, prefix = oracle.line_weights_prefix(Ah, n2)
+    assert abs(prefix[-1] - R * (n1 + n2)) < 1e-11 * R * (n1 + n2)
+
+
+def test_uniform_factor_rows_give_uniform_scores():
+    n1, R = 16, 4
+    F = oracle.dft_matrix(n1)[:, :R]           # every entry has |.|^2 = 1/n1
+    s = oracle.line_scores(F.astype(np.complex64), 10)
+    assert np.allclose(s, 1.0 / n1, atol=1e-7)
+
+
+def test_zero_column_is_skipped():
+    rng = _rng(16)
+    Ah = _cn(rng, (12, 3)); Ah[:, 1] = 0
+    s = oracle.line_scores(Ah, 7)
+    assert np.all(np.isfinite(s)) and abs(s.sum() - 1) < 1e-13
+
+
+def test_expected_sample_count_and_draw_frequencies():
+    rng = _rng(17)
+    n1, n2, R, K = 32, 20, 4, 10
+    Ah = _cn(rng, (n1, R)) * np.exp(-0.15 * np.arange(n1))[:, None]
+    s = oracle.line_scores(Ah, n2)
+    counts, freq = [], np.zeros(n1)
+    n_streams = 3000
+    for stream in range(n_streams):
+        rows, draws = oracle.draw_lines(Ah, n2, K, seed=99, stream=stream, t=1)
+        counts.append(rows.size)
+        np.add.at(freq, draws, 1)
+    counts = np.array(counts, float)
+    mean, se = counts.mean(), counts.std(ddof=1) / np.sqrt(n_streams)
+    assert abs(mean - expected_count(s, K)) < 2.58 * se + 1e-9     # 99 % interval (Sec. V-B)
+    exp = s * K * n_streams
+    chi2 = float(np.sum((freq - exp) ** 2 / exp))
+    import scipy.stats
+    assert chi2 < scipy.stats.chi2.ppf(1 - 1e-4, n1 - 1)
+
+
+def test_draws_are_deterministic_sorted_unique():
+    rng = _rng(18)
+    Ah = _cn(rng, (40, 6)).astype(np.complex64)
+    r1, d1 = oracle.draw_lines(Ah, 33, 12, seed=5, stream=2, t=9)
+    r2, d2 = oracle.draw_lines(Ah, 33, 12, seed=5, stream=2, t=9)
+    assert np.array_equal(r1, r2) and np.array_equal(d1, d2)
+    assert np.all(np.diff(r1) > 0) and r1.size <= 12 and set(d1.tolist()) == set(r1.tolist())
+    d_other = [oracle.draw_lines(Ah, 33, 12, seed=5, stream=2, t=t)[1] for t in (10, 11, 12)]
+    assert any(not np.array_equal(d1, d) for d in d_other)      # the counter carries t
+
+
+# ----------------------------------------------------------------- regression fixture
+def test_oracle_matches_its_committed_fixture():
+    import json
+    with open(os.path.join(GOLDEN, "oracle_config1_first_frames.json")) as fh:
+        gold = json.load(fh)
+    c = I.config1(T=len(gold["gamma"]))
+    o = oracle.TslOracle(c["n1"], c["n2"], c["r"], 0.1, c["A0"], c["B0"])
+    for t, fr in enumerate(c["frames"]):
+        s = o.push_points(fr.mask, fr.y)
+        g = np.array(gold["gamma"][t][0]) + 1j * np.array(gold["gamma"][t][1])
+        assert _nr(s.gamma, g) < 1e-12
+        assert abs(s.alpha_bar - gold["alpha_bar"][t]) < 1e-9 * gold["alpha_bar"][t]
