@@ -1,0 +1,205 @@
+/*
+ * tsl.h -- C ABI of the MI355X online PARAFAC subspace-tracking step.
+ *
+ * Method: Mardani, Giannakis, Ugurbil, "Tracking Tensor Subspaces with
+ * Informative Random Sampling for Real-Time MR Imaging" (arXiv 1609.04104).
+ * One sequence ("scan") is a stream of N1 x N2 k-space frames acquired with a
+ * single coil.  Its state is a pair of image-domain factors A (N1 x R) and
+ * B (N2 x R) plus the step-size accumulator alpha_bar and the frame counter t.
+ * Each pushed frame runs one pass of Algorithm 3 with one coil (Sec. IV-B):
+ * the ridge solve for gamma_t (Sec. III-A, S1), the residual of the sampled
+ * k-space against F(A diag(gamma_t) B^T), its back-projection F^{-1}(Xi) and the
+ * majorization-minimization factor updates (eq. 6, Algorithm 3 S2); it returns
+ * X_t = A[t] diag(gamma_t) B[t]^T (Sec. IV-A).  tsl_sample_lines draws the
+ * next frame's phase-encode rows by Algorithm 4 with the row score of Sec. VI-C.
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer (e.g. torch.Tensor.data_ptr()),
+ *     unless its comment says "host".  Complex numbers are interleaved
+ *     (re, im) float32 pairs, i.e. torch.complex64.  Arrays are row-major:
+ *     a frame is [n1][n2] (row = phase-encode line, column = readout sample),
+ *     a factor is [n][r].
+ *   - k-space is in natural FFT order (DC at index 0); the 2-D transform is
+ *     unitary, F(X) = F_l X F_r with [F_N]_{km} = N^{-1/2} exp(-2 pi i k m / N).
+ *   - `stream` is a hipStream_t (torch.cuda.current_stream().cuda_stream;
+ *     NULL = the null stream).  Calls are stream-ordered and asynchronous:
+ *     the caller keeps every buffer valid until the stream has passed the call.
+ *   - Supported transform lengths: see tsl_size_supported (products of
+ *     2, 3 and 5 between 8 and 512 from a fixed list).  1 <= r <= TSL_MAX_R.
+ *
+ * Ownership
+ *   - The caller owns every buffer it passes; the library never frees them.
+ *   - The library owns a tsl_seq (its device state and workspace); tsl_close
+ *     releases it.  One handle is used by one host thread at a time.
+ *
+ * Errors
+ *   - Argument errors are detected before anything is enqueued and return a
+ *     negative code; the state is untouched and tsl_last_error() (thread-local)
+ *     says why.
+ *   - Errors the device detects (a non-positive-definite ridge Gram, NaN/Inf in
+ *     a sample or in a result, rows out of range / not ascending) latch into the
+ *     sequence's status word.  The frame that raised it is not committed (A, B,
+ *     alpha_bar and t keep their values) and later frames of that sequence are
+ *     skipped on the device until the status is cleared; tsl_status reports it.
+ *   - HIP runtime failures return TSL_EDEVICE.
+ */
+#ifndef TSL_H
+#define TSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSL_MAX_R 128
+
+typedef struct tsl_seq tsl_seq;
+typedef struct tsl_pool tsl_pool;
+typedef struct { float re, im; } tsl_c32;
+
+enum {
+    TSL_OK = 0,
+    TSL_EINVAL = -1,         /* bad argument, or (device) bad row list            */
+    TSL_ENOMEM = -2,         /* device allocation failed                          */
+    TSL_EDEVICE = -3,        /* HIP runtime error                                 */
+    TSL_ENOTPD = -4,         /* (device) ridge Gram not positive definite         */
+    TSL_ENONFINITE = -5,     /* (device) NaN or Inf in a sample or a result       */
+    TSL_EBUSY = -6,          /* pool budget exhausted                             */
+    TSL_EUNSUPPORTED = -7    /* transform length not in the supported list        */
+};
+
+enum { TSL_STEP_MM = 0, TSL_STEP_CONST = 1 };
+
+typedef struct {
+    int      step_mode;      /* TSL_STEP_MM: mu_t = 1/alpha_bar_t, the recursion of
+                                eq. (6) (default).  TSL_STEP_CONST: mu_t = mu.       */
+    double   mu;             /* constant step, used iff step_mode == TSL_STEP_CONST   */
+    int      allow_lambda0;  /* accept lambda == 0 (tests of exact recovery)          */
+    uint64_t seed;           /* sampler key word 0 (Philox4x64-10)                    */
+    uint64_t stream_id;      /* sampler key word 1                                    */
+} tsl_opts;
+
+/* One frame of one sequence, for tsl_step_many.  Exactly one of `rows` (line
+   mask) or `mask` (point mask) is non-NULL; see tsl_push_lines / _points. */
+typedef struct {
+    int            n_rows;   /* host: number of rows (line masks), 0..n1             */
+    const int32_t* rows;     /* [n_rows] ascending row indices, or NULL               */
+    const uint8_t* mask;     /* [n1][n2] 0/1 point mask, or NULL                      */
+    const tsl_c32* y;        /* [n_rows][n2] (lines) or [n1][n2] (points) samples     */
+    tsl_c32*       X_out;    /* [n1][n2] or NULL                                      */
+    tsl_c32*       A_out;    /* [n1][r] or NULL                                       */
+    tsl_c32*       B_out;    /* [n2][r] or NULL                                       */
+    tsl_c32*       gamma_out;/* [r] or NULL                                           */
+} tsl_frame;
+
+/* Fills *o with the defaults: MM step, lambda > 0 required, seed 0, stream 0. */
+void tsl_opts_default(tsl_opts* o);
+
+/* 1 if n is a supported transform length, else 0.  Host only. */
+int tsl_size_supported(int n);
+
+/* Device bytes one sequence of this shape holds (state plus workspace); the
+   unit of the pool's admission.  Host only; returns TSL_OK or TSL_EINVAL. */
+int tsl_footprint(int n1, int n2, int r, size_t* bytes);
+
+/* Opens a sequence: validates, allocates, copies A0 [n1][r] and B0 [n2][r]
+   (device) into the resident state, sets alpha_bar = 0 and t = 0 (Algorithm 3's
+   initialisation; the caller draws the start, e.g. at random or from a warm
+   start), and computes the k-space factors F_l A0, F_r B0.  lambda >= 0 is the
+   Tikhonov weight of (P2); lambda == 0 needs opts->allow_lambda0.  opts may be
+   NULL (defaults). */
+int tsl_open(tsl_seq** out, int n1, int n2, int r, double lambda, const tsl_opts* opts,
+             const tsl_c32* A0, const tsl_c32* B0, void* stream);
+
+/* Releases the sequence after synchronising its last stream.  NULL is a no-op. */
+int tsl_close(tsl_seq* s);
+
+/* Pushes frame t = t+1 whose sample set is the full k-space rows `rows`
+   (Sec. VI: Cartesian phase-encode lines), per Algorithm 3 with one coil:
+     gamma_t = (Phi^H Phi + lambda I)^{-1} Phi^H y   (S1, Sec. III-A),
+     Xi      = M .* (Y - F(A diag(gamma_t) B^T)),     Theta = F^{-1}(Xi),
+     A <- (1 - lambda mu_t / t) A + mu_t Theta conj(B) conj(diag(gamma_t)),
+     B <- (1 - lambda mu_t / t) B + mu_t Theta^T conj(A) conj(diag(gamma_t)),
+   with mu_t from the MM recursion (eq. 6) or constant, both updates reading the
+   factors of frame t-1.  rows: [n_rows] int32, strictly ascending, in [0, n1)
+   (checked on the device: TSL_EINVAL latches otherwise); y: [n_rows][n2]
+   complex64, y[s][j] the sample at (rows[s], j).  n_rows == 0 is allowed
+   (gamma = 0, pure shrink).  Outputs (each may be NULL): X_out [n1][n2] =
+   A[t] diag(gamma_t) B[t]^T, A_out [n1][r], B_out [n2][r], gamma_out [r]. */
+int tsl_push_lines(tsl_seq* s, int n_rows, const int32_t* rows, const tsl_c32* y,
+                   tsl_c32* X_out, tsl_c32* A_out, tsl_c32* B_out, tsl_c32* gamma_out,
+                   void* stream);
+
+/* As tsl_push_lines for an arbitrary sample set: mask [n1][n2] uint8 (nonzero =
+   sampled), y [n1][n2] complex64 read only where mask is set (eq. 10). */
+int tsl_push_points(tsl_seq* s, const uint8_t* mask, const tsl_c32* y,
+                    tsl_c32* X_out, tsl_c32* A_out, tsl_c32* B_out, tsl_c32* gamma_out,
+                    void* stream);
+
+/* Draws the row set of frame t+1 by Algorithm 4 on rows (Sec. VI-C): row score
+   s(i) proportional to N2 ||abar_i||^2 + R with abar the column-normalised
+   k-space factor F_l A[t]; K >= 1 draws with replacement from Philox4x64-10 at
+   counter (t+1, k, 0, 0) and key (seed, stream_id); every weight and sum in
+   float64 in index order.  rows_out [K] receives the distinct rows ascending,
+   n_out [1] their count (<= K).  Optional (may be NULL): draws_out [K] int32,
+   the row of each trial; prefix_out [n1] float64, the inclusive prefix of the
+   unnormalised weights. */
+int tsl_sample_lines(tsl_seq* s, int K, int32_t* rows_out, int32_t* n_out,
+                     int32_t* draws_out, double* prefix_out, void* stream);
+
+/* Batched push: frame frames[i] for sequence seqs[i], i < n, as n independent
+   tsl_push_* calls would, in one stream-ordered step.  Sequences of equal
+   shape share launches; the launch sequence of a batch composition is captured
+   once in a HIP graph and replayed while the composition repeats.  The
+   sequences must be distinct. */
+int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* stream);
+
+/* Synchronises the sequence's last stream and returns its latched device
+   status (TSL_OK or a negative code); clears it if clear != 0. */
+int tsl_status(tsl_seq* s, int clear);
+
+/* Copies the current factors (device): A [n1][r], B [n2][r] and the k-space
+   factors F_l A [n1][r], F_r B [n2][r]; any pointer may be NULL. */
+int tsl_get_factors(tsl_seq* s, tsl_c32* A, tsl_c32* B, tsl_c32* Ahat, tsl_c32* Bhat,
+                    void* stream);
+
+/* Host-blob checkpoint of the whole state (A, B, alpha_bar, t, options).
+   tsl_get_state with blob == NULL stores the size in *nbytes.  Both
+   synchronise the sequence's stream.  tsl_set_state needs a blob of the same
+   shape (TSL_EINVAL otherwise) and clears the status. */
+int tsl_get_state(tsl_seq* s, void* host_blob, size_t* nbytes);
+int tsl_set_state(tsl_seq* s, const void* host_blob, size_t nbytes);
+
+/* Shape queries (host). */
+int tsl_shape(const tsl_seq* s, int* n1, int* n2, int* r);
+
+/* Standalone batched unitary 2-D transform of `batch` frames [n1][n2]
+   (forward exp(-2 pi i k n / N) if inverse == 0, else its inverse), the
+   transform the step applies to full frames (Sec. IV).  in and out may alias. */
+int tsl_fft2(int n1, int n2, int batch, const tsl_c32* in, tsl_c32* out, int inverse,
+             void* stream);
+
+/* Serving admission: a pool with a device-byte budget.  tsl_open_in_pool is
+   tsl_open that first reserves tsl_footprint bytes from the pool and returns
+   TSL_EBUSY (nothing allocated) if the budget would be exceeded; closing the
+   sequence returns its bytes. */
+int tsl_pool_create(tsl_pool** out, size_t budget_bytes);
+int tsl_pool_destroy(tsl_pool* p);
+int tsl_pool_used(const tsl_pool* p, size_t* used, size_t* budget);
+int tsl_open_in_pool(tsl_pool* p, tsl_seq** out, int n1, int n2, int r, double lambda,
+                     const tsl_opts* opts, const tsl_c32* A0, const tsl_c32* B0, void* stream);
+
+/* Text of the last failing call on this thread ("" if none). */
+const char* tsl_last_error(void);
+
+/* Host-side self-test of the in-register DFT codelets against a direct DFT in
+   double precision; returns the largest relative error.  No device use. */
+double tsl_selftest_codelets(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSL_H */

@@ -1,0 +1,620 @@
+// Host side of the library: sequence state and workspace, argument checks,
+// the launch sequence of one step, batched steps replayed from HIP graphs, the
+// admission pool and state checkpoints.  Exposed through the C ABI in tsl.h.
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+#include "tsl.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return TSL_EDEVICE;
+}
+
+#define TSL_HIP(call)                                       \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, part, hpart, total;
+};
+
+Layout layout_for(int n1, int n2, int r) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L.A = take(size_t(n1) * r * sizeof(float2));
+    L.B = take(size_t(n2) * r * sizeof(float2));
+    L.Ahat = take(size_t(n1) * r * sizeof(float2));
+    L.Bhat = take(size_t(n2) * r * sizeof(float2));
+    L.dev = take(sizeof(tsl::SeqDev));
+    L.g64 = take(size_t(r) * sizeof(double2));
+    L.g32 = take(size_t(r) * sizeof(float2));
+    L.frame = take(size_t(n1) * n2 * sizeof(float2));
+    L.Wb = take(size_t(n2) * r * sizeof(float2));
+    L.GA = take(size_t(n1) * r * sizeof(float2));
+    L.part = take(size_t(tsl::n_parts(n1, n2)) * r * r * sizeof(double2));
+    L.hpart = take(size_t(tsl::n_sparts(n1)) * r * sizeof(double2));
+    L.total = o;
+    return L;
+}
+
+std::mutex g_graph_mu;
+
+}  // namespace
+
+struct tsl_pool {
+    std::mutex mu;
+    size_t budget = 0, used = 0;
+};
+
+struct tsl_seq {
+    int n1 = 0, n2 = 0, r = 0, device = 0;
+    double lambda = 0;
+    tsl_opts opts{};
+    char* arena = nullptr;
+    size_t bytes = 0;
+    Layout lay{};
+    hipStream_t last = nullptr;
+    tsl_pool* pool = nullptr;
+    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(arena + off); }
+};
+
+namespace {
+
+// -------------------------------------------------------------- frame descriptors
+tsl::FrameArgs frame_args(const tsl_seq* s, int mode, int n_rows, const int32_t* rows, const uint8_t* mask,
+                          const tsl_c32* y, tsl_c32* X_out, tsl_c32* A_out, tsl_c32* B_out, tsl_c32* g_out) {
+    tsl::FrameArgs a{};
+    a.n1 = s->n1; a.n2 = s->n2; a.r = s->r; a.mode = mode;
+    a.lambda = s->lambda; a.mu_const = s->opts.mu; a.step_mode = s->opts.step_mode;
+    a.n_rows = n_rows;
+    a.A = s->at<float2>(s->lay.A); a.B = s->at<float2>(s->lay.B);
+    a.Ahat = s->at<float2>(s->lay.Ahat); a.Bhat = s->at<float2>(s->lay.Bhat);
+    a.dev = s->at<tsl::SeqDev>(s->lay.dev);
+    a.gamma64 = s->at<double2>(s->lay.g64); a.gamma32 = s->at<float2>(s->lay.g32);
+    a.frame = s->at<float2>(s->lay.frame); a.Wb = s->at<float2>(s->lay.Wb); a.GA = s->at<float2>(s->lay.GA);
+    a.part = s->at<double2>(s->lay.part); a.hpart = s->at<double2>(s->lay.hpart);
+    a.rows = rows; a.mask = mask; a.y = reinterpret_cast<const float2*>(y);
+    a.X_out = reinterpret_cast<float2*>(X_out); a.A_out = reinterpret_cast<float2*>(A_out);
+    a.B_out = reinterpret_cast<float2*>(B_out); a.gamma_out = reinterpret_cast<float2*>(g_out);
+    return a;
+}
+
+// The launch sequence of one step (Algorithm 3 with one coil) for one group.
+int run_phases(const tsl::Batch& b, hipStream_t st) {
+    hipError_t e;
+    if ((e = tsl::launch_stats(b, st)) != hipSuccess) return hip_fail(e, "stats");            // a2
+    if ((e = tsl::launch_solve(b, st)) != hipSuccess) return hip_fail(e, "solve");            // a3, a8
+    if ((e = tsl::launch_synth_rowfft(b, st)) != hipSuccess) return hip_fail(e, "synth");     // a4, a5 rows
+    if ((e = tsl::launch_col_resid(b, st)) != hipSuccess) return hip_fail(e, "col");          // a5 cols, a6, a7 cols
+    if ((e = tsl::launch_row_inv_grad(b, st)) != hipSuccess) return hip_fail(e, "rowinv");    // a7 rows, a9
+    if ((e = tsl::launch_update_a(b, st)) != hipSuccess) return hip_fail(e, "update_a");      // a9, a1
+    if ((e = tsl::launch_update_b(b, st)) != hipSuccess) return hip_fail(e, "update_b");      // a9, a1
+    if ((e = tsl::launch_synth_out(b, st)) != hipSuccess) return hip_fail(e, "synth_out");    // a10
+    return TSL_OK;
+}
+
+int check_seq(const tsl_seq* s) {
+    if (!s) return fail(TSL_EINVAL, "null sequence handle");
+    return TSL_OK;
+}
+
+int set_dev(const tsl_seq* s) {
+    TSL_HIP(hipSetDevice(s->device));
+    return TSL_OK;
+}
+
+// -------------------------------------------------------------- batched step state
+struct GroupKey {
+    int n1, n2, mode, count, r_max, rows_max;
+    bool want_x;
+    bool operator==(const GroupKey& o) const {
+        return n1 == o.n1 && n2 == o.n2 && mode == o.mode && count == o.count && r_max == o.r_max &&
+               rows_max == o.rows_max && want_x == o.want_x;
+    }
+};
+
+struct Composition {
+    std::vector<const tsl_seq*> seqs;     // in the order of the call
+    std::vector<int> wants;               // per frame: bit0 X, bit1 A, bit2 B, bit3 gamma, bit4 points
+    std::vector<int> order;               // frame indices sorted by group
+    std::vector<GroupKey> groups;
+    std::vector<int> group_start;         // offset into order / table
+    bool operator==(const Composition& o) const {
+        return seqs == o.seqs && wants == o.wants;
+    }
+};
+
+struct BatchEngine {
+    int device = -1;
+    hipStream_t cap = nullptr;            // capture stream (never executes work)
+    tsl::FrameArgs* table = nullptr;      // device table
+    size_t table_cap = 0;
+    static constexpr int kRing = 8;
+    tsl::FrameArgs* staging[kRing] = {};
+    hipEvent_t staged[kRing] = {};
+    int ring_pos = 0;
+    size_t staging_cap = 0;
+    Composition comp;
+    bool have_graph = false;
+    hipGraphExec_t exec = nullptr;
+    int rows_cap = 0;                     // rows_max the graph was sized for (per group)
+};
+
+BatchEngine g_batch;
+
+void drop_graph(BatchEngine& be) {
+    if (be.exec) hipGraphExecDestroy(be.exec);
+    be.exec = nullptr;
+    be.have_graph = false;
+    be.comp = Composition{};
+}
+
+int ensure_batch_buffers(BatchEngine& be, size_t n) {
+    int dev = 0;
+    TSL_HIP(hipGetDevice(&dev));
+    if (be.device != dev) {
+        drop_graph(be);
+        be.device = dev;
+        if (be.cap) hipStreamDestroy(be.cap);
+        TSL_HIP(hipStreamCreateWithFlags(&be.cap, hipStreamNonBlocking));
+        be.table_cap = 0;
+        be.staging_cap = 0;
+    }
+    if (be.table_cap < n) {
+        drop_graph(be);
+        if (be.table) hipFree(be.table);
+        size_t cap = n < 64 ? 64 : n;
+        TSL_HIP(hipMalloc(&be.table, cap * sizeof(tsl::FrameArgs)));
+        be.table_cap = cap;
+    }
+    if (be.staging_cap < n) {
+        for (int k = 0; k < BatchEngine::kRing; ++k) {
+            if (be.staged[k]) hipEventSynchronize(be.staged[k]);
+            if (be.staging[k]) hipHostFree(be.staging[k]);
+            size_t cap = n < 64 ? 64 : n;
+            TSL_HIP(hipHostMalloc(&be.staging[k], cap * sizeof(tsl::FrameArgs), hipHostMallocDefault));
+            if (!be.staged[k]) TSL_HIP(hipEventCreateWithFlags(&be.staged[k], hipEventDisableTiming));
+        }
+        be.staging_cap = n < 64 ? 64 : n;
+    }
+    return TSL_OK;
+}
+
+int launch_groups(const Composition& c, const tsl::FrameArgs* table, hipStream_t st) {
+    for (size_t g = 0; g < c.groups.size(); ++g) {
+        const GroupKey& k = c.groups[g];
+        tsl::Batch b{};
+        b.one = nullptr;
+        b.table = table + c.group_start[g];
+        b.count = k.count;
+        b.n1 = k.n1; b.n2 = k.n2; b.r_max = k.r_max; b.rows_max = k.rows_max;
+        b.mode = k.mode; b.want_x = k.want_x;
+        int rc = run_phases(b, st);
+        if (rc != TSL_OK) return rc;
+    }
+    return TSL_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void tsl_opts_default(tsl_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->step_mode = TSL_STEP_MM;
+    o->mu = 0.0;
+    o->allow_lambda0 = 0;
+}
+
+int tsl_size_supported(int n) { return tsl::size_supported(n) ? 1 : 0; }
+
+static int validate_shape(int n1, int n2, int r) {
+    if (!tsl::size_supported(n1) || !tsl::size_supported(n2))
+        return fail(TSL_EUNSUPPORTED, "n1 and n2 must be supported transform lengths (see tsl_size_supported)");
+    if (r < 1 || r > TSL_MAX_R) return fail(TSL_EINVAL, "r must be in [1, TSL_MAX_R]");
+    return TSL_OK;
+}
+
+int tsl_footprint(int n1, int n2, int r, size_t* bytes) {
+    int rc = validate_shape(n1, n2, r);
+    if (rc != TSL_OK) return rc;
+    if (!bytes) return fail(TSL_EINVAL, "null bytes");
+    *bytes = layout_for(n1, n2, r).total;
+    return TSL_OK;
+}
+
+const char* tsl_last_error(void) { return g_err.c_str(); }
+
+static int open_impl(tsl_pool* pool, tsl_seq** out, int n1, int n2, int r, double lambda, const tsl_opts* opts,
+                     const tsl_c32* A0, const tsl_c32* B0, void* stream) {
+    if (!out) return fail(TSL_EINVAL, "null output handle");
+    *out = nullptr;
+    int rc = validate_shape(n1, n2, r);
+    if (rc != TSL_OK) return rc;
+    tsl_opts o;
+    tsl_opts_default(&o);
+    if (opts) o = *opts;
+    if (!std::isfinite(lambda) || lambda < 0.0) return fail(TSL_EINVAL, "lambda must be finite and >= 0");
+    if (lambda == 0.0 && !o.allow_lambda0) return fail(TSL_EINVAL, "lambda == 0 needs allow_lambda0");
+    if (o.step_mode != TSL_STEP_MM && o.step_mode != TSL_STEP_CONST) return fail(TSL_EINVAL, "bad step_mode");
+    if (o.step_mode == TSL_STEP_CONST && !(o.mu > 0.0 && std::isfinite(o.mu)))
+        return fail(TSL_EINVAL, "constant step needs a finite mu > 0");
+    if (!A0 || !B0) return fail(TSL_EINVAL, "null A0 or B0");
+    Layout L = layout_for(n1, n2, r);
+    tsl::init_kernel_attributes();
+    if (pool) {
+        std::lock_guard<std::mutex> lk(pool->mu);
+        if (pool->used + L.total > pool->budget) return fail(TSL_EBUSY, "pool budget exhausted");
+        pool->used += L.total;
+    }
+    auto release = [&]() {
+        if (pool) {
+            std::lock_guard<std::mutex> lk(pool->mu);
+            pool->used -= L.total;
+        }
+    };
+    tsl_seq* s = new tsl_seq();
+    s->n1 = n1; s->n2 = n2; s->r = r; s->lambda = lambda; s->opts = o; s->lay = L; s->bytes = L.total;
+    s->pool = pool;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    s->last = st;
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipMalloc(&s->arena, L.total);
+    if (e != hipSuccess) {
+        delete s;
+        release();
+        return e == hipErrorOutOfMemory ? fail(TSL_ENOMEM, "device allocation failed")
+                                        : hip_fail(e, "hipMalloc");
+    }
+    auto bail = [&](hipError_t err, const char* what) {
+        hipFree(s->arena);
+        delete s;
+        release();
+        return hip_fail(err, what);
+    };
+    if ((e = hipMemsetAsync(s->arena, 0, L.total, st)) != hipSuccess) return bail(e, "memset");
+    if ((e = hipMemcpyAsync(s->at<void>(L.A), A0, size_t(n1) * r * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
+        hipSuccess)
+        return bail(e, "copy A0");
+    if ((e = hipMemcpyAsync(s->at<void>(L.B), B0, size_t(n2) * r * sizeof(float2), hipMemcpyDeviceToDevice, st)) !=
+        hipSuccess)
+        return bail(e, "copy B0");
+    if ((e = tsl::launch_factor_fft(n1, r, s->at<float2>(L.A), s->at<float2>(L.Ahat), false, st)) != hipSuccess)
+        return bail(e, "F_l A0");
+    if ((e = tsl::launch_factor_fft(n2, r, s->at<float2>(L.B), s->at<float2>(L.Bhat), false, st)) != hipSuccess)
+        return bail(e, "F_r B0");
+    *out = s;
+    return TSL_OK;
+}
+
+int tsl_open(tsl_seq** out, int n1, int n2, int r, double lambda, const tsl_opts* opts, const tsl_c32* A0,
+             const tsl_c32* B0, void* stream) {
+    return open_impl(nullptr, out, n1, n2, r, lambda, opts, A0, B0, stream);
+}
+
+int tsl_open_in_pool(tsl_pool* p, tsl_seq** out, int n1, int n2, int r, double lambda, const tsl_opts* opts,
+                     const tsl_c32* A0, const tsl_c32* B0, void* stream) {
+    if (!p) return fail(TSL_EINVAL, "null pool");
+    return open_impl(p, out, n1, n2, r, lambda, opts, A0, B0, stream);
+}
+
+int tsl_close(tsl_seq* s) {
+    if (!s) return TSL_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (const tsl_seq* q : g_batch.comp.seqs)
+            if (q == s) { drop_graph(g_batch); break; }
+    }
+    hipSetDevice(s->device);
+    hipError_t e = hipStreamSynchronize(s->last);
+    hipFree(s->arena);
+    if (s->pool) {
+        std::lock_guard<std::mutex> lk(s->pool->mu);
+        s->pool->used -= s->bytes;
+    }
+    delete s;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return TSL_OK;
+}
+
+static int push_impl(tsl_seq* s, int mode, int n_rows, const int32_t* rows, const uint8_t* mask, const tsl_c32* y,
+                     tsl_c32* X_out, tsl_c32* A_out, tsl_c32* B_out, tsl_c32* g_out, void* stream) {
+    int rc = check_seq(s);
+    if (rc != TSL_OK) return rc;
+    if (mode == tsl::MODE_LINES) {
+        if (n_rows < 0 || n_rows > s->n1) return fail(TSL_EINVAL, "n_rows must be in [0, n1]");
+        if (n_rows > 0 && (!rows || !y)) return fail(TSL_EINVAL, "null rows or y");
+    } else {
+        if (!mask || !y) return fail(TSL_EINVAL, "null mask or y");
+    }
+    if ((rc = set_dev(s)) != TSL_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    s->last = st;
+    tsl::FrameArgs a = frame_args(s, mode, n_rows, rows, mask, y, X_out, A_out, B_out, g_out);
+    tsl::Batch b{};
+    b.one = &a;
+    b.table = nullptr;
+    b.count = 1;
+    b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r; b.rows_max = n_rows; b.mode = mode;
+    b.want_x = X_out != nullptr;
+    return run_phases(b, st);
+}
+
+int tsl_push_lines(tsl_seq* s, int n_rows, const int32_t* rows, const tsl_c32* y, tsl_c32* X_out, tsl_c32* A_out,
+                   tsl_c32* B_out, tsl_c32* gamma_out, void* stream) {
+    return push_impl(s, tsl::MODE_LINES, n_rows, rows, nullptr, y, X_out, A_out, B_out, gamma_out, stream);
+}
+
+int tsl_push_points(tsl_seq* s, const uint8_t* mask, const tsl_c32* y, tsl_c32* X_out, tsl_c32* A_out,
+                    tsl_c32* B_out, tsl_c32* gamma_out, void* stream) {
+    return push_impl(s, tsl::MODE_POINTS, 0, nullptr, mask, y, X_out, A_out, B_out, gamma_out, stream);
+}
+
+int tsl_sample_lines(tsl_seq* s, int K, int32_t* rows_out, int32_t* n_out, int32_t* draws_out, double* prefix_out,
+                     void* stream) {
+    int rc = check_seq(s);
+    if (rc != TSL_OK) return rc;
+    if (K < 1) return fail(TSL_EINVAL, "K must be >= 1");
+    if (!rows_out || !n_out) return fail(TSL_EINVAL, "null rows_out or n_out");
+    if ((rc = set_dev(s)) != TSL_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    s->last = st;
+    tsl::FrameArgs a = frame_args(s, tsl::MODE_LINES, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                  nullptr);
+    hipError_t e = tsl::launch_sample(a, K, s->opts.seed, s->opts.stream_id, rows_out, n_out, draws_out, prefix_out,
+                                      st);
+    if (e != hipSuccess) return hip_fail(e, "sample");
+    return TSL_OK;
+}
+
+int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* stream) {
+    if (n < 0 || (n > 0 && (!seqs || !frames))) return fail(TSL_EINVAL, "bad batch arguments");
+    if (n == 0) return TSL_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    Composition c;
+    c.seqs.resize(n);
+    c.wants.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const tsl_seq* s = seqs[i];
+        const tsl_frame& fr = frames[i];
+        if (!s) return fail(TSL_EINVAL, "null sequence in batch");
+        for (int j = 0; j < i; ++j)
+            if (seqs[j] == s) return fail(TSL_EINVAL, "a sequence appears twice in one batch");
+        const bool points = fr.mask != nullptr;
+        if (points && fr.rows != nullptr) return fail(TSL_EINVAL, "a frame has both rows and a mask");
+        if (!points) {
+            if (fr.n_rows < 0 || fr.n_rows > s->n1) return fail(TSL_EINVAL, "n_rows must be in [0, n1]");
+            if (fr.n_rows > 0 && (!fr.rows || !fr.y)) return fail(TSL_EINVAL, "null rows or y");
+        } else if (!fr.y) {
+            return fail(TSL_EINVAL, "null y");
+        }
+        c.seqs[i] = s;
+        c.wants[i] = (fr.X_out ? 1 : 0) | (fr.A_out ? 2 : 0) | (fr.B_out ? 4 : 0) | (fr.gamma_out ? 8 : 0) |
+                     (points ? 16 : 0);
+    }
+    // group frames by (n1, n2, mode), keeping call order inside a group
+    std::map<std::tuple<int, int, int>, std::vector<int>> by;
+    for (int i = 0; i < n; ++i)
+        by[{seqs[i]->n1, seqs[i]->n2, (c.wants[i] & 16) ? 1 : 0}].push_back(i);
+    for (auto& kv : by) {
+        GroupKey k{};
+        k.n1 = std::get<0>(kv.first); k.n2 = std::get<1>(kv.first); k.mode = std::get<2>(kv.first);
+        k.count = int(kv.second.size());
+        k.r_max = 0; k.rows_max = 0; k.want_x = false;
+        for (int i : kv.second) {
+            k.r_max = std::max(k.r_max, seqs[i]->r);
+            k.rows_max = k.n1;   // grids are sized for a full row set so any n_rows replays
+            k.want_x = k.want_x || frames[i].X_out != nullptr;
+        }
+        c.group_start.push_back(int(c.order.size()));
+        for (int i : kv.second) c.order.push_back(i);
+        c.groups.push_back(k);
+    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    BatchEngine& be = g_batch;
+    int rc = ensure_batch_buffers(be, size_t(n));
+    if (rc != TSL_OK) return rc;
+    // stage the descriptors (pinned ring) and copy them to the device table
+    const int slot = be.ring_pos;
+    be.ring_pos = (be.ring_pos + 1) % BatchEngine::kRing;
+    TSL_HIP(hipEventSynchronize(be.staged[slot]));
+    tsl::FrameArgs* host = be.staging[slot];
+    for (int p = 0; p < n; ++p) {
+        const int i = c.order[p];
+        const tsl_frame& fr = frames[i];
+        tsl_seq* s = const_cast<tsl_seq*>(seqs[i]);
+        s->last = st;
+        host[p] = frame_args(s, fr.mask ? tsl::MODE_POINTS : tsl::MODE_LINES, fr.mask ? 0 : fr.n_rows, fr.rows,
+                             fr.mask, fr.y, fr.X_out, fr.A_out, fr.B_out, fr.gamma_out);
+    }
+    TSL_HIP(hipMemcpyAsync(be.table, host, size_t(n) * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice, st));
+    TSL_HIP(hipEventRecord(be.staged[slot], st));
+    if (!(be.have_graph && be.comp == c)) {
+        drop_graph(be);
+        hipGraph_t graph = nullptr;
+        TSL_HIP(hipStreamBeginCapture(be.cap, hipStreamCaptureModeThreadLocal));
+        int lrc = launch_groups(c, be.table, be.cap);
+        hipError_t ec = hipStreamEndCapture(be.cap, &graph);
+        if (lrc != TSL_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return lrc;
+        }
+        if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+        hipError_t ei = hipGraphInstantiate(&be.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            be.exec = nullptr;
+            return hip_fail(ei, "hipGraphInstantiate");
+        }
+        be.comp = c;
+        be.have_graph = true;
+    }
+    TSL_HIP(hipGraphLaunch(be.exec, st));
+    return TSL_OK;
+}
+
+int tsl_status(tsl_seq* s, int clear) {
+    int rc = check_seq(s);
+    if (rc != TSL_OK) return rc;
+    if ((rc = set_dev(s)) != TSL_OK) return rc;
+    TSL_HIP(hipStreamSynchronize(s->last));
+    tsl::SeqDev d{};
+    TSL_HIP(hipMemcpy(&d, s->at<void>(s->lay.dev), sizeof(d), hipMemcpyDeviceToHost));
+    if (clear && d.status != 0) {
+        int zero = 0;
+        TSL_HIP(hipMemcpy(s->at<char>(s->lay.dev) + offsetof(tsl::SeqDev, status), &zero, sizeof(int),
+                          hipMemcpyHostToDevice));
+    }
+    return d.status;
+}
+
+int tsl_get_factors(tsl_seq* s, tsl_c32* A, tsl_c32* B, tsl_c32* Ahat, tsl_c32* Bhat, void* stream) {
+    int rc = check_seq(s);
+    if (rc != TSL_OK) return rc;
+    if ((rc = set_dev(s)) != TSL_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    s->last = st;
+    const size_t a = size_t(s->n1) * s->r * sizeof(float2), b = size_t(s->n2) * s->r * sizeof(float2);
+    if (A) TSL_HIP(hipMemcpyAsync(A, s->at<void>(s->lay.A), a, hipMemcpyDeviceToDevice, st));
+    if (B) TSL_HIP(hipMemcpyAsync(B, s->at<void>(s->lay.B), b, hipMemcpyDeviceToDevice, st));
+    if (Ahat) TSL_HIP(hipMemcpyAsync(Ahat, s->at<void>(s->lay.Ahat), a, hipMemcpyDeviceToDevice, st));
+    if (Bhat) TSL_HIP(hipMemcpyAsync(Bhat, s->at<void>(s->lay.Bhat), b, hipMemcpyDeviceToDevice, st));
+    return TSL_OK;
+}
+
+namespace {
+struct BlobHeader {
+    char magic[8];
+    int version, n1, n2, r;
+    double lambda;
+    tsl_opts opts;
+    double abar;
+    long long t;
+};
+}  // namespace
+
+int tsl_get_state(tsl_seq* s, void* host_blob, size_t* nbytes) {
+    int rc = check_seq(s);
+    if (rc != TSL_OK) return rc;
+    if (!nbytes) return fail(TSL_EINVAL, "null nbytes");
+    const size_t a = size_t(s->n1) * s->r * sizeof(float2), b = size_t(s->n2) * s->r * sizeof(float2);
+    const size_t need = sizeof(BlobHeader) + 2 * a + 2 * b;
+    if (!host_blob) {
+        *nbytes = need;
+        return TSL_OK;
+    }
+    if (*nbytes < need) return fail(TSL_EINVAL, "blob too small");
+    if ((rc = set_dev(s)) != TSL_OK) return rc;
+    TSL_HIP(hipStreamSynchronize(s->last));
+    tsl::SeqDev d{};
+    TSL_HIP(hipMemcpy(&d, s->at<void>(s->lay.dev), sizeof(d), hipMemcpyDeviceToHost));
+    BlobHeader h{};
+    std::memcpy(h.magic, "TSLSTAT", 8);
+    h.version = 1; h.n1 = s->n1; h.n2 = s->n2; h.r = s->r; h.lambda = s->lambda; h.opts = s->opts;
+    h.abar = d.abar; h.t = d.t;
+    char* p = static_cast<char*>(host_blob);
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    TSL_HIP(hipMemcpy(p, s->at<void>(s->lay.A), a, hipMemcpyDeviceToHost)); p += a;
+    TSL_HIP(hipMemcpy(p, s->at<void>(s->lay.B), b, hipMemcpyDeviceToHost)); p += b;
+    TSL_HIP(hipMemcpy(p, s->at<void>(s->lay.Ahat), a, hipMemcpyDeviceToHost)); p += a;
+    TSL_HIP(hipMemcpy(p, s->at<void>(s->lay.Bhat), b, hipMemcpyDeviceToHost));
+    *nbytes = need;
+    return TSL_OK;
+}
+
+int tsl_set_state(tsl_seq* s, const void* host_blob, size_t nbytes) {
+    int rc = check_seq(s);
+    if (rc != TSL_OK) return rc;
+    if (!host_blob || nbytes < sizeof(BlobHeader)) return fail(TSL_EINVAL, "bad blob");
+    BlobHeader h{};
+    std::memcpy(&h, host_blob, sizeof(h));
+    const size_t a = size_t(s->n1) * s->r * sizeof(float2), b = size_t(s->n2) * s->r * sizeof(float2);
+    if (std::memcmp(h.magic, "TSLSTAT", 8) != 0 || h.version != 1 || h.n1 != s->n1 || h.n2 != s->n2 ||
+        h.r != s->r || nbytes < sizeof(BlobHeader) + 2 * a + 2 * b)
+        return fail(TSL_EINVAL, "blob does not match this sequence");
+    if ((rc = set_dev(s)) != TSL_OK) return rc;
+    TSL_HIP(hipStreamSynchronize(s->last));
+    const char* p = static_cast<const char*>(host_blob) + sizeof(h);
+    TSL_HIP(hipMemcpy(s->at<void>(s->lay.A), p, a, hipMemcpyHostToDevice)); p += a;
+    TSL_HIP(hipMemcpy(s->at<void>(s->lay.B), p, b, hipMemcpyHostToDevice)); p += b;
+    TSL_HIP(hipMemcpy(s->at<void>(s->lay.Ahat), p, a, hipMemcpyHostToDevice)); p += a;
+    TSL_HIP(hipMemcpy(s->at<void>(s->lay.Bhat), p, b, hipMemcpyHostToDevice));
+    tsl::SeqDev d{};
+    d.abar = h.abar;
+    d.t = h.t;
+    TSL_HIP(hipMemcpy(s->at<void>(s->lay.dev), &d, sizeof(d), hipMemcpyHostToDevice));
+    s->lambda = h.lambda;
+    s->opts = h.opts;
+    return TSL_OK;
+}
+
+int tsl_shape(const tsl_seq* s, int* n1, int* n2, int* r) {
+    if (!s) return fail(TSL_EINVAL, "null sequence handle");
+    if (n1) *n1 = s->n1;
+    if (n2) *n2 = s->n2;
+    if (r) *r = s->r;
+    return TSL_OK;
+}
+
+int tsl_fft2(int n1, int n2, int batch, const tsl_c32* in, tsl_c32* out, int inverse, void* stream) {
+    if (!tsl::size_supported(n1) || !tsl::size_supported(n2)) return fail(TSL_EUNSUPPORTED, "unsupported length");
+    if (batch < 0 || (batch > 0 && (!in || !out))) return fail(TSL_EINVAL, "bad fft2 arguments");
+    if (batch == 0) return TSL_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const float2* src = reinterpret_cast<const float2*>(in);
+    float2* dst = reinterpret_cast<float2*>(out);
+    hipError_t e = tsl::launch_rowfft(n1, n2, batch, src, dst, inverse != 0, st);
+    if (e != hipSuccess) return hip_fail(e, "row pass");
+    e = tsl::launch_colfft(n1, n2, batch, dst, dst, inverse != 0, st);
+    if (e != hipSuccess) return hip_fail(e, "column pass");
+    return TSL_OK;
+}
+
+int tsl_pool_create(tsl_pool** out, size_t budget_bytes) {
+    if (!out) return fail(TSL_EINVAL, "null pool output");
+    *out = new tsl_pool();
+    (*out)->budget = budget_bytes;
+    return TSL_OK;
+}
+
+int tsl_pool_destroy(tsl_pool* p) {
+    if (!p) return TSL_OK;
+    if (p->used != 0) return fail(TSL_EBUSY, "pool still has open sequences");
+    delete p;
+    return TSL_OK;
+}
+
+int tsl_pool_used(const tsl_pool* p, size_t* used, size_t* budget) {
+    if (!p) return fail(TSL_EINVAL, "null pool");
+    if (used) *used = p->used;
+    if (budget) *budget = p->budget;
+    return TSL_OK;
+}
+
+}  // extern "C"

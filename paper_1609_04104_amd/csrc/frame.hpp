@@ -1,0 +1,95 @@
+// Per-sequence device state, per-frame launch descriptors and the status word.
+#pragma once
+
+#include "common.hpp"
+
+namespace tsl {
+
+// Device status codes (same values as the TSL_* codes of the C ABI).
+enum : int { ST_OK = 0, ST_EINVAL = -1, ST_ENOTPD = -4, ST_ENONFINITE = -5 };
+
+// Scalars resident on the device for one sequence.
+struct SeqDev {
+    double abar;        // alpha_bar of the last committed frame
+    long long t;        // frames committed
+    int status;         // sticky: 0 or a negative ST_* code
+    int frame_ok;       // the current frame's solve succeeded
+    // written by the solve kernel, read by the later kernels of the same frame
+    double mu, shrink, alpha, abar_new;
+    long long t_new;
+    double kappa_proxy; // max pivot^2 / min pivot^2 of the Cholesky factor
+};
+
+enum : int { MODE_LINES = 0, MODE_POINTS = 1 };
+
+// Row chunks of the partial Gram statistics.
+constexpr int kGramRows = 64;   // rows of F_l A or F_r B per Gram partial
+constexpr int kSRows = 16;      // sampled rows per (Gram, rhs) partial, line masks
+constexpr int kPRows = 8;       // rows per (Gram, rhs) partial, point masks
+
+__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ inline int n_gram_a(int n1) { return cdiv(n1, kGramRows); }
+__host__ __device__ inline int n_gram_b(int n2) { return cdiv(n2, kGramRows); }
+__host__ __device__ inline int n_sparts(int n1) { return cdiv(n1, kPRows); }   // >= cdiv(n1, kSRows)
+__host__ __device__ inline int n_parts(int n1, int n2) { return n_gram_a(n1) + n_gram_b(n2) + n_sparts(n1); }
+
+// Everything the kernels of one frame of one sequence read or write.
+struct FrameArgs {
+    int n1, n2, r, mode;
+    double lambda, mu_const;
+    int step_mode, n_rows;
+    // resident state
+    float2 *A, *B, *Ahat, *Bhat;
+    SeqDev* dev;
+    double2* gamma64;
+    float2* gamma32;
+    // workspace
+    float2* frame;      // [n1][n2]: row-transformed synthesis, then the column-back-projected residual
+    float2* Wb;         // [n2][r]: Z^T conj(A), Z the column-back-projected residual
+    float2* GA;         // [n1][r]: Theta conj(B)
+    double2* part;      // [n_parts][r][r] partial Grams
+    double2* hpart;     // [n_sparts][r] partial right-hand sides
+    // inputs of the frame
+    const int* rows;
+    const unsigned char* mask;
+    const float2* y;
+    // outputs (may be null)
+    float2 *X_out, *A_out, *B_out, *gamma_out;
+};
+
+// Where a kernel finds its descriptor: one by value (single-sequence push) or
+// entry blockIdx.y of a device table (batched step).
+struct OneFrame {
+    FrameArgs a;
+    __device__ __forceinline__ const FrameArgs& get() const { return a; }
+};
+struct FrameTable {
+    const FrameArgs* t;
+    __device__ __forceinline__ const FrameArgs& get() const { return t[blockIdx.y]; }
+};
+
+// Latch an error code if none is latched yet (first error wins).
+__device__ __forceinline__ void latch(SeqDev* d, int code) {
+    atomicCAS(&d->status, 0, code);
+}
+
+// A block-uniform read of the frame's go/no-go flags: thread 0 reads, the
+// block agrees through LDS, so every thread takes the same branch.
+__device__ __forceinline__ bool block_frame_ok(const SeqDev* d, bool need_solve) {
+    __shared__ int s_go;
+    if (threadIdx.x == 0) {
+        int st = __hip_atomic_load(&d->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = need_solve ? d->frame_ok : 1;
+        s_go = (st == 0 && ok) ? 1 : 0;
+    }
+    __syncthreads();
+    int go = s_go;
+    __syncthreads();
+    return go != 0;
+}
+
+__device__ __forceinline__ bool finite2(float2 v) {
+    return isfinite(v.x) && isfinite(v.y);
+}
+
+}  // namespace tsl

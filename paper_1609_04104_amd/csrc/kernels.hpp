@@ -1,0 +1,54 @@
+// Host-side launchers of the step's kernels.  A Batch describes the frames of
+// one launch group: either one frame passed by value, or `count` frames of the
+// same (n1, n2) read from a device table (entry blockIdx.y).
+#pragma once
+
+#include "frame.hpp"
+
+namespace tsl {
+
+struct Batch {
+    const FrameArgs* one;        // single frame (by value), or null
+    const FrameArgs* table;      // device table of `count` frames, or null
+    int count;
+    int n1, n2;                  // shared by every frame of the group
+    int r_max;                   // largest rank in the group
+    int rows_max;                // largest n_rows (line masks)
+    int mode;                    // MODE_LINES or MODE_POINTS (shared)
+    bool want_x;                 // some frame asks for X_t
+};
+
+// Threads per block of the kernels that are not templated on a length.
+constexpr int kBlock = 256;
+
+// Row direction (length n2): K1 synthesis + row transform, K3 row inverse +
+// Theta conj(B); standalone row pass of the 2-D transform.
+hipError_t launch_synth_rowfft(const Batch& b, hipStream_t st);
+hipError_t launch_row_inv_grad(const Batch& b, hipStream_t st);
+hipError_t launch_rowfft(int n1, int n2, int batch, const float2* in, float2* out, bool inv, hipStream_t st);
+
+// Column direction (length n1 / n2): K2 column transform + residual + column
+// inverse + Z^T conj(A); K4 factor updates with the k-space factor transforms;
+// standalone column pass; plain column transform of a [n][r] factor.
+hipError_t launch_col_resid(const Batch& b, hipStream_t st);
+hipError_t launch_update_a(const Batch& b, hipStream_t st);
+hipError_t launch_update_b(const Batch& b, hipStream_t st);
+hipError_t launch_colfft(int n1, int n2, int batch, const float2* in, float2* out, bool inv, hipStream_t st);
+hipError_t launch_factor_fft(int n, int r, const float2* in, float2* out, bool inv, hipStream_t st);
+
+// Length-independent kernels: partial Grams (a2), ridge solve and step size
+// (a3, a8), output synthesis (a10), line sampler (a11), status clear.
+hipError_t launch_stats(const Batch& b, hipStream_t st);
+hipError_t launch_solve(const Batch& b, hipStream_t st);
+hipError_t launch_synth_out(const Batch& b, hipStream_t st);
+hipError_t launch_sample(const FrameArgs& a, int K, uint64_t seed, uint64_t stream_id, int* rows_out,
+                         int* n_out, int* draws_out, double* prefix_out, hipStream_t st);
+
+// Raises the dynamic-LDS limit of the kernels that need more than the default
+// (idempotent; called before any launch or graph capture).
+void init_kernel_attributes();
+
+bool size_supported(int n);
+int plan_threads(int n);   // T of Plan<n>, 0 if unsupported
+
+}  // namespace tsl
