@@ -1,0 +1,338 @@
+#!/usr/bin/env python3
+"""Throughput and latency of the online PARAFAC tracking step on one MI355X.
+
+Workload (synthetic cardiac-like cine; the paper's in-vivo scans are not
+available): S sequences of N x N frames (default 64 x 256^2), rank R = 32,
+lambda = 0.05, MM step size.  Every sequence starts with 5 fully sampled frames
+(warm start) and then acquires the rows that the previous step drew on the
+device (Algorithm 4, row score of Sec. VI-C, K = N/8 draws with replacement).
+One step = one frame of every sequence through the whole hot path: partial
+Grams, ridge solve and step size, synthesis + row transform, column transform +
+residual + column inverse, row inverse + gradients, factor updates with their
+k-space transforms, the output frame X_t, and the next rows -- all inputs
+resident in HBM before the timed region.
+
+Prints one JSON line: batched frames/s (value), the plain single-sequence path
+on the same GPU, p50/p99 per-frame latency of both, the per-phase split, the
+roofline of the dominant kernel and the FP64 CPU oracle's frames/s.
+"""
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VALU_PEAK_TFS = 157.3     # MI355X published FP32 vector peak
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--seqs", type=int, default=64)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--r", type=int, default=32)
+    ap.add_argument("--lam", type=float, default=0.05)
+    ap.add_argument("--frames", type=int, default=25, help="distinct k-space frames per sequence (cycled)")
+    ap.add_argument("--plain-frames", type=int, default=200)
+    ap.add_argument("--phase-steps", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+# ----------------------------------------------------------------------------- inputs
+def _gen(args):
+    n, r, frames, seq = args
+    from paper_1609_04104_amd import inputs as I
+    c = I.config3_kspace(T=frames, n1=n, n2=n, r=r, seq=seq)
+    return c["kspace"], c["A0"], c["B0"]
+
+
+def make_inputs(seqs, n, r, frames):
+    procs = max(1, min(16, os.cpu_count() or 1, seqs))
+    with mp.get_context("spawn").Pool(procs) as pool:
+        return pool.map(_gen, [(n, r, frames, s) for s in range(seqs)])
+
+
+# ----------------------------------------------------------------------------- work model
+def phase_work(n1, n2, r, rows, K):
+    """Algorithmic bytes and flops per frame of each phase (complex64 = 8 B,
+    complex MAC = 8 flop, length-N complex FFT = 5 N log2 N flop)."""
+    P, c = n1 * n2, 8
+    f1, f2 = 5 * P * math.log2(n1), 5 * P * math.log2(n2)
+    a, b = n1 * r, n2 * r
+    return {
+        "partial Grams": (c * (a + b + rows * n2) + 4 * rows, 8 * (a + b + rows) * r * r / 2 + 8 * rows * n2 * r),
+        "ridge solve + step size": (16 * r * r, 8 * r ** 3 / 3),
+        "synthesis + row pass": (c * (P + a + b), 8 * P * r + f2),
+        "column pass + residual": (c * (2 * P + rows * n2 + a + b) + 4 * rows, 2 * f1 + 8 * P * r),
+        "row inverse + A grad": (c * (P + a + b), f2 + 8 * P * r),
+        "A update + F_l A": (c * 4 * a, 5 * a * math.log2(n1) + 8 * a),
+        "B grad + update + F_r B": (c * 4 * b, 10 * b * math.log2(n2) + 8 * b),
+        "output synthesis": (c * (P + a + b), 8 * P * r),
+        "row draw": (2 * c * a + 4 * K, 6 * a),
+    }
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
+
+
+# ----------------------------------------------------------------------------- main
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                          "described, not built)"}))
+        return 2
+    import torch
+    from paper_1609_04104_amd import tsl
+
+    tsl.lib()
+    torch.cuda.set_device(0)
+    S, n, r, lam, F = a.seqs, a.n, a.r, a.lam, a.frames
+    K = max(1, n // 8)
+    warm = 5
+    print(f"[bench] generating {S} x {F} frames of {n}x{n}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    data = make_inputs(S, n, r, F)
+    print(f"[bench] inputs in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    Kd = [torch.from_numpy(d[0]).to(dev) for d in data]                  # [F, n, n] per sequence
+    full = torch.arange(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def open_seq(s):
+        A0, B0 = data[s][1], data[s][2]
+        return tsl.Sequence(n, n, r, lam, torch.from_numpy(A0).to(dev), torch.from_numpy(B0).to(dev),
+                            seed=1609, stream_id=s)
+
+    # ------------------------------------------------------------------ batched
+    seqs = [open_seq(s) for s in range(S)]
+    rows = [[torch.zeros(K, dtype=torch.int32, device=dev) for _ in range(S)] for _ in range(2)]
+    cnt = [[torch.zeros(1, dtype=torch.int32, device=dev) for _ in range(S)] for _ in range(2)]
+    X = [torch.empty(n, n, dtype=torch.complex64, device=dev) for _ in range(S)]
+
+    def frames_for(t):
+        fr = []
+        for s, q in enumerate(seqs):
+            y = Kd[s][t % F]
+            nxt = dict(K_next=K, rows_next=rows[(t + 1) % 2][s], n_next=cnt[(t + 1) % 2][s])
+            if t < warm:
+                fr.append(q.frame(rows=full, y=y, y_full=True, X_out=X[s], **nxt))
+            else:
+                fr.append(q.frame(rows=rows[t % 2][s], n_rows_dev=cnt[t % 2][s], y=y, y_full=True,
+                                  X_out=X[s], **nxt))
+        return fr
+
+    period = 2 * F
+    prepared = {}
+
+    def step(t):
+        key = t if t < warm else warm + (t - warm) % period
+        p = prepared.get(key)
+        if p is None:
+            p = prepared[key] = tsl.PreparedStep(seqs, frames_for(t))
+        p.launch(stream)
+
+    total = a.warmup + a.steps
+    for t in range(warm + period):          # build every descriptor set once, untimed
+        if t >= warm:
+            prepared.setdefault(warm + (t - warm) % period, tsl.PreparedStep(seqs, frames_for(t)))
+    t = 0
+    for _ in range(a.warmup):
+        step(t)
+        t += 1
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    w0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(a.steps):
+        step(t)
+        t += 1
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps)]
+    gpu_ms = ev[0].elapsed_time(ev[-1])
+    ms_per_step = max(wall * 1e3, gpu_ms) / a.steps
+    value = S * 1000.0 / ms_per_step
+    bad = [q for q in seqs if q.status() != 0]
+    print(f"[bench] batched {ms_per_step:.3f} ms/step, {value:.0f} frames/s", file=sys.stderr, flush=True)
+
+    # per-phase split (profiling form of the same step, HIP events between phases)
+    phase_ms = [0.0] * tsl.N_PHASES
+    for _ in range(a.phase_steps):
+        phase_ms = tsl.step_many_timed(seqs, frames_for(t), phase_ms, stream)
+        t += 1
+    phase_ms = [x / a.phase_steps for x in phase_ms]
+    mean_rows = float(np.mean([int(c.item()) for c in cnt[t % 2]]))
+    work = phase_work(n, n, r, mean_rows, K)
+    dom = int(np.argmax(phase_ms))
+    dname = tsl.PHASES[dom]
+    dbytes, dflops = work[dname]
+    dbytes, dflops = dbytes * S, dflops * S
+    dt = phase_ms[dom] * 1e-3
+    ai = dflops / dbytes
+    ridge = FP32_VALU_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if ai > ridge:
+        roof = {"bound": "alu", "achieved": dflops / dt / 1e12, "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": dbytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dname
+    roof["algorithmic_bytes_per_launch"] = dbytes
+    roof["algorithmic_flops_per_launch"] = dflops
+    roof["avg_launch_ms"] = phase_ms[dom]
+    for q in seqs:
+        q.close()
+
+    # ------------------------------------------------------------------ plain
+    q = open_seq(0)
+    pr = [torch.zeros(K, dtype=torch.int32, device=dev) for _ in range(2)]
+    pc = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in range(2)]
+    X0 = torch.empty(n, n, dtype=torch.complex64, device=dev)
+
+    def plain_frame(t):
+        nxt = dict(K_next=K, rows_next=pr[(t + 1) % 2], n_next=pc[(t + 1) % 2])
+        if t < warm:
+            return q.frame(rows=full, y=Kd[0][t % F], y_full=True, X_out=X0, **nxt)
+        return q.frame(rows=pr[t % 2], n_rows_dev=pc[t % 2], y=Kd[0][t % F], y_full=True, X_out=X0, **nxt)
+
+    pframes = [plain_frame(t) for t in range(warm + period)]
+
+    def pf(t):
+        return pframes[t if t < warm else warm + (t - warm) % period]
+
+    for t in range(a.warmup):
+        q.push(pf(t), stream)
+    torch.cuda.synchronize()
+    P = a.plain_frames
+    pev = [torch.cuda.Event(enable_timing=True) for _ in range(P + 1)]
+    w0 = time.perf_counter()
+    pev[0].record(stream)
+    for k in range(P):
+        q.push(pf(a.warmup + k), stream)
+        pev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    pwall = time.perf_counter() - w0
+    plain_ms = [pev[k].elapsed_time(pev[k + 1]) for k in range(P)]
+    plain_fps = P / max(pwall, pev[0].elapsed_time(pev[-1]) * 1e-3)
+    bad += [q] if q.status() != 0 else []
+    q.close()
+    print(f"[bench] plain {plain_fps:.0f} frames/s", file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------------ parity + CPU oracle
+    parity, cpu = None, None
+    if not a.no_cpu:
+        parity, cpu = oracle_leg(a, data, Kd, n, r, lam, K, warm, dev, tsl, torch)
+
+    out = {
+        "metric": "frames/s at 256²,R=32 (batched vs plain); p50/p99 frame latency",
+        "value": value,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{S} concurrent {n}x{n} cine sequences, R={r}, lambda={lam}, informative row "
+                        f"sampling with K={K} draws (12.5% line budget) after 5 fully sampled frames; one step "
+                        f"= one frame of every sequence through the whole step incl. the next-row draw",
+            "sequences": S, "n1": n, "n2": n, "r": r, "lambda": lam, "K": K,
+            "precision": "complex FP32 frame path, FP64 RxR statistics and solve",
+        },
+        "latency_ms": {"batched_p50": pct(step_ms, 50), "batched_p99": pct(step_ms, 99),
+                       "plain_p50": pct(plain_ms, 50), "plain_p99": pct(plain_ms, 99)},
+        "plain": {"frames_per_s": plain_fps, "ms_per_frame": 1e3 / plain_fps},
+        "batched_over_plain": value / plain_fps,
+        "phases_ms": {name: phase_ms[i] for i, name in enumerate(tsl.PHASES)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "device_status_errors": len(bad),
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def oracle_leg(a, data, Kd, n, r, lam, K, warm, dev, tsl, torch):
+    """FP64 oracle on sequence 0: teacher-forced parity of the GPU's plain path,
+    then the oracle's own frames/s on a bounded sample of the same workload."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    kspace, A0, B0 = data[0]
+    F = kspace.shape[0]
+    # parity: GPU plain path draws its own rows; the oracle follows them
+    q = tsl.Sequence(n, n, r, lam, torch.from_numpy(A0).to(dev), torch.from_numpy(B0).to(dev),
+                     seed=1609, stream_id=0)
+    o = oracle.TslOracle(n, n, r, lam, A0, B0)
+    full = torch.arange(n, dtype=torch.int32, device=dev)
+    rows_d = torch.zeros(K, dtype=torch.int32, device=dev)
+    cnt_d = torch.zeros(1, dtype=torch.int32, device=dev)
+    X = torch.empty(n, n, dtype=torch.complex64, device=dev)
+    Ah = torch.empty(n, r, dtype=torch.complex64, device=dev)
+    rows_h = np.arange(n, dtype=np.int32)
+    worst, agree, draws = 0.0, 0, 0
+    n_par = 20
+    for t in range(n_par):
+        rin = full if t < warm else torch.from_numpy(rows_h).to(dev)
+        fr = q.frame(rows=rin, y=Kd[0][t % F], y_full=True, X_out=X, K_next=K, rows_next=rows_d, n_next=cnt_d)
+        q.push(fr)
+        torch.cuda.synchronize()
+        s = o.push_lines(rows_h, kspace[t % F][rows_h])
+        worst = max(worst, float(np.linalg.norm(X.cpu().numpy() - s.X) / np.linalg.norm(s.X)))
+        q.factors(Ahat=Ah)
+        nr = int(cnt_d.item())
+        g_rows = rows_d.cpu().numpy()[:nr].copy()
+        o_rows, _ = oracle.draw_lines(Ah.cpu().numpy(), n, K, 1609, 0, t + 2)
+        draws += 1
+        agree += int(np.array_equal(o_rows, g_rows))
+        rows_h = g_rows if t + 1 >= warm else np.arange(n, dtype=np.int32)
+    q.close()
+    parity = {"frames": n_par, "max_nrmse_X_vs_oracle": worst,
+              "row_draws_bit_exact": f"{agree}/{draws}", "tolerance": 1e-4}
+    # CPU baseline: the oracle alone (its own FP64 draws), bounded time
+    o = oracle.TslOracle(n, n, r, lam, A0, B0)
+    rows_o = np.arange(n, dtype=np.int32)
+    frames = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < a.cpu_seconds:
+        o.push_lines(rows_o, kspace[frames % F][rows_o])
+        Ah_o, _ = o.kspace_factors()
+        frames += 1
+        rows_o = (oracle.draw_lines(Ah_o, n, K, 1609, 0, frames + 1)[0] if frames >= warm
+                  else np.arange(n, dtype=np.int32))
+    el = time.perf_counter() - t0
+    cpu = {"value": frames / el, "unit": "frames/s", "cores": threads, "kind": "oracle",
+           "sample": f"{frames} frames of sequence 0 ({n}x{n}, R={r}, informative rows) in {el:.1f}s, "
+                     f"FP64 NumPy with dense DFT matrices"}
+    print(f"[bench] oracle {cpu['value']:.1f} frames/s on {threads} threads; parity {parity}",
+          file=sys.stderr, flush=True)
+    return parity, cpu
+
+
+if __name__ == "__main__":
+    sys.exit(main())

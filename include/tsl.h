@@ -81,17 +81,33 @@ typedef struct {
     uint64_t stream_id;      /* sampler key word 1                                    */
 } tsl_opts;
 
-/* One frame of one sequence, for tsl_step_many.  Exactly one of `rows` (line
-   mask) or `mask` (point mask) is non-NULL; see tsl_push_lines / _points. */
+/* Number of timed phases reported by tsl_step_many_timed. */
+#define TSL_N_PHASES 9
+
+/* One frame of one sequence, for tsl_push_frame and tsl_step_many.  `mask`
+   non-NULL selects a point mask (see tsl_push_points); otherwise the sample
+   set is the rows `rows` (see tsl_push_lines).  Zero-initialise the struct
+   and fill what is used. */
 typedef struct {
-    int            n_rows;   /* host: number of rows (line masks), 0..n1             */
-    const int32_t* rows;     /* [n_rows] ascending row indices, or NULL               */
-    const uint8_t* mask;     /* [n1][n2] 0/1 point mask, or NULL                      */
-    const tsl_c32* y;        /* [n_rows][n2] (lines) or [n1][n2] (points) samples     */
-    tsl_c32*       X_out;    /* [n1][n2] or NULL                                      */
-    tsl_c32*       A_out;    /* [n1][r] or NULL                                       */
-    tsl_c32*       B_out;    /* [n2][r] or NULL                                       */
-    tsl_c32*       gamma_out;/* [r] or NULL                                           */
+    int            n_rows;     /* host: number of rows, 0..n1 (ignored if n_rows_dev)   */
+    const int32_t* rows;       /* [n_rows] strictly ascending row indices, or NULL      */
+    const uint8_t* mask;       /* [n1][n2] 0/1 point mask, or NULL                      */
+    const tsl_c32* y;          /* [n_rows][n2] rows' samples; [n1][n2] if y_full or a
+                                  point mask                                            */
+    tsl_c32*       X_out;      /* [n1][n2] or NULL                                      */
+    tsl_c32*       A_out;      /* [n1][r] or NULL                                       */
+    tsl_c32*       B_out;      /* [n2][r] or NULL                                       */
+    tsl_c32*       gamma_out;  /* [r] or NULL                                           */
+    const int32_t* n_rows_dev; /* device word holding the row count (in [0, n1]; checked
+                                  on the device, TSL_EINVAL latches otherwise), so a row
+                                  set drawn on the device needs no host round trip; or
+                                  NULL to use n_rows                                    */
+    int            y_full;     /* line masks: y is a whole [n1][n2] frame of which only
+                                  the listed rows are read                              */
+    int            K_next;     /* > 0: after the update, draw the rows of frame t+1 as
+                                  tsl_sample_lines does, into rows_next / n_next        */
+    int32_t*       rows_next;  /* [K_next] device, or NULL if K_next == 0               */
+    int32_t*       n_next;     /* [1] device, or NULL if K_next == 0                    */
 } tsl_frame;
 
 /* Fills *o with the defaults: MM step, lambda > 0 required, seed 0, stream 0. */
@@ -149,12 +165,27 @@ int tsl_push_points(tsl_seq* s, const uint8_t* mask, const tsl_c32* y,
 int tsl_sample_lines(tsl_seq* s, int K, int32_t* rows_out, int32_t* n_out,
                      int32_t* draws_out, double* prefix_out, void* stream);
 
+/* Pushes one frame described by a tsl_frame (the general form of
+   tsl_push_lines / tsl_push_points, with device-side row counts, full-frame
+   sample arrays and the next frame's row draw in the same call). */
+int tsl_push_frame(tsl_seq* s, const tsl_frame* frame, void* stream);
+
 /* Batched push: frame frames[i] for sequence seqs[i], i < n, as n independent
-   tsl_push_* calls would, in one stream-ordered step.  Sequences of equal
-   shape share launches; the launch sequence of a batch composition is captured
-   once in a HIP graph and replayed while the composition repeats.  The
-   sequences must be distinct. */
+   tsl_push_frame calls would, in one stream-ordered step.  Sequences of equal
+   shape share launches; the launch sequence of a batch composition (which
+   sequences, which outputs, which mask kinds, whether rows are drawn) is
+   captured once in a HIP graph and replayed while the composition repeats.
+   The sequences must be distinct. */
 int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* stream);
+
+/* Profiling form of tsl_step_many: runs the same kernels without a graph,
+   brackets each of the TSL_N_PHASES phases (partial Grams; solve and step
+   size; synthesis + row transform; column transform + residual + column
+   inverse; row inverse + A gradient; A update + F_l A; B gradient + update +
+   F_r B; output synthesis; row draw) with HIP events on `stream`, waits, and
+   ADDS each phase's elapsed milliseconds to phase_ms[TSL_N_PHASES] (host). */
+int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, double* phase_ms,
+                        void* stream);
 
 /* Synchronises the sequence's last stream and returns its latched device
    status (TSL_OK or a negative code); clears it if clear != 0. */

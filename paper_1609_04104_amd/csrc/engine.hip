@@ -84,35 +84,73 @@ struct tsl_seq {
 namespace {
 
 // -------------------------------------------------------------- frame descriptors
-tsl::FrameArgs frame_args(const tsl_seq* s, int mode, int n_rows, const int32_t* rows, const uint8_t* mask,
-                          const tsl_c32* y, tsl_c32* X_out, tsl_c32* A_out, tsl_c32* B_out, tsl_c32* g_out) {
+tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     tsl::FrameArgs a{};
-    a.n1 = s->n1; a.n2 = s->n2; a.r = s->r; a.mode = mode;
+    a.n1 = s->n1; a.n2 = s->n2; a.r = s->r;
+    a.mode = fr.mask ? tsl::MODE_POINTS : tsl::MODE_LINES;
     a.lambda = s->lambda; a.mu_const = s->opts.mu; a.step_mode = s->opts.step_mode;
-    a.n_rows = n_rows;
+    a.n_rows = fr.mask ? 0 : fr.n_rows;
     a.A = s->at<float2>(s->lay.A); a.B = s->at<float2>(s->lay.B);
     a.Ahat = s->at<float2>(s->lay.Ahat); a.Bhat = s->at<float2>(s->lay.Bhat);
     a.dev = s->at<tsl::SeqDev>(s->lay.dev);
     a.gamma64 = s->at<double2>(s->lay.g64); a.gamma32 = s->at<float2>(s->lay.g32);
     a.frame = s->at<float2>(s->lay.frame); a.Wb = s->at<float2>(s->lay.Wb); a.GA = s->at<float2>(s->lay.GA);
     a.part = s->at<double2>(s->lay.part); a.hpart = s->at<double2>(s->lay.hpart);
-    a.rows = rows; a.mask = mask; a.y = reinterpret_cast<const float2*>(y);
-    a.X_out = reinterpret_cast<float2*>(X_out); a.A_out = reinterpret_cast<float2*>(A_out);
-    a.B_out = reinterpret_cast<float2*>(B_out); a.gamma_out = reinterpret_cast<float2*>(g_out);
+    a.rows = fr.rows; a.n_rows_dev = fr.mask ? nullptr : fr.n_rows_dev; a.y_full = fr.y_full ? 1 : 0;
+    a.mask = fr.mask; a.y = reinterpret_cast<const float2*>(fr.y);
+    a.X_out = reinterpret_cast<float2*>(fr.X_out); a.A_out = reinterpret_cast<float2*>(fr.A_out);
+    a.B_out = reinterpret_cast<float2*>(fr.B_out); a.gamma_out = reinterpret_cast<float2*>(fr.gamma_out);
+    a.K_next = fr.K_next > 0 ? fr.K_next : 0;
+    a.rows_next = fr.rows_next; a.n_next = fr.n_next;
+    a.draws_next = nullptr; a.prefix_next = nullptr;
+    a.seed = s->opts.seed; a.sid = s->opts.stream_id;
     return a;
 }
 
-// The launch sequence of one step (Algorithm 3 with one coil) for one group.
-int run_phases(const tsl::Batch& b, hipStream_t st) {
-    hipError_t e;
-    if ((e = tsl::launch_stats(b, st)) != hipSuccess) return hip_fail(e, "stats");            // a2
-    if ((e = tsl::launch_solve(b, st)) != hipSuccess) return hip_fail(e, "solve");            // a3, a8
-    if ((e = tsl::launch_synth_rowfft(b, st)) != hipSuccess) return hip_fail(e, "synth");     // a4, a5 rows
-    if ((e = tsl::launch_col_resid(b, st)) != hipSuccess) return hip_fail(e, "col");          // a5 cols, a6, a7 cols
-    if ((e = tsl::launch_row_inv_grad(b, st)) != hipSuccess) return hip_fail(e, "rowinv");    // a7 rows, a9
-    if ((e = tsl::launch_update_a(b, st)) != hipSuccess) return hip_fail(e, "update_a");      // a9, a1
-    if ((e = tsl::launch_update_b(b, st)) != hipSuccess) return hip_fail(e, "update_b");      // a9, a1
-    if ((e = tsl::launch_synth_out(b, st)) != hipSuccess) return hip_fail(e, "synth_out");    // a10
+// The phases of one step (Algorithm 3 with one coil, then Algorithm 4's draw).
+using PhaseFn = hipError_t (*)(const tsl::Batch&, hipStream_t);
+struct Phase {
+    PhaseFn fn;
+    const char* name;
+};
+const Phase kPhases[TSL_N_PHASES] = {
+    {tsl::launch_stats, "partial Grams"},                  // a2
+    {tsl::launch_solve, "ridge solve + step size"},        // a3, a8
+    {tsl::launch_synth_rowfft, "synthesis + row pass"},    // a4, a5 (rows)
+    {tsl::launch_col_resid, "column pass + residual"},     // a5 (columns), a6, a7 (columns)
+    {tsl::launch_row_inv_grad, "row inverse + A grad"},    // a7 (rows), a9
+    {tsl::launch_update_a, "A update + F_l A"},            // a9, a1
+    {tsl::launch_update_b, "B grad + update + F_r B"},     // a9, a1
+    {tsl::launch_synth_out, "output synthesis"},           // a10
+    {tsl::launch_sample, "row draw"},                      // a11
+};
+
+// Launches every phase for every group, phase by phase; with `ev` non-null,
+// records ev[p] before phase p and ev[TSL_N_PHASES] after the last.
+int run_groups(const std::vector<tsl::Batch>& groups, hipStream_t st, hipEvent_t* ev = nullptr) {
+    for (int p = 0; p < TSL_N_PHASES; ++p) {
+        if (ev) TSL_HIP(hipEventRecord(ev[p], st));
+        for (const tsl::Batch& b : groups) {
+            hipError_t e = kPhases[p].fn(b, st);
+            if (e != hipSuccess) return hip_fail(e, kPhases[p].name);
+        }
+    }
+    if (ev) TSL_HIP(hipEventRecord(ev[TSL_N_PHASES], st));
+    return TSL_OK;
+}
+
+int check_frame(const tsl_seq* s, const tsl_frame& fr) {
+    if (fr.mask) {
+        if (fr.rows) return fail(TSL_EINVAL, "a frame has both rows and a mask");
+        if (!fr.y) return fail(TSL_EINVAL, "null y");
+    } else if (fr.n_rows_dev) {
+        if (!fr.rows || !fr.y) return fail(TSL_EINVAL, "a device row count needs rows and y");
+    } else {
+        if (fr.n_rows < 0 || fr.n_rows > s->n1) return fail(TSL_EINVAL, "n_rows must be in [0, n1]");
+        if (fr.n_rows > 0 && (!fr.rows || !fr.y)) return fail(TSL_EINVAL, "null rows or y");
+    }
+    if (fr.K_next < 0) return fail(TSL_EINVAL, "K_next must be >= 0");
+    if (fr.K_next > 0 && (!fr.rows_next || !fr.n_next)) return fail(TSL_EINVAL, "null rows_next or n_next");
     return TSL_OK;
 }
 
@@ -128,17 +166,13 @@ int set_dev(const tsl_seq* s) {
 
 // -------------------------------------------------------------- batched step state
 struct GroupKey {
-    int n1, n2, mode, count, r_max, rows_max;
-    bool want_x;
-    bool operator==(const GroupKey& o) const {
-        return n1 == o.n1 && n2 == o.n2 && mode == o.mode && count == o.count && r_max == o.r_max &&
-               rows_max == o.rows_max && want_x == o.want_x;
-    }
+    int n1, n2, mode, count, r_max;
+    bool want_x, want_sample;
 };
 
 struct Composition {
     std::vector<const tsl_seq*> seqs;     // in the order of the call
-    std::vector<int> wants;               // per frame: bit0 X, bit1 A, bit2 B, bit3 gamma, bit4 points
+    std::vector<int> wants;               // per frame: bit0 X, bit4 points, bit5 row draw
     std::vector<int> order;               // frame indices sorted by group
     std::vector<GroupKey> groups;
     std::vector<int> group_start;         // offset into order / table
@@ -160,7 +194,6 @@ struct BatchEngine {
     Composition comp;
     bool have_graph = false;
     hipGraphExec_t exec = nullptr;
-    int rows_cap = 0;                     // rows_max the graph was sized for (per group)
 };
 
 BatchEngine g_batch;
@@ -203,18 +236,69 @@ int ensure_batch_buffers(BatchEngine& be, size_t n) {
     return TSL_OK;
 }
 
-int launch_groups(const Composition& c, const tsl::FrameArgs* table, hipStream_t st) {
+std::vector<tsl::Batch> group_batches(const Composition& c, const tsl::FrameArgs* table) {
+    std::vector<tsl::Batch> out;
     for (size_t g = 0; g < c.groups.size(); ++g) {
         const GroupKey& k = c.groups[g];
         tsl::Batch b{};
         b.one = nullptr;
         b.table = table + c.group_start[g];
         b.count = k.count;
-        b.n1 = k.n1; b.n2 = k.n2; b.r_max = k.r_max; b.rows_max = k.rows_max;
-        b.mode = k.mode; b.want_x = k.want_x;
-        int rc = run_phases(b, st);
-        if (rc != TSL_OK) return rc;
+        b.n1 = k.n1; b.n2 = k.n2; b.r_max = k.r_max; b.rows_max = k.n1;
+        b.mode = k.mode; b.want_x = k.want_x; b.want_sample = k.want_sample;
+        out.push_back(b);
     }
+    return out;
+}
+
+// Validates a batch and groups it by (n1, n2, mask kind), call order kept inside a group.
+int compose(tsl_seq* const* seqs, int n, const tsl_frame* frames, Composition& c) {
+    c.seqs.resize(n);
+    c.wants.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const tsl_seq* s = seqs[i];
+        if (!s) return fail(TSL_EINVAL, "null sequence in batch");
+        for (int j = 0; j < i; ++j)
+            if (seqs[j] == s) return fail(TSL_EINVAL, "a sequence appears twice in one batch");
+        int rc = check_frame(s, frames[i]);
+        if (rc != TSL_OK) return rc;
+        c.seqs[i] = s;
+        c.wants[i] = (frames[i].X_out ? 1 : 0) | (frames[i].mask ? 16 : 0) | (frames[i].K_next > 0 ? 32 : 0);
+    }
+    std::map<std::tuple<int, int, int>, std::vector<int>> by;
+    for (int i = 0; i < n; ++i) by[{seqs[i]->n1, seqs[i]->n2, (c.wants[i] & 16) ? 1 : 0}].push_back(i);
+    for (auto& kv : by) {
+        GroupKey k{};
+        k.n1 = std::get<0>(kv.first); k.n2 = std::get<1>(kv.first); k.mode = std::get<2>(kv.first);
+        k.count = int(kv.second.size());
+        for (int i : kv.second) {
+            k.r_max = std::max(k.r_max, seqs[i]->r);
+            k.want_x = k.want_x || (c.wants[i] & 1);
+            k.want_sample = k.want_sample || (c.wants[i] & 32);
+        }
+        c.group_start.push_back(int(c.order.size()));
+        for (int i : kv.second) c.order.push_back(i);
+        c.groups.push_back(k);
+    }
+    return TSL_OK;
+}
+
+// Writes the descriptors of a composed batch into the pinned ring and copies
+// them to the device table on `st`.
+int stage_table(BatchEngine& be, const Composition& c, tsl_seq* const* seqs, const tsl_frame* frames,
+                hipStream_t st) {
+    const int n = int(c.order.size());
+    const int slot = be.ring_pos;
+    be.ring_pos = (be.ring_pos + 1) % BatchEngine::kRing;
+    TSL_HIP(hipEventSynchronize(be.staged[slot]));
+    tsl::FrameArgs* host = be.staging[slot];
+    for (int p = 0; p < n; ++p) {
+        const int i = c.order[p];
+        seqs[i]->last = st;
+        host[p] = frame_args(seqs[i], frames[i]);
+    }
+    TSL_HIP(hipMemcpyAsync(be.table, host, size_t(n) * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice, st));
+    TSL_HIP(hipEventRecord(be.staged[slot], st));
     return TSL_OK;
 }
 
@@ -342,37 +426,40 @@ int tsl_close(tsl_seq* s) {
     return TSL_OK;
 }
 
-static int push_impl(tsl_seq* s, int mode, int n_rows, const int32_t* rows, const uint8_t* mask, const tsl_c32* y,
-                     tsl_c32* X_out, tsl_c32* A_out, tsl_c32* B_out, tsl_c32* g_out, void* stream) {
+int tsl_push_frame(tsl_seq* s, const tsl_frame* frame, void* stream) {
     int rc = check_seq(s);
     if (rc != TSL_OK) return rc;
-    if (mode == tsl::MODE_LINES) {
-        if (n_rows < 0 || n_rows > s->n1) return fail(TSL_EINVAL, "n_rows must be in [0, n1]");
-        if (n_rows > 0 && (!rows || !y)) return fail(TSL_EINVAL, "null rows or y");
-    } else {
-        if (!mask || !y) return fail(TSL_EINVAL, "null mask or y");
-    }
+    if (!frame) return fail(TSL_EINVAL, "null frame");
+    if ((rc = check_frame(s, *frame)) != TSL_OK) return rc;
     if ((rc = set_dev(s)) != TSL_OK) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     s->last = st;
-    tsl::FrameArgs a = frame_args(s, mode, n_rows, rows, mask, y, X_out, A_out, B_out, g_out);
+    tsl::FrameArgs a = frame_args(s, *frame);
     tsl::Batch b{};
     b.one = &a;
     b.table = nullptr;
     b.count = 1;
-    b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r; b.rows_max = n_rows; b.mode = mode;
-    b.want_x = X_out != nullptr;
-    return run_phases(b, st);
+    b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r; b.rows_max = s->n1; b.mode = a.mode;
+    b.want_x = frame->X_out != nullptr;
+    b.want_sample = a.K_next > 0;
+    return run_groups({b}, st);
 }
 
 int tsl_push_lines(tsl_seq* s, int n_rows, const int32_t* rows, const tsl_c32* y, tsl_c32* X_out, tsl_c32* A_out,
                    tsl_c32* B_out, tsl_c32* gamma_out, void* stream) {
-    return push_impl(s, tsl::MODE_LINES, n_rows, rows, nullptr, y, X_out, A_out, B_out, gamma_out, stream);
+    tsl_frame f{};
+    f.n_rows = n_rows; f.rows = rows; f.y = y;
+    f.X_out = X_out; f.A_out = A_out; f.B_out = B_out; f.gamma_out = gamma_out;
+    return tsl_push_frame(s, &f, stream);
 }
 
 int tsl_push_points(tsl_seq* s, const uint8_t* mask, const tsl_c32* y, tsl_c32* X_out, tsl_c32* A_out,
                     tsl_c32* B_out, tsl_c32* gamma_out, void* stream) {
-    return push_impl(s, tsl::MODE_POINTS, 0, nullptr, mask, y, X_out, A_out, B_out, gamma_out, stream);
+    if (!mask) return fail(TSL_EINVAL, "null mask");
+    tsl_frame f{};
+    f.mask = mask; f.y = y;
+    f.X_out = X_out; f.A_out = A_out; f.B_out = B_out; f.gamma_out = gamma_out;
+    return tsl_push_frame(s, &f, stream);
 }
 
 int tsl_sample_lines(tsl_seq* s, int K, int32_t* rows_out, int32_t* n_out, int32_t* draws_out, double* prefix_out,
@@ -384,10 +471,15 @@ int tsl_sample_lines(tsl_seq* s, int K, int32_t* rows_out, int32_t* n_out, int32
     if ((rc = set_dev(s)) != TSL_OK) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     s->last = st;
-    tsl::FrameArgs a = frame_args(s, tsl::MODE_LINES, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                  nullptr);
-    hipError_t e = tsl::launch_sample(a, K, s->opts.seed, s->opts.stream_id, rows_out, n_out, draws_out, prefix_out,
-                                      st);
+    tsl_frame fr{};
+    tsl::FrameArgs a = frame_args(s, fr);
+    a.K_next = K; a.rows_next = rows_out; a.n_next = n_out; a.draws_next = draws_out; a.prefix_next = prefix_out;
+    tsl::Batch b{};
+    b.one = &a;
+    b.count = 1;
+    b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r;
+    b.want_sample = true;
+    hipError_t e = tsl::launch_sample(b, st);
     if (e != hipSuccess) return hip_fail(e, "sample");
     return TSL_OK;
 }
@@ -397,68 +489,17 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
     if (n == 0) return TSL_OK;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     Composition c;
-    c.seqs.resize(n);
-    c.wants.resize(n);
-    for (int i = 0; i < n; ++i) {
-        const tsl_seq* s = seqs[i];
-        const tsl_frame& fr = frames[i];
-        if (!s) return fail(TSL_EINVAL, "null sequence in batch");
-        for (int j = 0; j < i; ++j)
-            if (seqs[j] == s) return fail(TSL_EINVAL, "a sequence appears twice in one batch");
-        const bool points = fr.mask != nullptr;
-        if (points && fr.rows != nullptr) return fail(TSL_EINVAL, "a frame has both rows and a mask");
-        if (!points) {
-            if (fr.n_rows < 0 || fr.n_rows > s->n1) return fail(TSL_EINVAL, "n_rows must be in [0, n1]");
-            if (fr.n_rows > 0 && (!fr.rows || !fr.y)) return fail(TSL_EINVAL, "null rows or y");
-        } else if (!fr.y) {
-            return fail(TSL_EINVAL, "null y");
-        }
-        c.seqs[i] = s;
-        c.wants[i] = (fr.X_out ? 1 : 0) | (fr.A_out ? 2 : 0) | (fr.B_out ? 4 : 0) | (fr.gamma_out ? 8 : 0) |
-                     (points ? 16 : 0);
-    }
-    // group frames by (n1, n2, mode), keeping call order inside a group
-    std::map<std::tuple<int, int, int>, std::vector<int>> by;
-    for (int i = 0; i < n; ++i)
-        by[{seqs[i]->n1, seqs[i]->n2, (c.wants[i] & 16) ? 1 : 0}].push_back(i);
-    for (auto& kv : by) {
-        GroupKey k{};
-        k.n1 = std::get<0>(kv.first); k.n2 = std::get<1>(kv.first); k.mode = std::get<2>(kv.first);
-        k.count = int(kv.second.size());
-        k.r_max = 0; k.rows_max = 0; k.want_x = false;
-        for (int i : kv.second) {
-            k.r_max = std::max(k.r_max, seqs[i]->r);
-            k.rows_max = k.n1;   // grids are sized for a full row set so any n_rows replays
-            k.want_x = k.want_x || frames[i].X_out != nullptr;
-        }
-        c.group_start.push_back(int(c.order.size()));
-        for (int i : kv.second) c.order.push_back(i);
-        c.groups.push_back(k);
-    }
+    int rc = compose(seqs, n, frames, c);
+    if (rc != TSL_OK) return rc;
     std::lock_guard<std::mutex> lk(g_graph_mu);
     BatchEngine& be = g_batch;
-    int rc = ensure_batch_buffers(be, size_t(n));
-    if (rc != TSL_OK) return rc;
-    // stage the descriptors (pinned ring) and copy them to the device table
-    const int slot = be.ring_pos;
-    be.ring_pos = (be.ring_pos + 1) % BatchEngine::kRing;
-    TSL_HIP(hipEventSynchronize(be.staged[slot]));
-    tsl::FrameArgs* host = be.staging[slot];
-    for (int p = 0; p < n; ++p) {
-        const int i = c.order[p];
-        const tsl_frame& fr = frames[i];
-        tsl_seq* s = const_cast<tsl_seq*>(seqs[i]);
-        s->last = st;
-        host[p] = frame_args(s, fr.mask ? tsl::MODE_POINTS : tsl::MODE_LINES, fr.mask ? 0 : fr.n_rows, fr.rows,
-                             fr.mask, fr.y, fr.X_out, fr.A_out, fr.B_out, fr.gamma_out);
-    }
-    TSL_HIP(hipMemcpyAsync(be.table, host, size_t(n) * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice, st));
-    TSL_HIP(hipEventRecord(be.staged[slot], st));
+    if ((rc = ensure_batch_buffers(be, size_t(n))) != TSL_OK) return rc;
+    if ((rc = stage_table(be, c, seqs, frames, st)) != TSL_OK) return rc;
     if (!(be.have_graph && be.comp == c)) {
         drop_graph(be);
         hipGraph_t graph = nullptr;
         TSL_HIP(hipStreamBeginCapture(be.cap, hipStreamCaptureModeThreadLocal));
-        int lrc = launch_groups(c, be.table, be.cap);
+        int lrc = run_groups(group_batches(c, be.table), be.cap);
         hipError_t ec = hipStreamEndCapture(be.cap, &graph);
         if (lrc != TSL_OK) {
             if (graph) hipGraphDestroy(graph);
@@ -476,6 +517,33 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
     }
     TSL_HIP(hipGraphLaunch(be.exec, st));
     return TSL_OK;
+}
+
+int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, double* phase_ms, void* stream) {
+    if (n < 0 || (n > 0 && (!seqs || !frames)) || !phase_ms) return fail(TSL_EINVAL, "bad batch arguments");
+    if (n == 0) return TSL_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    Composition c;
+    int rc = compose(seqs, n, frames, c);
+    if (rc != TSL_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    BatchEngine& be = g_batch;
+    if ((rc = ensure_batch_buffers(be, size_t(n))) != TSL_OK) return rc;
+    if ((rc = stage_table(be, c, seqs, frames, st)) != TSL_OK) return rc;
+    hipEvent_t ev[TSL_N_PHASES + 1] = {};
+    for (auto& e : ev) TSL_HIP(hipEventCreate(&e));
+    rc = run_groups(group_batches(c, be.table), st, ev);
+    if (rc == TSL_OK) {
+        hipError_t e = hipEventSynchronize(ev[TSL_N_PHASES]);
+        for (int p = 0; p < TSL_N_PHASES && e == hipSuccess; ++p) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[p], ev[p + 1]);
+            phase_ms[p] += ms;
+        }
+        if (e != hipSuccess) rc = hip_fail(e, "phase events");
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    return rc;
 }
 
 int tsl_status(tsl_seq* s, int clear) {

@@ -51,11 +51,33 @@ struct FrameArgs {
     double2* hpart;     // [n_sparts][r] partial right-hand sides
     // inputs of the frame
     const int* rows;
+    const int* n_rows_dev;   // device row count (lines), or null to use n_rows
+    int y_full;              // lines: y is [n1][n2] and row k is read at y + k*n2
     const unsigned char* mask;
     const float2* y;
     // outputs (may be null)
     float2 *X_out, *A_out, *B_out, *gamma_out;
+    // draw of the next frame's rows (K_next == 0: none)
+    int K_next;
+    int* rows_next;
+    int* n_next;
+    int* draws_next;         // [K_next] rows of the individual trials, or null
+    double* prefix_next;     // [n1] weight prefix, or null
+    unsigned long long seed, sid;
 };
+
+// Row count of a line-mask frame, clamped to [0, n1] so that no kernel reads
+// outside the row list; the partial-Gram kernel latches ST_EINVAL when the
+// device count was out of range.
+__device__ __forceinline__ int frame_rows(const FrameArgs& f) {
+    int n = f.n_rows_dev ? *f.n_rows_dev : f.n_rows;
+    return n < 0 ? 0 : (n > f.n1 ? f.n1 : n);
+}
+
+// Samples of row `row`, listed at position q of the row set (lines).
+__device__ __forceinline__ const float2* line_samples(const FrameArgs& f, int q, int row) {
+    return f.y + size_t(f.y_full ? row : q) * f.n2;
+}
 
 // Where a kernel finds its descriptor: one by value (single-sequence push) or
 // entry blockIdx.y of a device table (batched step).

@@ -102,7 +102,8 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
     if (f.mode == MODE_LINES) {
         for (int k = tid; k < N1; k += blockDim.x) s_map[k] = -1;
         __syncthreads();
-        for (int q = tid; q < f.n_rows; q += blockDim.x) {
+        const int nr = frame_rows(f);
+        for (int q = tid; q < nr; q += blockDim.x) {
             const int k = f.rows[q];
             if (k >= 0 && k < N1) s_map[k] = q;
         }
@@ -130,7 +131,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
             if (cv) {
                 if (lines) {
                     const int q = s_map[k];
-                    if (q >= 0) e = csub(f.y[size_t(q) * n2 + col], K);
+                    if (q >= 0) e = csub(line_samples(f, q, k)[col], K);
                 } else if (f.mask[size_t(k) * n2 + col]) {
                     e = csub(f.y[size_t(k) * n2 + col], K);
                 }

@@ -80,14 +80,19 @@ __global__ void __launch_bounds__(256) k_stats(Src src) {
     if (tid == 0) s_err = 0;
     __syncthreads();
     if (f.mode == MODE_LINES) {
+        const int n_rows = frame_rows(f);
+        if (k == 0 && tid == 0 && f.n_rows_dev) {
+            const int nd = *f.n_rows_dev;
+            if (nd < 0 || nd > n1) latch(f.dev, ST_EINVAL);
+        }
         const int q0 = k * kSRows;
-        if (q0 >= f.n_rows) return;
-        const int nq = min(f.n_rows, q0 + kSRows) - q0;
+        if (q0 >= n_rows) return;
+        const int nq = min(n_rows, q0 + kSRows) - q0;
         // validate this chunk's rows: inside [0, n1), strictly ascending
         if (tid < nq) {
             const int q = q0 + tid, row = f.rows[q];
             bool ok = row >= 0 && row < n1;
-            if (q + 1 < f.n_rows) ok = ok && f.rows[q + 1] > row;
+            if (q + 1 < n_rows) ok = ok && f.rows[q + 1] > row;
             if (!ok) atomicCAS(&s_err, 0, ST_EINVAL);
         }
         auto row_of = [&](int q) {
@@ -98,16 +103,18 @@ __global__ void __launch_bounds__(256) k_stats(Src src) {
         // z_q[r] = sum_j conj(Bhat_jr) y_qj, then h[r] = sum_q conj(Ahat_{row_q, r}) z_q[r]
         for (int e = tid; e < nq * R; e += blockDim.x) {
             const int q = e / R, r = e % R;
-            const float2* yq = f.y + size_t(q0 + q) * n2;
+            const int row = row_of(q);
             double2 z{0.0, 0.0};
             bool fin = true;
-            for (int j = 0; j < n2; ++j) {
-                const float2 yy = yq[j];
-                fin = fin && finite2(yy);
-                dacc_cj(z, f.Bhat[size_t(j) * R + r], yy);
+            if (row >= 0) {
+                const float2* yq = line_samples(f, q0 + q, row);
+                for (int j = 0; j < n2; ++j) {
+                    const float2 yy = yq[j];
+                    fin = fin && finite2(yy);
+                    dacc_cj(z, f.Bhat[size_t(j) * R + r], yy);
+                }
             }
             if (!fin) atomicCAS(&s_err, 0, ST_ENONFINITE);
-            const int row = row_of(q);
             const float2 a = row >= 0 ? f.Ahat[size_t(row) * R + r] : float2{0.f, 0.f};
             s_h[q * R + r] = dcmulc(z, double2{a.x, a.y});
         }
@@ -184,7 +191,7 @@ __global__ void __launch_bounds__(256) k_solve(Src src) {
     const int R = f.r, n1 = f.n1, n2 = f.n2, tid = threadIdx.x;
     const int na = n_gram_a(n1), nb = n_gram_b(n2);
     const bool lines = f.mode == MODE_LINES;
-    const int ns = lines ? cdiv(f.n_rows, kSRows) : cdiv(n1, kPRows);
+    const int ns = lines ? cdiv(frame_rows(f), kSRows) : cdiv(n1, kPRows);
     const size_t RR = size_t(R) * R;
     const double2* pa = f.part;
     const double2* pb = f.part + na * RR;
@@ -393,12 +400,15 @@ __device__ __forceinline__ void philox4x64_10(uint64_t (&x)[4], uint64_t k0, uin
     }
 }
 
-__global__ void __launch_bounds__(256) k_sample(FrameArgs f, int K, uint64_t seed, uint64_t sid, int* rows_out,
-                                                 int* n_out, int* draws_out, double* prefix_out) {
+template <class Src>
+__global__ void __launch_bounds__(256) k_sample(Src src) {
 #pragma clang fp contract(off)
     extern __shared__ double s_pref[];           // [n1] weights, then their prefix
     __shared__ double s_c[TSL_MAX_R];
     __shared__ int s_mark[kMaxN];
+    const FrameArgs& f = src.get();
+    const int K = f.K_next;
+    if (K <= 0) return;
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
     // column energies ||ahat_r||^2, sequential in i
     for (int r = tid; r < R; r += blockDim.x) {
@@ -442,7 +452,7 @@ __global__ void __launch_bounds__(256) k_sample(FrameArgs f, int K, uint64_t see
     const uint64_t t_next = uint64_t(f.dev->t + 1);
     for (int k = tid; k < K; k += blockDim.x) {
         uint64_t x[4] = {t_next, uint64_t(k), 0ull, 0ull};
-        philox4x64_10(x, seed, sid);
+        philox4x64_10(x, f.seed, f.sid);
         const double u = double(x[0] >> 11) * 0x1.0p-53;
         const double target = u * W;
         int lo = 0, hi = n1;               // first i with target < prefix[i]
@@ -451,18 +461,18 @@ __global__ void __launch_bounds__(256) k_sample(FrameArgs f, int K, uint64_t see
             if (target < s_pref[mid]) hi = mid; else lo = mid + 1;
         }
         const int idx = lo < n1 ? lo : n1 - 1;
-        if (draws_out) draws_out[k] = idx;
+        if (f.draws_next) f.draws_next[k] = idx;
         s_mark[idx] = 1;
     }
     __syncthreads();
     if (tid == 0) {
         int cnt = 0;
         for (int i = 0; i < n1; ++i)
-            if (s_mark[i]) rows_out[cnt++] = i;
-        n_out[0] = cnt;
+            if (s_mark[i]) f.rows_next[cnt++] = i;
+        f.n_next[0] = cnt;
     }
-    if (prefix_out)
-        for (int i = tid; i < n1; i += blockDim.x) prefix_out[i] = s_pref[i];
+    if (f.prefix_next)
+        for (int i = tid; i < n1; i += blockDim.x) f.prefix_next[i] = s_pref[i];
 }
 
 size_t solve_lds(int R) { return size_t(R * (R + 1) / 2 + R) * sizeof(double2); }
@@ -509,10 +519,12 @@ hipError_t launch_synth_out(const Batch& b, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_sample(const FrameArgs& a, int K, uint64_t seed, uint64_t stream_id, int* rows_out, int* n_out,
-                         int* draws_out, double* prefix_out, hipStream_t st) {
-    k_sample<<<1, kBlock, size_t(a.n1) * sizeof(double), st>>>(a, K, seed, stream_id, rows_out, n_out, draws_out,
-                                                             prefix_out);
+hipError_t launch_sample(const Batch& b, hipStream_t st) {
+    if (!b.want_sample) return hipSuccess;
+    dim3 grid(1, b.table ? b.count : 1);
+    const size_t lds = size_t(b.n1) * sizeof(double);
+    if (b.table) k_sample<FrameTable><<<grid, kBlock, lds, st>>>(FrameTable{b.table});
+    else k_sample<OneFrame><<<grid, kBlock, lds, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ struct Batch {
     int rows_max;                // largest n_rows (line masks)
     int mode;                    // MODE_LINES or MODE_POINTS (shared)
     bool want_x;                 // some frame asks for X_t
+    bool want_sample;            // some frame draws its next rows
 };
 
 // Threads per block of the kernels that are not templated on a length.
@@ -41,8 +42,7 @@ hipError_t launch_factor_fft(int n, int r, const float2* in, float2* out, bool i
 hipError_t launch_stats(const Batch& b, hipStream_t st);
 hipError_t launch_solve(const Batch& b, hipStream_t st);
 hipError_t launch_synth_out(const Batch& b, hipStream_t st);
-hipError_t launch_sample(const FrameArgs& a, int K, uint64_t seed, uint64_t stream_id, int* rows_out,
-                         int* n_out, int* draws_out, double* prefix_out, hipStream_t st);
+hipError_t launch_sample(const Batch& b, hipStream_t st);
 
 // Raises the dynamic-LDS limit of the kernels that need more than the default
 // (idempotent; called before any launch or graph capture).

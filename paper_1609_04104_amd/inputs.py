@@ -115,16 +115,28 @@ def _grid(n, ss):
 
 
 def _ellipse_coverage(spec, k, scale, ss):
-    yy = _grid(spec.n1, ss)[:, None]
-    xx = _grid(spec.n2, ss)[None, :]
+    """Fraction of each pixel inside ellipse k (ss x ss sub-pixel samples),
+    evaluated only on the pixels of the ellipse's bounding box."""
     cx, cy = spec.centres[k]
     a, b = spec.axes[k] * scale
     c, s = np.cos(spec.angles[k]), np.sin(spec.angles[k])
+    wx = np.sqrt((a * c) ** 2 + (b * s) ** 2)
+    wy = np.sqrt((a * s) ** 2 + (b * c) ** 2)
+    out = np.zeros((spec.n1, spec.n2))
+    r0 = max(0, int(np.floor((cy - wy + 1.0) * spec.n1 / 2.0)) - 1)
+    r1 = min(spec.n1, int(np.ceil((cy + wy + 1.0) * spec.n1 / 2.0)) + 1)
+    c0 = max(0, int(np.floor((cx - wx + 1.0) * spec.n2 / 2.0)) - 1)
+    c1 = min(spec.n2, int(np.ceil((cx + wx + 1.0) * spec.n2 / 2.0)) + 1)
+    if r0 >= r1 or c0 >= c1:
+        return out
+    yy = _grid(spec.n1, ss)[r0 * ss:r1 * ss, None]
+    xx = _grid(spec.n2, ss)[None, c0 * ss:c1 * ss]
     dx, dy = xx - cx, yy - cy
     u = (dx * c + dy * s) / a
     v = (-dx * s + dy * c) / b
     inside = (u * u + v * v) <= 1.0
-    return inside.reshape(spec.n1, ss, spec.n2, ss).mean(axis=(1, 3))
+    out[r0:r1, c0:c1] = inside.reshape(r1 - r0, ss, c1 - c0, ss).mean(axis=(1, 3))
+    return out
 
 
 def phantom_frame(spec, t, ss=4, period=25.0, amplitude=0.1, _static_cache={}):

@@ -22,7 +22,8 @@ _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOTPD: "ENOTP
 
 EXPORTS = [
     "tsl_opts_default", "tsl_size_supported", "tsl_footprint", "tsl_open", "tsl_close",
-    "tsl_push_lines", "tsl_push_points", "tsl_sample_lines", "tsl_step_many", "tsl_status",
+    "tsl_push_lines", "tsl_push_points", "tsl_push_frame", "tsl_sample_lines", "tsl_step_many",
+    "tsl_step_many_timed", "tsl_status",
     "tsl_get_factors", "tsl_get_state", "tsl_set_state", "tsl_shape", "tsl_fft2",
     "tsl_pool_create", "tsl_pool_destroy", "tsl_pool_used", "tsl_open_in_pool",
     "tsl_last_error", "tsl_selftest_codelets",
@@ -40,10 +41,17 @@ class Opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64)]
 
 
+N_PHASES = 9
+PHASES = ["partial Grams", "ridge solve + step size", "synthesis + row pass", "column pass + residual",
+          "row inverse + A grad", "A update + F_l A", "B grad + update + F_r B", "output synthesis", "row draw"]
+
+
 class Frame(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int), ("rows", ctypes.c_void_p), ("mask", ctypes.c_void_p),
                 ("y", ctypes.c_void_p), ("X_out", ctypes.c_void_p), ("A_out", ctypes.c_void_p),
-                ("B_out", ctypes.c_void_p), ("gamma_out", ctypes.c_void_p)]
+                ("B_out", ctypes.c_void_p), ("gamma_out", ctypes.c_void_p), ("n_rows_dev", ctypes.c_void_p),
+                ("y_full", ctypes.c_int), ("K_next", ctypes.c_int), ("rows_next", ctypes.c_void_p),
+                ("n_next", ctypes.c_void_p)]
 
 
 _lib = None
@@ -67,7 +75,9 @@ def lib():
             "tsl_push_lines": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
             "tsl_push_points": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
             "tsl_sample_lines": (i, [vp, i, vp, vp, vp, vp, vp]),
+            "tsl_push_frame": (i, [vp, P(Frame), vp]),
             "tsl_step_many": (i, [P(vp), i, P(Frame), vp]),
+            "tsl_step_many_timed": (i, [P(vp), i, P(Frame), P(d), vp]),
             "tsl_status": (i, [vp, i]),
             "tsl_get_factors": (i, [vp, vp, vp, vp, vp, vp]),
             "tsl_get_state": (i, [vp, vp, P(sz)]),
@@ -205,21 +215,34 @@ class Sequence:
                                       _dev(prefix_out, torch.float64, (self.n1,), "prefix_out"),
                                       _stream(stream)))
 
-    def frame(self, rows=None, y=None, mask=None, X_out=None, A_out=None, B_out=None, gamma_out=None):
-        """A tsl_frame for step_many (keeps the tensors alive on the struct)."""
+    def frame(self, rows=None, y=None, mask=None, X_out=None, A_out=None, B_out=None, gamma_out=None,
+              n_rows_dev=None, y_full=False, K_next=0, rows_next=None, n_next=None):
+        """A tsl_frame for push_frame / step_many (keeps the tensors alive on the struct).
+
+        rows: int32 [n] (or a capacity-sized buffer when n_rows_dev holds the count);
+        y: [n, n2] samples, or [n1, n2] with y_full=True / a point mask."""
         f = Frame()
         if mask is not None:
-            f.n_rows = 0
             f.mask = _dev(mask, torch.uint8, (self.n1, self.n2), "mask")
             f.y = _dev(y, torch.complex64, (self.n1, self.n2), "y")
         else:
             n = int(rows.shape[0])
             f.n_rows = n
             f.rows = _dev(rows, torch.int32, (n,), "rows")
-            f.y = _dev(y, torch.complex64, (n, self.n2), "y")
+            f.y_full = int(bool(y_full))
+            f.y = _dev(y, torch.complex64, (self.n1, self.n2) if y_full else (n, self.n2), "y")
+            f.n_rows_dev = _dev(n_rows_dev, torch.int32, (1,), "n_rows_dev")
         f.X_out, f.A_out, f.B_out, f.gamma_out = self._outs(X_out, A_out, B_out, gamma_out)
-        f._keep = (rows, y, mask, X_out, A_out, B_out, gamma_out)
+        if K_next:
+            f.K_next = int(K_next)
+            f.rows_next = _dev(rows_next, torch.int32, (int(K_next),), "rows_next")
+            f.n_next = _dev(n_next, torch.int32, (1,), "n_next")
+        f._keep = (rows, y, mask, X_out, A_out, B_out, gamma_out, n_rows_dev, rows_next, n_next)
         return f
+
+    def push(self, frame, stream=None):
+        """tsl_push_frame with a Frame from self.frame(...)."""
+        _check(lib().tsl_push_frame(self.h, ctypes.byref(frame), _stream(stream)))
 
     # ---------------------------------------------------------------- state
     def status(self, clear=False):
@@ -261,6 +284,31 @@ def step_many(seqs, frames, stream=None):
     hs = (ctypes.c_void_p * n)(*[s.h for s in seqs])
     fs = (Frame * n)(*frames)
     _check(lib().tsl_step_many(hs, n, fs, _stream(stream)))
+
+
+class PreparedStep:
+    """A batched step whose handle and frame arrays are built once, so that
+    launching it again costs one C call (the frames' tensors must stay alive)."""
+
+    def __init__(self, seqs, frames):
+        self.n = len(seqs)
+        self.hs = (ctypes.c_void_p * self.n)(*[s.h for s in seqs])
+        self.fs = (Frame * self.n)(*frames)
+        self._keep = (list(seqs), list(frames))
+
+    def launch(self, stream=None):
+        _check(lib().tsl_step_many(self.hs, self.n, self.fs, _stream(stream)))
+
+
+def step_many_timed(seqs, frames, phase_ms=None, stream=None):
+    """Profiling form of step_many (no graph; waits).  Adds per-phase milliseconds
+    to phase_ms (a list of N_PHASES floats) and returns it."""
+    n = len(seqs)
+    hs = (ctypes.c_void_p * n)(*[s.h for s in seqs])
+    fs = (Frame * n)(*frames)
+    acc = (ctypes.c_double * N_PHASES)(*(phase_ms or [0.0] * N_PHASES))
+    _check(lib().tsl_step_many_timed(hs, n, fs, acc, _stream(stream)))
+    return list(acc)
 
 
 def fft2(x, out=None, inverse=False, stream=None):

@@ -373,3 +373,104 @@ def test_runs_are_deterministic(T):
         res.append((host(o.X).copy(), host(o.A).copy()))
         seq.close()
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+# ---------------------------------------------------------------------------- device-drawn rows
+def test_config3_device_drawn_rows_match_oracle(T):
+    """Informative sampling loop with no host round trip on the device path:
+    the GPU draws the rows of frame t+1 from its own F_l A[t]; the oracle's
+    sampler on the same (exported) factor must give the same rows bit for bit,
+    and the oracle, fed those rows, must track the GPU within the tolerance."""
+    print("config 3 device-drawn rows", flush=True)
+    Tn = 40
+    c = I.config3_kspace(T=Tn)
+    n1, n2, r = c["n1"], c["n2"], c["r"]
+    K = n1 // 8
+    warm = 5
+    seq = T.Sequence(n1, n2, r, 0.05, dev(c["A0"]), dev(c["B0"]), seed=77, stream_id=3)
+    ora = oracle.TslOracle(n1, n2, r, 0.05, c["A0"], c["B0"])
+    Kd = dev(c["kspace"])
+    full = torch.arange(n1, dtype=torch.int32, device="cuda")
+    rows_buf = [torch.zeros(K, dtype=torch.int32, device="cuda") for _ in range(2)]
+    cnt_buf = [torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(2)]
+    o = Outs(n1, n2, r)
+    Ah = torch.zeros(n1, r, dtype=torch.complex64, device="cuda")
+    rows_h = np.arange(n1, dtype=np.int32)
+    worst, fp64_agree = {}, 0
+    for t in range(Tn):
+        nxt = dict(K_next=K, rows_next=rows_buf[(t + 1) % 2], n_next=cnt_buf[(t + 1) % 2])
+        if t < warm:
+            fr = seq.frame(rows=full, y=Kd[t], y_full=True, **o.kw(), **nxt)
+        else:
+            fr = seq.frame(rows=rows_buf[t % 2], n_rows_dev=cnt_buf[t % 2], y=Kd[t], y_full=True, **o.kw(), **nxt)
+        seq.push(fr)
+        s = ora.push_lines(rows_h, c["kspace"][t][rows_h])
+        e = compare_step(o, s, f"t={t + 1}")
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0), v)
+        seq.factors(Ahat=Ah)
+        nr_ = int(host(cnt_buf[(t + 1) % 2])[0])
+        g_rows = host(rows_buf[(t + 1) % 2])[:nr_].copy()
+        o_rows, _ = oracle.draw_lines(host(Ah), n2, K, 77, 3, t + 2)
+        assert np.array_equal(o_rows, g_rows), f"row draw differs at t={t + 2}"
+        own, _ = oracle.draw_lines(ora.kspace_factors()[0], n2, K, 77, 3, t + 2)
+        fp64_agree += int(np.array_equal(own, g_rows))
+        rows_h = g_rows if t + 1 >= warm else np.arange(n1, dtype=np.int32)
+    print("config 3 worst NRMSE", worst, f"oracle's own FP64 draws agree {fp64_agree}/{Tn}", flush=True)
+    assert seq.status() == 0
+    seq.close()
+
+
+def test_step_many_with_draws_equals_push_frame(T):
+    print("step_many with draws", flush=True)
+    specs = [(128, 128, 16), (256, 256, 32), (128, 128, 8), (192, 160, 24)]
+    rng = np.random.default_rng(5)
+    A_seqs, B_seqs, data = [], [], []
+    for k, (n1, n2, r) in enumerate(specs):
+        _, A0, B0 = _random_state(n1, n2, r, 900 + k)
+        A_seqs.append(T.Sequence(n1, n2, r, 0.05, dev(A0), dev(B0), seed=5, stream_id=k))
+        B_seqs.append(T.Sequence(n1, n2, r, 0.05, dev(A0), dev(B0), seed=5, stream_id=k))
+        data.append(dev(cn(rng, (6, n1, n2), 1e-3).astype(np.complex64)))
+    bufs = {}
+    for side in ("batch", "solo"):
+        bufs[side] = [dict(rows=[torch.zeros(n1 // 8, dtype=torch.int32, device="cuda") for _ in range(2)],
+                           cnt=[torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(2)],
+                           out=Outs(n1, n2, r)) for (n1, n2, r) in specs]
+    for t in range(6):
+        frames = []
+        for k, (n1, n2, r) in enumerate(specs):
+            for side, sq in (("batch", A_seqs[k]), ("solo", B_seqs[k])):
+                b = bufs[side][k]
+                nxt = dict(K_next=n1 // 8, rows_next=b["rows"][(t + 1) % 2], n_next=b["cnt"][(t + 1) % 2])
+                if t == 0:
+                    fr = sq.frame(rows=torch.arange(n1, dtype=torch.int32, device="cuda"), y=data[k][t],
+                                  y_full=True, **b["out"].kw(), **nxt)
+                else:
+                    fr = sq.frame(rows=b["rows"][t % 2], n_rows_dev=b["cnt"][t % 2], y=data[k][t], y_full=True,
+                                  **b["out"].kw(), **nxt)
+                if side == "batch":
+                    frames.append(fr)
+                else:
+                    sq.push(fr)
+        T.step_many(A_seqs, frames)
+        for k in range(len(specs)):
+            bb, bs = bufs["batch"][k], bufs["solo"][k]
+            assert np.array_equal(host(bb["out"].X), host(bs["out"].X))
+            assert np.array_equal(host(bb["cnt"][(t + 1) % 2]), host(bs["cnt"][(t + 1) % 2]))
+            n_ = int(host(bb["cnt"][(t + 1) % 2])[0])
+            assert np.array_equal(host(bb["rows"][(t + 1) % 2])[:n_], host(bs["rows"][(t + 1) % 2])[:n_])
+    for s in A_seqs + B_seqs:
+        assert s.status() == 0
+        s.close()
+
+
+def test_device_row_count_out_of_range_latches(T):
+    n1, n2, r = 64, 64, 4
+    _, A0, B0 = _random_state(n1, n2, r, 8)
+    seq = T.Sequence(n1, n2, r, 0.1, dev(A0), dev(B0))
+    rows = torch.arange(8, dtype=torch.int32, device="cuda")
+    cnt = torch.tensor([65], dtype=torch.int32, device="cuda")
+    y = torch.zeros(n1, n2, dtype=torch.complex64, device="cuda")
+    seq.push(seq.frame(rows=rows, n_rows_dev=cnt, y=y, y_full=True))
+    assert seq.status(clear=True) == T.EINVAL
+    seq.close()
