@@ -157,15 +157,22 @@ def main():
         t += 1
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    host_us = []
     w0 = time.perf_counter()
     ev[0].record(stream)
     for k in range(a.steps):
+        h0 = time.perf_counter()
         step(t)
+        host_us.append((time.perf_counter() - h0) * 1e6)
         t += 1
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps)]
+    slow = sorted(range(a.steps), key=lambda k: -step_ms[k])[:5]
+    print(f"[bench] host launch us p50 {pct(host_us, 50):.1f} max {max(host_us):.1f}; slowest steps "
+          + ", ".join(f"#{k}: {step_ms[k]:.3f} ms (host {host_us[k]:.0f} us)" for k in slow),
+          file=sys.stderr, flush=True)
     gpu_ms = ev[0].elapsed_time(ev[-1])
     ms_per_step = max(wall * 1e3, gpu_ms) / a.steps
     value = S * 1000.0 / ms_per_step

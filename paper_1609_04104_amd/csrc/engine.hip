@@ -166,18 +166,19 @@ int set_dev(const tsl_seq* s) {
 
 // -------------------------------------------------------------- batched step state
 struct GroupKey {
-    int n1, n2, mode, count, r_max;
+    int n1, n2, mode, count, r_max, rows_cap;
     bool want_x, want_sample;
 };
 
 struct Composition {
     std::vector<const tsl_seq*> seqs;     // in the order of the call
     std::vector<int> wants;               // per frame: bit0 X, bit4 points, bit5 row draw
+    std::vector<int> caps;                // per frame: row capacity (sizes the statistics grid)
     std::vector<int> order;               // frame indices sorted by group
     std::vector<GroupKey> groups;
     std::vector<int> group_start;         // offset into order / table
     bool operator==(const Composition& o) const {
-        return seqs == o.seqs && wants == o.wants;
+        return seqs == o.seqs && wants == o.wants && caps == o.caps;
     }
 };
 
@@ -186,10 +187,14 @@ struct BatchEngine {
     hipStream_t cap = nullptr;            // capture stream (never executes work)
     tsl::FrameArgs* table = nullptr;      // device table
     size_t table_cap = 0;
-    static constexpr int kRing = 8;
+    // Descriptor ring: slot k is reused only after the step that last used it
+    // has finished on the device, which also bounds how far the host runs ahead
+    // of the GPU (kRing steps); a deeper queue has been seen to stall the host
+    // for milliseconds while the runtime drains it.
+    static constexpr int kRing = 3;
     tsl::FrameArgs* staging[kRing] = {};
     hipEvent_t staged[kRing] = {};
-    int ring_pos = 0;
+    int ring_pos = 0, cur_slot = 0;
     size_t staging_cap = 0;
     Composition comp;
     bool have_graph = false;
@@ -244,7 +249,7 @@ std::vector<tsl::Batch> group_batches(const Composition& c, const tsl::FrameArgs
         b.one = nullptr;
         b.table = table + c.group_start[g];
         b.count = k.count;
-        b.n1 = k.n1; b.n2 = k.n2; b.r_max = k.r_max; b.rows_max = k.n1;
+        b.n1 = k.n1; b.n2 = k.n2; b.r_max = k.r_max; b.rows_max = k.rows_cap;
         b.mode = k.mode; b.want_x = k.want_x; b.want_sample = k.want_sample;
         out.push_back(b);
     }
@@ -255,6 +260,7 @@ std::vector<tsl::Batch> group_batches(const Composition& c, const tsl::FrameArgs
 int compose(tsl_seq* const* seqs, int n, const tsl_frame* frames, Composition& c) {
     c.seqs.resize(n);
     c.wants.resize(n);
+    c.caps.resize(n);
     for (int i = 0; i < n; ++i) {
         const tsl_seq* s = seqs[i];
         if (!s) return fail(TSL_EINVAL, "null sequence in batch");
@@ -264,6 +270,7 @@ int compose(tsl_seq* const* seqs, int n, const tsl_frame* frames, Composition& c
         if (rc != TSL_OK) return rc;
         c.seqs[i] = s;
         c.wants[i] = (frames[i].X_out ? 1 : 0) | (frames[i].mask ? 16 : 0) | (frames[i].K_next > 0 ? 32 : 0);
+        c.caps[i] = frames[i].mask ? s->n1 : std::min(std::max(frames[i].n_rows, 0), s->n1);
     }
     std::map<std::tuple<int, int, int>, std::vector<int>> by;
     for (int i = 0; i < n; ++i) by[{seqs[i]->n1, seqs[i]->n2, (c.wants[i] & 16) ? 1 : 0}].push_back(i);
@@ -273,6 +280,7 @@ int compose(tsl_seq* const* seqs, int n, const tsl_frame* frames, Composition& c
         k.count = int(kv.second.size());
         for (int i : kv.second) {
             k.r_max = std::max(k.r_max, seqs[i]->r);
+            k.rows_cap = std::max(k.rows_cap, c.caps[i]);
             k.want_x = k.want_x || (c.wants[i] & 1);
             k.want_sample = k.want_sample || (c.wants[i] & 32);
         }
@@ -298,7 +306,7 @@ int stage_table(BatchEngine& be, const Composition& c, tsl_seq* const* seqs, con
         host[p] = frame_args(seqs[i], frames[i]);
     }
     TSL_HIP(hipMemcpyAsync(be.table, host, size_t(n) * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice, st));
-    TSL_HIP(hipEventRecord(be.staged[slot], st));
+    be.cur_slot = slot;
     return TSL_OK;
 }
 
@@ -439,7 +447,8 @@ int tsl_push_frame(tsl_seq* s, const tsl_frame* frame, void* stream) {
     b.one = &a;
     b.table = nullptr;
     b.count = 1;
-    b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r; b.rows_max = s->n1; b.mode = a.mode;
+    b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r; b.mode = a.mode;
+    b.rows_max = frame->mask ? s->n1 : std::min(std::max(frame->n_rows, 0), s->n1);
     b.want_x = frame->X_out != nullptr;
     b.want_sample = a.K_next > 0;
     return run_groups({b}, st);
@@ -516,6 +525,7 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
         be.have_graph = true;
     }
     TSL_HIP(hipGraphLaunch(be.exec, st));
+    TSL_HIP(hipEventRecord(be.staged[be.cur_slot], st));
     return TSL_OK;
 }
 
@@ -533,6 +543,7 @@ int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, do
     hipEvent_t ev[TSL_N_PHASES + 1] = {};
     for (auto& e : ev) TSL_HIP(hipEventCreate(&e));
     rc = run_groups(group_batches(c, be.table), st, ev);
+    if (rc == TSL_OK) rc = hipEventRecord(be.staged[be.cur_slot], st) == hipSuccess ? TSL_OK : TSL_EDEVICE;
     if (rc == TSL_OK) {
         hipError_t e = hipEventSynchronize(ev[TSL_N_PHASES]);
         for (int p = 0; p < TSL_N_PHASES && e == hipSuccess; ++p) {

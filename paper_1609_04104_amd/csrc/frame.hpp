@@ -22,16 +22,15 @@ struct SeqDev {
 
 enum : int { MODE_LINES = 0, MODE_POINTS = 1 };
 
-// Row chunks of the partial Gram statistics.
-constexpr int kGramRows = 64;   // rows of F_l A or F_r B per Gram partial
-constexpr int kSRows = 16;      // sampled rows per (Gram, rhs) partial, line masks
-constexpr int kPRows = 8;       // rows per (Gram, rhs) partial, point masks
+// Slots of the Gram statistics: [0] = (F_l A)^H F_l A, [1] = (F_r B)^H F_r B (one
+// block each, all rows), then the partials of the sampled part: kSRows sampled
+// rows per slot for line masks, kPRows mask rows per slot for point masks.
+constexpr int kSRows = 32;      // sampled rows per (Gram, rhs) partial, line masks
+constexpr int kPRows = 32;      // mask rows per (Gram, rhs) partial, point masks
 
 __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
-__host__ __device__ inline int n_gram_a(int n1) { return cdiv(n1, kGramRows); }
-__host__ __device__ inline int n_gram_b(int n2) { return cdiv(n2, kGramRows); }
 __host__ __device__ inline int n_sparts(int n1) { return cdiv(n1, kPRows); }   // >= cdiv(n1, kSRows)
-__host__ __device__ inline int n_parts(int n1, int n2) { return n_gram_a(n1) + n_gram_b(n2) + n_sparts(n1); }
+__host__ __device__ inline int n_parts(int n1, int n2) { return 2 + n_sparts(n1); }
 
 // Everything the kernels of one frame of one sequence read or write.
 struct FrameArgs {
@@ -66,12 +65,19 @@ struct FrameArgs {
     unsigned long long seed, sid;
 };
 
-// Row count of a line-mask frame, clamped to [0, n1] so that no kernel reads
-// outside the row list; the partial-Gram kernel latches ST_EINVAL when the
-// device count was out of range.
+// Row capacity of a line-mask frame: n_rows (the length of the row list), at
+// most n1.  With a device row count, n_rows is the capacity of the list.
+__device__ __forceinline__ int frame_rows_cap(const FrameArgs& f) {
+    return f.n_rows < 0 ? 0 : (f.n_rows > f.n1 ? f.n1 : f.n_rows);
+}
+// Row count of a line-mask frame, clamped to [0, capacity] so that no kernel
+// reads outside the row list; the sampled-row statistics kernel latches
+// ST_EINVAL when a device count was out of range.
 __device__ __forceinline__ int frame_rows(const FrameArgs& f) {
-    int n = f.n_rows_dev ? *f.n_rows_dev : f.n_rows;
-    return n < 0 ? 0 : (n > f.n1 ? f.n1 : n);
+    const int cap = frame_rows_cap(f);
+    if (!f.n_rows_dev) return cap;
+    const int n = *f.n_rows_dev;
+    return n < 0 ? 0 : (n > cap ? cap : n);
 }
 
 // Samples of row `row`, listed at position q of the row set (lines).
@@ -112,6 +118,26 @@ __device__ __forceinline__ bool block_frame_ok(const SeqDev* d, bool need_solve)
 
 __device__ __forceinline__ bool finite2(float2 v) {
     return isfinite(v.x) && isfinite(v.y);
+}
+
+// Block-cooperative copy of n elements, element e = load(e) stored by store(e, v):
+// each thread issues U independent loads before it stores any of them, so U
+// memory latencies overlap instead of following one another.
+template <int U, class T, class Load, class Store>
+__device__ __forceinline__ void stage_copy(int n, Load load, Store store) {
+    for (int e0 = threadIdx.x; e0 < n; e0 += int(blockDim.x) * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * int(blockDim.x);
+            if (e < n) v[u] = load(e);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * int(blockDim.x);
+            if (e < n) store(e, v[u]);
+        }
+    }
 }
 
 }  // namespace tsl

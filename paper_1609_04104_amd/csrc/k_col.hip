@@ -155,10 +155,13 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
     bool bad = false;
     for (int r0 = 0; r0 < R; r0 += kRW) {
         __syncthreads();
-        for (int e = tid; e < N1 * kRW; e += blockDim.x) {
-            const int ii = e / kRW, cc = e % kRW;
-            s_A[e] = (r0 + cc < R) ? f.A[size_t(ii) * R + r0 + cc] : float2{0.f, 0.f};
-        }
+        stage_copy<8, float2>(
+            N1 * kRW,
+            [&](int e) {
+                const int ii = e / kRW, cc = e % kRW;
+                return (r0 + cc < R) ? f.A[size_t(ii) * R + r0 + cc] : float2{0.f, 0.f};
+            },
+            [&](int e, float2 v) { s_A[e] = v; });
         __syncthreads();
         if (s < Q) {
 #pragma unroll

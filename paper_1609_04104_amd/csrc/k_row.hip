@@ -67,10 +67,13 @@ __global__ void __launch_bounds__(256) k_synth_rowfft(Src src) {
     sfor<T>([&](auto k) { v[decltype(k)::value] = float2{0.f, 0.f}; });
     for (int r0 = 0; r0 < R; r0 += kRC) {
         __syncthreads();
-        for (int e = tid; e < kRC * N2; e += blockDim.x) {
-            const int j = e / kRC, c = e % kRC;
-            s_B[c * N2 + j] = (r0 + c < R) ? f.B[j * R + r0 + c] : float2{0.f, 0.f};
-        }
+        stage_copy<8, float2>(
+            kRC * N2,
+            [&](int e) {
+                const int j = e / kRC, c = e % kRC;
+                return (r0 + c < R) ? f.B[j * R + r0 + c] : float2{0.f, 0.f};
+            },
+            [&](int e, float2 v) { s_B[(e % kRC) * N2 + e / kRC] = v; });
         for (int e = tid; e < ROWS * kRC; e += blockDim.x) {
             const int rr = e / kRC, c = e % kRC, ii = blockIdx.x * ROWS + rr;
             s_ag[e] = (r0 + c < R && ii < n1) ? cmul(f.A[ii * R + r0 + c], f.gamma32[r0 + c])
@@ -138,10 +141,13 @@ __global__ void __launch_bounds__(256) k_row_inv_grad(Src src) {
     bool bad = false;
     for (int r0 = 0; r0 < R; r0 += kRC) {
         __syncthreads();
-        for (int e = tid; e < kRC * N2; e += blockDim.x) {
-            const int j = e / kRC, c = e % kRC;
-            s_B[c * N2 + j] = (r0 + c < R) ? f.B[j * R + r0 + c] : float2{0.f, 0.f};
-        }
+        stage_copy<8, float2>(
+            kRC * N2,
+            [&](int e) {
+                const int j = e / kRC, c = e % kRC;
+                return (r0 + c < R) ? f.B[j * R + r0 + c] : float2{0.f, 0.f};
+            },
+            [&](int e, float2 v) { s_B[(e % kRC) * N2 + e / kRC] = v; });
         __syncthreads();
         if (s < P) {
 #pragma unroll
