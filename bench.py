@@ -18,6 +18,7 @@ roofline of the dominant kernel and the FP64 CPU oracle's frames/s.
 """
 
 import argparse
+import gc
 import json
 import math
 import multiprocessing as mp
@@ -48,6 +49,10 @@ def parse():
     ap.add_argument("--phase-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--procs", type=int, default=16, help="host processes generating the inputs (1: in-process)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -59,10 +64,13 @@ def _gen(args):
     return c["kspace"], c["A0"], c["B0"]
 
 
-def make_inputs(seqs, n, r, frames):
-    procs = max(1, min(16, os.cpu_count() or 1, seqs))
+def make_inputs(seqs, n, r, frames, procs=16):
+    procs = max(1, min(procs, os.cpu_count() or 1, seqs))
+    jobs = [(n, r, frames, s) for s in range(seqs)]
+    if procs == 1:
+        return [_gen(j) for j in jobs]
     with mp.get_context("spawn").Pool(procs) as pool:
-        return pool.map(_gen, [(n, r, frames, s) for s in range(seqs)])
+        return pool.map(_gen, jobs)
 
 
 # ----------------------------------------------------------------------------- work model
@@ -101,12 +109,20 @@ def main():
 
     tsl.lib()
     torch.cuda.set_device(0)
+    if a.copy_calib_mib:
+        src = torch.ones(a.copy_calib_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] reference copy of {a.copy_calib_mib} MiB done", file=sys.stderr, flush=True)
+        del src, dst
     S, n, r, lam, F = a.seqs, a.n, a.r, a.lam, a.frames
     K = max(1, n // 8)
     warm = 5
     print(f"[bench] generating {S} x {F} frames of {n}x{n}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    data = make_inputs(S, n, r, F)
+    data = make_inputs(S, n, r, F, a.procs)
     print(f"[bench] inputs in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
@@ -157,6 +173,10 @@ def main():
         t += 1
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    # a full collection of Python's cyclic garbage inside the loop stalls the
+    # host for milliseconds; collect now and exempt everything alive from it
+    gc.collect()
+    gc.freeze()
     host_us = []
     w0 = time.perf_counter()
     ev[0].record(stream)
@@ -229,6 +249,8 @@ def main():
     torch.cuda.synchronize()
     P = a.plain_frames
     pev = [torch.cuda.Event(enable_timing=True) for _ in range(P + 1)]
+    gc.collect()
+    gc.freeze()
     w0 = time.perf_counter()
     pev[0].record(stream)
     for k in range(P):

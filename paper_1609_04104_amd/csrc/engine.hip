@@ -55,7 +55,7 @@ Layout layout_for(int n1, int n2, int r) {
     L.Wb = take(size_t(n2) * r * sizeof(float2));
     L.GA = take(size_t(n1) * r * sizeof(float2));
     L.part = take(size_t(tsl::n_parts(n1, n2)) * r * r * sizeof(double2));
-    L.hpart = take(size_t(tsl::n_sparts(n1)) * r * sizeof(double2));
+    L.hpart = take(size_t(tsl::n_hparts(n1, n2)) * r * sizeof(double2));
     L.total = o;
     return L;
 }

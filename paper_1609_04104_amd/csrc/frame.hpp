@@ -22,58 +22,88 @@ struct SeqDev {
 
 enum : int { MODE_LINES = 0, MODE_POINTS = 1 };
 
-// Slots of the Gram statistics: [0] = (F_l A)^H F_l A, [1] = (F_r B)^H F_r B (one
-// block each, all rows), then the partials of the sampled part: kSRows sampled
-// rows per slot for line masks, kPRows mask rows per slot for point masks.
+// Slots of the Gram statistics, each [r][r] (upper entries): first the partials
+// of (F_l A)^H F_l A over kGRows rows of F_l A each, then those of
+// (F_r B)^H F_r B, then the partials of the sampled part (kSRows sampled rows
+// per slot for line masks, kPRows mask rows per slot for point masks).  The
+// right-hand side partials are [sampled slot][readout chunk of kJCH samples]
+// for line masks and [sampled slot] for point masks.
+constexpr int kGRows = 32;      // rows of F_l A or F_r B per factor-Gram partial
 constexpr int kSRows = 32;      // sampled rows per (Gram, rhs) partial, line masks
 constexpr int kPRows = 32;      // mask rows per (Gram, rhs) partial, point masks
+constexpr int kJCH = 32;        // readout samples per right-hand-side partial, line masks
 
 __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ inline int n_gparts(int n) { return cdiv(n, kGRows); }
 __host__ __device__ inline int n_sparts(int n1) { return cdiv(n1, kPRows); }   // >= cdiv(n1, kSRows)
-__host__ __device__ inline int n_parts(int n1, int n2) { return 2 + n_sparts(n1); }
+__host__ __device__ inline int n_jparts(int n2) { return cdiv(n2, kJCH); }
+__host__ __device__ inline int n_parts(int n1, int n2) { return n_gparts(n1) + n_gparts(n2) + n_sparts(n1); }
+__host__ __device__ inline int n_hparts(int n1, int n2) { return n_sparts(n1) * n_jparts(n2); }
+
+// Pointer types of a frame descriptor.  The host fills descriptors with plain
+// pointers; device code reads the same bits as pointers into the global address
+// space (every one addresses device global memory), which lets the compiler use
+// global rather than flat memory instructions (flat loads also count against the
+// LDS wait counter, which serialises LDS traffic behind them).
+template <class T> using HostPtr = T*;
+#ifdef __HIP_DEVICE_COMPILE__
+template <class T> using GlobalPtr = __attribute__((address_space(1))) T*;
+#else
+template <class T> using GlobalPtr = T*;
+#endif
 
 // Everything the kernels of one frame of one sequence read or write.
-struct FrameArgs {
+template <template <class> class P>
+struct FrameArgsT {
     int n1, n2, r, mode;
     double lambda, mu_const;
     int step_mode, n_rows;
     // resident state
-    float2 *A, *B, *Ahat, *Bhat;
-    SeqDev* dev;
-    double2* gamma64;
-    float2* gamma32;
+    P<float2> A, B, Ahat, Bhat;
+    P<SeqDev> dev;
+    P<double2> gamma64;
+    P<float2> gamma32;
     // workspace
-    float2* frame;      // [n1][n2]: row-transformed synthesis, then the column-back-projected residual
-    float2* Wb;         // [n2][r]: Z^T conj(A), Z the column-back-projected residual
-    float2* GA;         // [n1][r]: Theta conj(B)
-    double2* part;      // [n_parts][r][r] partial Grams
-    double2* hpart;     // [n_sparts][r] partial right-hand sides
+    P<float2> frame;      // [n1][n2]: row-transformed synthesis, then the column-back-projected residual
+    P<float2> Wb;         // [n2][r]: Z^T conj(A), Z the column-back-projected residual
+    P<float2> GA;         // [n1][r]: Theta conj(B)
+    P<double2> part;      // [n_parts][r][r] partial Grams
+    P<double2> hpart;     // [n_hparts][r] partial right-hand sides
     // inputs of the frame
-    const int* rows;
-    const int* n_rows_dev;   // device row count (lines), or null to use n_rows
-    int y_full;              // lines: y is [n1][n2] and row k is read at y + k*n2
-    const unsigned char* mask;
-    const float2* y;
+    P<const int> rows;
+    P<const int> n_rows_dev;   // device row count (lines), or null to use n_rows
+    int y_full;                // lines: y is [n1][n2] and row k is read at y + k*n2
+    P<const unsigned char> mask;
+    P<const float2> y;
     // outputs (may be null)
-    float2 *X_out, *A_out, *B_out, *gamma_out;
+    P<float2> X_out, A_out, B_out, gamma_out;
     // draw of the next frame's rows (K_next == 0: none)
     int K_next;
-    int* rows_next;
-    int* n_next;
-    int* draws_next;         // [K_next] rows of the individual trials, or null
-    double* prefix_next;     // [n1] weight prefix, or null
+    P<int> rows_next;
+    P<int> n_next;
+    P<int> draws_next;         // [K_next] rows of the individual trials, or null
+    P<double> prefix_next;     // [n1] weight prefix, or null
     unsigned long long seed, sid;
 };
+using FrameArgs = FrameArgsT<HostPtr>;
+using DevFrame = FrameArgsT<GlobalPtr>;
+static_assert(sizeof(FrameArgs) == sizeof(DevFrame), "host and device descriptors share one layout");
+
+__device__ __forceinline__ DevFrame dev_frame(const FrameArgs& a) {
+    DevFrame d;
+    __builtin_memcpy(&d, &a, sizeof(d));
+    return d;
+}
 
 // Row capacity of a line-mask frame: n_rows (the length of the row list), at
 // most n1.  With a device row count, n_rows is the capacity of the list.
-__device__ __forceinline__ int frame_rows_cap(const FrameArgs& f) {
+__device__ __forceinline__ int frame_rows_cap(const DevFrame& f) {
     return f.n_rows < 0 ? 0 : (f.n_rows > f.n1 ? f.n1 : f.n_rows);
 }
 // Row count of a line-mask frame, clamped to [0, capacity] so that no kernel
 // reads outside the row list; the sampled-row statistics kernel latches
 // ST_EINVAL when a device count was out of range.
-__device__ __forceinline__ int frame_rows(const FrameArgs& f) {
+__device__ __forceinline__ int frame_rows(const DevFrame& f) {
     const int cap = frame_rows_cap(f);
     if (!f.n_rows_dev) return cap;
     const int n = *f.n_rows_dev;
@@ -81,7 +111,7 @@ __device__ __forceinline__ int frame_rows(const FrameArgs& f) {
 }
 
 // Samples of row `row`, listed at position q of the row set (lines).
-__device__ __forceinline__ const float2* line_samples(const FrameArgs& f, int q, int row) {
+__device__ __forceinline__ GlobalPtr<const float2> line_samples(const DevFrame& f, int q, int row) {
     return f.y + size_t(f.y_full ? row : q) * f.n2;
 }
 
@@ -89,11 +119,11 @@ __device__ __forceinline__ const float2* line_samples(const FrameArgs& f, int q,
 // entry blockIdx.y of a device table (batched step).
 struct OneFrame {
     FrameArgs a;
-    __device__ __forceinline__ const FrameArgs& get() const { return a; }
+    __device__ __forceinline__ DevFrame get() const { return dev_frame(a); }
 };
 struct FrameTable {
-    const FrameArgs* t;
-    __device__ __forceinline__ const FrameArgs& get() const { return t[blockIdx.y]; }
+    const FrameArgs* __restrict__ t;
+    __device__ __forceinline__ DevFrame get() const { return dev_frame(t[blockIdx.y]); }
 };
 
 // Latch an error code if none is latched yet (first error wins).

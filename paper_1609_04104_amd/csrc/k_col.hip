@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
     __shared__ float2 s_u[cmax(S::XSIZE, AW + RW)];
     __shared__ int s_bad;
 
-    const FrameArgs& f = src.get();
+    const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, true)) return;
     const int n2 = f.n2, R = f.r;
     const int tid = threadIdx.x, c = tid % kTW, s = tid / kTW;
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(512) k_update_a(Src src) {
     constexpr int P = S::P, Q = S::Q, T = S::T;
     __shared__ float2 s_tw[N1];
     __shared__ float2 s_x[S::XSIZE];
-    const FrameArgs& f = src.get();
+    const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, true)) return;
     const int R = f.r;
     if (int(blockIdx.x) * kTW >= R) return;
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(512) k_update_b(Src src) {
     constexpr int P = S::P, Q = S::Q, T = S::T;
     __shared__ float2 s_tw[N2];
     __shared__ float2 s_x[S::XSIZE];
-    const FrameArgs& f = src.get();
+    const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, true)) return;
     const int R = f.r;
     if (int(blockIdx.x) * kTW >= R) return;

@@ -6,7 +6,7 @@
 //               Hadamard product (Ahat_S^H Ahat_S) .* (Bhat^H Bhat) and
 //               Phi^H y = sum_{i in S} conj(Ahat_i) .* (y_i conj(Bhat)); with a
 //               point mask both are summed entry by entry.  Partials cover row
-//               chunks and are reduced in a fixed order by k_solve.
+//               chunks and are reduced in a fixed order by the solve.
 //  k_solve      G = Phi^H Phi + lambda I, Cholesky, gamma_t = G^{-1} Phi^H y (the
 //               closed form of the ridge problem), the step size alpha_t of the
 //               majorizer (Sec. III-A; Gershgorin bound of diag(g)^H A^H A diag(g)
@@ -15,6 +15,7 @@
 //  k_sample     Algorithm 4 on rows with the score of Sec. VI-C.
 #include "fft_engine.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 #include "tsl.h"
 
 #include <mutex>
@@ -36,142 +37,99 @@ __device__ __forceinline__ double2 dcmulc(double2 a, double2 b) {   // a conj(b)
 __device__ __forceinline__ double dabs(double2 a) { return sqrt(a.x * a.x + a.y * a.y); }
 
 // ---------------------------------------------------------------- Gram statistics
-// Blocks of kGThreads threads in kGGroups row groups: every group owns the same
-// upper-triangle entries (kGE per thread per pass) and takes every kGGroups-th
-// staged row; the groups' partial sums are added in group order at the end.
-// Rows are staged once per pass as FP64 (s_x, kGStage complex entries).
-constexpr int kGThreads = 1024;
-constexpr int kGGroups = 4;
-constexpr int kGTh = kGThreads / kGGroups;
-constexpr int kGStage = 4096;
+// Blocks of kSB threads.  A Gram is accumulated from rows staged in LDS as FP64
+// (products of FP32 values are exact there); a thread owns kGE upper entries
+// per pass.  Every block writes its own partial slot and the solve sums the
+// slots in slot order, so the result does not depend on block scheduling.
+constexpr int kSB = 256;
 constexpr int kGE = 4;
-constexpr int kGRed = (kGGroups - 1) * kGTh * kGE;   // complex entries of s_red
+constexpr int kZU = (kSRows * TSL_MAX_R + kSB - 1) / kSB;   // (row, rank) entries per thread, rhs partial
+static_assert(kJCH >= kSRows, "the rhs products reuse the readout-chunk staging area");
 
-__device__ __forceinline__ double2 dconj_mul(double2 a, double2 b) {   // conj(a) b
-    return double2{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+__device__ __forceinline__ void upper_index(int e, int R, int& r, int& s) {   // packed upper triangle, by rows
+    r = 0;
+    while (e >= R - r) { e -= R - r; ++r; }
+    s = r + e;
 }
 
-template <class RowOf>
-__device__ void gram_upper(const float2* X, int R, int nq, RowOf row_of, double2* out, double2* s_x,
-                           double2* s_red) {
-    const int tid = threadIdx.x, g = tid / kGTh, t = tid % kGTh;
+// Upper entries (r <= s) of sum_q conj(x_qr) x_qs over the nq rows of s_x ([nq][R]).
+__device__ void gram_staged(const double2* s_x, int nq, int R, double2* out) {
+    const int tid = threadIdx.x;
     const int npairs = R * (R + 1) / 2;
-    const int npass = cdiv(npairs, kGTh * kGE);
-    const int stage_rows = max(1, kGStage / R);
-    for (int pass = 0; pass < npass; ++pass) {
+    for (int e0 = 0; e0 < npairs; e0 += kSB * kGE) {
         int er[kGE], es[kGE];
         double2 acc[kGE];
 #pragma unroll
         for (int u = 0; u < kGE; ++u) {
-            int e = t + (pass * kGE + u) * kGTh, r = 0;
-            if (e < npairs) {
-                while (e >= R - r) { e -= R - r; ++r; }
-                er[u] = r;
-                es[u] = r + e;
-            } else {
-                er[u] = 0;
-                es[u] = -1;
-            }
+            const int e = e0 + tid + u * kSB;
+            if (e < npairs) upper_index(e, R, er[u], es[u]);
+            else er[u] = es[u] = 0;
             acc[u] = double2{0.0, 0.0};
         }
-        for (int q0 = 0; q0 < nq; q0 += stage_rows) {
-            const int ns = min(stage_rows, nq - q0);
-            __syncthreads();
-            stage_copy<8, float2>(
-                ns * R,
-                [&](int e) {
-                    const int row = row_of(q0 + e / R);
-                    return row >= 0 ? X[size_t(row) * R + e % R] : float2{0.f, 0.f};
-                },
-                [&](int e, float2 v) { s_x[e] = double2{v.x, v.y}; });
-            __syncthreads();
-            for (int q = g; q < ns; q += kGGroups) {
-                const double2* xq = s_x + q * R;
-                double2 a[kGE], b[kGE];
+        for (int q = 0; q < nq; ++q) {
+            const double2* xq = s_x + q * R;
+            double2 a[kGE], b[kGE];
 #pragma unroll
-                for (int u = 0; u < kGE; ++u) {
-                    a[u] = xq[er[u]];
-                    b[u] = xq[es[u] < 0 ? 0 : es[u]];
-                }
-#pragma unroll
-                for (int u = 0; u < kGE; ++u) {
-                    const double2 p = dconj_mul(a[u], b[u]);
-                    acc[u].x += p.x;
-                    acc[u].y += p.y;
-                }
-            }
-        }
-        __syncthreads();
-        if (g > 0) {
-#pragma unroll
-            for (int u = 0; u < kGE; ++u) s_red[((g - 1) * kGTh + t) * kGE + u] = acc[u];
-        }
-        __syncthreads();
-        if (g == 0) {
+            for (int u = 0; u < kGE; ++u) { a[u] = xq[er[u]]; b[u] = xq[es[u]]; }
 #pragma unroll
             for (int u = 0; u < kGE; ++u) {
-                if (es[u] < 0) continue;
-                double2 v = acc[u];
-                for (int gg = 1; gg < kGGroups; ++gg) {
-                    const double2 w = s_red[((gg - 1) * kGTh + t) * kGE + u];
-                    v.x += w.x;
-                    v.y += w.y;
-                }
-                out[size_t(er[u]) * R + es[u]] = v;
+                acc[u].x = fma(a[u].x, b[u].x, fma(a[u].y, b[u].y, acc[u].x));
+                acc[u].y = fma(a[u].x, b[u].y, fma(-a[u].y, b[u].x, acc[u].y));
             }
+        }
+#pragma unroll
+        for (int u = 0; u < kGE; ++u) {
+            const int e = e0 + tid + u * kSB;
+            if (e < npairs) out[size_t(er[u]) * R + es[u]] = acc[u];
         }
     }
 }
 
-// (F_l A)^H F_l A (block 0) and (F_r B)^H F_r B (block 1), upper entries.
-template <class Src>
-__global__ void __launch_bounds__(kGThreads) k_gram2(Src src) {
-    __shared__ double2 s_x[kGStage];
-    __shared__ double2 s_red[kGRed];
-    const FrameArgs& f = src.get();
-    if (!block_frame_ok(f.dev, false)) return;
-    const int R = f.r;
-    double2* out = f.part + size_t(blockIdx.x) * R * R;
-    const float2* X = blockIdx.x == 0 ? f.Ahat : f.Bhat;
-    gram_upper(X, R, blockIdx.x == 0 ? f.n1 : f.n2, [](int q) { return q; }, out, s_x, s_red);
+// Factor-Gram block b: rows [kGRows b, kGRows (b+1)) of F_l A for b < n_gparts(n1),
+// else the corresponding rows of F_r B; the partial goes to slot b.
+__device__ void factor_gram_block(const DevFrame& f, int b, double2* s_x) {
+    const int gA = n_gparts(f.n1), R = f.r;
+    const bool isA = b < gA;
+    const int n = isA ? f.n1 : f.n2, q0 = (isA ? b : b - gA) * kGRows, nq = min(kGRows, n - q0);
+    GlobalPtr<const float2> X = (isA ? f.Ahat : f.Bhat) + size_t(q0) * R;
+    stage_copy<8, float2>(nq * R, [&](int e) { return X[e]; },
+                          [&](int e, float2 v) { s_x[e] = double2{v.x, v.y}; });
+    __syncthreads();
+    gram_staged(s_x, nq, R, f.part + size_t(b) * R * R);
 }
 
-constexpr int kJC = 32;          // readout samples staged per pass of the right-hand side
-static_assert(kSRows * kJC <= kGThreads, "one staged sample per thread");
-constexpr int kZ = (kSRows * TSL_MAX_R + kGThreads - 1) / kGThreads;
-
-// Line masks: Gram of the sampled rows of F_l A and the right-hand side
-// Phi^H y over sampled rows [kSRows k, kSRows (k+1)); also checks the rows.
-// Blocks 0 and 1 compute the Grams of F_l A and F_r B (as k_gram2); blocks
-// 2.. are the sampled-row blocks, so one launch covers all of S1's statistics.
+// Line masks, one launch for all of S1's statistics.  Blocks [0, gAB) are the
+// factor-Gram partials (gAB = n_gparts(n1) + n_gparts(n2)); block gAB + k nJ + c
+// covers sampled rows [kSRows k, kSRows (k+1)) and readout samples
+// [kJCH c, kJCH (c+1)): for c = 0 it validates those rows and writes the Gram of
+// the sampled rows of F_l A to slot gAB + k; every such block writes the
+// right-hand-side partial h_r = sum_q conj(Ahat_{row_q, r}) sum_j y_qj conj(Bhat_jr)
+// (Phi^H y restricted to the block's samples) to hpart[k nJ + c].
 template <class Src>
-__global__ void __launch_bounds__(kGThreads) k_lstats(Src src) {
-    __shared__ double2 s_x[kGStage];
-    __shared__ double2 s_red[kGRed];
+__global__ void __launch_bounds__(kSB) k_lstats(Src src) {
+    extern __shared__ double2 s_dyn[];
     __shared__ int s_err;
-    const FrameArgs& f = src.get();
+    const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, false)) return;
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
-    if (blockIdx.x < 2) {
-        const float2* X = blockIdx.x == 0 ? f.Ahat : f.Bhat;
-        gram_upper(X, R, blockIdx.x == 0 ? n1 : n2, [](int q) { return q; },
-                   f.part + size_t(blockIdx.x) * R * R, s_x, s_red);
+    const int gAB = n_gparts(n1) + n_gparts(n2);
+    if (int(blockIdx.x) < gAB) {
+        factor_gram_block(f, blockIdx.x, s_dyn);
         return;
     }
-    const int k = blockIdx.x - 2;
-    double2* out = f.part + size_t(2 + k) * R * R;
+    const int nJ = n_jparts(n2);
+    const int k = (blockIdx.x - gAB) / nJ, c = (blockIdx.x - gAB) % nJ;
     if (tid == 0) s_err = 0;
     __syncthreads();
     const int n_rows = frame_rows(f);
-    if (k == 0 && tid == 0 && f.n_rows_dev) {
+    if (k == 0 && c == 0 && tid == 0 && f.n_rows_dev) {
         const int nd = *f.n_rows_dev;
         if (nd < 0 || nd > frame_rows_cap(f)) latch(f.dev, ST_EINVAL);
     }
     const int q0 = k * kSRows;
     if (q0 >= n_rows) return;
     const int nq = min(n_rows, q0 + kSRows) - q0;
-    // validate this chunk's rows: inside [0, n1), strictly ascending
-    if (tid < nq) {
+    if (c == 0 && tid < nq) {                 // rows inside [0, n1), strictly ascending
         const int q = q0 + tid, row = f.rows[q];
         bool ok = row >= 0 && row < n1;
         if (q + 1 < n_rows) ok = ok && f.rows[q + 1] > row;
@@ -181,117 +139,106 @@ __global__ void __launch_bounds__(kGThreads) k_lstats(Src src) {
         const int row = f.rows[q0 + q];
         return (row >= 0 && row < n1) ? row : -1;
     };
-    gram_upper(f.Ahat, R, nq, row_of, out, s_x, s_red);
-    // Z[q][r] = sum_j y_qj conj(Bhat_jr): Bhat staged in s_x ([kJC][R]), the
-    // samples in s_red ([nq][kJC]), kJC readout samples per pass.
-    double2 z[kZ];
-#pragma unroll
-    for (int u = 0; u < kZ; ++u) z[u] = double2{0.0, 0.0};
+    double2* s_x = s_dyn;                     // [kSRows][R]  sampled rows of F_l A
+    double2* s_b = s_x + kSRows * R;          // [kJCH][R]    rows of F_r B in the readout chunk
+    double2* s_y = s_b + kJCH * R;            // [kSRows][kJCH] samples
+    const int j0 = c * kJCH, nj = min(kJCH, n2 - j0);
+    stage_copy<8, float2>(nq * R,
+                          [&](int e) {
+                              const int row = row_of(e / R);
+                              return row >= 0 ? f.Ahat[size_t(row) * R + e % R] : float2{0.f, 0.f};
+                          },
+                          [&](int e, float2 v) { s_x[e] = double2{v.x, v.y}; });
+    stage_copy<8, float2>(nj * R, [&](int e) { return f.Bhat[size_t(j0) * R + e]; },
+                          [&](int e, float2 v) { s_b[e] = double2{v.x, v.y}; });
     bool fin = true;
-    // register prefetch of the next chunk: kPB Bhat values and one sample per thread
-    constexpr int kPB = (kJC * TSL_MAX_R + kGThreads - 1) / kGThreads;
-    float2 pb[kPB], py = float2{0.f, 0.f};
-    auto fetch = [&](int j0) {
-        const int nj = min(kJC, n2 - j0);
+    stage_copy<4, float2>(nq * kJCH,
+                          [&](int e) {
+                              const int q = e / kJCH, jj = e % kJCH, row = row_of(q);
+                              return (row >= 0 && jj < nj) ? float2(line_samples(f, q0 + q, row)[j0 + jj])
+                                                           : float2{0.f, 0.f};
+                          },
+                          [&](int e, float2 v) {
+                              fin = fin && finite2(v);
+                              s_y[e] = double2{v.x, v.y};
+                          });
+    __syncthreads();
+    if (c == 0) gram_staged(s_x, nq, R, f.part + size_t(gAB + k) * R * R);
+
+    // z[q][r] = sum_j y_qj conj(Bhat_jr) over the chunk, one (q, r) entry per slot u
+    const int nqr = nq * R;
+    double2 z[kZU];
+    int zq[kZU], zr[kZU];
 #pragma unroll
-        for (int u = 0; u < kPB; ++u) {
-            const int e = tid + u * kGThreads;
-            pb[u] = e < nj * R ? f.Bhat[size_t(j0) * R + e] : float2{0.f, 0.f};
-        }
-        py = float2{0.f, 0.f};
-        if (tid < nq * kJC) {
-            const int q = tid / kJC, jj = tid % kJC, row = row_of(q);
-            if (row >= 0 && jj < nj) {
-                py = line_samples(f, q0 + q, row)[j0 + jj];
-                fin = fin && finite2(py);
-            }
-        }
-    };
-    fetch(0);
-    for (int j0 = 0; j0 < n2; j0 += kJC) {
-        const int nj = min(kJC, n2 - j0);
-        __syncthreads();
+    for (int u = 0; u < kZU; ++u) {
+        const int e = tid + u * kSB;
+        zq[u] = e / R;
+        zr[u] = e % R;
+        z[u] = double2{0.0, 0.0};
+    }
+    for (int jj = 0; jj < nj; ++jj) {
 #pragma unroll
-        for (int u = 0; u < kPB; ++u) {
-            const int e = tid + u * kGThreads;
-            if (e < nj * R) s_x[e] = double2{pb[u].x, pb[u].y};
-        }
-        if (tid < nq * kJC) s_red[tid] = double2{py.x, py.y};
-        __syncthreads();
-        if (j0 + kJC < n2) fetch(j0 + kJC);
-#pragma unroll
-        for (int u = 0; u < kZ; ++u) {
-            const int e = tid + u * kGThreads;
-            if (e < nq * R) {
-                const int q = e / R, r = e % R;
-                const double2* yq = s_red + q * kJC;
-                int jj = 0;
-                for (; jj + 4 <= nj; jj += 4) {
-                    double2 b[4], yv[4];
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) { b[w] = s_x[(jj + w) * R + r]; yv[w] = yq[jj + w]; }
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        const double2 p = dconj_mul(b[w], yv[w]);
-                        z[u].x += p.x;
-                        z[u].y += p.y;
-                    }
-                }
-                for (; jj < nj; ++jj) {
-                    const double2 p = dconj_mul(s_x[jj * R + r], yq[jj]);
-                    z[u].x += p.x;
-                    z[u].y += p.y;
-                }
+        for (int u = 0; u < kZU; ++u) {
+            if (tid + u * kSB < nqr) {
+                const double2 b = s_b[jj * R + zr[u]], yv = s_y[zq[u] * kJCH + jj];
+                z[u].x = fma(b.x, yv.x, fma(b.y, yv.y, z[u].x));
+                z[u].y = fma(b.x, yv.y, fma(-b.y, yv.x, z[u].y));
             }
         }
     }
-    if (!fin) atomicCAS(&s_err, 0, ST_ENONFINITE);
-    // h = sum_q conj(Ahat_{row_q}) .* Z[q], summed over q in ascending order
-    __syncthreads();
+    __syncthreads();                          // s_b is reused for the products below
+    double2* s_p = s_b;                       // [nq][R]: z[q][r] conj(Ahat_{row_q, r})
 #pragma unroll
-    for (int u = 0; u < kZ; ++u) {
-        const int e = tid + u * kGThreads;
-        if (e < nq * R) {
-            const int row = row_of(e / R);
-            const float2 a = row >= 0 ? f.Ahat[size_t(row) * R + e % R] : float2{0.f, 0.f};
-            s_x[e] = dcmulc(z[u], double2{a.x, a.y});
-        }
+    for (int u = 0; u < kZU; ++u) {
+        const int e = tid + u * kSB;
+        if (e < nqr) s_p[e] = dcmulc(z[u], s_x[e]);
     }
     __syncthreads();
     if (tid < R) {
         double2 h{0.0, 0.0};
-        for (int q = 0; q < nq; ++q) { h.x += s_x[q * R + tid].x; h.y += s_x[q * R + tid].y; }
-        f.hpart[size_t(k) * R + tid] = h;
+        for (int q = 0; q < nq; ++q) { h.x += s_p[q * R + tid].x; h.y += s_p[q * R + tid].y; }
+        f.hpart[size_t(k * nJ + c) * R + tid] = h;
     }
+    if (!fin) atomicCAS(&s_err, 0, ST_ENONFINITE);
     __syncthreads();
     if (tid == 0 && s_err) latch(f.dev, s_err);
 }
 
+size_t lstats_lds(int R) { return (size_t(kSRows + kJCH) * R + size_t(kSRows) * kJCH) * sizeof(double2); }
+
 constexpr int kPW = 32;        // sampled entries staged per window of a point-mask Gram
 constexpr int kMaxAcc = 8;     // Gram entries one thread accumulates per pass (point masks)
+static_assert(kPW >= kGRows, "the factor-Gram staging fits the point window");
 
-// Point masks: explicit Phi^H Phi and Phi^H y over mask rows [kPRows k, kPRows (k+1)).
+// Point masks.  Blocks [0, gAB) are the factor-Gram partials as above; block
+// gAB + k forms explicit Phi^H Phi and Phi^H y over mask rows [kPRows k, kPRows (k+1))
+// into slot gAB + k and hpart[k].
 template <class Src>
-__global__ void __launch_bounds__(256) k_pstats(Src src) {
-    extern __shared__ float2 s_rows[];            // kPW * R double2s
+__global__ void __launch_bounds__(kSB) k_pstats(Src src) {
+    extern __shared__ double2 s_dyn[];            // kPW * R
     __shared__ double2 s_yw[kPW];
     __shared__ int s_err;
-    const FrameArgs& f = src.get();
+    const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, false)) return;
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
-    const int k = blockIdx.x;
-    double2* out = f.part + size_t(2 + k) * R * R;
+    const int gAB = n_gparts(n1) + n_gparts(n2);
+    if (int(blockIdx.x) < gAB) {
+        factor_gram_block(f, blockIdx.x, s_dyn);
+        return;
+    }
+    const int k = blockIdx.x - gAB;
+    double2* out = f.part + size_t(gAB + k) * R * R;
     if (tid == 0) s_err = 0;
     __syncthreads();
-    // Point mask: the sampled entries of rows [i0, i1) taken in windows of kPW
-    // candidates; each window stages phi_{(i,j),r} = Ahat_ir Bhat_jr (zero where
-    // not sampled) and accumulates Phi^H Phi (r <= s) and Phi^H y.
+    // The sampled entries of rows [i0, i1) taken in windows of kPW candidates;
+    // each window stages phi_{(i,j),r} = Ahat_ir Bhat_jr (zero where not sampled)
+    // and accumulates Phi^H Phi (r <= s) and Phi^H y.
     const int i0 = k * kPRows;
     if (i0 >= n1) return;
     const int ncand = (min(n1, i0 + kPRows) - i0) * n2;
-    double2* s_phi = reinterpret_cast<double2*>(s_rows);   // [kPW][R]
+    double2* s_phi = s_dyn;                       // [kPW][R]
     const int RR = R * R;
-    const int npass = cdiv(cdiv(RR, kBlock), kMaxAcc);
+    const int npass = cdiv(cdiv(RR, kSB), kMaxAcc);
     bool fin = true;
     for (int pass = 0; pass < npass; ++pass) {
         double2 acc[kMaxAcc];
@@ -328,7 +275,7 @@ __global__ void __launch_bounds__(256) k_pstats(Src src) {
             __syncthreads();
 #pragma unroll
             for (int u = 0; u < kMaxAcc; ++u) {
-                const int e = tid + (pass * kMaxAcc + u) * kBlock;
+                const int e = tid + (pass * kMaxAcc + u) * kSB;
                 if (e < RR) {
                     const int r = e / R, s2 = e % R;
                     if (r <= s2) {
@@ -352,7 +299,7 @@ __global__ void __launch_bounds__(256) k_pstats(Src src) {
         }
 #pragma unroll
         for (int u = 0; u < kMaxAcc; ++u) {
-            const int e = tid + (pass * kMaxAcc + u) * kBlock;
+            const int e = tid + (pass * kMaxAcc + u) * kSB;
             if (e < RR && (e / R) <= (e % R)) out[e] = acc[u];
         }
         if (pass == 0 && tid < R) f.hpart[size_t(k) * R + tid] = hacc;
@@ -362,25 +309,53 @@ __global__ void __launch_bounds__(256) k_pstats(Src src) {
     if (tid == 0 && s_err) latch(f.dev, s_err);
 }
 
+// Sums of slot ranges of the statistics for U entries per thread: out[u] =
+// sum over slots s < n (in slot order) of base[s * stride + up[u]]; loads are
+// issued kSlotPF slots at a time for all U entries together.
+constexpr int kSlotPF = 8;
+template <int U>
+__device__ __forceinline__ void slot_sums(const double2* base, size_t stride, int n, const size_t (&up)[U],
+                                          const bool (&ok)[U], double2 (&out)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) out[u] = double2{0.0, 0.0};
+    for (int k0 = 0; k0 < n; k0 += kSlotPF) {
+        double2 w[U][kSlotPF];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < kSlotPF; ++q)
+                w[u][q] = (ok[u] && k0 + q < n) ? base[size_t(k0 + q) * stride + up[u]] : double2{0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < kSlotPF; ++q) { out[u].x += w[u][q].x; out[u].y += w[u][q].y; }
+    }
+}
+
+// Right-hand side h = Phi^H y of thread r's entry: the sum of its partials in order.
+__device__ __forceinline__ double2 rhs_sum(const DevFrame& f, int r, int nh) {
+    size_t up[1] = {size_t(r)};
+    bool ok[1] = {true};
+    double2 out[1];
+    slot_sums<1>(f.hpart, size_t(f.r), nh, up, ok, out);
+    return out[0];
+}
+
 // ---------------------------------------------------------------- solve
 __device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }   // j <= i
 
-// One wavefront per sequence: every barrier below is a single-wave barrier.
-constexpr int kSolveThreads = 64;
-constexpr int kPF = 16;      // independent global loads a lane issues before using them
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
+// General R: one block per sequence, G packed in LDS, row-parallel right-looking
+// Cholesky with block barriers between the steps.
+constexpr int kSolveThreads = 256;
+constexpr int kSolveU = 4;   // entries of G a thread gathers per pass
 
 template <class Src>
 __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
     extern __shared__ double2 s_dyn[];
     __shared__ int s_fail;
     __shared__ double s_piv_lo, s_piv_hi;
-    const FrameArgs& f = src.get();
+    __shared__ double s_wbest[kSolveThreads / 64];
+    const DevFrame f = src.get();
     SeqDev* d = f.dev;
     if (!block_frame_ok(d, false)) {
         if (threadIdx.x == 0) d->frame_ok = 0;
@@ -389,60 +364,48 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
     const int R = f.r, n1 = f.n1, tid = threadIdx.x;
     const bool lines = f.mode == MODE_LINES;
     const int ns = lines ? cdiv(frame_rows(f), kSRows) : cdiv(n1, kPRows);
+    const int gA = n_gparts(n1), gB = n_gparts(f.n2), gAB = gA + gB;
+    const int nh = ns * (lines ? n_jparts(f.n2) : 1);
     const size_t RR = size_t(R) * R;
-    const double2* pa = f.part;               // (F_l A)^H F_l A
-    const double2* pb = f.part + RR;          // (F_r B)^H F_r B
-    const double2* ps = f.part + 2 * RR;      // partials of the sampled part
+    const double2* pa = f.part;               // slots of (F_l A)^H F_l A
+    const double2* pb = f.part + gA * RR;     // slots of (F_r B)^H F_r B
+    const double2* ps = f.part + gAB * RR;    // slots of the sampled part
     double2* L = s_dyn;                       // packed lower triangle of G, then of its factor
     double2* h = s_dyn + R * (R + 1) / 2;     // right-hand side, then gamma
     const double lam = f.lambda;
 
-    // G = Phi^H Phi + lambda I from the statistics (stored upper entries (j, i), j <= i):
-    // the sampled part summed over its partials in slot order, then (lines) times
-    // the B Gram entrywise.  Each lane issues kPF independent loads before using them.
+    // G = Phi^H Phi + lambda I from the statistics (slot entry (j, i), j <= i,
+    // holds G_ji = conj(G_ij)): the sampled part summed over its slots, then
+    // (lines) times the B Gram entrywise.
     const int npairs = R * (R + 1) / 2;
-    for (int e0 = 0; e0 < npairs; e0 += kSolveThreads * kPF) {
-        double2 g[kPF], gb[kPF];
-        int ii[kPF], jj[kPF];
+    for (int e0 = 0; e0 < npairs; e0 += kSolveThreads * kSolveU) {
+        size_t up[kSolveU];
+        bool ok[kSolveU];
+        int ii[kSolveU], jj[kSolveU];
 #pragma unroll
-        for (int u = 0; u < kPF; ++u) {
+        for (int u = 0; u < kSolveU; ++u) {
             const int e = e0 + tid + kSolveThreads * u;
             int i = int((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
             while (i * (i + 1) / 2 > e) --i;
             while ((i + 1) * (i + 2) / 2 <= e) ++i;
-            ii[u] = e < npairs ? i : -1;
+            ok[u] = e < npairs;
+            ii[u] = i;
             jj[u] = e - i * (i + 1) / 2;
-            const size_t up = size_t(jj[u]) * R + i;
-            g[u] = (e < npairs && ns > 0) ? ps[up] : double2{0.0, 0.0};
-            gb[u] = (e < npairs && lines) ? pb[up] : double2{0.0, 0.0};
+            up[u] = ok[u] ? size_t(jj[u]) * R + i : 0;
         }
-        for (int k = 1; k < ns; ++k) {
+        double2 g[kSolveU], gb[kSolveU];
+        slot_sums<kSolveU>(ps, RR, ns, up, ok, g);
+        if (lines) slot_sums<kSolveU>(pb, RR, gB, up, ok, gb);
 #pragma unroll
-            for (int u = 0; u < kPF; ++u) {
-                if (ii[u] < 0) continue;
-                const double2 v = ps[k * RR + size_t(jj[u]) * R + ii[u]];
-                g[u].x += v.x;
-                g[u].y += v.y;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kPF; ++u) {
-            if (ii[u] < 0) continue;
+        for (int u = 0; u < kSolveU; ++u) {
+            if (!ok[u]) continue;
             double2 v = lines ? dcmul(g[u], gb[u]) : g[u];
-            v.y = -v.y;                          // G_ij = conj(G_ji)
+            v.y = -v.y;
             if (ii[u] == jj[u]) v = double2{v.x + lam, 0.0};
             L[pk(ii[u], jj[u])] = v;
         }
     }
-    for (int r = tid; r < R; r += kSolveThreads) {
-        double2 hv{0.0, 0.0};
-        for (int k = 0; k < ns; ++k) {
-            const double2 v = f.hpart[size_t(k) * R + r];
-            hv.x += v.x;
-            hv.y += v.y;
-        }
-        h[r] = hv;
-    }
+    for (int r = tid; r < R; r += kSolveThreads) h[r] = rhs_sum(f, r, nh);
     if (tid == 0) { s_fail = 0; s_piv_lo = 1e308; s_piv_hi = 0.0; }
     __syncthreads();
 
@@ -526,8 +489,9 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
         }
         return;
     }
-    // Gershgorin row sums of diag(g)^H M diag(g), M = A^H A and B^H B; the
-    // factor's LDS (R(R+1) doubles >= R*R) holds the |entries| of one M at a time.
+    // Gershgorin row sums of diag(g)^H M diag(g), M = A^H A and B^H B (each
+    // summed over its slots); the factor's LDS (R(R+1) doubles >= R*R) holds the
+    // |entries| of one M at a time.
     double* mag = reinterpret_cast<double*>(s_dyn);
     double* s_ag = s_inv + R;                 // |gamma_r|
     for (int r = tid; r < R; r += kSolveThreads) s_ag[r] = dabs(h[r]);
@@ -535,20 +499,24 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
     double best = 0.0;
     for (int which = 0; which < 2; ++which) {
         const double2* pm = which ? pb : pa;
+        const int nm = which ? gB : gA;
         __syncthreads();
-        for (int e0 = 0; e0 < R * R; e0 += kSolveThreads * kPF) {
-            double2 v[kPF];
+        for (int e0 = 0; e0 < R * R; e0 += kSolveThreads * kSolveU) {
+            size_t up[kSolveU];
+            bool ok[kSolveU];
 #pragma unroll
-            for (int u = 0; u < kPF; ++u) {
+            for (int u = 0; u < kSolveU; ++u) {
                 const int e = e0 + tid + kSolveThreads * u;
                 const int r = e / R, c = e % R;
-                const size_t up = r <= c ? size_t(r) * R + c : size_t(c) * R + r;
-                v[u] = e < R * R ? pm[up] : double2{0.0, 0.0};
+                ok[u] = e < R * R;
+                up[u] = !ok[u] ? 0 : (r <= c ? size_t(r) * R + c : size_t(c) * R + r);
             }
+            double2 v[kSolveU];
+            slot_sums<kSolveU>(pm, RR, nm, up, ok, v);
 #pragma unroll
-            for (int u = 0; u < kPF; ++u) {
+            for (int u = 0; u < kSolveU; ++u) {
                 const int e = e0 + tid + kSolveThreads * u;
-                if (e < R * R) mag[e] = s_ag[e / R] * dabs(v[u]) * s_ag[e % R];
+                if (ok[u]) mag[e] = s_ag[e / R] * dabs(v[u]) * s_ag[e % R];
             }
         }
         __syncthreads();
@@ -569,6 +537,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
     }
     __syncthreads();
     for (int m = 32; m > 0; m >>= 1) best = fmax(best, __shfl_xor(best, m, 64));
+    if (tid % 64 == 0) s_wbest[tid / 64] = best;
+    __syncthreads();
+    if (tid == 0)
+        for (int w = 0; w < kSolveThreads / 64; ++w) best = fmax(best, s_wbest[w]);
     for (int r = tid; r < R; r += kSolveThreads) {
         f.gamma64[r] = h[r];
         const float2 g32{float(h[r].x), float(h[r].y)};
@@ -591,10 +563,14 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
 }
 
 // ---------------------------------------------------------------- register solve (R <= 32)
-// One wavefront, no barriers: lane i keeps row i of G (then of its Cholesky
-// factor L) in registers, and column k is broadcast lane to lane with
-// readlane at step k.  Rows R..RB-1 are padded with the identity (and a zero
-// right-hand side), which leaves gamma unchanged.
+// A block of kRegBlk threads per sequence.  The whole block first gathers G, h
+// and the magnitudes of the two factor Grams into LDS with all of its loads in
+// flight at once.  Wavefront 0 then factors G = L L^H with lane i keeping row i
+// in registers (column k goes lane to lane by readlane at step k) and runs the
+// forward substitution L z = h inside the same sweep; the back substitution
+// L^H gamma = z reads the columns of L back through LDS.  Rows R..RB-1 are
+// padded with the identity and a zero right-hand side, which leaves gamma
+// unchanged.  The Gershgorin sums of the step size use the whole block.
 __device__ __forceinline__ double readlane_d(double v, int lane) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane(int(b), lane);
@@ -605,140 +581,187 @@ __device__ __forceinline__ double2 readlane_d2(double2 v, int lane) {
     return double2{readlane_d(v.x, lane), readlane_d(v.y, lane)};
 }
 
+constexpr int kRegBlk = 256;
+
 template <int RB, class Src>
-__global__ void __launch_bounds__(kSolveThreads) k_solve_reg(Src src) {
-    __shared__ double2 s_l[RB * RB];              // L, row-major, for the back substitution
-    const FrameArgs& f = src.get();
+__global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
+    static_assert(RB <= 64 && kRegBlk % RB == 0 && (kRegBlk / RB) <= 64, "row groups must sit inside a wavefront");
+    constexpr int U = (RB * RB + kRegBlk - 1) / kRegBlk;   // entries of G per thread
+    constexpr int TPR = kRegBlk / RB;                       // threads per row in the Gershgorin sums
+    __shared__ double2 s_g[RB * RB];       // G row-major, then L row-major
+    __shared__ double s_m[2][RB * RB];     // |(F_l A)^H F_l A|, |(F_r B)^H F_r B|
+    __shared__ double2 s_h[RB];            // h, then gamma
+    __shared__ double s_ag[RB];            // |gamma|
+    __shared__ double s_best[kRegBlk / 64];
+    __shared__ double s_kappa;
+    __shared__ int s_fail;
+    const DevFrame f = src.get();
     SeqDev* d = f.dev;
     if (!block_frame_ok(d, false)) {
         if (threadIdx.x == 0) d->frame_ok = 0;
         return;
     }
-    const int R = f.r, lane = threadIdx.x;
+    const int R = f.r, tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const bool lines = f.mode == MODE_LINES;
     const int ns = lines ? cdiv(frame_rows(f), kSRows) : cdiv(f.n1, kPRows);
+    const int gA = n_gparts(f.n1), gB = n_gparts(f.n2), gAB = gA + gB;
+    const int nh = ns * (lines ? n_jparts(f.n2) : 1);
     const size_t RR = size_t(R) * R;
-    const double2* pa = f.part;               // (F_l A)^H F_l A
-    const double2* pb = f.part + RR;          // (F_r B)^H F_r B
-    const double2* ps = f.part + 2 * RR;      // partials of the sampled part
+    const double2* pa = f.part;               // slots of (F_l A)^H F_l A
+    const double2* pb = f.part + gA * RR;     // slots of (F_r B)^H F_r B
+    const double2* ps = f.part + gAB * RR;    // slots of the sampled part
     const double lam = f.lambda;
-    const bool live = lane < R;
 
-    // row i = lane of G = Phi^H Phi + lambda I; stored upper entries (j, i) give G_ij = conj(.)
-    double2 g[RB];
-    sfor<RB>([&](auto jc) {
-        constexpr int j = decltype(jc)::value;
-        double2 v{0.0, 0.0};
-        if (live && j <= lane) {
-            const size_t up = size_t(j) * R + lane;
-            for (int k = 0; k < ns; ++k) { const double2 w = ps[k * RR + up]; v.x += w.x; v.y += w.y; }
-            if (lines) v = dcmul(v, pb[up]);
-            v.y = -v.y;
-            if (j == lane) v = double2{v.x + lam, 0.0};
-        } else if (!live && j == lane) {
-            v = double2{1.0, 0.0};
+    // Gather.  A slot holds the upper triangle: entry (r, c), r <= c, is G_rc,
+    // so G_ij = conj(entry (j, i)) below the diagonal.
+    {
+        size_t up[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = tid + u * kRegBlk, i = e / RB, j = e % RB;
+            ok[u] = e < RB * RB && i < R && j < R;
+            up[u] = ok[u] ? (i <= j ? size_t(i) * R + j : size_t(j) * R + i) : 0;
         }
-        g[j] = v;
-    });
-    double2 hv{0.0, 0.0};
-    if (live)
-        for (int k = 0; k < ns; ++k) { const double2 w = f.hpart[size_t(k) * R + lane]; hv.x += w.x; hv.y += w.y; }
+        double2 g[U], ma[U], mb[U];
+        slot_sums<U>(pa, RR, gA, up, ok, ma);
+        slot_sums<U>(pb, RR, gB, up, ok, mb);
+        slot_sums<U>(ps, RR, ns, up, ok, g);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = tid + u * kRegBlk, i = e / RB, j = e % RB;
+            if (e >= RB * RB) continue;
+            double2 v{0.0, 0.0};
+            if (ok[u]) {
+                v = lines ? dcmul(g[u], mb[u]) : g[u];
+                if (i > j) v.y = -v.y;
+                if (i == j) v = double2{v.x + lam, 0.0};
+            }
+            s_g[e] = v;
+            s_m[0][e] = dabs(ma[u]);
+            s_m[1][e] = dabs(mb[u]);
+        }
+    }
+    if (tid < RB) s_h[tid] = tid < R ? rhs_sum(f, tid, nh) : double2{0.0, 0.0};
+    __syncthreads();
 
-    // right-looking Cholesky (dkk is the same in every lane, so `fail` is uniform)
-    bool fail = false;
-    double piv_lo = 1e308, piv_hi = 0.0;
-    sfor<RB>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        if (fail) return;
-        const double dkk = readlane_d(g[k].x, k);
-        if (!(dkk > 0.0) || !isfinite(dkk)) { fail = true; return; }
-        const double p = sqrt(dkk), ip = 1.0 / p;
-        if (k < R) { piv_lo = fmin(piv_lo, p); piv_hi = fmax(piv_hi, p); }
-        if (lane == k) g[k] = double2{p, 0.0};
-        else if (lane > k) g[k] = double2{g[k].x * ip, g[k].y * ip};
+    // Wavefront 0: right-looking Cholesky with the forward substitution fused in
+    // (z_k = h_k / L_kk once h_k has received every earlier column).  The pivot
+    // is the same in every lane, so `fail` is uniform.  Entries above the
+    // diagonal are updated too (never read), which keeps the sweep branch-free.
+    double2 g[RB];
+    double2 hv{0.0, 0.0};
+    double dinv = 0.0;                           // 1 / L_{lane, lane}
+    if (wave == 0) {
+        const bool live = lane < R;
         sfor<RB>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            if constexpr (j > k) {
-                const double2 ljk = readlane_d2(g[k], j);
-                if (lane >= j) {
-                    const double2 t = dcmulc(g[k], ljk);      // L_ik conj(L_jk)
-                    g[j].x -= t.x;
-                    g[j].y -= t.y;
-                }
-            }
+            g[j] = live ? s_g[lane * RB + j] : double2{j == lane ? 1.0 : 0.0, 0.0};
         });
-    });
-    if (!fail) {
-        // L z = h
+        if (lane < RB) hv = s_h[lane];
+        bool fail = false;
+        double piv_lo = 1e308, piv_hi = 0.0;
         sfor<RB>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const double ip = 1.0 / readlane_d(g[k].x, k);
+            if (fail) return;
+            const double dkk = readlane_d(g[k].x, k);
+            if (!(dkk > 0.0) || !isfinite(dkk)) { fail = true; return; }
+            const double p = sqrt(dkk), ip = 1.0 / p;
+            if (k < R) { piv_lo = fmin(piv_lo, p); piv_hi = fmax(piv_hi, p); }
+            if (lane == k) dinv = ip;
+            g[k] = lane == k ? double2{p, 0.0} : double2{g[k].x * ip, g[k].y * ip};
             const double2 hk = readlane_d2(hv, k);
             const double2 zk{hk.x * ip, hk.y * ip};
             if (lane == k) hv = zk;
             else if (lane > k) {
-                const double2 t = dcmul(g[k], zk);
-                hv.x -= t.x;
-                hv.y -= t.y;
+                hv.x = fma(-g[k].x, zk.x, fma(g[k].y, zk.y, hv.x));
+                hv.y = fma(-g[k].x, zk.y, fma(-g[k].y, zk.x, hv.y));
             }
+            sfor<RB>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                if constexpr (j > k) {
+                    const double2 ljk = readlane_d2(g[k], j);          // L_jk
+                    g[j].x = fma(-g[k].x, ljk.x, fma(-g[k].y, ljk.y, g[j].x));   // - L_ik conj(L_jk)
+                    g[j].y = fma(-g[k].y, ljk.x, fma(g[k].x, ljk.y, g[j].y));
+                }
+            });
         });
-        // L^H gamma = z, with column `lane` of L read back from LDS
-        sfor<RB>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            if (lane < RB) s_l[lane * RB + j] = (j <= lane) ? g[j] : double2{0.0, 0.0};
-        });
-        __syncthreads();
-        double2 lcol[RB];
+        if (lane < RB)
+            sfor<RB>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                s_g[lane * RB + j] = j <= lane ? g[j] : double2{0.0, 0.0};
+            });
+        if (lane == 0) {
+            s_fail = fail ? ST_ENOTPD : 0;
+            s_kappa = (piv_hi / piv_lo) * (piv_hi / piv_lo);
+        }
+    }
+    __syncthreads();
+    if (wave == 0 && !s_fail) {
+        double2 lcol[RB];                         // lcol[k] = L_{k, lane}
         sfor<RB>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            lcol[k] = (lane < RB) ? s_l[k * RB + lane] : double2{0.0, 0.0};   // L_{k, lane}
+            lcol[k] = lane < RB ? s_g[k * RB + lane] : double2{0.0, 0.0};
         });
         sfor<RB>([&](auto kc) {
             constexpr int k = RB - 1 - decltype(kc)::value;
-            const double ip = 1.0 / readlane_d(g[k].x, k);
             const double2 zk = readlane_d2(hv, k);
-            const double2 gk{zk.x * ip, zk.y * ip};
+            const double ik = readlane_d(dinv, k);
+            const double2 gk{zk.x * ik, zk.y * ik};
             if (lane == k) hv = gk;
             else if (lane < k) {
-                const double2 t = dcmulc(gk, lcol[k]);    // conj(L_{k,lane}) gamma_k
-                hv.x -= t.x;
-                hv.y -= t.y;
+                hv.x = fma(-lcol[k].x, gk.x, fma(-lcol[k].y, gk.y, hv.x));   // - conj(L_{k,lane}) gamma_k
+                hv.y = fma(-lcol[k].x, gk.y, fma(lcol[k].y, gk.x, hv.y));
             }
         });
+        const bool live = lane < R;
+        const bool nonfinite = __any(live && (!isfinite(hv.x) || !isfinite(hv.y)));
+        if (live) {
+            s_h[lane] = hv;
+            s_ag[lane] = dabs(hv);
+        }
+        if (lane == 0 && nonfinite) s_fail = ST_ENONFINITE;
     }
-    const bool nonfinite = __any(live && !fail && (!isfinite(hv.x) || !isfinite(hv.y)));
-    if (fail || nonfinite) {
-        if (lane == 0) {
-            latch(d, fail ? ST_ENOTPD : ST_ENONFINITE);
+    __syncthreads();
+    if (s_fail) {
+        if (tid == 0) {
+            latch(d, s_fail);
             d->frame_ok = 0;
         }
         return;
     }
-    // |gamma_s| for every s, then the Gershgorin row sums of diag(g)^H M diag(g)
-    const double ga = live ? dabs(hv) : 0.0;
-    double gab[RB];
-    sfor<RB>([&](auto sc) { gab[decltype(sc)::value] = readlane_d(ga, decltype(sc)::value); });
-    double best = 0.0;
-    for (int which = 0; which < 2; ++which) {
-        const double2* pm = which ? pb : pa;
-        double row = 0.0;
-        sfor<RB>([&](auto sc) {
-            constexpr int c = decltype(sc)::value;
-            if (live && c < R) {
-                const size_t up = lane <= c ? size_t(lane) * R + c : size_t(c) * R + lane;
-                row += dabs(pm[up]) * gab[c];
+    // Gershgorin row sums of diag(g)^H M diag(g) for M = A^H A and B^H B:
+    // TPR consecutive threads share a row, then the block takes the maximum.
+    {
+        const int r = tid / TPR, p = tid % TPR;
+        double ra = 0.0, rb = 0.0;
+        if (r < R)
+            for (int c = p; c < R; c += TPR) {
+                ra += s_m[0][r * RB + c] * s_ag[c];
+                rb += s_m[1][r * RB + c] * s_ag[c];
             }
-        });
-        best = fmax(best, row * ga);
+#pragma unroll
+        for (int m = 1; m < TPR; m <<= 1) {
+            ra += __shfl_xor(ra, m, 64);
+            rb += __shfl_xor(rb, m, 64);
+        }
+        double best = r < R ? fmax(ra, rb) * s_ag[r] : 0.0;
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) best = fmax(best, __shfl_xor(best, m, 64));
+        if (lane == 0) s_best[wave] = best;
     }
-    sfor<RB>([&](auto sc) { best = fmax(best, readlane_d(best, decltype(sc)::value)); });
-    if (live) {
-        f.gamma64[lane] = hv;
-        const float2 g32{float(hv.x), float(hv.y)};
-        f.gamma32[lane] = g32;
-        if (f.gamma_out) f.gamma_out[lane] = g32;
+    __syncthreads();
+    if (tid < R) {
+        const double2 gv = s_h[tid];
+        f.gamma64[tid] = gv;
+        const float2 g32{float(gv.x), float(gv.y)};
+        f.gamma32[tid] = g32;
+        if (f.gamma_out) f.gamma_out[tid] = g32;
     }
-    if (lane == 0) {
+    if (tid == 0) {
+        double best = 0.0;
+#pragma unroll
+        for (int w = 0; w < kRegBlk / 64; ++w) best = fmax(best, s_best[w]);
         const long long tn = d->t + 1;
         const double alpha = lam / double(tn) + best;
         const double abar = d->abar + alpha;
@@ -748,60 +771,60 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_reg(Src src) {
         d->abar_new = abar;
         d->mu = mu;
         d->shrink = 1.0 - lam * mu / double(tn);
-        d->kappa_proxy = (piv_hi / piv_lo) * (piv_hi / piv_lo);
+        d->kappa_proxy = s_kappa;
         d->frame_ok = 1;
     }
 }
 
 // ---------------------------------------------------------------- output synthesis
-constexpr int kOutRows = 32, kOutCols = 64, kOutRC = 8;
+// X_t = A diag(gamma) B^T on the matrix cores.  A complex product is two real
+// ones with the rank index split into (r, re/im): with P_re = [Re AG, -Im AG],
+// P_im = [Im AG, Re AG] and Q = [Re B; Im B] (AG = A diag(gamma)),
+// Re X = P_re Q^T and Im X = P_im Q^T, so each rank is one K = 2 step of a
+// 32x32x2 FP32 MFMA for each of the two parts.  A wavefront owns a 32x32 tile
+// of X, a block four of them (64 x 64).
+constexpr int kOutTile = 64;       // block tile edge
+constexpr int kOutRC = 32;         // ranks loaded per round of operand loads
 
 template <class Src>
 __global__ void __launch_bounds__(256) k_synth_out(Src src) {
-    __shared__ float2 s_a[kOutRows * kOutRC];    // [row][c] = A[i][r0+c] gamma[r0+c]
-    __shared__ float2 s_b[kOutRC * kOutCols];    // [c][col] = B[j][r0+c]
-    const FrameArgs& f = src.get();
+    const DevFrame f = src.get();
     if (f.X_out == nullptr) return;
     if (!block_frame_ok(f.dev, true)) return;
-    const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
-    const int tiles_x = cdiv(n2, kOutCols);
-    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-    const int i0 = ty * kOutRows, j0 = tx * kOutCols;
-    if (i0 >= n1) return;
-    const int lx = tid % kOutCols, ly = tid / kOutCols;   // ly < 4: rows ly*8 .. ly*8+7
-    float2 acc[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = float2{0.f, 0.f};
+    const int n1 = f.n1, n2 = f.n2, R = f.r;
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    const int tiles_x = cdiv(n2, kOutTile);
+    const int i0 = (int(blockIdx.x) / tiles_x) * kOutTile + 32 * (w / 2);
+    const int j0 = (int(blockIdx.x) % tiles_x) * kOutTile + 32 * (w % 2);
+    if (i0 >= n1 || j0 >= n2) return;          // whole wavefront; no block barrier follows
+    const int m = lane % 32, h = lane / 32;
+    const int i = i0 + m, j = j0 + m;           // operand row of A (this lane) and of B
+    const bool iv = i < n1, jv = j < n2;
+    f32x16 accr = {}, acci = {};
     for (int r0 = 0; r0 < R; r0 += kOutRC) {
-        __syncthreads();
-        {
-            const int rr = tid / kOutRC, c = tid % kOutRC, i = i0 + rr;
-            const float2 av = (i < n1 && r0 + c < R) ? f.A[size_t(i) * R + r0 + c] : float2{0.f, 0.f};
-            const float2 gv = (r0 + c < R) ? f.gamma32[r0 + c] : float2{0.f, 0.f};
-            stage_copy<2, float2>(
-                kOutRC * kOutCols,
-                [&](int e) {
-                    const int col = e / kOutRC, cc = e % kOutRC, j = j0 + col;
-                    return (j < n2 && r0 + cc < R) ? f.B[size_t(j) * R + r0 + cc] : float2{0.f, 0.f};
-                },
-                [&](int e, float2 v) { s_b[(e % kOutRC) * kOutCols + e / kOutRC] = v; });
-            s_a[tid] = cmul(av, gv);
-        }
-        __syncthreads();
+        float2 a[kOutRC], g[kOutRC];
+        float b[kOutRC];
 #pragma unroll
         for (int c = 0; c < kOutRC; ++c) {
-            const float2 b = s_b[c * kOutCols + lx];
+            const int r = r0 + c;
+            const bool rv = r < R;
+            a[c] = (iv && rv) ? float2(f.A[size_t(i) * R + r]) : float2{0.f, 0.f};
+            const float2 bb = (jv && rv) ? float2(f.B[size_t(j) * R + r]) : float2{0.f, 0.f};
+            b[c] = h ? bb.y : bb.x;
+            g[c] = rv ? float2(f.gamma32[r]) : float2{0.f, 0.f};
+        }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) cfma(acc[u], s_a[(ly * 8 + u) * kOutRC + c], b);
+        for (int c = 0; c < kOutRC; ++c) {
+            const float2 ag = cmul(a[c], g[c]);
+            accr = mfma_32x32x2(h ? -ag.y : ag.x, b[c], accr);
+            acci = mfma_32x32x2(h ? ag.x : ag.y, b[c], acci);
         }
     }
-    const int j = j0 + lx;
-    if (j < n2) {
+    if (!jv) return;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + ly * 8 + u;
-            if (i < n1) f.X_out[size_t(i) * n2 + j] = acc[u];
-        }
+    for (int v = 0; v < 16; ++v) {
+        const int row = i0 + mfma32_row(v, lane);
+        if (row < n1) f.X_out[size_t(row) * n2 + j] = float2{accr[v], acci[v]};
     }
 }
 
@@ -832,7 +855,7 @@ __global__ void __launch_bounds__(256) k_sample(Src src) {
     __shared__ double s_pref[kMaxN];             // weights, then their inclusive prefix
     __shared__ double s_c[TSL_MAX_R];
     __shared__ int s_mark[kMaxN];
-    const FrameArgs& f = src.get();
+    const DevFrame f = src.get();
     const int K = f.K_next;
     if (K <= 0) return;
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
@@ -967,6 +990,11 @@ void init_kernel_attributes() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, ms);
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pstats<OneFrame>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, ms);
+        const int ml = int(lstats_lds(TSL_MAX_R));
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lstats<FrameTable>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, ml);
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lstats<OneFrame>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, ml);
         const int mr = int(size_t(kSampleStage) * sizeof(float2));
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sample<FrameTable>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, mr);
@@ -982,25 +1010,25 @@ void init_kernel_attributes() {
 
 hipError_t launch_stats(const Batch& b, hipStream_t st) {
     const unsigned ny = b.table ? b.count : 1;
+    const int gAB = n_gparts(b.n1) + n_gparts(b.n2);
     if (b.mode == MODE_LINES) {
-        dim3 grid(2 + cdiv(b.rows_max > 0 ? b.rows_max : 1, kSRows), ny);
-        if (b.table) k_lstats<FrameTable><<<grid, kGThreads, 0, st>>>(FrameTable{b.table});
-        else k_lstats<OneFrame><<<grid, kGThreads, 0, st>>>(OneFrame{*b.one});
+        dim3 grid(gAB + cdiv(b.rows_max > 0 ? b.rows_max : 1, kSRows) * n_jparts(b.n2), ny);
+        const size_t lds = lstats_lds(b.r_max);
+        if (b.table) k_lstats<FrameTable><<<grid, kSB, lds, st>>>(FrameTable{b.table});
+        else k_lstats<OneFrame><<<grid, kSB, lds, st>>>(OneFrame{*b.one});
     } else {
-        if (b.table) k_gram2<FrameTable><<<dim3(2, ny), kGThreads, 0, st>>>(FrameTable{b.table});
-        else k_gram2<OneFrame><<<dim3(2, ny), kGThreads, 0, st>>>(OneFrame{*b.one});
         const size_t lds = size_t(kPW) * b.r_max * sizeof(double2);
-        dim3 grid(cdiv(b.n1, kPRows), ny);
-        if (b.table) k_pstats<FrameTable><<<grid, kBlock, lds, st>>>(FrameTable{b.table});
-        else k_pstats<OneFrame><<<grid, kBlock, lds, st>>>(OneFrame{*b.one});
+        dim3 grid(gAB + n_sparts(b.n1), ny);
+        if (b.table) k_pstats<FrameTable><<<grid, kSB, lds, st>>>(FrameTable{b.table});
+        else k_pstats<OneFrame><<<grid, kSB, lds, st>>>(OneFrame{*b.one});
     }
     return hipGetLastError();
 }
 
 template <int RB> void launch_solve_reg(const Batch& b, hipStream_t st) {
     dim3 grid(1, b.table ? b.count : 1);
-    if (b.table) k_solve_reg<RB, FrameTable><<<grid, kSolveThreads, 0, st>>>(FrameTable{b.table});
-    else k_solve_reg<RB, OneFrame><<<grid, kSolveThreads, 0, st>>>(OneFrame{*b.one});
+    if (b.table) k_solve_reg<RB, FrameTable><<<grid, kRegBlk, 0, st>>>(FrameTable{b.table});
+    else k_solve_reg<RB, OneFrame><<<grid, kRegBlk, 0, st>>>(OneFrame{*b.one});
 }
 
 hipError_t launch_solve(const Batch& b, hipStream_t st) {
@@ -1016,7 +1044,7 @@ hipError_t launch_solve(const Batch& b, hipStream_t st) {
 
 hipError_t launch_synth_out(const Batch& b, hipStream_t st) {
     if (!b.want_x) return hipSuccess;
-    dim3 grid(cdiv(b.n1, kOutRows) * cdiv(b.n2, kOutCols), b.table ? b.count : 1);
+    dim3 grid(cdiv(b.n1, kOutTile) * cdiv(b.n2, kOutTile), b.table ? b.count : 1);
     if (b.table) k_synth_out<FrameTable><<<grid, kBlock, 0, st>>>(FrameTable{b.table});
     else k_synth_out<OneFrame><<<grid, kBlock, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();

@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) k_synth_rowfft(Src src) {
     __shared__ float2 s_ag[ROWS * kRC];     // [row][c] = A[i][r0 + c] gamma[r0 + c]
     __shared__ float2 s_x[S::XSIZE];
 
-    const FrameArgs& f = src.get();
+    const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, true)) return;
     const int n1 = f.n1, R = f.r;
     const int tid = threadIdx.x, s = tid % T, rl = tid / T;
@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(256) k_row_inv_grad(Src src) {
     __shared__ float2 s_red[ROWS * P * kRC];      // [row][s][c] partial sums
     __shared__ int s_bad;
 
-    const FrameArgs& f = src.get();
+    const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, true)) return;
     const int n1 = f.n1, R = f.r;
     const int tid = threadIdx.x, s = tid % T, rl = tid / T;

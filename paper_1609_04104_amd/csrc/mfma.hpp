@@ -1,0 +1,19 @@
+// Matrix-core (MFMA) helpers for gfx950.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace tsl {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// One 32x32x2 FP32 step, D += A B with A 32x2 and B 2x32.  Lane l supplies
+// A[l % 32][l / 32] and B[l / 32][l % 32]; element v of lane l of D is
+// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+__device__ __forceinline__ f32x16 mfma_32x32x2(float a, float b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// Row of D held by element v of lane l in the 32x32 layout above.
+__device__ __forceinline__ int mfma32_row(int v, int lane) { return 8 * (v / 4) + 4 * (lane / 32) + v % 4; }
+
+}  // namespace tsl
