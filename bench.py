@@ -32,14 +32,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_VALU_PEAK_TFS = 157.3     # MI355X published FP32 vector peak
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--seqs", type=int, default=64)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--r", type=int, default=32)
@@ -50,6 +49,16 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--procs", type=int, default=16, help="host processes generating the inputs (1: in-process)")
+    ap.add_argument("--bank-frames", type=int, default=16, help="distinct frames per shape, mixed and served legs")
+    ap.add_argument("--mixed-steps", type=int, default=50)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--serve-scans", type=int, default=128)
+    ap.add_argument("--serve-rate", type=float, default=16.0, help="scan arrivals per second at load 1")
+    ap.add_argument("--serve-T", type=int, default=150, help="frames per scan")
+    ap.add_argument("--serve-loads", type=str, default="1,8,32",
+                    help="offered-load factors: arrival rate and frame rate (30/s) both times the factor")
+    ap.add_argument("--serve-limit", type=float, default=20.0, help="wall-time cap per served run (s)")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -75,26 +84,151 @@ def make_inputs(seqs, n, r, frames, procs=16):
 
 # ----------------------------------------------------------------------------- work model
 def phase_work(n1, n2, r, rows, K):
-    """Algorithmic bytes and flops per frame of each phase (complex64 = 8 B,
-    complex MAC = 8 flop, length-N complex FFT = 5 N log2 N flop)."""
+    """Algorithmic bytes, flops and arithmetic kind per frame of each phase
+    (complex64 = 8 B, complex128 = 16 B, complex MAC = 8 flop, length-N complex
+    FFT = 5 N log2 N flop).  Bytes are the phase's inputs and outputs, not the
+    implementation's partial sums; kinds: fp64 (FP64 vector), mfma (FP32 matrix
+    cores, with the transforms' FP32 vector work counted in), fp32 (FP32 vector)."""
     P, c = n1 * n2, 8
     f1, f2 = 5 * P * math.log2(n1), 5 * P * math.log2(n2)
     a, b = n1 * r, n2 * r
     return {
-        "partial Grams": (c * (a + b + rows * n2) + 4 * rows, 8 * (a + b + rows) * r * r / 2 + 8 * rows * n2 * r),
-        "ridge solve + step size": (16 * r * r, 8 * r ** 3 / 3),
-        "synthesis + row pass": (c * (P + a + b), 8 * P * r + f2),
-        "column pass + residual": (c * (2 * P + rows * n2 + a + b) + 4 * rows, 2 * f1 + 8 * P * r),
-        "row inverse + A grad": (c * (P + a + b), f2 + 8 * P * r),
-        "A update + F_l A": (c * 4 * a, 5 * a * math.log2(n1) + 8 * a),
-        "B grad + update + F_r B": (c * 4 * b, 10 * b * math.log2(n2) + 8 * b),
-        "output synthesis": (c * (P + a + b), 8 * P * r),
-        "row draw": (2 * c * a + 4 * K, 6 * a),
+        "partial Grams": (c * (a + b + rows * n2) + 4 * rows + 16 * (r * r + r),
+                          8 * (n1 + n2 + rows) * r * (r + 1) / 2 + 8 * rows * n2 * r, "fp64"),
+        "ridge solve + step size": (16 * 3 * r * r + 16 * r, 8 * r ** 3 / 3 + 6 * r * r, "fp64"),
+        "synthesis + row pass": (c * (P + a + b), 8 * P * r + f2, "mfma"),
+        "column pass + residual": (c * (2 * P + rows * n2 + a + b) + 4 * rows, 2 * f1 + 8 * P * r, "mfma"),
+        "row inverse + A grad": (c * (P + a + b), f2 + 8 * P * r, "mfma"),
+        "A update + F_l A": (c * 4 * a, 5 * a * math.log2(n1) + 8 * a, "fp32"),
+        "B grad + update + F_r B": (c * 4 * b, 10 * b * math.log2(n2) + 8 * b, "fp32"),
+        "output synthesis": (c * (P + a + b), 8 * P * r, "mfma"),
+        "row draw": (c * a + 4 * K, 6 * a, "fp64"),
     }
+
+
+PEAK_TFS = {"fp64": 78.6, "mfma": 157.3, "fp32": 157.3}   # MI355X published: FP64 vector, FP32 matrix, FP32 vector
+
+
+PHASE_KERNELS = {   # kernel of each phase in a table launch of n x n frames
+    "partial Grams": "void k_lstats<FrameTable>",
+    "ridge solve + step size": "void k_solve",
+    "synthesis + row pass": "void k_synth_rowfft<{n}, FrameTable>",
+    "column pass + residual": "void k_col_resid<{n}, FrameTable>",
+    "row inverse + A grad": "void k_row_inv_grad<{n}, FrameTable>",
+    "A update + F_l A": "void k_update_a<{n}, FrameTable>",
+    "B grad + update + F_r B": "void k_update_b<{n}, FrameTable>",
+    "output synthesis": "void k_synth_out<FrameTable>",
+    "row draw": "void k_sample<FrameTable>",
+}
+COUNTERS = os.path.join(ROOT, "profiles", "step_64x256sq_r32_counters.json")
+
+
+def counter_traffic(phase, n, grid=None):
+    """HBM bytes per launch of the phase's kernel from the committed byte-counter
+    record (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is no
+    record or the kernel sources changed since it was taken."""
+    try:
+        with open(COUNTERS) as f:
+            rec = json.load(f)
+        from paper_1609_04104_amd.prof_summary import source_sha
+    except (OSError, ValueError, ImportError):
+        return None
+    if rec.get("source_sha") != source_sha():
+        return None
+    want = PHASE_KERNELS[phase].format(n=n)
+    hits = [v for k, v in rec.get("kernels", {}).items() if k.startswith(want) and "FrameTable" in k]
+    hits = [v for v in hits if v.get("dispatches", 0) > 0]
+    if not hits:
+        return None
+    if phase == "partial Grams" and grid is not None:           # warm and informative launches differ
+        hits = [v for k, v in rec["kernels"].items() if k.startswith(want) and f"[grid {grid}]" in k] or hits
+    v = max(hits, key=lambda v: v["dispatches"])
+    return v["fetch_bytes"] + v["write_bytes"]
 
 
 def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
+
+
+# ----------------------------------------------------------------------------- batched driver
+class BatchDriver:
+    """A fixed batch of open sequences: sequence s acquires, at frame t, rows of
+    banks[s][t % len(banks[s])] (full frames on the device) -- every row for the
+    first `warm` frames, then the rows its previous step drew (K[s] draws).
+    Descriptor sets are built once per distinct step and replayed."""
+
+    def __init__(self, tsl, torch, seqs, banks, Ks, warm, dev):
+        self.tsl, self.seqs, self.banks, self.Ks, self.warm = tsl, seqs, banks, Ks, warm
+        S = len(seqs)
+        self.rows = [[torch.zeros(Ks[s], dtype=torch.int32, device=dev) for s in range(S)] for _ in range(2)]
+        self.cnt = [[torch.zeros(1, dtype=torch.int32, device=dev) for _ in range(S)] for _ in range(2)]
+        self.full = {q.n1: torch.arange(q.n1, dtype=torch.int32, device=dev) for q in seqs}
+        self.X = [torch.empty(q.n1, q.n2, dtype=torch.complex64, device=dev) for q in seqs]
+        F = 1
+        for bk in banks:
+            F = F * int(bk.shape[0]) // math.gcd(F, int(bk.shape[0]))
+        self.period = 2 * F
+        self.prepared = {}
+
+    def frames_for(self, t):
+        fr = []
+        for s, q in enumerate(self.seqs):
+            y = self.banks[s][t % self.banks[s].shape[0]]
+            nxt = dict(K_next=self.Ks[s], rows_next=self.rows[(t + 1) % 2][s], n_next=self.cnt[(t + 1) % 2][s])
+            if t < self.warm:
+                fr.append(q.frame(rows=self.full[q.n1], y=y, y_full=True, X_out=self.X[s], **nxt))
+            else:
+                fr.append(q.frame(rows=self.rows[t % 2][s], n_rows_dev=self.cnt[t % 2][s], y=y, y_full=True,
+                                  X_out=self.X[s], **nxt))
+        return fr
+
+    def key(self, t):
+        return t if t < self.warm else self.warm + (t - self.warm) % self.period
+
+    def prepare(self, t):
+        k = self.key(t)
+        if k not in self.prepared:
+            self.prepared[k] = self.tsl.PreparedStep(self.seqs, self.frames_for(t))
+        return self.prepared[k]
+
+    def step(self, t, stream):
+        self.prepare(t).launch(stream)
+
+
+def time_steps(drv, warmup, steps, stream, torch, label):
+    """Runs `warmup` untimed steps, then times `steps` steps between HIP events."""
+    for t in range(drv.warm + drv.period):          # every descriptor set built once, untimed
+        drv.prepare(t)
+    t = 0
+    for _ in range(warmup):
+        drv.step(t, stream)
+        t += 1
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    # a full collection of Python's cyclic garbage inside the loop stalls the
+    # host for milliseconds; collect now and exempt everything alive from it
+    gc.collect()
+    gc.freeze()
+    host_us = []
+    w0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(steps):
+        h0 = time.perf_counter()
+        drv.step(t, stream)
+        host_us.append((time.perf_counter() - h0) * 1e6)
+        t += 1
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    slow = sorted(range(steps), key=lambda k: -step_ms[k])[:5]
+    gpu_ms = ev[0].elapsed_time(ev[-1])
+    ms_per_step = max(wall * 1e3, gpu_ms) / steps
+    print(f"[bench] {label}: {ms_per_step:.3f} ms/step, {len(drv.seqs) * 1000.0 / ms_per_step:.0f} frames/s; "
+          f"host launch us p50 {pct(host_us, 50):.1f} max {max(host_us):.1f}; slowest steps "
+          + ", ".join(f"#{k}: {step_ms[k]:.3f} ms (host {host_us[k]:.0f} us)" for k in slow),
+          file=sys.stderr, flush=True)
+    return {"ms_per_step": ms_per_step, "step_ms": step_ms, "t": t}
 
 
 # ----------------------------------------------------------------------------- main
@@ -137,67 +271,12 @@ def main():
 
     # ------------------------------------------------------------------ batched
     seqs = [open_seq(s) for s in range(S)]
-    rows = [[torch.zeros(K, dtype=torch.int32, device=dev) for _ in range(S)] for _ in range(2)]
-    cnt = [[torch.zeros(1, dtype=torch.int32, device=dev) for _ in range(S)] for _ in range(2)]
-    X = [torch.empty(n, n, dtype=torch.complex64, device=dev) for _ in range(S)]
-
-    def frames_for(t):
-        fr = []
-        for s, q in enumerate(seqs):
-            y = Kd[s][t % F]
-            nxt = dict(K_next=K, rows_next=rows[(t + 1) % 2][s], n_next=cnt[(t + 1) % 2][s])
-            if t < warm:
-                fr.append(q.frame(rows=full, y=y, y_full=True, X_out=X[s], **nxt))
-            else:
-                fr.append(q.frame(rows=rows[t % 2][s], n_rows_dev=cnt[t % 2][s], y=y, y_full=True,
-                                  X_out=X[s], **nxt))
-        return fr
-
-    period = 2 * F
-    prepared = {}
-
-    def step(t):
-        key = t if t < warm else warm + (t - warm) % period
-        p = prepared.get(key)
-        if p is None:
-            p = prepared[key] = tsl.PreparedStep(seqs, frames_for(t))
-        p.launch(stream)
-
-    total = a.warmup + a.steps
-    for t in range(warm + period):          # build every descriptor set once, untimed
-        if t >= warm:
-            prepared.setdefault(warm + (t - warm) % period, tsl.PreparedStep(seqs, frames_for(t)))
-    t = 0
-    for _ in range(a.warmup):
-        step(t)
-        t += 1
-    torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
-    # a full collection of Python's cyclic garbage inside the loop stalls the
-    # host for milliseconds; collect now and exempt everything alive from it
-    gc.collect()
-    gc.freeze()
-    host_us = []
-    w0 = time.perf_counter()
-    ev[0].record(stream)
-    for k in range(a.steps):
-        h0 = time.perf_counter()
-        step(t)
-        host_us.append((time.perf_counter() - h0) * 1e6)
-        t += 1
-        ev[k + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps)]
-    slow = sorted(range(a.steps), key=lambda k: -step_ms[k])[:5]
-    print(f"[bench] host launch us p50 {pct(host_us, 50):.1f} max {max(host_us):.1f}; slowest steps "
-          + ", ".join(f"#{k}: {step_ms[k]:.3f} ms (host {host_us[k]:.0f} us)" for k in slow),
-          file=sys.stderr, flush=True)
-    gpu_ms = ev[0].elapsed_time(ev[-1])
-    ms_per_step = max(wall * 1e3, gpu_ms) / a.steps
+    drv = BatchDriver(tsl, torch, seqs, Kd, [K] * S, warm, dev)
+    res = time_steps(drv, a.warmup, a.steps, stream, torch, "batched")
+    ms_per_step, step_ms, t = res["ms_per_step"], res["step_ms"], res["t"]
     value = S * 1000.0 / ms_per_step
     bad = [q for q in seqs if q.status() != 0]
-    print(f"[bench] batched {ms_per_step:.3f} ms/step, {value:.0f} frames/s", file=sys.stderr, flush=True)
+    frames_for, cnt = drv.frames_for, drv.cnt
 
     # per-phase split (profiling form of the same step, HIP events between phases)
     phase_ms = [0.0] * tsl.N_PHASES
@@ -205,21 +284,23 @@ def main():
         phase_ms = tsl.step_many_timed(seqs, frames_for(t), phase_ms, stream)
         t += 1
     phase_ms = [x / a.phase_steps for x in phase_ms]
-    mean_rows = float(np.mean([int(c.item()) for c in cnt[t % 2]]))
+    mean_rows = float(np.mean([int(cnt[t % 2][i].item()) for i in range(S)]))
     work = phase_work(n, n, r, mean_rows, K)
     dom = int(np.argmax(phase_ms))
     dname = tsl.PHASES[dom]
-    dbytes, dflops = work[dname]
+    dbytes, dflops, kind = work[dname]
     dbytes, dflops = dbytes * S, dflops * S
     dt = phase_ms[dom] * 1e-3
     ai = dflops / dbytes
-    ridge = FP32_VALU_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    ridge = PEAK_TFS[kind] * 1e12 / (HBM_PEAK_GBS * 1e9)
     if ai > ridge:
-        roof = {"bound": "alu", "achieved": dflops / dt / 1e12, "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s"}
+        roof = {"bound": "mfma" if kind == "mfma" else "alu", "achieved": dflops / dt / 1e12,
+                "peak": PEAK_TFS[kind], "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": dbytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    gx = (-(-n // 32)) * 2 + (-(-K // 32)) * (-(-n // 32))          # statistics blocks per frame
+    roof["traffic"] = counter_traffic(dname, n, grid=gx * 256 * (-(-S // 8) * 8))
     roof["kernel"] = dname
     roof["algorithmic_bytes_per_launch"] = dbytes
     roof["algorithmic_flops_per_launch"] = dflops
@@ -239,6 +320,7 @@ def main():
             return q.frame(rows=full, y=Kd[0][t % F], y_full=True, X_out=X0, **nxt)
         return q.frame(rows=pr[t % 2], n_rows_dev=pc[t % 2], y=Kd[0][t % F], y_full=True, X_out=X0, **nxt)
 
+    period = 2 * F
     pframes = [plain_frame(t) for t in range(warm + period)]
 
     def pf(t):
@@ -263,6 +345,10 @@ def main():
     bad += [q] if q.status() != 0 else []
     q.close()
     print(f"[bench] plain {plain_fps:.0f} frames/s", file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------------ mixed shapes, served arrivals
+    mixed = None if a.no_mixed else mixed_leg(a, tsl, torch, dev, stream)
+    served = None if a.no_serve else serving_leg(a, tsl, torch, dev, stream)
 
     # ------------------------------------------------------------------ parity + CPU oracle
     parity, cpu = None, None
@@ -290,8 +376,15 @@ def main():
             "precision": "complex FP32 frame path, FP64 RxR statistics and solve",
         },
         "latency_ms": {"batched_p50": pct(step_ms, 50), "batched_p99": pct(step_ms, 99),
-                       "plain_p50": pct(plain_ms, 50), "plain_p99": pct(plain_ms, 99)},
+                       "plain_p50": pct(plain_ms, 50), "plain_p99": pct(plain_ms, 99),
+                       **({"served_p50": served["loads"][0]["batched"]["latency_p50_ms"],
+                           "served_p99": served["loads"][0]["batched"]["latency_p99_ms"],
+                           "served_plain_p50": served["loads"][0]["plain"]["latency_p50_ms"],
+                           "served_plain_p99": served["loads"][0]["plain"]["latency_p99_ms"]}
+                          if served else {})},
         "plain": {"frames_per_s": plain_fps, "ms_per_frame": 1e3 / plain_fps},
+        "mixed": mixed,
+        "serving": served,
         "batched_over_plain": value / plain_fps,
         "phases_ms": {name: phase_ms[i] for i, name in enumerate(tsl.PHASES)},
         "roofline": roof,
@@ -301,6 +394,72 @@ def main():
     }
     print(json.dumps(out))
     return 0
+
+
+def mixed_leg(a, tsl, torch, dev, stream):
+    """64 concurrent sequences of mixed shapes (128x128, 192x160, 256x256), ranks
+    16/32/64 and accelerations 4-12 (K = N1/acceleration draws), one step per frame."""
+    from paper_1609_04104_amd import inputs as I
+    specs = I.mixed_batch_specs(64)
+    shapes = sorted({(d["n1"], d["n2"]) for d in specs})
+    banks = {sh: torch.from_numpy(I.phantom_bank(sh[0], a.bank_frames, seq=k, n2=sh[1], config=4)).to(dev)
+             for k, sh in enumerate(shapes)}
+    seqs = []
+    for d in specs:
+        A0, B0 = I.init_factors(d["n1"], d["n2"], d["r"], I.rng_for(4, d["seq"], 3))
+        seqs.append(tsl.Sequence(d["n1"], d["n2"], d["r"], a.lam, torch.from_numpy(A0).to(dev),
+                                 torch.from_numpy(B0).to(dev), seed=1609, stream_id=1000 + d["seq"]))
+    Ks = [max(1, round(d["n1"] / d["accel"])) for d in specs]
+    drv = BatchDriver(tsl, torch, seqs, [banks[(d["n1"], d["n2"])] for d in specs], Ks, 5, dev)
+    res = time_steps(drv, a.warmup, a.mixed_steps, stream, torch, "mixed")
+    bad = sum(1 for q in seqs if q.status() != 0)
+    for q in seqs:
+        q.close()
+    n_pix = sum(d["n1"] * d["n2"] for d in specs)
+    return {
+        "workload": "64 sequences: 22 x 128x128, 21 x 192x160, 21 x 256x256 (seeded order), R in {16, 32, 64}, "
+                    "acceleration 4-12, informative rows after 5 full frames, lambda 0.05",
+        "frames_per_s": len(seqs) * 1000.0 / res["ms_per_step"],
+        "ms_per_step": res["ms_per_step"],
+        "step_p50_ms": pct(res["step_ms"], 50), "step_p99_ms": pct(res["step_ms"], 99),
+        "pixels_per_step": n_pix, "device_status_errors": bad,
+    }
+
+
+def serving_leg(a, tsl, torch, dev, stream):
+    """Scans arriving as a Poisson process, each streaming frames, served by
+    continuous batching and by the plain one-frame-at-a-time loop."""
+    from paper_1609_04104_amd import inputs as I
+    from paper_1609_04104_amd import serve as SV
+    specs = I.serving_specs(a.serve_scans, a.serve_rate)
+    sizes = sorted({d["n"] for d in specs})
+    banks = {n: torch.from_numpy(I.phantom_bank(n, a.bank_frames, seq=k)).to(dev) for k, n in enumerate(sizes)}
+    init = {d["scan"]: (torch.from_numpy(d["A0"]).to(dev), torch.from_numpy(d["B0"]).to(dev)) for d in specs}
+    free, _ = torch.cuda.mem_get_info()
+    budget = free // 2
+    loads = [float(x) for x in a.serve_loads.split(",") if x]
+    last_arrival = max(d["arrival"] for d in specs)
+    out = []
+    for k in loads:
+        fps = 30.0 * k
+        row = {"load": k, "frame_rate_per_scan": fps,
+               "offered_frames_per_s": len(specs) * a.serve_T / (last_arrival / k + a.serve_T / fps)}
+        for mode in ("batched", "plain"):
+            scans = [SV.Scan(d["scan"], d["n"], d["r"], a.lam, *init[d["scan"]], banks[d["n"]], a.serve_T,
+                             d["arrival"] / k, fps) for d in specs]
+            gc.collect()
+            r = SV.serve(scans, budget, stream, plain=(mode == "plain"), time_limit=a.serve_limit)
+            row[mode] = r
+            print(f"[bench] served load x{k:g} {mode}: {r['frames']} frames, {r['frames_per_s']:.0f} frames/s, "
+                  f"latency p50 {r['latency_p50_ms']:.2f} ms p99 {r['latency_p99_ms']:.2f} ms, "
+                  f"mean batch {r['mean_batch']:.1f}", file=sys.stderr, flush=True)
+        out.append(row)
+    return {
+        "workload": f"{a.serve_scans} scans, Poisson arrivals at {a.serve_rate:g}/s x load, N x N with N in "
+                    f"{sizes}, R in {{16, 32, 48, 64}}, {a.serve_T} frames each at 30/s x load, informative rows "
+                    f"(K = N/8) after 5 full frames; HBM pool budget {budget} bytes",
+        "loads": out,
+    }
 
 
 def oracle_leg(a, data, Kd, n, r, lam, K, warm, dev, tsl, torch):

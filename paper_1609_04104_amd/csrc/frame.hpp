@@ -116,14 +116,32 @@ __device__ __forceinline__ GlobalPtr<const float2> line_samples(const DevFrame& 
 }
 
 // Where a kernel finds its descriptor: one by value (single-sequence push) or
-// entry blockIdx.y of a device table (batched step).
+// an entry of a device table (batched step).
+// bx() is the block's index inside its frame; live() is false for the padding
+// blocks of a table launch (they return at once).
 struct OneFrame {
     FrameArgs a;
     __device__ __forceinline__ DevFrame get() const { return dev_frame(a); }
+    __device__ __forceinline__ int bx() const { return int(blockIdx.x); }
+    __device__ __forceinline__ bool live() const { return true; }
 };
+
+// The hardware deals consecutive workgroup ids round-robin to the kXcds XCDs,
+// each with its own L2.  A table launch therefore numbers its blocks so that
+// all X blocks of one frame share an XCD: a group of kXcds frames takes
+// kXcds * X consecutive ids and frame kXcds * G + j gets the ids with residue j.
+// A frame's factors are then fetched into one L2 once instead of into all of them.
+constexpr int kXcds = 8;
 struct FrameTable {
     const FrameArgs* __restrict__ t;
-    __device__ __forceinline__ DevFrame get() const { return dev_frame(t[blockIdx.y]); }
+    int X, count;
+    __device__ __forceinline__ int y() const {
+        const int L = int(blockIdx.x), span = kXcds * X;
+        return kXcds * (L / span) + (L % span) % kXcds;
+    }
+    __device__ __forceinline__ int bx() const { return (int(blockIdx.x) % (kXcds * X)) / kXcds; }
+    __device__ __forceinline__ bool live() const { return y() < count; }
+    __device__ __forceinline__ DevFrame get() const { return dev_frame(t[y()]); }
 };
 
 // Latch an error code if none is latched yet (first error wins).

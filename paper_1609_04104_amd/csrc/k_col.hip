@@ -18,16 +18,18 @@
 //  k_factor_fft  column transform of an [n][r] factor (start-up transforms).
 #include "fft_engine.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace tsl {
 namespace {
 
 constexpr int kTW = 16;   // columns per block (128-byte row segments)
-constexpr int kRW = 8;    // rank columns per pass of Z^T conj(A)
+constexpr int kWNT = 2;   // 16-rank MFMA tiles per pass of Z^T conj(A)
 
 template <int N> struct ColShape {
     static constexpr int P = Plan<N>::P, Q = Plan<N>::Q, T = Plan<N>::T;
     static constexpr int THREADS = kTW * T;
+    static constexpr int THREADS64 = (THREADS + 63) / 64 * 64;   // whole wavefronts (matrix-core passes)
     static constexpr int PITCH_NK = odd_pitch(Q, kTW);   // entry (k1, n2, c) at k1*PITCH_NK + n2*kTW + c
     static constexpr int PITCH_KN = odd_pitch(P, kTW);   // entry (m1, k1, c) at m1*PITCH_KN + k1*kTW + c
     static constexpr int XSIZE = (P * PITCH_NK > Q * PITCH_KN) ? P * PITCH_NK : Q * PITCH_KN;
@@ -84,18 +86,20 @@ template <int N1, class Src>
 __global__ void __launch_bounds__(512) k_col_resid(Src src) {
     using S = ColShape<N1>;
     constexpr int P = S::P, Q = S::Q, T = S::T;
-    constexpr int AW = N1 * kRW;            // A chunk [i][cc]
-    constexpr int RW = Q * kTW * kRW;       // partials [s][c][cc]
+    constexpr int kWaves = S::THREADS64 / 64;
+    constexpr int WNT = P > 16 ? 1 : kWNT;         // rank tiles per pass (register budget)
+    constexpr int SW = kWaves * kTW * WNT * 16;    // per-wavefront partials of W
     __shared__ float2 s_tw[N1];
     __shared__ int s_map[N1];
-    __shared__ float2 s_u[cmax(S::XSIZE, AW + RW)];
+    __shared__ float2 s_u[cmax(S::XSIZE, SW)];
     __shared__ int s_bad;
 
+    if (!src.live()) return;
     const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, true)) return;
     const int n2 = f.n2, R = f.r;
     const int tid = threadIdx.x, c = tid % kTW, s = tid / kTW;
-    const int col = blockIdx.x * kTW + c;
+    const int col = src.bx() * kTW + c;
     const bool cv = col < n2;
     load_tw<N1>(s_tw);
     if (tid == 0) s_bad = 0;
@@ -149,39 +153,58 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
             if (cv) f.frame[size_t(s + Q * m2) * n2 + col] = v[m2];
         });
     }
-    // v[m2] = Z[s + Q*m2][col] for threads s < Q.  W[col][r] = sum_i Z[i][col] conj(A[i][r]).
-    float2* s_A = s_u;
-    float2* s_r = s_u + AW;
+    // v[m2] = Z[s + Q*m2][col] for threads s < Q.  W[col][r] = sum_i Z[i][col] conj(A[i][r])
+    // on the matrix cores: M = the block's kTW columns (lane % 16), N = 16 ranks
+    // per tile, and the K index runs over (row, re/im), each lane feeding its own
+    // rows.  With Re W = sum Zr Ar + Zi Ai and Im W = sum Zi Ar - Zr Ai, a row
+    // costs four 16x16x4 steps per rank tile.  The wavefronts' partial sums over
+    // their rows meet in LDS and are added in wavefront order.
+    static_assert(kTW == 16, "one MFMA row per column of the tile");
+    float2* s_w = s_u;                                   // [wave][c][WNT * 16]
+    const int lane = tid % 64, wave = tid / 64, n = lane % 16;
     bool bad = false;
-    for (int r0 = 0; r0 < R; r0 += kRW) {
-        __syncthreads();
-        stage_copy<8, float2>(
-            N1 * kRW,
-            [&](int e) {
-                const int ii = e / kRW, cc = e % kRW;
-                return (r0 + cc < R) ? f.A[size_t(ii) * R + r0 + cc] : float2{0.f, 0.f};
-            },
-            [&](int e, float2 v) { s_A[e] = v; });
-        __syncthreads();
-        if (s < Q) {
+    for (int n0 = 0; n0 < R; n0 += WNT * 16) {
+        f32x4 accr[WNT], acci[WNT];
 #pragma unroll
-            for (int cc = 0; cc < kRW; ++cc) {
-                float2 acc{0.f, 0.f};
-                sfor<P>([&](auto m) {
-                    constexpr int m2 = decltype(m)::value;
-                    acc = cadd(acc, cmulc(v[m2], s_A[(s + Q * m2) * kRW + cc]));
-                });
-                s_r[(s * kTW + c) * kRW + cc] = acc;
+        for (int u = 0; u < WNT; ++u) accr[u] = acci[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        float2 av[P][WNT];                               // all factor operands in flight at once
+        sfor<P>([&](auto mc) {
+            constexpr int m2 = decltype(mc)::value;
+            const int i = s + Q * m2;
+#pragma unroll
+            for (int u = 0; u < WNT; ++u) {
+                const int r = n0 + 16 * u + n;
+                av[m2][u] = (s < Q && r < R) ? float2(f.A[size_t(i) * R + r]) : float2{0.f, 0.f};
             }
-        }
+        });
+        sfor<P>([&](auto mc) {
+            constexpr int m2 = decltype(mc)::value;
+            const float2 z = (s < Q) ? v[m2] : float2{0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < WNT; ++u) {
+                const float2 a = av[m2][u];
+                accr[u] = mfma_16x16x4(z.x, a.x, accr[u]);
+                accr[u] = mfma_16x16x4(z.y, a.y, accr[u]);
+                acci[u] = mfma_16x16x4(z.y, a.x, acci[u]);
+                acci[u] = mfma_16x16x4(-z.x, a.y, acci[u]);
+            }
+        });
         __syncthreads();
-        for (int e = tid; e < kTW * kRW; e += blockDim.x) {
-            const int c2 = e / kRW, cc = e % kRW, colw = blockIdx.x * kTW + c2;
-            if (colw < n2 && r0 + cc < R) {
-                float2 w{0.f, 0.f};
-                for (int q = 0; q < Q; ++q) w = cadd(w, s_r[(q * kTW + c2) * kRW + cc]);
+#pragma unroll
+        for (int u = 0; u < WNT; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int cc = 4 * (lane / 16) + e;                // column of the tile
+                s_w[(wave * kTW + cc) * (WNT * 16) + 16 * u + n] = float2{accr[u][e], acci[u][e]};
+            }
+        __syncthreads();
+        for (int e = tid; e < kTW * WNT * 16; e += blockDim.x) {
+            const int c2 = e / (WNT * 16), rr = e % (WNT * 16), colw = src.bx() * kTW + c2;
+            if (colw < n2 && n0 + rr < R) {
+                float2 w = s_w[c2 * (WNT * 16) + rr];
+                for (int q = 1; q < kWaves; ++q) w = cadd(w, s_w[(q * kTW + c2) * (WNT * 16) + rr]);
                 bad |= !finite2(w);
-                f.Wb[size_t(colw) * R + r0 + cc] = w;
+                f.Wb[size_t(colw) * R + n0 + rr] = w;
             }
         }
     }
@@ -197,18 +220,19 @@ __global__ void __launch_bounds__(512) k_update_a(Src src) {
     constexpr int P = S::P, Q = S::Q, T = S::T;
     __shared__ float2 s_tw[N1];
     __shared__ float2 s_x[S::XSIZE];
+    if (!src.live()) return;
     const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, true)) return;
     const int R = f.r;
-    if (int(blockIdx.x) * kTW >= R) return;
+    if (src.bx() * kTW >= R) return;
     SeqDev* d = f.dev;
     const double mu = d->mu, sh = d->shrink;
     const int tid = threadIdx.x, c = tid % kTW, s = tid / kTW;
-    const int r = blockIdx.x * kTW + c;
+    const int r = src.bx() * kTW + c;
     const bool rv = r < R;
     const double2 g = rv ? f.gamma64[r] : double2{0.0, 0.0};
     load_tw<N1>(s_tw);
-    if (blockIdx.x == 0 && tid == 0) {
+    if (src.bx() == 0 && tid == 0) {
         d->abar = d->abar_new;
         d->t = d->t_new;
     }
@@ -249,14 +273,15 @@ __global__ void __launch_bounds__(512) k_update_b(Src src) {
     constexpr int P = S::P, Q = S::Q, T = S::T;
     __shared__ float2 s_tw[N2];
     __shared__ float2 s_x[S::XSIZE];
+    if (!src.live()) return;
     const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, true)) return;
     const int R = f.r;
-    if (int(blockIdx.x) * kTW >= R) return;
+    if (src.bx() * kTW >= R) return;
     const SeqDev* d = f.dev;
     const double mu = d->mu, sh = d->shrink;
     const int tid = threadIdx.x, c = tid % kTW, s = tid / kTW;
-    const int r = blockIdx.x * kTW + c;
+    const int r = src.bx() * kTW + c;
     const bool rv = r < R;
     const double2 g = rv ? f.gamma64[r] : double2{0.0, 0.0};
     load_tw<N2>(s_tw);
@@ -343,22 +368,25 @@ __global__ void __launch_bounds__(512) k_colfft(const float2* in, float2* out, i
 
 template <int N1> hipError_t launch_k2_n(const Batch& b, hipStream_t st) {
     using S = ColShape<N1>;
-    dim3 grid(cdiv(b.n2, kTW), b.table ? b.count : 1);
-    if (b.table) k_col_resid<N1, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table});
-    else k_col_resid<N1, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one});
+    const int gx = cdiv(b.n2, kTW);
+    const dim3 grid = frame_grid(b, gx);
+    if (b.table) k_col_resid<N1, FrameTable><<<grid, S::THREADS64, 0, st>>>(FrameTable{b.table, gx, b.count});
+    else k_col_resid<N1, OneFrame><<<grid, S::THREADS64, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 template <int N1> hipError_t launch_k4a_n(const Batch& b, hipStream_t st) {
     using S = ColShape<N1>;
-    dim3 grid(cdiv(b.r_max, kTW), b.table ? b.count : 1);
-    if (b.table) k_update_a<N1, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table});
+    const int gx = cdiv(b.r_max, kTW);
+    const dim3 grid = frame_grid(b, gx);
+    if (b.table) k_update_a<N1, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table, gx, b.count});
     else k_update_a<N1, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 template <int N2> hipError_t launch_k4b_n(const Batch& b, hipStream_t st) {
     using S = ColShape<N2>;
-    dim3 grid(cdiv(b.r_max, kTW), b.table ? b.count : 1);
-    if (b.table) k_update_b<N2, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table});
+    const int gx = cdiv(b.r_max, kTW);
+    const dim3 grid = frame_grid(b, gx);
+    if (b.table) k_update_b<N2, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table, gx, b.count});
     else k_update_b<N2, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }

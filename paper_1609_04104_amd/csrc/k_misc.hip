@@ -109,16 +109,17 @@ template <class Src>
 __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     extern __shared__ double2 s_dyn[];
     __shared__ int s_err;
+    if (!src.live()) return;
     const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, false)) return;
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
     const int gAB = n_gparts(n1) + n_gparts(n2);
-    if (int(blockIdx.x) < gAB) {
-        factor_gram_block(f, blockIdx.x, s_dyn);
+    if (src.bx() < gAB) {
+        factor_gram_block(f, src.bx(), s_dyn);
         return;
     }
     const int nJ = n_jparts(n2);
-    const int k = (blockIdx.x - gAB) / nJ, c = (blockIdx.x - gAB) % nJ;
+    const int k = (src.bx() - gAB) / nJ, c = (src.bx() - gAB) % nJ;
     if (tid == 0) s_err = 0;
     __syncthreads();
     const int n_rows = frame_rows(f);
@@ -218,15 +219,16 @@ __global__ void __launch_bounds__(kSB) k_pstats(Src src) {
     extern __shared__ double2 s_dyn[];            // kPW * R
     __shared__ double2 s_yw[kPW];
     __shared__ int s_err;
+    if (!src.live()) return;
     const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, false)) return;
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
     const int gAB = n_gparts(n1) + n_gparts(n2);
-    if (int(blockIdx.x) < gAB) {
-        factor_gram_block(f, blockIdx.x, s_dyn);
+    if (src.bx() < gAB) {
+        factor_gram_block(f, src.bx(), s_dyn);
         return;
     }
-    const int k = blockIdx.x - gAB;
+    const int k = src.bx() - gAB;
     double2* out = f.part + size_t(gAB + k) * R * R;
     if (tid == 0) s_err = 0;
     __syncthreads();
@@ -355,6 +357,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
     __shared__ int s_fail;
     __shared__ double s_piv_lo, s_piv_hi;
     __shared__ double s_wbest[kSolveThreads / 64];
+    if (!src.live()) return;
     const DevFrame f = src.get();
     SeqDev* d = f.dev;
     if (!block_frame_ok(d, false)) {
@@ -595,6 +598,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     __shared__ double s_best[kRegBlk / 64];
     __shared__ double s_kappa;
     __shared__ int s_fail;
+    if (!src.live()) return;
     const DevFrame f = src.get();
     SeqDev* d = f.dev;
     if (!block_frame_ok(d, false)) {
@@ -781,46 +785,58 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
 // ones with the rank index split into (r, re/im): with P_re = [Re AG, -Im AG],
 // P_im = [Im AG, Re AG] and Q = [Re B; Im B] (AG = A diag(gamma)),
 // Re X = P_re Q^T and Im X = P_im Q^T, so each rank is one K = 2 step of a
-// 32x32x2 FP32 MFMA for each of the two parts.  A wavefront owns a 32x32 tile
-// of X, a block four of them (64 x 64).
-constexpr int kOutTile = 64;       // block tile edge
-constexpr int kOutRC = 32;         // ranks loaded per round of operand loads
+// 32x32x2 FP32 MFMA for each of the two parts.  A block owns a 64 x 64 tile of
+// X (four 32 x 32 wavefront tiles); the 64 rows of AG and of B it needs are
+// staged in LDS with coalesced loads, kOutRC ranks at a time.
+constexpr int kOutTile = 64;                 // block tile edge
+constexpr int kOutRC = 32;                   // ranks staged per pass
+constexpr int kOutPitch = kOutRC + 1;        // LDS row pitch (float2): conflict-free column reads
 
 template <class Src>
 __global__ void __launch_bounds__(256) k_synth_out(Src src) {
+    __shared__ float2 s_ag[kOutTile * kOutPitch];   // [row][c] = A[i0 + row][r0 + c] gamma[r0 + c]
+    __shared__ float2 s_b[kOutTile * kOutPitch];    // [row][c] = B[j0 + row][r0 + c]
+    if (!src.live()) return;
     const DevFrame f = src.get();
     if (f.X_out == nullptr) return;
     if (!block_frame_ok(f.dev, true)) return;
-    const int n1 = f.n1, n2 = f.n2, R = f.r;
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
+    const int lane = tid % 64, w = tid / 64;
     const int tiles_x = cdiv(n2, kOutTile);
-    const int i0 = (int(blockIdx.x) / tiles_x) * kOutTile + 32 * (w / 2);
-    const int j0 = (int(blockIdx.x) % tiles_x) * kOutTile + 32 * (w % 2);
-    if (i0 >= n1 || j0 >= n2) return;          // whole wavefront; no block barrier follows
+    const int bi = (src.bx() / tiles_x) * kOutTile, bj = (src.bx() % tiles_x) * kOutTile;
+    const int wi = 32 * (w / 2), wj = 32 * (w % 2);    // wavefront tile inside the block tile
     const int m = lane % 32, h = lane / 32;
-    const int i = i0 + m, j = j0 + m;           // operand row of A (this lane) and of B
-    const bool iv = i < n1, jv = j < n2;
     f32x16 accr = {}, acci = {};
     for (int r0 = 0; r0 < R; r0 += kOutRC) {
-        float2 a[kOutRC], g[kOutRC];
-        float b[kOutRC];
-#pragma unroll
-        for (int c = 0; c < kOutRC; ++c) {
-            const int r = r0 + c;
-            const bool rv = r < R;
-            a[c] = (iv && rv) ? float2(f.A[size_t(i) * R + r]) : float2{0.f, 0.f};
-            const float2 bb = (jv && rv) ? float2(f.B[size_t(j) * R + r]) : float2{0.f, 0.f};
-            b[c] = h ? bb.y : bb.x;
-            g[c] = rv ? float2(f.gamma32[r]) : float2{0.f, 0.f};
-        }
-#pragma unroll
-        for (int c = 0; c < kOutRC; ++c) {
-            const float2 ag = cmul(a[c], g[c]);
-            accr = mfma_32x32x2(h ? -ag.y : ag.x, b[c], accr);
-            acci = mfma_32x32x2(h ? ag.x : ag.y, b[c], acci);
+        const int nr = min(kOutRC, R - r0);
+        __syncthreads();
+        stage_copy<8, float2>(
+            kOutTile * kOutRC,
+            [&](int e) {
+                const int row = e / kOutRC, c = e % kOutRC, i = bi + row;
+                return (i < n1 && c < nr) ? cmul(float2(f.A[size_t(i) * R + r0 + c]), float2(f.gamma32[r0 + c]))
+                                          : float2{0.f, 0.f};
+            },
+            [&](int e, float2 v) { s_ag[(e / kOutRC) * kOutPitch + e % kOutRC] = v; });
+        stage_copy<8, float2>(
+            kOutTile * kOutRC,
+            [&](int e) {
+                const int row = e / kOutRC, c = e % kOutRC, j = bj + row;
+                return (j < n2 && c < nr) ? float2(f.B[size_t(j) * R + r0 + c]) : float2{0.f, 0.f};
+            },
+            [&](int e, float2 v) { s_b[(e / kOutRC) * kOutPitch + e % kOutRC] = v; });
+        __syncthreads();
+        const float2* pa = s_ag + (wi + m) * kOutPitch;
+        const float2* pb = s_b + (wj + m) * kOutPitch;
+        for (int c = 0; c < nr; ++c) {
+            const float2 ag = pa[c], bb = pb[c];
+            const float bv = h ? bb.y : bb.x;
+            accr = mfma_32x32x2(h ? -ag.y : ag.x, bv, accr);
+            acci = mfma_32x32x2(h ? ag.x : ag.y, bv, acci);
         }
     }
-    if (!jv) return;
+    const int i0 = bi + wi, j = bj + wj + m;
+    if (i0 >= n1 || j >= n2) return;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int row = i0 + mfma32_row(v, lane);
@@ -855,6 +871,7 @@ __global__ void __launch_bounds__(256) k_sample(Src src) {
     __shared__ double s_pref[kMaxN];             // weights, then their inclusive prefix
     __shared__ double s_c[TSL_MAX_R];
     __shared__ int s_mark[kMaxN];
+    if (!src.live()) return;
     const DevFrame f = src.get();
     const int K = f.K_next;
     if (K <= 0) return;
@@ -1009,25 +1026,27 @@ void init_kernel_attributes() {
 }
 
 hipError_t launch_stats(const Batch& b, hipStream_t st) {
-    const unsigned ny = b.table ? b.count : 1;
     const int gAB = n_gparts(b.n1) + n_gparts(b.n2);
     if (b.mode == MODE_LINES) {
-        dim3 grid(gAB + cdiv(b.rows_max > 0 ? b.rows_max : 1, kSRows) * n_jparts(b.n2), ny);
+        const int gx = gAB + cdiv(b.rows_max > 0 ? b.rows_max : 1, kSRows) * n_jparts(b.n2);
+        const dim3 grid = frame_grid(b, gx);
         const size_t lds = lstats_lds(b.r_max);
-        if (b.table) k_lstats<FrameTable><<<grid, kSB, lds, st>>>(FrameTable{b.table});
+        if (b.table) k_lstats<FrameTable><<<grid, kSB, lds, st>>>(FrameTable{b.table, gx, b.count});
         else k_lstats<OneFrame><<<grid, kSB, lds, st>>>(OneFrame{*b.one});
     } else {
         const size_t lds = size_t(kPW) * b.r_max * sizeof(double2);
-        dim3 grid(gAB + n_sparts(b.n1), ny);
-        if (b.table) k_pstats<FrameTable><<<grid, kSB, lds, st>>>(FrameTable{b.table});
+        const int gx = gAB + n_sparts(b.n1);
+        const dim3 grid = frame_grid(b, gx);
+        if (b.table) k_pstats<FrameTable><<<grid, kSB, lds, st>>>(FrameTable{b.table, gx, b.count});
         else k_pstats<OneFrame><<<grid, kSB, lds, st>>>(OneFrame{*b.one});
     }
     return hipGetLastError();
 }
 
 template <int RB> void launch_solve_reg(const Batch& b, hipStream_t st) {
-    dim3 grid(1, b.table ? b.count : 1);
-    if (b.table) k_solve_reg<RB, FrameTable><<<grid, kRegBlk, 0, st>>>(FrameTable{b.table});
+    const int gx = 1;
+    const dim3 grid = frame_grid(b, gx);
+    if (b.table) k_solve_reg<RB, FrameTable><<<grid, kRegBlk, 0, st>>>(FrameTable{b.table, gx, b.count});
     else k_solve_reg<RB, OneFrame><<<grid, kRegBlk, 0, st>>>(OneFrame{*b.one});
 }
 
@@ -1035,26 +1054,29 @@ hipError_t launch_solve(const Batch& b, hipStream_t st) {
     if (b.r_max <= 8) { launch_solve_reg<8>(b, st); return hipGetLastError(); }
     if (b.r_max <= 16) { launch_solve_reg<16>(b, st); return hipGetLastError(); }
     if (b.r_max <= 32) { launch_solve_reg<32>(b, st); return hipGetLastError(); }
-    dim3 grid(1, b.table ? b.count : 1);
+    const int gx = 1;
+    const dim3 grid = frame_grid(b, gx);
     const size_t lds = solve_lds(b.r_max);
-    if (b.table) k_solve<FrameTable><<<grid, kSolveThreads, lds, st>>>(FrameTable{b.table});
+    if (b.table) k_solve<FrameTable><<<grid, kSolveThreads, lds, st>>>(FrameTable{b.table, gx, b.count});
     else k_solve<OneFrame><<<grid, kSolveThreads, lds, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 
 hipError_t launch_synth_out(const Batch& b, hipStream_t st) {
     if (!b.want_x) return hipSuccess;
-    dim3 grid(cdiv(b.n1, kOutTile) * cdiv(b.n2, kOutTile), b.table ? b.count : 1);
-    if (b.table) k_synth_out<FrameTable><<<grid, kBlock, 0, st>>>(FrameTable{b.table});
+    const int gx = cdiv(b.n1, kOutTile) * cdiv(b.n2, kOutTile);
+    const dim3 grid = frame_grid(b, gx);
+    if (b.table) k_synth_out<FrameTable><<<grid, kBlock, 0, st>>>(FrameTable{b.table, gx, b.count});
     else k_synth_out<OneFrame><<<grid, kBlock, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 
 hipError_t launch_sample(const Batch& b, hipStream_t st) {
     if (!b.want_sample) return hipSuccess;
-    dim3 grid(1, b.table ? b.count : 1);
+    const int gx = 1;
+    const dim3 grid = frame_grid(b, gx);
     const size_t lds = size_t(kSampleStage) * sizeof(float2);
-    if (b.table) k_sample<FrameTable><<<grid, kBlock, lds, st>>>(FrameTable{b.table});
+    if (b.table) k_sample<FrameTable><<<grid, kBlock, lds, st>>>(FrameTable{b.table, gx, b.count});
     else k_sample<OneFrame><<<grid, kBlock, lds, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }

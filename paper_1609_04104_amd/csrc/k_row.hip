@@ -10,11 +10,11 @@
 //  k_rowfft        plain row pass of the standalone 2-D transform.
 #include "fft_engine.hpp"
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace tsl {
 namespace {
 
-constexpr int kRC = 8;   // rank columns staged per pass
 
 template <int N> struct RowShape {
     static constexpr int P = Plan<N>::P, Q = Plan<N>::Q, T = Plan<N>::T;
@@ -46,131 +46,249 @@ __device__ __forceinline__ void row_swap_nk(float2 (&v)[T], float2* s_x, int rl,
     }
 }
 
-// ---------------------------------------------------------------- K1
-template <int N2, class Src>
-__global__ void __launch_bounds__(256) k_synth_rowfft(Src src) {
-    using S = RowShape<N2>;
-    constexpr int P = S::P, Q = S::Q, T = S::T, ROWS = S::ROWS;
-    __shared__ float2 s_tw[N2];
-    __shared__ float2 s_B[kRC * N2];        // [c][j] = B[j][r0 + c]
-    __shared__ float2 s_ag[ROWS * kRC];     // [row][c] = A[i][r0 + c] gamma[r0 + c]
-    __shared__ float2 s_x[S::XSIZE];
+// ---------------------------------------------------------------- matrix-core tiles
+// A block of 256 threads (four wavefronts) covers ROWS frame rows.  The frame's
+// complex contractions run on 16x16x4 FP32 MFMAs with the complex product split
+// into real ones over a K index (rank or column, re/im).  MT x NT tiles of 16 x 16.
+constexpr int kRowBlock = 256;
+constexpr int kRowWaves = kRowBlock / 64;
+template <int N> struct RowTiles {
+    static constexpr int ROWS = RowShape<N>::ROWS;
+    static constexpr int PITCH = N + 2;                 // natural [row][col] tile pitch: conflict-free 16-row reads
+    static constexpr int MT = (ROWS + 15) / 16;
+    static constexpr int NT = (N + 15) / 16;
+    static constexpr int TPW = (MT * NT + kRowWaves - 1) / kRowWaves;   // synthesis tiles per wavefront
+};
+constexpr int cmax2(int a, int b) { return a > b ? a : b; }
 
+// ---------------------------------------------------------------- K1
+// X-[i][j] = sum_r AG[i][r] B[j][r] (AG = A diag(gamma)): with K = (r, re/im),
+// P_re = [Re AG, -Im AG], P_im = [Im AG, Re AG] and Q = [Re B; Im B],
+// Re X = P_re Q and Im X = P_im Q.  kSynRC ranks of B (all n2 rows) and of AG
+// (the block's rows) are staged in LDS per pass with coalesced loads; the
+// operands of the 16x16x4 steps are read from there.  The tiles land in LDS as
+// [row][col] and the row transform reads its natural-layout inputs from there.
+constexpr int kSynRC = 8;                  // ranks staged per pass (four K steps)
+constexpr int kSynBP = kSynRC + 1;         // LDS pitch (float2) of a staged row
+template <int N2, class Src>
+__global__ void __launch_bounds__(kRowBlock) k_synth_rowfft(Src src) {
+    using S = RowShape<N2>;
+    using RT = RowTiles<N2>;
+    constexpr int P = S::P, Q = S::Q, T = S::T, ROWS = S::ROWS, PITCH = RT::PITCH;
+    constexpr int SB = N2 * kSynBP, SA = RT::MT * 16 * kSynBP;      // staged B rows, staged AG rows
+    __shared__ float2 s_tw[N2];
+    __shared__ float2 s_x[cmax2(cmax2(S::XSIZE, ROWS * PITCH), SB + SA)];
+
+    if (!src.live()) return;
     const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, true)) return;
     const int n1 = f.n1, R = f.r;
     const int tid = threadIdx.x, s = tid % T, rl = tid / T;
-    const int i = blockIdx.x * ROWS + rl;
+    const int i = src.bx() * ROWS + rl;
+    const bool live = rl < ROWS && i < n1;
+    const int lane = tid % 64, wave = tid / 64, m = lane % 16, g = lane / 16;
+    const int i0 = src.bx() * ROWS;
     load_tw<N2>(s_tw);
 
-    float2 v[T];
-    sfor<T>([&](auto k) { v[decltype(k)::value] = float2{0.f, 0.f}; });
-    for (int r0 = 0; r0 < R; r0 += kRC) {
-        __syncthreads();
-        stage_copy<8, float2>(
-            kRC * N2,
-            [&](int e) {
-                const int j = e / kRC, c = e % kRC;
-                return (r0 + c < R) ? f.B[j * R + r0 + c] : float2{0.f, 0.f};
-            },
-            [&](int e, float2 v) { s_B[(e % kRC) * N2 + e / kRC] = v; });
-        for (int e = tid; e < ROWS * kRC; e += blockDim.x) {
-            const int rr = e / kRC, c = e % kRC, ii = blockIdx.x * ROWS + rr;
-            s_ag[e] = (r0 + c < R && ii < n1) ? cmul(f.A[ii * R + r0 + c], f.gamma32[r0 + c])
-                                               : float2{0.f, 0.f};
-        }
-        __syncthreads();
-        if (s < Q) {
+    {
+        float2* s_b = s_x;                  // [j][c] = B[j][r0 + c]
+        float2* s_ag = s_x + SB;            // [row][c] = A[i0 + row][r0 + c] gamma[r0 + c]
+        f32x4 accr[RT::TPW], acci[RT::TPW];
 #pragma unroll
-            for (int c = 0; c < kRC; ++c) {
-                const float2 a = s_ag[rl * kRC + c];
-                sfor<P>([&](auto q) {
-                    constexpr int n1c = decltype(q)::value;
-                    cfma(v[n1c], a, s_B[c * N2 + Q * n1c + s]);
-                });
+        for (int u = 0; u < RT::TPW; ++u) accr[u] = acci[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const bool im = g & 1;
+        for (int r0 = 0; r0 < R; r0 += kSynRC) {
+            const int nr = min(kSynRC, R - r0);
+            __syncthreads();
+            stage_copy<8, float2>(
+                N2 * kSynRC,
+                [&](int e) {
+                    const int j = e / kSynRC, c = e % kSynRC;
+                    return c < nr ? float2(f.B[size_t(j) * R + r0 + c]) : float2{0.f, 0.f};
+                },
+                [&](int e, float2 v) { s_b[(e / kSynRC) * kSynBP + e % kSynRC] = v; });
+            for (int e = tid; e < RT::MT * 16 * kSynRC; e += blockDim.x) {
+                const int row = e / kSynRC, c = e % kSynRC, ia = i0 + row;
+                s_ag[row * kSynBP + c] = (c < nr && row < ROWS && ia < n1)
+                                             ? cmul(float2(f.A[size_t(ia) * R + r0 + c]), float2(f.gamma32[r0 + c]))
+                                             : float2{0.f, 0.f};
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kSynRC / 2; ++k) {
+                const int c = 2 * k + g / 2;
+#pragma unroll
+                for (int u = 0; u < RT::TPW; ++u) {
+                    const int tile = wave + kRowWaves * u;
+                    if (tile >= RT::MT * RT::NT) break;
+                    const int mt = tile / RT::NT, nt = tile % RT::NT, j = 16 * nt + m;
+                    const float2 a = s_ag[(16 * mt + m) * kSynBP + c];
+                    const float2 b = j < N2 ? s_b[j * kSynBP + c] : float2{0.f, 0.f};
+                    const float bv = im ? b.y : b.x;
+                    accr[u] = mfma_16x16x4(im ? -a.y : a.x, bv, accr[u]);
+                    acci[u] = mfma_16x16x4(im ? a.x : a.y, bv, acci[u]);
+                }
+            }
+        }
+        __syncthreads();                    // staging area becomes the output tile
+#pragma unroll
+        for (int u = 0; u < RT::TPW; ++u) {
+            const int tile = wave + kRowWaves * u;
+            if (tile >= RT::MT * RT::NT) break;
+            const int mt = tile / RT::NT, nt = tile % RT::NT, j = 16 * nt + m;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 16 * mt + 4 * g + e;
+                if (row < ROWS && j < N2) s_x[row * PITCH + j] = float2{accr[u][e], acci[u][e]};
             }
         }
     }
+    __syncthreads();
+    float2 v[T];
+    sfor<T>([&](auto k) { v[decltype(k)::value] = float2{0.f, 0.f}; });
+    if (s < Q && rl < ROWS)
+        sfor<P>([&](auto q) {
+            constexpr int n1c = decltype(q)::value;
+            v[n1c] = s_x[rl * PITCH + Q * n1c + s];
+        });
+    __syncthreads();   // the row exchange below reuses s_x
     if (s < Q) dft_twiddle<N2, P, false>(v, s, s_tw);
-    row_swap_nk<N2>(v, s_x, rl, s);
-    if (s < P) {
+    row_swap_nk<N2>(v, s_x, rl < ROWS ? rl : 0, rl < ROWS ? s : T);
+    if (s < P && live) {
         dft_only<Q, false>(v);
-        if (i < n1) {
-            float2* out = f.frame + size_t(i) * N2;
-            sfor<Q>([&](auto k) {
-                constexpr int k2 = decltype(k)::value;
-                out[s + P * k2] = cscale(v[k2], InvSqrt<N2>::value);
-            });
-        }
+        float2* out = f.frame + size_t(i) * N2;
+        sfor<Q>([&](auto k) {
+            constexpr int k2 = decltype(k)::value;
+            out[s + P * k2] = cscale(v[k2], InvSqrt<N2>::value);
+        });
     }
 }
 
 // ---------------------------------------------------------------- K3
+// G_A[i][r] = sum_j Theta[i][j] conj(B[j][r]): with K = (j, re/im),
+// P_re = [Re Th, Im Th], P_im = [Im Th, -Re Th] and Q = [Re B; Im B],
+// Re G_A = P_re Q and Im G_A = P_im Q.  Theta sits in LDS as [row][col]; the
+// wavefronts split the M tiles and, when there are fewer than four of them, the
+// K range, and partial sums over K ranges are added in a fixed order.
+constexpr int kGNT = 2;   // 16-rank tiles per pass
 template <int N2, class Src>
-__global__ void __launch_bounds__(256) k_row_inv_grad(Src src) {
+__global__ void __launch_bounds__(kRowBlock) k_row_inv_grad(Src src) {
     using S = RowShape<N2>;
-    constexpr int P = S::P, Q = S::Q, T = S::T, ROWS = S::ROWS;
+    using RT = RowTiles<N2>;
+    constexpr int P = S::P, Q = S::Q, T = S::T, ROWS = S::ROWS, PITCH = RT::PITCH, MT = RT::MT;
+    constexpr int MW = MT < kRowWaves ? MT : kRowWaves;      // wavefronts across M tiles
+    constexpr int KS = kRowWaves / MW;                        // ... and across K ranges
+    constexpr int MPW = (MT + MW - 1) / MW;                   // M tiles per wavefront
+    constexpr int KSTEPS = (N2 + 1) / 2;                      // two columns per 16x16x4 step
+    constexpr int KPW = (KSTEPS + KS - 1) / KS;
+    constexpr int SP = KS * MT * 16 * kGNT * 16;              // partials [ks][row][rank]
     __shared__ float2 s_tw[N2];
-    __shared__ float2 s_B[kRC * N2];              // [c][j] = B[j][r0 + c]
-    __shared__ float2 s_x[S::XSIZE];
-    __shared__ float2 s_red[ROWS * P * kRC];      // [row][s][c] partial sums
+    __shared__ float2 s_x[cmax2(S::XSIZE, ROWS * PITCH)];
+    __shared__ float2 s_p[SP];
     __shared__ int s_bad;
 
+    if (!src.live()) return;
     const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, true)) return;
     const int n1 = f.n1, R = f.r;
     const int tid = threadIdx.x, s = tid % T, rl = tid / T;
-    const int i = blockIdx.x * ROWS + rl;
+    const int i = src.bx() * ROWS + rl;
+    const bool live = rl < ROWS && i < n1;
     if (tid == 0) s_bad = 0;
     load_tw<N2>(s_tw);
 
     float2 v[T];
     sfor<T>([&](auto k) { v[decltype(k)::value] = float2{0.f, 0.f}; });
-    if (s < Q && i < n1) {
+    if (s < Q && live) {
         const float2* in = f.frame + size_t(i) * N2;
         sfor<P>([&](auto q) { v[decltype(q)::value] = in[Q * decltype(q)::value + s]; });
     }
     __syncthreads();   // twiddles visible
     if (s < Q) dft_twiddle<N2, P, true>(v, s, s_tw);
-    row_swap_nk<N2>(v, s_x, rl, s);
+    row_swap_nk<N2>(v, s_x, rl < ROWS ? rl : 0, rl < ROWS ? s : T);
     if (s < P) {
         dft_only<Q, true>(v);
         sfor<Q>([&](auto k) { v[decltype(k)::value] = cscale(v[decltype(k)::value], InvSqrt<N2>::value); });
     }
-    // v[k2] = Theta[i][s + P*k2] for threads s < P.
+    __syncthreads();   // every thread is done with the exchange area
+    // v[k2] = Theta[i][s + P*k2] for threads s < P: natural tile into LDS (zero rows past n1)
+    if (s < P && rl < ROWS)
+        sfor<Q>([&](auto k) {
+            constexpr int k2 = decltype(k)::value;
+            s_x[rl * PITCH + s + P * k2] = live ? v[k2] : float2{0.f, 0.f};
+        });
+    __syncthreads();
+
+    const int lane = tid % 64, wave = tid / 64, m = lane % 16, g = lane / 16;
+    const int mw = wave % MW, ks = wave / MW;
+    const bool im = g & 1;
     bool bad = false;
-    for (int r0 = 0; r0 < R; r0 += kRC) {
-        __syncthreads();
-        stage_copy<8, float2>(
-            kRC * N2,
-            [&](int e) {
-                const int j = e / kRC, c = e % kRC;
-                return (r0 + c < R) ? f.B[j * R + r0 + c] : float2{0.f, 0.f};
-            },
-            [&](int e, float2 v) { s_B[(e % kRC) * N2 + e / kRC] = v; });
-        __syncthreads();
-        if (s < P) {
+    for (int n0 = 0; n0 < R; n0 += kGNT * 16) {
+        f32x4 accr[MPW][kGNT], acci[MPW][kGNT];
 #pragma unroll
-            for (int c = 0; c < kRC; ++c) {
-                float2 acc{0.f, 0.f};
-                sfor<Q>([&](auto k) {
-                    constexpr int k2 = decltype(k)::value;
-                    const float2 b = s_B[c * N2 + s + P * k2];
-                    acc = cadd(acc, cmulc(v[k2], b));
-                });
-                s_red[(rl * P + s) * kRC + c] = acc;
+        for (int a = 0; a < MPW; ++a)
+#pragma unroll
+            for (int u = 0; u < kGNT; ++u) accr[a][u] = acci[a][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (ks < KS) {
+            constexpr int KB = 16;                        // steps whose B operands load together
+            const int t0 = ks * KPW, t1 = min(KSTEPS, t0 + KPW);
+            for (int tb = t0; tb < t1; tb += KB) {
+                float bv[KB][kGNT];
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    const int j = 2 * (tb + k) + g / 2;
+#pragma unroll
+                    for (int u = 0; u < kGNT; ++u) {
+                        const int r = n0 + 16 * u + m;
+                        const bool ok = tb + k < t1 && j < N2 && r < R;
+                        const float2 b = ok ? float2(f.B[size_t(j) * R + r]) : float2{0.f, 0.f};
+                        bv[k][u] = im ? b.y : b.x;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    const int j = 2 * (tb + k) + g / 2;
+#pragma unroll
+                    for (int a = 0; a < MPW; ++a) {
+                        const int mt = mw + MW * a;
+                        const int row = 16 * mt + m;
+                        const float2 th = (tb + k < t1 && mt < MT && row < ROWS && j < N2) ? s_x[row * PITCH + j]
+                                                                                            : float2{0.f, 0.f};
+                        const float pr = im ? th.y : th.x, pi = im ? -th.x : th.y;
+#pragma unroll
+                        for (int u = 0; u < kGNT; ++u) {
+                            accr[a][u] = mfma_16x16x4(pr, bv[k][u], accr[a][u]);
+                            acci[a][u] = mfma_16x16x4(pi, bv[k][u], acci[a][u]);
+                        }
+                    }
+                }
+            }
+        }
+        // partial sums: D[4 g + e][m] = (row 16 mt + 4 g + e, rank n0 + 16 u + m)
+        if (ks < KS)
+#pragma unroll
+            for (int a = 0; a < MPW; ++a) {
+                const int mt = mw + MW * a;
+                if (mt >= MT) continue;
+#pragma unroll
+                for (int u = 0; u < kGNT; ++u)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int row = 16 * mt + 4 * g + e;
+                        s_p[(ks * MT * 16 + row) * (kGNT * 16) + 16 * u + m] = float2{accr[a][u][e], acci[a][u][e]};
+                    }
+            }
+        __syncthreads();
+        for (int e = tid; e < ROWS * kGNT * 16; e += blockDim.x) {
+            const int row = e / (kGNT * 16), rr = e % (kGNT * 16), ii = src.bx() * ROWS + row;
+            if (ii < n1 && n0 + rr < R) {
+                float2 gsum = s_p[row * (kGNT * 16) + rr];
+                for (int q = 1; q < KS; ++q) gsum = cadd(gsum, s_p[(q * MT * 16 + row) * (kGNT * 16) + rr]);
+                bad |= !finite2(gsum);
+                f.GA[size_t(ii) * R + n0 + rr] = gsum;
             }
         }
         __syncthreads();
-        for (int e = tid; e < ROWS * kRC; e += blockDim.x) {
-            const int rr = e / kRC, c = e % kRC, ii = blockIdx.x * ROWS + rr;
-            if (ii < n1 && r0 + c < R) {
-                float2 g{0.f, 0.f};
-                for (int q = 0; q < P; ++q) g = cadd(g, s_red[(rr * P + q) * kRC + c]);
-                bad |= !finite2(g);
-                f.GA[size_t(ii) * R + r0 + c] = g;
-            }
-        }
     }
     if (bad) s_bad = 1;
     __syncthreads();
@@ -210,16 +328,18 @@ __global__ void __launch_bounds__(256) k_rowfft(const float2* in, float2* out, i
 
 template <int N2> hipError_t launch_k1_n(const Batch& b, hipStream_t st) {
     using S = RowShape<N2>;
-    dim3 grid(cdiv(b.n1, S::ROWS), b.table ? b.count : 1);
-    if (b.table) k_synth_rowfft<N2, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table});
-    else k_synth_rowfft<N2, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one});
+    const int gx = cdiv(b.n1, S::ROWS);
+    const dim3 grid = frame_grid(b, gx);
+    if (b.table) k_synth_rowfft<N2, FrameTable><<<grid, kRowBlock, 0, st>>>(FrameTable{b.table, gx, b.count});
+    else k_synth_rowfft<N2, OneFrame><<<grid, kRowBlock, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 template <int N2> hipError_t launch_k3_n(const Batch& b, hipStream_t st) {
     using S = RowShape<N2>;
-    dim3 grid(cdiv(b.n1, S::ROWS), b.table ? b.count : 1);
-    if (b.table) k_row_inv_grad<N2, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table});
-    else k_row_inv_grad<N2, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one});
+    const int gx = cdiv(b.n1, S::ROWS);
+    const dim3 grid = frame_grid(b, gx);
+    if (b.table) k_row_inv_grad<N2, FrameTable><<<grid, kRowBlock, 0, st>>>(FrameTable{b.table, gx, b.count});
+    else k_row_inv_grad<N2, OneFrame><<<grid, kRowBlock, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 template <int N2> hipError_t launch_rowfft_n(int nrows, const float2* in, float2* out, bool inv, hipStream_t st) {

@@ -1,6 +1,6 @@
 // Host-side launchers of the step's kernels.  A Batch describes the frames of
 // one launch group: either one frame passed by value, or `count` frames of the
-// same (n1, n2) read from a device table (entry blockIdx.y).
+// same (n1, n2) read from a device table (see FrameTable for the block order).
 #pragma once
 
 #include "frame.hpp"
@@ -21,6 +21,12 @@ struct Batch {
 
 // Threads per block of the kernels that are not templated on a length.
 constexpr int kBlock = 256;
+
+// Grid of a launch with x blocks per frame (table launches pad the frame count
+// to a multiple of kXcds; see FrameTable).
+inline dim3 frame_grid(const Batch& b, int x) {
+    return b.table ? dim3(unsigned(x) * unsigned((b.count + kXcds - 1) / kXcds * kXcds)) : dim3(unsigned(x));
+}
 
 // Row direction (length n2): K1 synthesis + row transform, K3 row inverse +
 // Theta conj(B); standalone row pass of the 2-D transform.

@@ -5,6 +5,14 @@
 namespace tsl {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One 16x16x4 FP32 step, D += A B with A 16x4 and B 4x16.  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; element i of lane l of D is
+// D[4 (l / 16) + i][l % 16].
+__device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
 // One 32x32x2 FP32 step, D += A B with A 32x2 and B 2x32.  Lane l supplies
 // A[l % 32][l / 32] and B[l / 32][l % 32]; element v of lane l of D is

@@ -32,7 +32,7 @@ __all__ = [
     "rng_for", "cn", "lowrank_truth", "lowrank_frame", "point_mask", "kspace",
     "signed_freq", "vd_line_mask", "PhantomSpec", "phantom_spec", "phantom_frame",
     "init_factors", "LineFrame", "PointFrame", "config1", "config2", "config3_kspace",
-    "mixed_batch_specs",
+    "mixed_batch_specs", "phantom_bank", "serving_specs",
 ]
 
 
@@ -273,4 +273,33 @@ def mixed_batch_specs(n_seq=64, seed_config=4):
         n1, n2 = shapes[pick[s]]
         out.append(dict(n1=n1, n2=n2, r=int(rng.choice([16, 32, 64])),
                         accel=int(rng.integers(4, 13)), seq=s))
+    return out
+
+
+def phantom_bank(n, frames, seq=0, sigma=0.005, config=5, n2=None):
+    """Full noisy k-space frames (complex64 [frames, n, n2], n2 = n by default)
+    of one phantom cine."""
+    n2 = n if n2 is None else n2
+    rng_ph, rng_noise = rng_for(config, seq, 0), rng_for(config, seq, 2)
+    spec = phantom_spec(n, n2, rng_ph)
+    K = np.empty((frames, n, n2), dtype=np.complex64)
+    for t in range(1, frames + 1):
+        K[t - 1] = kspace(phantom_frame(spec, t)) + cn(rng_noise, (n, n2), sigma * sigma)
+    return K
+
+
+def serving_specs(n_scans=128, rate=16.0, sizes=(128, 160, 192, 256, 320, 384), ranks=(16, 32, 48, 64),
+                  seed_config=5):
+    """Scans of the serving workload: Poisson arrivals at `rate` scans/s (the
+    first at 0), size N (N x N frames) and rank R drawn uniformly per scan, and
+    each scan's start factors A0 ~ CN(0, 1/N), B0 ~ CN(0, 1/N)."""
+    rng = rng_for(seed_config, 0, 98)
+    gaps = rng.exponential(1.0 / rate, size=n_scans)
+    arrivals = np.concatenate([[0.0], np.cumsum(gaps[1:])])
+    out = []
+    for s in range(n_scans):
+        n = int(rng.choice(sizes))
+        r = int(rng.choice(ranks))
+        A0, B0 = init_factors(n, n, r, rng_for(seed_config, s, 3))
+        out.append(dict(scan=s, n=n, r=r, arrival=float(arrivals[s]), A0=A0, B0=B0))
     return out

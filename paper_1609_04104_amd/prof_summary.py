@@ -1,8 +1,17 @@
-"""Per-kernel summary (calls, average/min/max duration, grid, registers, LDS) of a
-rocprofv3 --kernel-trace run, from its CSV trace or its SQLite database:
+"""Summaries of rocprofv3 runs.
+
+Per-kernel durations (calls, average/min/max, grid, registers, LDS) of a
+--kernel-trace run, from its CSV trace or its SQLite database:
 
     python -m paper_1609_04104_amd.prof_summary RUN_kernel_trace.csv
     python -m paper_1609_04104_amd.prof_summary RUN_results.db
+
+Per-dispatch HBM bytes of every kernel from two --pmc runs (FETCH_SIZE, then
+WRITE_SIZE) of a program that first makes one plain device copy of a known
+size (bench.py --copy-calib-mib M), written as a JSON record keyed by kernel:
+
+    python -m paper_1609_04104_amd.prof_summary counters FETCH_counter_collection.csv \
+        WRITE_counter_collection.csv M OUT.json
 """
 import csv
 import sqlite3
@@ -49,5 +58,65 @@ def summarize(path, out=sys.stdout):
               f"{sum(d) / 1e3:.1f} | {gx} x {gy} | {wx} | {vgpr} | {lds} | {scratch} |", file=out)
 
 
+
+
+# ----------------------------------------------------------------------------- byte counters
+def source_sha():
+    """SHA-256 over the HIP sources of the library (names and contents, sorted),
+    so a counter record can tell whether the kernels changed since it was taken."""
+    import glob
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for p in sorted(glob.glob(os.path.join(here, "*.hip")) + glob.glob(os.path.join(here, "*.hpp"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _per_dispatch(path, counter):
+    acc, disp, grid = defaultdict(float), defaultdict(set), {}
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            key = r["Kernel_Name"].replace("tsl::(anonymous namespace)::", "").replace("tsl::", "").split("(")[0]
+            key = f"{key} [grid {r['Grid_Size']}]"
+            acc[key] += float(r["Counter_Value"])
+            disp[key].add(r["Dispatch_Id"])
+    return {k: acc[k] / len(disp[k]) for k in acc}, {k: len(disp[k]) for k in acc}
+
+
+def counters(fetch_csv, write_csv, copy_mib, out):
+    """Per-dispatch HBM bytes of every kernel from a FETCH_SIZE run and a
+    WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
+    reads for the reference copy of copy_mib MiB (the copyBuffer dispatch of
+    that size) so that the figures are true bytes."""
+    import json
+    fetch, nf = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write, _ = _per_dispatch(write_csv, "WRITE_SIZE")
+    kib = copy_mib * 1024.0
+    ref = [k for k in write if "copyBuffer" in k and abs(write[k] - kib) < 0.02 * kib]
+    if not ref:
+        raise SystemExit("no reference copy dispatch of the given size in the WRITE_SIZE run")
+    fscale = kib / fetch[ref[0]]
+    wscale = kib / write[ref[0]]
+    rec = {"source_sha": source_sha(), "reference_copy_mib": copy_mib,
+           "fetch_scale": fscale, "write_scale": wscale, "kernels": {}}
+    for k in sorted(fetch):
+        if k not in write:
+            continue
+        rec["kernels"][k] = {"fetch_bytes": fetch[k] * 1024.0 * fscale, "write_bytes": write[k] * 1024.0 * wscale,
+                             "dispatches": nf[k]}
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(f"fetch scale {fscale:.3f}, write scale {wscale:.3f}, {len(rec['kernels'])} kernels -> {out}")
+
+
 if __name__ == "__main__":
-    summarize(sys.argv[1])
+    if sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5])
+    else:
+        summarize(sys.argv[1])
