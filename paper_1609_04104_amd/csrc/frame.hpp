@@ -28,7 +28,7 @@ enum : int { MODE_LINES = 0, MODE_POINTS = 1 };
 // per slot for line masks, kPRows mask rows per slot for point masks).  The
 // right-hand side partials are [sampled slot][readout chunk of kJCH samples]
 // for line masks and [sampled slot] for point masks.
-constexpr int kGRows = 32;      // rows of F_l A or F_r B per factor-Gram partial
+constexpr int kGRows = 64;      // rows of F_l A or F_r B per factor-Gram partial
 constexpr int kSRows = 32;      // sampled rows per (Gram, rhs) partial, line masks
 constexpr int kPRows = 32;      // mask rows per (Gram, rhs) partial, point masks
 constexpr int kJCH = 32;        // readout samples per right-hand-side partial, line masks

@@ -209,14 +209,14 @@ size_t lstats_lds(int R) { return (size_t(kSRows + kJCH) * R + size_t(kSRows) * 
 
 constexpr int kPW = 32;        // sampled entries staged per window of a point-mask Gram
 constexpr int kMaxAcc = 8;     // Gram entries one thread accumulates per pass (point masks)
-static_assert(kPW >= kGRows, "the factor-Gram staging fits the point window");
+constexpr int kPStage = kPW > kGRows ? kPW : kGRows;   // staged rows: a point window or a factor-Gram chunk
 
 // Point masks.  Blocks [0, gAB) are the factor-Gram partials as above; block
 // gAB + k forms explicit Phi^H Phi and Phi^H y over mask rows [kPRows k, kPRows (k+1))
 // into slot gAB + k and hpart[k].
 template <class Src>
 __global__ void __launch_bounds__(kSB) k_pstats(Src src) {
-    extern __shared__ double2 s_dyn[];            // kPW * R
+    extern __shared__ double2 s_dyn[];            // kPStage * R
     __shared__ double2 s_yw[kPW];
     __shared__ int s_err;
     if (!src.live()) return;
@@ -585,6 +585,7 @@ __device__ __forceinline__ double2 readlane_d2(double2 v, int lane) {
 }
 
 constexpr int kRegBlk = 256;
+constexpr int kGatherPF = 4;   // partial slots of each statistic loaded per round
 
 template <int RB, class Src>
 __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
@@ -627,10 +628,39 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
             ok[u] = e < RB * RB && i < R && j < R;
             up[u] = ok[u] ? (i <= j ? size_t(i) * R + j : size_t(j) * R + i) : 0;
         }
+        // the right-hand side's partials and all three slot ranges of every entry
+        // are loaded together (kGatherPF slots of each at a time), then added in
+        // slot order
+        constexpr int kHPF = 16;
+        double2 hw[kHPF];
+        const bool hlive = tid < R;
+#pragma unroll
+        for (int q = 0; q < kHPF; ++q)
+            hw[q] = (hlive && q < nh) ? f.hpart[size_t(q) * R + tid] : double2{0.0, 0.0};
         double2 g[U], ma[U], mb[U];
-        slot_sums<U>(pa, RR, gA, up, ok, ma);
-        slot_sums<U>(pb, RR, gB, up, ok, mb);
-        slot_sums<U>(ps, RR, ns, up, ok, g);
+#pragma unroll
+        for (int u = 0; u < U; ++u) g[u] = ma[u] = mb[u] = double2{0.0, 0.0};
+        const int nmax = max(gA, max(gB, ns));
+        for (int k0 = 0; k0 < nmax; k0 += kGatherPF) {
+            double2 wa[U][kGatherPF], wb[U][kGatherPF], ws[U][kGatherPF];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < kGatherPF; ++q) {
+                    const size_t o = size_t(k0 + q) * RR + up[u];
+                    wa[u][q] = (ok[u] && k0 + q < gA) ? pa[o] : double2{0.0, 0.0};
+                    wb[u][q] = (ok[u] && k0 + q < gB) ? pb[o] : double2{0.0, 0.0};
+                    ws[u][q] = (ok[u] && k0 + q < ns) ? ps[o] : double2{0.0, 0.0};
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < kGatherPF; ++q) {
+                    ma[u].x += wa[u][q].x; ma[u].y += wa[u][q].y;
+                    mb[u].x += wb[u][q].x; mb[u].y += wb[u][q].y;
+                    g[u].x += ws[u][q].x; g[u].y += ws[u][q].y;
+                }
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = tid + u * kRegBlk, i = e / RB, j = e % RB;
@@ -645,8 +675,14 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
             s_m[0][e] = dabs(ma[u]);
             s_m[1][e] = dabs(mb[u]);
         }
+        if (tid < RB) {
+            double2 hv{0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < kHPF; ++q) { hv.x += hw[q].x; hv.y += hw[q].y; }
+            for (int q = kHPF; q < nh && hlive; ++q) { hv.x += f.hpart[size_t(q) * R + tid].x; hv.y += f.hpart[size_t(q) * R + tid].y; }
+            s_h[tid] = hv;
+        }
     }
-    if (tid < RB) s_h[tid] = tid < R ? rhs_sum(f, tid, nh) : double2{0.0, 0.0};
     __syncthreads();
 
     // Wavefront 0: right-looking Cholesky with the forward substitution fused in
@@ -882,8 +918,8 @@ __global__ void __launch_bounds__(256) k_sample(Src src) {
     for (int i0 = 0; i0 < n1; i0 += chunk) {
         const int ni = min(chunk, n1 - i0);
         __syncthreads();
-        stage_copy<8, float2>(ni * R, [&](int e) { return f.Ahat[size_t(i0) * R + e]; },
-                              [&](int e, float2 v) { s_a[e] = v; });
+        stage_copy<32, float2>(ni * R, [&](int e) { return f.Ahat[size_t(i0) * R + e]; },
+                               [&](int e, float2 v) { s_a[e] = v; });
         __syncthreads();
         if (tid < R) {
             int i = 0;
@@ -1002,7 +1038,7 @@ size_t solve_lds(int R) { return size_t(R * (R + 1) / 2 + R) * sizeof(double2) +
 void init_kernel_attributes() {
     static std::once_flag once;
     std::call_once(once, [] {
-        const int ms = int(size_t(kPW) * TSL_MAX_R * sizeof(double2));
+        const int ms = int(size_t(kPStage) * TSL_MAX_R * sizeof(double2));
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pstats<FrameTable>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, ms);
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pstats<OneFrame>),
@@ -1034,7 +1070,7 @@ hipError_t launch_stats(const Batch& b, hipStream_t st) {
         if (b.table) k_lstats<FrameTable><<<grid, kSB, lds, st>>>(FrameTable{b.table, gx, b.count});
         else k_lstats<OneFrame><<<grid, kSB, lds, st>>>(OneFrame{*b.one});
     } else {
-        const size_t lds = size_t(kPW) * b.r_max * sizeof(double2);
+        const size_t lds = size_t(kPStage) * b.r_max * sizeof(double2);
         const int gx = gAB + n_sparts(b.n1);
         const dim3 grid = frame_grid(b, gx);
         if (b.table) k_pstats<FrameTable><<<grid, kSB, lds, st>>>(FrameTable{b.table, gx, b.count});
