@@ -299,7 +299,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": dbytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    gx = (-(-n // 32)) * 2 + (-(-K // 32)) * (-(-n // 32))          # statistics blocks per frame
+    gx = (-(-n // 64)) * 2 + (-(-K // 32)) * (-(-n // 32))          # statistics blocks per frame
     roof["traffic"] = counter_traffic(dname, n, grid=gx * 256 * (-(-S // 8) * 8))
     roof["kernel"] = dname
     roof["algorithmic_bytes_per_launch"] = dbytes

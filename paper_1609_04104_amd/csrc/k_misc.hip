@@ -38,49 +38,39 @@ __device__ __forceinline__ double dabs(double2 a) { return sqrt(a.x * a.x + a.y 
 
 // ---------------------------------------------------------------- Gram statistics
 // Blocks of kSB threads.  A Gram is accumulated from rows staged in LDS as FP64
-// (products of FP32 values are exact there); a thread owns kGE upper entries
-// per pass.  Every block writes its own partial slot and the solve sums the
-// slots in slot order, so the result does not depend on block scheduling.
+// (products of FP32 values are exact there).  Every block writes its own
+// partial slot and the solve sums the slots in slot order, so the result does
+// not depend on block scheduling.
 constexpr int kSB = 256;
-constexpr int kGE = 4;
-constexpr int kZU = (kSRows * TSL_MAX_R + kSB - 1) / kSB;   // (row, rank) entries per thread, rhs partial
 static_assert(kJCH >= kSRows, "the rhs products reuse the readout-chunk staging area");
 
-__device__ __forceinline__ void upper_index(int e, int R, int& r, int& s) {   // packed upper triangle, by rows
-    r = 0;
-    while (e >= R - r) { e -= R - r; ++r; }
-    s = r + e;
-}
-
-// Upper entries (r <= s) of sum_q conj(x_qr) x_qs over the nq rows of s_x ([nq][R]).
+// Upper entries (r <= s) of sum_q conj(x_qr) x_qs over the nq rows of s_x ([nq][R])
+// on FP64 matrix cores (products of FP32 values are exact in FP64).  With the K
+// index over (row, re/im), Re = sum Xr_r Xr_s + Xi_r Xi_s and
+// Im = sum Xr_r Xi_s - Xi_r Xr_s are each one 16x16x4 step per two rows; the
+// wavefronts take the 16 x 16 tiles on and above the diagonal.
 __device__ void gram_staged(const double2* s_x, int nq, int R, double2* out) {
-    const int tid = threadIdx.x;
-    const int npairs = R * (R + 1) / 2;
-    for (int e0 = 0; e0 < npairs; e0 += kSB * kGE) {
-        int er[kGE], es[kGE];
-        double2 acc[kGE];
-#pragma unroll
-        for (int u = 0; u < kGE; ++u) {
-            const int e = e0 + tid + u * kSB;
-            if (e < npairs) upper_index(e, R, er[u], es[u]);
-            else er[u] = es[u] = 0;
-            acc[u] = double2{0.0, 0.0};
-        }
-        for (int q = 0; q < nq; ++q) {
-            const double2* xq = s_x + q * R;
-            double2 a[kGE], b[kGE];
-#pragma unroll
-            for (int u = 0; u < kGE; ++u) { a[u] = xq[er[u]]; b[u] = xq[es[u]]; }
-#pragma unroll
-            for (int u = 0; u < kGE; ++u) {
-                acc[u].x = fma(a[u].x, b[u].x, fma(a[u].y, b[u].y, acc[u].x));
-                acc[u].y = fma(a[u].x, b[u].y, fma(-a[u].y, b[u].x, acc[u].y));
-            }
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nw = blockDim.x / 64;
+    const int m = lane % 16, g = lane / 16;
+    const bool p = g & 1;
+    const int TM = (R + 15) / 16, ntiles = TM * (TM + 1) / 2;
+    for (int tile = wave; tile < ntiles; tile += nw) {
+        int mi = 0, t = tile;
+        while (t >= TM - mi) { t -= TM - mi; ++mi; }
+        const int ni = mi + t;
+        const int ra = 16 * mi + m, sb = 16 * ni + m;
+        f64x4 are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 < nq; q0 += 2) {
+            const int q = q0 + g / 2;
+            const double2 xa = (q < nq && ra < R) ? s_x[q * R + ra] : double2{0.0, 0.0};
+            const double2 xb = (q < nq && sb < R) ? s_x[q * R + sb] : double2{0.0, 0.0};
+            are = mfma_16x16x4_f64(p ? xa.y : xa.x, p ? xb.y : xb.x, are);
+            aim = mfma_16x16x4_f64(p ? -xa.y : xa.x, p ? xb.x : xb.y, aim);
         }
 #pragma unroll
-        for (int u = 0; u < kGE; ++u) {
-            const int e = e0 + tid + u * kSB;
-            if (e < npairs) out[size_t(er[u]) * R + es[u]] = acc[u];
+        for (int i = 0; i < 4; ++i) {
+            const int rr = 16 * mi + 4 * i + g, ss = 16 * ni + m;
+            if (rr < R && ss < R && rr <= ss) out[size_t(rr) * R + ss] = double2{are[i], aim[i]};
         }
     }
 }
@@ -166,33 +156,41 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     __syncthreads();
     if (c == 0) gram_staged(s_x, nq, R, f.part + size_t(gAB + k) * R * R);
 
-    // z[q][r] = sum_j y_qj conj(Bhat_jr) over the chunk, one (q, r) entry per slot u
-    const int nqr = nq * R;
-    double2 z[kZU];
-    int zq[kZU], zr[kZU];
+    // z[q][r] = sum_j y_qj conj(Bhat_jr) over the chunk on FP64 matrix cores: M = the
+    // sampled rows, N = ranks, K = (sample, re/im); Re z = sum yr br + yi bi and
+    // Im z = sum yi br - yr bi share the B operand [Re B; Im B].
+    const int lane = tid % 64, wave = tid / 64, m = lane % 16, g = lane / 16;
+    const bool p = g & 1;
+    const int TMq = (nq + 15) / 16, TMr = (R + 15) / 16, nzt = TMq * TMr;
+    constexpr int kZT = ((kSRows + 15) / 16 * ((TSL_MAX_R + 15) / 16) + kSB / 64 - 1) / (kSB / 64);
+    f64x4 zre[kZT], zim[kZT];
 #pragma unroll
-    for (int u = 0; u < kZU; ++u) {
-        const int e = tid + u * kSB;
-        zq[u] = e / R;
-        zr[u] = e % R;
-        z[u] = double2{0.0, 0.0};
-    }
-    for (int jj = 0; jj < nj; ++jj) {
+    for (int u = 0; u < kZT; ++u) zre[u] = zim[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j0 = 0; j0 < nj; j0 += 2) {
+        const int j = j0 + g / 2;
 #pragma unroll
-        for (int u = 0; u < kZU; ++u) {
-            if (tid + u * kSB < nqr) {
-                const double2 b = s_b[jj * R + zr[u]], yv = s_y[zq[u] * kJCH + jj];
-                z[u].x = fma(b.x, yv.x, fma(b.y, yv.y, z[u].x));
-                z[u].y = fma(b.x, yv.y, fma(-b.y, yv.x, z[u].y));
-            }
+        for (int u = 0; u < kZT; ++u) {
+            const int tile = wave + (kSB / 64) * u;
+            if (tile >= nzt) break;
+            const int q = 16 * (tile / TMr) + m, r = 16 * (tile % TMr) + m;
+            const double2 yv = (q < nq && j < nj) ? s_y[q * kJCH + j] : double2{0.0, 0.0};
+            const double2 bv = (r < R && j < nj) ? s_b[j * R + r] : double2{0.0, 0.0};
+            const double bb = p ? bv.y : bv.x;
+            zre[u] = mfma_16x16x4_f64(p ? yv.y : yv.x, bb, zre[u]);
+            zim[u] = mfma_16x16x4_f64(p ? -yv.x : yv.y, bb, zim[u]);
         }
     }
     __syncthreads();                          // s_b is reused for the products below
     double2* s_p = s_b;                       // [nq][R]: z[q][r] conj(Ahat_{row_q, r})
 #pragma unroll
-    for (int u = 0; u < kZU; ++u) {
-        const int e = tid + u * kSB;
-        if (e < nqr) s_p[e] = dcmulc(z[u], s_x[e]);
+    for (int u = 0; u < kZT; ++u) {
+        const int tile = wave + (kSB / 64) * u;
+        if (tile >= nzt) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = 16 * (tile / TMr) + 4 * i + g, r = 16 * (tile % TMr) + m;
+            if (q < nq && r < R) s_p[q * R + r] = dcmulc(double2{zre[u][i], zim[u][i]}, s_x[q * R + r]);
+        }
     }
     __syncthreads();
     if (tid < R) {

@@ -23,9 +23,9 @@ __device__ __forceinline__ f32x16 mfma_32x32x2(float a, float b, f32x16 c) {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// One 16x16x4 FP64 step (products and sums in FP64), same lane layout as the
-// FP32 16x16x4 step: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16],
-// element i of lane l of D is D[4 (l / 16) + i][l % 16].
+// One 16x16x4 FP64 step (products and sums in FP64).  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] as in the FP32 step, but the output
+// rows interleave differently: element i of lane l of D is D[4 i + l / 16][l % 16].
 __device__ __forceinline__ f64x4 mfma_16x16x4_f64(double a, double b, f64x4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
