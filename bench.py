@@ -100,9 +100,8 @@ def phase_work(n1, n2, r, rows, K):
         "column pass + residual": (c * (2 * P + rows * n2 + a + b) + 4 * rows, 2 * f1 + 8 * P * r, "mfma"),
         "row inverse + A grad": (c * (P + a + b), f2 + 8 * P * r, "mfma"),
         "A update + F_l A": (c * 4 * a, 5 * a * math.log2(n1) + 8 * a, "fp32"),
-        "B grad + update + F_r B": (c * 4 * b, 10 * b * math.log2(n2) + 8 * b, "fp32"),
+        "B update + F_r B + row draw": (c * 4 * b + c * a + 4 * K, 10 * b * math.log2(n2) + 8 * b + 6 * a, "fp32"),
         "output synthesis": (c * (P + a + b), 8 * P * r, "mfma"),
-        "row draw": (c * a + 4 * K, 6 * a, "fp64"),
     }
 
 
@@ -116,9 +115,8 @@ PHASE_KERNELS = {   # kernel of each phase in a table launch of n x n frames
     "column pass + residual": "void k_col_resid<{n}, FrameTable>",
     "row inverse + A grad": "void k_row_inv_grad<{n}, FrameTable>",
     "A update + F_l A": "void k_update_a<{n}, FrameTable>",
-    "B grad + update + F_r B": "void k_update_b<{n}, FrameTable>",
+    "B update + F_r B + row draw": "void k_update_b<{n}, FrameTable>",
     "output synthesis": "void k_synth_out<FrameTable>",
-    "row draw": "void k_sample<FrameTable>",
 }
 COUNTERS = os.path.join(ROOT, "profiles", "step_64x256sq_r32_counters.json")
 

@@ -26,6 +26,10 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs (gfx950 has one register file):
+    # without it, MFMAs under loop-carried control flow get their accumulators
+    # copied into and out of AGPRs around every step
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-fconstexpr-steps=100000000",
     "-Wno-unused-command-line-argument",
     f"-I{INCLUDE}", f"-I{CSRC}",

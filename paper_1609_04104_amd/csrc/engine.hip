@@ -107,7 +107,8 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     return a;
 }
 
-// The phases of one step (Algorithm 3 with one coil, then Algorithm 4's draw).
+// The phases of one step (Algorithm 3 with one coil; Algorithm 4's draw of the
+// next rows runs inside the B-update launch).
 using PhaseFn = hipError_t (*)(const tsl::Batch&, hipStream_t);
 struct Phase {
     PhaseFn fn;
@@ -120,9 +121,8 @@ const Phase kPhases[TSL_N_PHASES] = {
     {tsl::launch_col_resid, "column pass + residual"},     // a5 (columns), a6, a7 (columns)
     {tsl::launch_row_inv_grad, "row inverse + A grad"},    // a7 (rows), a9
     {tsl::launch_update_a, "A update + F_l A"},            // a9, a1
-    {tsl::launch_update_b, "B grad + update + F_r B"},     // a9, a1
+    {tsl::launch_update_b, "B update + F_r B + row draw"}, // a9, a1; a11 in one more block per frame
     {tsl::launch_synth_out, "output synthesis"},           // a10
-    {tsl::launch_sample, "row draw"},                      // a11
 };
 
 // Launches every phase for every group, phase by phase; with `ev` non-null,

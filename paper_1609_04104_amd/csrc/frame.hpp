@@ -33,7 +33,7 @@ constexpr int kSRows = 32;      // sampled rows per (Gram, rhs) partial, line ma
 constexpr int kPRows = 32;      // mask rows per (Gram, rhs) partial, point masks
 constexpr int kJCH = 32;        // readout samples per right-hand-side partial, line masks
 
-__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ constexpr inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ inline int n_gparts(int n) { return cdiv(n, kGRows); }
 __host__ __device__ inline int n_sparts(int n1) { return cdiv(n1, kPRows); }   // >= cdiv(n1, kSRows)
 __host__ __device__ inline int n_jparts(int n2) { return cdiv(n2, kJCH); }

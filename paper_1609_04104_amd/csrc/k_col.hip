@@ -19,6 +19,7 @@
 #include "fft_engine.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
+#include "sampler.hpp"
 
 namespace tsl {
 namespace {
@@ -267,14 +268,23 @@ __global__ void __launch_bounds__(512) k_update_a(Src src) {
 }
 
 // ---------------------------------------------------------------- K4 (B)
+// Blocks [0, gb) of a frame update B; block gb, when present, draws the frame's
+// next rows (Algorithm 4), which needs only F_l A of the new A and so runs
+// beside the B update.  The two roles share one LDS area.
 template <int N2, class Src>
-__global__ void __launch_bounds__(512) k_update_b(Src src) {
+__global__ void __launch_bounds__(512) k_update_b(Src src, int gb) {
     using S = ColShape<N2>;
     constexpr int P = S::P, Q = S::Q, T = S::T;
-    __shared__ float2 s_tw[N2];
-    __shared__ float2 s_x[S::XSIZE];
+    constexpr size_t kUB = (size_t(N2) + S::XSIZE) * sizeof(float2);
+    __shared__ __align__(16) unsigned char s_raw[kUB > sizeof(SampleLds) ? kUB : sizeof(SampleLds)];
     if (!src.live()) return;
     const DevFrame f = src.get();
+    if (src.bx() >= gb) {
+        draw_rows(f, *reinterpret_cast<SampleLds*>(s_raw));
+        return;
+    }
+    float2* s_tw = reinterpret_cast<float2*>(s_raw);
+    float2* s_x = s_tw + N2;
     if (!block_frame_ok(f.dev, true)) return;
     const int R = f.r;
     if (src.bx() * kTW >= R) return;
@@ -384,10 +394,12 @@ template <int N1> hipError_t launch_k4a_n(const Batch& b, hipStream_t st) {
 }
 template <int N2> hipError_t launch_k4b_n(const Batch& b, hipStream_t st) {
     using S = ColShape<N2>;
-    const int gx = cdiv(b.r_max, kTW);
+    const int gb = cdiv(b.r_max, kTW);
+    const int gx = gb + (b.want_sample ? 1 : 0);
+    const int threads = b.want_sample ? std::max(S::THREADS64, kSampleThreads) : S::THREADS;
     const dim3 grid = frame_grid(b, gx);
-    if (b.table) k_update_b<N2, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table, gx, b.count});
-    else k_update_b<N2, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one});
+    if (b.table) k_update_b<N2, FrameTable><<<grid, threads, 0, st>>>(FrameTable{b.table, gx, b.count}, gb);
+    else k_update_b<N2, OneFrame><<<grid, threads, 0, st>>>(OneFrame{*b.one}, gb);
     return hipGetLastError();
 }
 template <int N1>

@@ -12,10 +12,11 @@
 //               majorizer (Sec. III-A; Gershgorin bound of diag(g)^H A^H A diag(g)
 //               and of the B analogue, plus lambda/t), alpha_bar_t and mu_t (eq. 6).
 //  k_synth_out  X_t = A[t] diag(gamma_t) B[t]^T (Sec. IV-A).
-//  k_sample     Algorithm 4 on rows with the score of Sec. VI-C.
+//  k_sample     Algorithm 4 on rows with the score of Sec. VI-C (sampler.hpp).
 #include "fft_engine.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
+#include "sampler.hpp"
 #include "tsl.h"
 
 #include <mutex>
@@ -50,7 +51,9 @@ static_assert(kJCH >= kSRows, "the rhs products reuse the readout-chunk staging 
 // Im = sum Xr_r Xi_s - Xi_r Xr_s are each one 16x16x4 step per two rows; the
 // wavefronts take the 16 x 16 tiles on and above the diagonal.
 __device__ void gram_staged(const double2* s_x, int nq, int R, double2* out) {
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nw = blockDim.x / 64;
+    // wavefront index in a scalar register: uniform tile loops, full exec masks
+    // around the matrix-core steps; operands are read at clamped indices and masked
+    const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), nw = blockDim.x / 64;
     const int m = lane % 16, g = lane / 16;
     const bool p = g & 1;
     const int TM = (R + 15) / 16, ntiles = TM * (TM + 1) / 2;
@@ -61,9 +64,10 @@ __device__ void gram_staged(const double2* s_x, int nq, int R, double2* out) {
         const int ra = 16 * mi + m, sb = 16 * ni + m;
         f64x4 are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
         for (int q0 = 0; q0 < nq; q0 += 2) {
-            const int q = q0 + g / 2;
-            const double2 xa = (q < nq && ra < R) ? s_x[q * R + ra] : double2{0.0, 0.0};
-            const double2 xb = (q < nq && sb < R) ? s_x[q * R + sb] : double2{0.0, 0.0};
+            const int q = q0 + g / 2, qc = min(q, nq - 1);
+            const double2 xa0 = s_x[qc * R + min(ra, R - 1)], xb0 = s_x[qc * R + min(sb, R - 1)];
+            const double2 xa = (q < nq && ra < R) ? xa0 : double2{0.0, 0.0};
+            const double2 xb = (q < nq && sb < R) ? xb0 : double2{0.0, 0.0};
             are = mfma_16x16x4_f64(p ? xa.y : xa.x, p ? xb.y : xb.x, are);
             aim = mfma_16x16x4_f64(p ? -xa.y : xa.x, p ? xb.x : xb.y, aim);
         }
@@ -99,6 +103,7 @@ template <class Src>
 __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     extern __shared__ double2 s_dyn[];
     __shared__ int s_err;
+    __shared__ int s_row[kSRows];
     if (!src.live()) return;
     const DevFrame f = src.get();
     if (!block_frame_ok(f.dev, false)) return;
@@ -120,46 +125,71 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     const int q0 = k * kSRows;
     if (q0 >= n_rows) return;
     const int nq = min(n_rows, q0 + kSRows) - q0;
-    if (c == 0 && tid < nq) {                 // rows inside [0, n1), strictly ascending
-        const int q = q0 + tid, row = f.rows[q];
-        bool ok = row >= 0 && row < n1;
-        if (q + 1 < n_rows) ok = ok && f.rows[q + 1] > row;
-        if (!ok) atomicCAS(&s_err, 0, ST_EINVAL);
-    }
-    auto row_of = [&](int q) {
-        const int row = f.rows[q0 + q];
-        return (row >= 0 && row < n1) ? row : -1;
-    };
     double2* s_x = s_dyn;                     // [kSRows][R]  sampled rows of F_l A
     double2* s_b = s_x + kSRows * R;          // [kJCH][R]    rows of F_r B in the readout chunk
     double2* s_y = s_b + kJCH * R;            // [kSRows][kJCH] samples
     const int j0 = c * kJCH, nj = min(kJCH, n2 - j0);
-    stage_copy<8, float2>(nq * R,
-                          [&](int e) {
-                              const int row = row_of(e / R);
-                              return row >= 0 ? f.Ahat[size_t(row) * R + e % R] : float2{0.f, 0.f};
-                          },
-                          [&](int e, float2 v) { s_x[e] = double2{v.x, v.y}; });
-    stage_copy<8, float2>(nj * R, [&](int e) { return f.Bhat[size_t(j0) * R + e]; },
-                          [&](int e, float2 v) { s_b[e] = double2{v.x, v.y}; });
+    // Staging in two rounds of loads: the readout chunk of F_r B goes out with
+    // the row indices; the sampled rows of F_l A and their samples follow once
+    // the indices are in LDS.
+    constexpr int kBL = cdiv(kJCH * TSL_MAX_R, kSB), kXL = cdiv(kSRows * TSL_MAX_R, kSB);
+    constexpr int kYL = cdiv(kSRows * kJCH, kSB);
+    const int nb = nj * R, nx = nq * R, ny = nq * kJCH;
+    float2 bv[kBL];
+#pragma unroll
+    for (int u = 0; u < kBL; ++u) {
+        const int e = tid + u * kSB;
+        bv[u] = e < nb ? float2(f.Bhat[size_t(j0) * R + e]) : float2{0.f, 0.f};
+    }
+    if (tid < nq) {                           // rows inside [0, n1), strictly ascending
+        const int q = q0 + tid, row = f.rows[q];
+        bool ok = row >= 0 && row < n1;
+        if (c == 0) {
+            if (q + 1 < n_rows) ok = ok && f.rows[q + 1] > row;
+            if (!ok) atomicCAS(&s_err, 0, ST_EINVAL);
+        }
+        s_row[tid] = (row >= 0 && row < n1) ? row : -1;
+    }
+    __syncthreads();
+    float2 xv[kXL], yv[kYL];
+#pragma unroll
+    for (int u = 0; u < kXL; ++u) {
+        const int e = tid + u * kSB;
+        const int row = e < nx ? s_row[e / R] : -1;
+        xv[u] = row >= 0 ? float2(f.Ahat[size_t(row) * R + e % R]) : float2{0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < kYL; ++u) {
+        const int e = tid + u * kSB, q = e / kJCH, jj = e % kJCH;
+        const int row = e < ny ? s_row[q] : -1;
+        yv[u] = (row >= 0 && jj < nj) ? float2(line_samples(f, q0 + q, row)[j0 + jj]) : float2{0.f, 0.f};
+    }
     bool fin = true;
-    stage_copy<4, float2>(nq * kJCH,
-                          [&](int e) {
-                              const int q = e / kJCH, jj = e % kJCH, row = row_of(q);
-                              return (row >= 0 && jj < nj) ? float2(line_samples(f, q0 + q, row)[j0 + jj])
-                                                           : float2{0.f, 0.f};
-                          },
-                          [&](int e, float2 v) {
-                              fin = fin && finite2(v);
-                              s_y[e] = double2{v.x, v.y};
-                          });
+#pragma unroll
+    for (int u = 0; u < kBL; ++u) {
+        const int e = tid + u * kSB;
+        if (e < nb) s_b[e] = double2{bv[u].x, bv[u].y};
+    }
+#pragma unroll
+    for (int u = 0; u < kXL; ++u) {
+        const int e = tid + u * kSB;
+        if (e < nx) s_x[e] = double2{xv[u].x, xv[u].y};
+    }
+#pragma unroll
+    for (int u = 0; u < kYL; ++u) {
+        const int e = tid + u * kSB;
+        if (e < ny) {
+            fin = fin && finite2(yv[u]);
+            s_y[e] = double2{yv[u].x, yv[u].y};
+        }
+    }
     __syncthreads();
     if (c == 0) gram_staged(s_x, nq, R, f.part + size_t(gAB + k) * R * R);
 
     // z[q][r] = sum_j y_qj conj(Bhat_jr) over the chunk on FP64 matrix cores: M = the
     // sampled rows, N = ranks, K = (sample, re/im); Re z = sum yr br + yi bi and
     // Im z = sum yi br - yr bi share the B operand [Re B; Im B].
-    const int lane = tid % 64, wave = tid / 64, m = lane % 16, g = lane / 16;
+    const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64), m = lane % 16, g = lane / 16;
     const bool p = g & 1;
     const int TMq = (nq + 15) / 16, TMr = (R + 15) / 16, nzt = TMq * TMr;
     constexpr int kZT = ((kSRows + 15) / 16 * ((TSL_MAX_R + 15) / 16) + kSB / 64 - 1) / (kSB / 64);
@@ -172,9 +202,10 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
         for (int u = 0; u < kZT; ++u) {
             const int tile = wave + (kSB / 64) * u;
             if (tile >= nzt) break;
-            const int q = 16 * (tile / TMr) + m, r = 16 * (tile % TMr) + m;
-            const double2 yv = (q < nq && j < nj) ? s_y[q * kJCH + j] : double2{0.0, 0.0};
-            const double2 bv = (r < R && j < nj) ? s_b[j * R + r] : double2{0.0, 0.0};
+            const int q = 16 * (tile / TMr) + m, r = 16 * (tile % TMr) + m, jc = min(j, nj - 1);
+            const double2 yv0 = s_y[min(q, nq - 1) * kJCH + jc], bv0 = s_b[jc * R + min(r, R - 1)];
+            const double2 yv = (q < nq && j < nj) ? yv0 : double2{0.0, 0.0};
+            const double2 bv = (r < R && j < nj) ? bv0 : double2{0.0, 0.0};
             const double bb = p ? bv.y : bv.x;
             zre[u] = mfma_16x16x4_f64(p ? yv.y : yv.x, bb, zre[u]);
             zim[u] = mfma_16x16x4_f64(p ? -yv.x : yv.y, bb, zim[u]);
@@ -593,6 +624,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     __shared__ double2 s_g[RB * RB];       // G row-major, then L row-major
     __shared__ double s_m[2][RB * RB];     // |(F_l A)^H F_l A|, |(F_r B)^H F_r B|
     __shared__ double2 s_h[RB];            // h, then gamma
+    __shared__ double2 s_col[64 / RB][RB]; // column k of L during step k, one copy per column group
     __shared__ double s_ag[RB];            // |gamma|
     __shared__ double s_best[kRegBlk / 64];
     __shared__ double s_kappa;
@@ -615,16 +647,24 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     const double2* ps = f.part + gAB * RR;    // slots of the sampled part
     const double lam = f.lambda;
 
-    // Gather.  A slot holds the upper triangle: entry (r, c), r <= c, is G_rc,
-    // so G_ij = conj(entry (j, i)) below the diagonal.
+    // Gather.  A slot holds the upper triangle: entry (r, c), r <= c, is G_rc.
+    // Each thread takes upper entries (packed by rows) and writes both (i, j)
+    // and its conjugate mirror (j, i).
     {
+        constexpr int NU = RB * (RB + 1) / 2;
+        constexpr int U = (NU + kRegBlk - 1) / kRegBlk;   // upper entries per thread
         size_t up[U];
         bool ok[U];
+        int ui[U], uj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = tid + u * kRegBlk, i = e / RB, j = e % RB;
-            ok[u] = e < RB * RB && i < R && j < R;
-            up[u] = ok[u] ? (i <= j ? size_t(i) * R + j : size_t(j) * R + i) : 0;
+            int e = tid + u * kRegBlk, i = 0;
+            if (e < NU)
+                while (e >= RB - i) { e -= RB - i; ++i; }
+            ui[u] = i;
+            uj[u] = i + e;
+            ok[u] = tid + u * kRegBlk < NU && uj[u] < R;
+            up[u] = ok[u] ? size_t(ui[u]) * R + uj[u] : 0;
         }
         // the right-hand side's partials and all three slot ranges of every entry
         // are loaded together (kGatherPF slots of each at a time), then added in
@@ -661,17 +701,22 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = tid + u * kRegBlk, i = e / RB, j = e % RB;
-            if (e >= RB * RB) continue;
+            if (tid + u * kRegBlk >= NU) continue;
+            const int i = ui[u], j = uj[u];
             double2 v{0.0, 0.0};
             if (ok[u]) {
                 v = lines ? dcmul(g[u], mb[u]) : g[u];
-                if (i > j) v.y = -v.y;
                 if (i == j) v = double2{v.x + lam, 0.0};
             }
-            s_g[e] = v;
-            s_m[0][e] = dabs(ma[u]);
-            s_m[1][e] = dabs(mb[u]);
+            const double am = dabs(ma[u]), bm = dabs(mb[u]);
+            s_g[i * RB + j] = v;
+            s_m[0][i * RB + j] = am;
+            s_m[1][i * RB + j] = bm;
+            if (i != j) {
+                s_g[j * RB + i] = double2{v.x, -v.y};
+                s_m[0][j * RB + i] = am;
+                s_m[1][j * RB + i] = bm;
+            }
         }
         if (tid < RB) {
             double2 hv{0.0, 0.0};
@@ -684,51 +729,67 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     __syncthreads();
 
     // Wavefront 0: right-looking Cholesky with the forward substitution fused in
-    // (z_k = h_k / L_kk once h_k has received every earlier column).  The pivot
-    // is the same in every lane, so `fail` is uniform.  Entries above the
-    // diagonal are updated too (never read), which keeps the sweep branch-free.
-    double2 g[RB];
+    // (z_k = h_k / L_kk once h_k has received every earlier column).  Lane l
+    // holds row l % RB of the columns j = NG m + l / RB (NG = 64 / RB column
+    // groups, so all 64 lanes work).  At step k the owner group scales column k
+    // and puts it in LDS; every lane then reads L_ik of its row and L_jk of its
+    // columns from there (a wavefront's LDS accesses complete in order, so no
+    // barrier is needed).  The pivot is the same in every lane, so `fail` is
+    // uniform.  Entries above the diagonal are updated too (never read).
+    constexpr int NG = 64 / RB, CPL = RB / NG;    // column groups, columns per lane
+    double2 g[CPL];
     double2 hv{0.0, 0.0};
-    double dinv = 0.0;                           // 1 / L_{lane, lane}
+    double dinv = 0.0;                            // 1 / L_{i,i}
     if (wave == 0) {
-        const bool live = lane < R;
-        sfor<RB>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            g[j] = live ? s_g[lane * RB + j] : double2{j == lane ? 1.0 : 0.0, 0.0};
+        const int i = lane % RB, h = lane / RB;
+        const bool live = i < R;
+        sfor<CPL>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int j = NG * m + h;
+            g[m] = live ? s_g[i * RB + j] : double2{j == i ? 1.0 : 0.0, 0.0};
         });
-        if (lane < RB) hv = s_h[lane];
+        hv = s_h[i];
         bool fail = false;
         double piv_lo = 1e308, piv_hi = 0.0;
         sfor<RB>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
+            constexpr int ko = k % NG, km = k / NG;
             if (fail) return;
-            const double dkk = readlane_d(g[k].x, k);
+            const double dkk = readlane_d(g[km].x, k + ko * RB);
             if (!(dkk > 0.0) || !isfinite(dkk)) { fail = true; return; }
             const double p = sqrt(dkk), ip = 1.0 / p;
             if (k < R) { piv_lo = fmin(piv_lo, p); piv_hi = fmax(piv_hi, p); }
-            if (lane == k) dinv = ip;
-            g[k] = lane == k ? double2{p, 0.0} : double2{g[k].x * ip, g[k].y * ip};
+            if (i == k) dinv = ip;
+            if (h == ko) g[km] = i == k ? double2{p, 0.0} : double2{g[km].x * ip, g[km].y * ip};
+            s_col[h][i] = g[km];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double2 lik = s_col[ko][i];             // L_ik
             const double2 hk = readlane_d2(hv, k);
             const double2 zk{hk.x * ip, hk.y * ip};
-            if (lane == k) hv = zk;
-            else if (lane > k) {
-                hv.x = fma(-g[k].x, zk.x, fma(g[k].y, zk.y, hv.x));
-                hv.y = fma(-g[k].x, zk.y, fma(-g[k].y, zk.x, hv.y));
+            if (i == k) hv = zk;
+            else if (i > k) {
+                hv.x = fma(-lik.x, zk.x, fma(lik.y, zk.y, hv.x));
+                hv.y = fma(-lik.x, zk.y, fma(-lik.y, zk.x, hv.y));
             }
-            sfor<RB>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                if constexpr (j > k) {
-                    const double2 ljk = readlane_d2(g[k], j);          // L_jk
-                    g[j].x = fma(-g[k].x, ljk.x, fma(-g[k].y, ljk.y, g[j].x));   // - L_ik conj(L_jk)
-                    g[j].y = fma(-g[k].y, ljk.x, fma(g[k].x, ljk.y, g[j].y));
+            sfor<CPL>([&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                if constexpr (NG * m + NG - 1 > k) {
+                    const int j = NG * m + h;
+                    const double2 ljk = s_col[ko][j];     // L_jk
+                    const double2 upd{fma(-lik.x, ljk.x, fma(-lik.y, ljk.y, g[m].x)),
+                                      fma(-lik.y, ljk.x, fma(lik.x, ljk.y, g[m].y))};   // - L_ik conj(L_jk)
+                    if constexpr (NG * m > k) g[m] = upd;
+                    else if (j > k) g[m] = upd;
                 }
             });
         });
-        if (lane < RB)
-            sfor<RB>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                s_g[lane * RB + j] = j <= lane ? g[j] : double2{0.0, 0.0};
-            });
+        sfor<CPL>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int j = NG * m + h;
+            s_g[i * RB + j] = j <= i ? g[m] : double2{0.0, 0.0};
+        });
         if (lane == 0) {
             s_fail = fail ? ST_ENOTPD : 0;
             s_kappa = (piv_hi / piv_lo) * (piv_hi / piv_lo);
@@ -879,153 +940,12 @@ __global__ void __launch_bounds__(256) k_synth_out(Src src) {
 }
 
 // ---------------------------------------------------------------- sampler
-__device__ __forceinline__ void philox4x64_10(uint64_t (&x)[4], uint64_t k0, uint64_t k1) {
-    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint64_t lo0 = M0 * x[0], hi0 = __umul64hi(M0, x[0]);
-        const uint64_t lo1 = M1 * x[2], hi1 = __umul64hi(M1, x[2]);
-        const uint64_t y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
-        x[0] = y0;
-        x[1] = lo1;
-        x[2] = y2;
-        x[3] = lo0;
-        k0 += W0;
-        k1 += W1;
-    }
-}
-
-constexpr int kSampleStage = 8192;   // factor entries staged per pass (64 KiB)
-
+// The draw on its own (tsl_sample_lines); a step draws inside the B-update launch.
 template <class Src>
-__global__ void __launch_bounds__(256) k_sample(Src src) {
-#pragma clang fp contract(off)
-    extern __shared__ float2 s_a[];              // staged rows of F_l A (kSampleStage entries)
-    __shared__ double s_pref[kMaxN];             // weights, then their inclusive prefix
-    __shared__ double s_c[TSL_MAX_R];
-    __shared__ int s_mark[kMaxN];
+__global__ void __launch_bounds__(kSampleThreads) k_sample(Src src) {
+    __shared__ SampleLds s_l;
     if (!src.live()) return;
-    const DevFrame f = src.get();
-    const int K = f.K_next;
-    if (K <= 0) return;
-    const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
-    const int chunk = kSampleStage / R;          // rows per staged pass
-    // pass 1: column energies ||ahat_r||^2, each summed in row order
-    double acc = 0.0;
-    for (int i0 = 0; i0 < n1; i0 += chunk) {
-        const int ni = min(chunk, n1 - i0);
-        __syncthreads();
-        stage_copy<32, float2>(ni * R, [&](int e) { return f.Ahat[size_t(i0) * R + e]; },
-                               [&](int e, float2 v) { s_a[e] = v; });
-        __syncthreads();
-        if (tid < R) {
-            int i = 0;
-            for (; i + 8 <= ni; i += 8) {          // loads batched; additions still in row order
-                float2 a[8];
-#pragma unroll
-                for (int w = 0; w < 8; ++w) a[w] = s_a[(i + w) * R + tid];
-#pragma unroll
-                for (int w = 0; w < 8; ++w) {
-                    const double ax = a[w].x, ay = a[w].y;
-                    const double e = ax * ax + ay * ay;
-                    acc = acc + e;
-                }
-            }
-            for (; i < ni; ++i) {
-                const float2 a = s_a[i * R + tid];
-                const double ax = a.x, ay = a.y;
-                const double e = ax * ax + ay * ay;
-                acc = acc + e;
-            }
-        }
-    }
-    if (tid < R) s_c[tid] = acc;
-    // pass 2: w_i = N2 ||abar_i||^2 + R, each summed in column order (the staged
-    // rows are still in LDS when the whole factor fits in one pass)
-    for (int i0 = 0; i0 < n1; i0 += chunk) {
-        const int ni = min(chunk, n1 - i0);
-        __syncthreads();
-        if (chunk < n1)
-            stage_copy<8, float2>(ni * R, [&](int e) { return f.Ahat[size_t(i0) * R + e]; },
-                                  [&](int e, float2 v) { s_a[e] = v; });
-        __syncthreads();
-        for (int il = tid; il < ni; il += blockDim.x) {
-            const int i = i0 + il;
-            double q = 0.0;
-            for (int r = 0; r < R; ++r) {
-                const double c = s_c[r];
-                if (c > 0.0) {
-                    const float2 a = s_a[il * R + r];
-                    const double ax = a.x, ay = a.y;
-                    const double e = ax * ax + ay * ay;
-                    q = q + e / c;
-                }
-            }
-            double w = double(n2) * q;
-            w = w + double(R);
-            s_pref[i] = w;
-            s_mark[i] = 0;
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {                        // sequential in i, loads batched by 8
-        double run = 0.0;
-        int i = 0;
-        for (; i + 8 <= n1; i += 8) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = s_pref[i + u];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                run = run + v[u];
-                v[u] = run;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s_pref[i + u] = v[u];
-        }
-        for (; i < n1; ++i) {
-            run = run + s_pref[i];
-            s_pref[i] = run;
-        }
-    }
-    __syncthreads();
-    const double W = s_pref[n1 - 1];
-    const uint64_t t_next = uint64_t(f.dev->t + 1);
-    for (int k = tid; k < K; k += blockDim.x) {
-        uint64_t x[4] = {t_next, uint64_t(k), 0ull, 0ull};
-        philox4x64_10(x, f.seed, f.sid);
-        const double u = double(x[0] >> 11) * 0x1.0p-53;
-        const double target = u * W;
-        int lo = 0, hi = n1;               // first i with target < prefix[i]
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (target < s_pref[mid]) hi = mid; else lo = mid + 1;
-        }
-        const int idx = lo < n1 ? lo : n1 - 1;
-        if (f.draws_next) f.draws_next[k] = idx;
-        s_mark[idx] = 1;
-    }
-    __syncthreads();
-    // ascending distinct rows: thread tid owns rows [2 tid, 2 tid + 2); exclusive
-    // scan of the per-thread counts (integers, so any order is exact)
-    const int i0 = 2 * tid;
-    const int m0 = (i0 < n1) ? s_mark[i0] : 0, m1 = (i0 + 1 < n1) ? s_mark[i0 + 1] : 0;
-    __shared__ int s_scan[kBlock];
-    s_scan[tid] = m0 + m1;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const int v = tid >= off ? s_scan[tid - off] : 0;
-        __syncthreads();
-        s_scan[tid] += v;
-        __syncthreads();
-    }
-    const int base = s_scan[tid] - (m0 + m1);
-    if (m0) f.rows_next[base] = i0;
-    if (m1) f.rows_next[base + m0] = i0 + 1;
-    if (tid == kBlock - 1) f.n_next[0] = s_scan[tid];
-    if (f.prefix_next)
-        for (int i = tid; i < n1; i += blockDim.x) f.prefix_next[i] = s_pref[i];
+    draw_rows(src.get(), s_l);
 }
 
 // packed factor, right-hand side / gamma, then 1/L_kk and |gamma_r| (R doubles each)
@@ -1046,11 +966,6 @@ void init_kernel_attributes() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, ml);
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lstats<OneFrame>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, ml);
-        const int mr = int(size_t(kSampleStage) * sizeof(float2));
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sample<FrameTable>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mr);
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sample<OneFrame>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mr);
         const int mv = int(solve_lds(TSL_MAX_R));
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve<FrameTable>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, mv);
@@ -1109,9 +1024,8 @@ hipError_t launch_sample(const Batch& b, hipStream_t st) {
     if (!b.want_sample) return hipSuccess;
     const int gx = 1;
     const dim3 grid = frame_grid(b, gx);
-    const size_t lds = size_t(kSampleStage) * sizeof(float2);
-    if (b.table) k_sample<FrameTable><<<grid, kBlock, lds, st>>>(FrameTable{b.table, gx, b.count});
-    else k_sample<OneFrame><<<grid, kBlock, lds, st>>>(OneFrame{*b.one});
+    if (b.table) k_sample<FrameTable><<<grid, kSampleThreads, 0, st>>>(FrameTable{b.table, gx, b.count});
+    else k_sample<OneFrame><<<grid, kSampleThreads, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 

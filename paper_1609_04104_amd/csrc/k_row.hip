@@ -86,7 +86,9 @@ __global__ void __launch_bounds__(kRowBlock) k_synth_rowfft(Src src) {
     const int tid = threadIdx.x, s = tid % T, rl = tid / T;
     const int i = src.bx() * ROWS + rl;
     const bool live = rl < ROWS && i < n1;
-    const int lane = tid % 64, wave = tid / 64, m = lane % 16, g = lane / 16;
+    // the wavefront index in a scalar register, so that tile loops branch uniformly
+    // and the matrix-core steps never run under a partial exec mask
+    const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64), m = lane % 16, g = lane / 16;
     const int i0 = src.bx() * ROWS;
     load_tw<N2>(s_tw);
 
@@ -123,8 +125,8 @@ __global__ void __launch_bounds__(kRowBlock) k_synth_rowfft(Src src) {
                     if (tile >= RT::MT * RT::NT) break;
                     const int mt = tile / RT::NT, nt = tile % RT::NT, j = 16 * nt + m;
                     const float2 a = s_ag[(16 * mt + m) * kSynBP + c];
-                    const float2 b = j < N2 ? s_b[j * kSynBP + c] : float2{0.f, 0.f};
-                    const float bv = im ? b.y : b.x;
+                    const float2 b = s_b[(j < N2 ? j : N2 - 1) * kSynBP + c];   // clamped, then masked
+                    const float bv = j < N2 ? (im ? b.y : b.x) : 0.f;
                     accr[u] = mfma_16x16x4(im ? -a.y : a.x, bv, accr[u]);
                     acci[u] = mfma_16x16x4(im ? a.x : a.y, bv, acci[u]);
                 }

@@ -1,0 +1,253 @@
+// Informative line sampling (Algorithm 4 on rows, with the row score of
+// Sec. VI-C) for one frame, run by one block of at least kSampleThreads threads.
+// Used by the standalone draw kernel and by the extra block per frame of the
+// B-update launch, which runs beside the B update (the draw reads F_l A of
+// the new A only).
+//
+// Row weight w_i = N2 ||abar_i||^2 + R where abar_i is row i of F_l A with
+// every column of nonzero norm normalised (a zero column is left out); K
+// trials with replacement, trial k taking u_k = (first Philox4x64-10 word at
+// counter (t+1, k, 0, 0), key (seed, stream id)) >> 11, times 2^-53, and
+// drawing the first row whose inclusive weight prefix exceeds u_k W (W the
+// computed total, the last row if none).  Every sum runs in index order in
+// FP64 without fused multiply-adds, so the rows drawn match any IEEE
+// implementation of the same order bit for bit.
+#pragma once
+
+#include "frame.hpp"
+#include "tsl.h"
+
+namespace tsl {
+
+constexpr int kSampleThreads = 256;   // threads that work on a draw (a bigger block idles the rest)
+constexpr int kUPre = 256;            // uniforms computed beside the prefix sum
+constexpr int kChunk = 2048;          // factor entries (or row terms) per staged chunk of rows (16 KiB)
+constexpr int kChunkLoads = kChunk / kSampleThreads;   // loads per thread that cover one chunk
+constexpr int kBatch = 8;             // LDS loads a sequential sum keeps one batch ahead
+// The staging area is padded so that every load and store of a chunk can be
+// unconditional: a row-term chunk at pitch R | 1 ends before 3 kChunk / 2, and
+// the column sums read at most one batch of rows past a chunk; the prefix
+// reads and writes at most two batches past n1.
+constexpr int kBuf = (3 * kChunk / 2 > kChunk + kBatch * TSL_MAX_R) ? 3 * kChunk / 2 : kChunk + kBatch * TSL_MAX_R;
+
+struct alignas(16) SampleLds {
+    double pref[kMaxN + 2 * kBatch];  // weights, then their inclusive prefix (padded)
+    double c[TSL_MAX_R];              // column energies
+    double u[kUPre];                  // u_k for k < kUPre
+    double buf[kBuf];                 // a chunk of energies E_ir, then of row terms
+    int mark[kMaxN];
+    int wcount[kMaxN / 64];
+};
+
+// Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64 x 64 -> 128-bit
+// products with the published multipliers and Weyl key increments.
+__device__ __forceinline__ void philox4x64_10(uint64_t (&x)[4], uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t lo0 = M0 * x[0], hi0 = __umul64hi(M0, x[0]);
+        const uint64_t lo1 = M1 * x[2], hi1 = __umul64hi(M1, x[2]);
+        const uint64_t y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
+        x[0] = y0;
+        x[1] = lo1;
+        x[2] = y2;
+        x[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+__device__ __forceinline__ double uniform_trial(uint64_t t, int k, uint64_t seed, uint64_t sid) {
+    uint64_t x[4] = {t, uint64_t(k), 0ull, 0ull};
+    philox4x64_10(x, seed, sid);
+    return double(x[0] >> 11) * 0x1.0p-53;
+}
+
+// Squared magnitude in FP64 (both products exact, one rounding in the sum).
+__device__ __forceinline__ double energy(float2 a) {
+#pragma clang fp contract(off)
+    const double ax = a.x, ay = a.y;
+    return ax * ax + ay * ay;
+}
+
+__device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
+#pragma clang fp contract(off)
+    const int K = f.K_next;
+    if (K <= 0) return;
+    const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x, nt = blockDim.x;
+    const bool worker = tid < kSampleThreads;        // whole wavefronts
+    GlobalPtr<const float2> Ah = f.Ahat;
+    const uint64_t t_next = uint64_t(f.dev->t + 1);
+
+    // Rows of F_l A come in chunks of ck rows: coalesced loads into registers
+    // (the index clamped into the factor, zero past the end), then LDS.  The
+    // next chunk's loads are in flight while the current one is consumed.
+    float2 a[kChunkLoads];
+    auto load_chunk = [&](int i0, int ck) {
+        const int ne = min(ck, n1 - i0) * R;
+#pragma unroll
+        for (int u = 0; u < kChunkLoads; ++u) {
+            const int e = tid + u * kSampleThreads;
+            const float2 v = Ah[size_t(i0) * R + min(e, ne - 1)];
+            a[u] = e < ne ? v : float2{0.f, 0.f};
+        }
+    };
+
+    // 1. Column energies c_r = sum_i E_ir in row order, one column per lane of
+    //    wavefront 0 (64 columns per sweep).  The whole block computes a
+    //    chunk's energies into LDS, so the summing wavefront only loads and
+    //    adds.  A chunk holds a multiple of kBatch rows; rows past n1 are zero,
+    //    and adding +0 leaves a nonnegative sum unchanged.
+    {
+        const int ck = min((kChunk / R) / kBatch * kBatch, cdiv(n1, kBatch) * kBatch);
+        for (int r0 = 0; r0 < R; r0 += 64) {
+            const int r = min(r0 + tid, R - 1);
+            double acc = 0.0;
+            if (worker) load_chunk(0, ck);
+            for (int i0 = 0; i0 < n1; i0 += ck) {
+                if (worker) {
+#pragma unroll
+                    for (int u = 0; u < kChunkLoads; ++u) L.buf[tid + u * kSampleThreads] = energy(a[u]);
+                }
+                __syncthreads();
+                if (worker && i0 + ck < n1) load_chunk(i0 + ck, ck);
+                if (tid < 64) {
+                    const int nb = min(ck, n1 - i0);
+                    double cur[kBatch], nxt[kBatch];
+#pragma unroll
+                    for (int w = 0; w < kBatch; ++w) cur[w] = L.buf[w * R + r];
+                    for (int il = 0; il < nb; il += kBatch) {
+#pragma unroll
+                        for (int w = 0; w < kBatch; ++w) nxt[w] = L.buf[(il + kBatch + w) * R + r];
+#pragma unroll
+                        for (int w = 0; w < kBatch; ++w) acc = acc + cur[w];
+#pragma unroll
+                        for (int w = 0; w < kBatch; ++w) cur[w] = nxt[w];
+                    }
+                }
+                __syncthreads();
+            }
+            if (tid < 64 && r0 + tid < R) L.c[r0 + tid] = acc;
+        }
+    }
+    for (int i = tid; i < n1; i += nt) L.mark[i] = 0;
+    __syncthreads();
+
+    // 2. w_i = N2 q_i + R with q_i = sum_r E_ir / c_r in column order: the block
+    //    turns a chunk into terms (zero for a zero column, which leaves q
+    //    unchanged) at an odd row pitch in LDS, then one thread per row adds
+    //    its terms up in order.
+    {
+        const int pitch = R | 1;
+        const int ck = min(kChunk / R, n1);
+        if (worker) load_chunk(0, ck);
+        for (int i0 = 0; i0 < n1; i0 += ck) {
+            const int ni = min(ck, n1 - i0);
+            if (worker) {
+#pragma unroll
+                for (int u = 0; u < kChunkLoads; ++u) {
+                    const int e = tid + u * kSampleThreads, r = e % R;
+                    const double c = L.c[r];
+                    const double q = energy(a[u]) / (c > 0.0 ? c : 1.0);
+                    L.buf[(e / R) * pitch + r] = c > 0.0 ? q : 0.0;
+                }
+            }
+            __syncthreads();
+            if (worker && i0 + ck < n1) load_chunk(i0 + ck, ck);
+            for (int il = tid; il < ni; il += nt) {
+                const double* tr = L.buf + il * pitch;
+                double q = 0.0;
+                int r = 0;
+                for (; r + kBatch <= R; r += kBatch) {
+                    double v[kBatch];
+#pragma unroll
+                    for (int w = 0; w < kBatch; ++w) v[w] = tr[r + w];
+#pragma unroll
+                    for (int w = 0; w < kBatch; ++w) q = q + v[w];
+                }
+                for (; r < R; ++r) q = q + tr[r];
+                double w = double(n2) * q;
+                w = w + double(R);
+                L.pref[i0 + il] = w;
+            }
+            __syncthreads();
+        }
+    }
+
+    // 3. Inclusive prefix in row order (one thread, loads a batch ahead; the
+    //    padded tail is read and written but never used); meanwhile the other
+    //    wavefronts draw the first kUPre uniforms.
+    if (tid >= 64) {
+        const int kp = min(K, kUPre);
+        for (int k = tid - 64; k < kp; k += nt - 64) L.u[k] = uniform_trial(t_next, k, f.seed, f.sid);
+    }
+    if (tid == 0) {
+        double2* p2 = reinterpret_cast<double2*>(L.pref);
+        constexpr int kH = kBatch / 2;
+        double run = 0.0;
+        double2 cur[kH], nxt[kH];
+#pragma unroll
+        for (int w = 0; w < kH; ++w) cur[w] = p2[w];
+        for (int h0 = 0; h0 < cdiv(n1, 2); h0 += kH) {
+#pragma unroll
+            for (int w = 0; w < kH; ++w) nxt[w] = p2[h0 + kH + w];
+#pragma unroll
+            for (int w = 0; w < kH; ++w) {
+                run = run + cur[w].x;
+                cur[w].x = run;
+                run = run + cur[w].y;
+                cur[w].y = run;
+            }
+#pragma unroll
+            for (int w = 0; w < kH; ++w) p2[h0 + w] = cur[w];
+#pragma unroll
+            for (int w = 0; w < kH; ++w) cur[w] = nxt[w];
+        }
+    }
+    __syncthreads();
+
+    // 4. Trials: first row whose prefix exceeds u_k W.
+    const double W = L.pref[n1 - 1];
+    for (int k = tid; k < K; k += nt) {
+        const double u = k < kUPre ? L.u[k] : uniform_trial(t_next, k, f.seed, f.sid);
+        const double target = u * W;
+        int lo = 0, hi = n1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (target < L.pref[mid]) hi = mid; else lo = mid + 1;
+        }
+        const int idx = lo < n1 ? lo : n1 - 1;
+        if (f.draws_next) f.draws_next[k] = idx;
+        L.mark[idx] = 1;
+    }
+    __syncthreads();
+
+    // 5. The distinct rows in ascending order: per 64-row word a ballot, its
+    //    population count gives the word's offset, the lane's rank inside the
+    //    word its position (integers, so the result is exact).
+    const int nw = cdiv(n1, 64), lane = tid % 64;
+    for (int wd = tid / 64; wd < nw; wd += nt / 64) {
+        const int i = wd * 64 + lane;
+        const unsigned long long m = __ballot(i < n1 && L.mark[i]);
+        if (lane == 0) L.wcount[wd] = __popcll(m);
+    }
+    __syncthreads();
+    for (int wd = tid / 64; wd < nw; wd += nt / 64) {
+        const int i = wd * 64 + lane;
+        const bool on = i < n1 && L.mark[i];
+        const unsigned long long m = __ballot(on);
+        int base = 0;
+        for (int v = 0; v < wd; ++v) base += L.wcount[v];
+        if (on) f.rows_next[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    }
+    if (tid == 0) {
+        int total = 0;
+        for (int v = 0; v < nw; ++v) total += L.wcount[v];
+        f.n_next[0] = total;
+    }
+    if (f.prefix_next)
+        for (int i = tid; i < n1; i += nt) f.prefix_next[i] = L.pref[i];
+}
+
+}  // namespace tsl

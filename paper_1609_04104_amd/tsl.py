@@ -41,9 +41,9 @@ class Opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64)]
 
 
-N_PHASES = 9
+N_PHASES = 8
 PHASES = ["partial Grams", "ridge solve + step size", "synthesis + row pass", "column pass + residual",
-          "row inverse + A grad", "A update + F_l A", "B grad + update + F_r B", "output synthesis", "row draw"]
+          "row inverse + A grad", "A update + F_l A", "B update + F_r B + row draw", "output synthesis"]
 
 
 class Frame(ctypes.Structure):
