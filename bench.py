@@ -59,6 +59,10 @@ def parse():
                     help="offered-load factors: arrival rate and frame rate (30/s) both times the factor")
     ap.add_argument("--serve-limit", type=float, default=20.0, help="wall-time cap per served run (s)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--route", choices=["kspace", "frame"], default="kspace",
+                    help="line-mask route of the headline measurement")
+    ap.add_argument("--frame-route-steps", type=int, default=20,
+                    help="steps of the same batch on the frame route (0: skip that leg)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -83,12 +87,13 @@ def make_inputs(seqs, n, r, frames, procs=16):
 
 
 # ----------------------------------------------------------------------------- work model
-def phase_work(n1, n2, r, rows, K):
+def phase_work(n1, n2, r, rows, K, kspace=True):
     """Algorithmic bytes, flops and arithmetic kind per frame of each phase
     (complex64 = 8 B, complex128 = 16 B, complex MAC = 8 flop, length-N complex
     FFT = 5 N log2 N flop).  Bytes are the phase's inputs and outputs, not the
     implementation's partial sums; kinds: fp64 (FP64 vector), mfma (FP32 matrix
-    cores, with the transforms' FP32 vector work counted in), fp32 (FP32 vector)."""
+    cores, with the transforms' FP32 vector work counted in), fp32 (FP32 vector).
+    On the k-space route the A update also applies F_l^H to E conj(Bhat)."""
     P, c = n1 * n2, 8
     f1, f2 = 5 * P * math.log2(n1), 5 * P * math.log2(n2)
     a, b = n1 * r, n2 * r
@@ -99,7 +104,9 @@ def phase_work(n1, n2, r, rows, K):
         "synthesis + row pass": (c * (P + a + b), 8 * P * r + f2, "mfma"),
         "column pass + residual": (c * (2 * P + rows * n2 + a + b) + 4 * rows, 2 * f1 + 8 * P * r, "mfma"),
         "row inverse + A grad": (c * (P + a + b), f2 + 8 * P * r, "mfma"),
-        "A update + F_l A": (c * 4 * a, 5 * a * math.log2(n1) + 8 * a, "fp32"),
+        "k-space residual + gradients": (c * (rows * n2 + 2 * rows * r + 2 * b) + 4 * rows,
+                                         3 * 8 * rows * n2 * r, "mfma"),
+        "A update + F_l A": (c * 4 * a, (10 if kspace else 5) * a * math.log2(n1) + 8 * a, "fp32"),
         "B update + F_r B + row draw": (c * 4 * b + c * a + 4 * K, 10 * b * math.log2(n2) + 8 * b + 6 * a, "fp32"),
         "output synthesis": (c * (P + a + b), 8 * P * r, "mfma"),
     }
@@ -114,6 +121,7 @@ PHASE_KERNELS = {   # kernel of each phase in a table launch of n x n frames
     "synthesis + row pass": "void k_synth_rowfft<{n}, FrameTable>",
     "column pass + residual": "void k_col_resid<{n}, FrameTable>",
     "row inverse + A grad": "void k_row_inv_grad<{n}, FrameTable>",
+    "k-space residual + gradients": "void k_kres<FrameTable>",
     "A update + F_l A": "void k_update_a<{n}, FrameTable>",
     "B update + F_r B + row draw": "void k_update_b<{n}, FrameTable>",
     "output synthesis": "void k_synth_out<FrameTable>",
@@ -262,10 +270,10 @@ def main():
     full = torch.arange(n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
-    def open_seq(s):
+    def open_seq(s, route=a.route):
         A0, B0 = data[s][1], data[s][2]
         return tsl.Sequence(n, n, r, lam, torch.from_numpy(A0).to(dev), torch.from_numpy(B0).to(dev),
-                            seed=1609, stream_id=s)
+                            seed=1609, stream_id=s, route=route)
 
     # ------------------------------------------------------------------ batched
     seqs = [open_seq(s) for s in range(S)]
@@ -283,7 +291,7 @@ def main():
         t += 1
     phase_ms = [x / a.phase_steps for x in phase_ms]
     mean_rows = float(np.mean([int(cnt[t % 2][i].item()) for i in range(S)]))
-    work = phase_work(n, n, r, mean_rows, K)
+    work = phase_work(n, n, r, mean_rows, K, kspace=a.route == "kspace")
     dom = int(np.argmax(phase_ms))
     dname = tsl.PHASES[dom]
     dbytes, dflops, kind = work[dname]
@@ -305,6 +313,26 @@ def main():
     roof["avg_launch_ms"] = phase_ms[dom]
     for q in seqs:
         q.close()
+
+    # ------------------------------------------------------------------ the same batch on the other route
+    other = "frame" if a.route == "kspace" else "kspace"
+    other_leg = None
+    if a.frame_route_steps > 0:
+        oseqs = [open_seq(s, other) for s in range(S)]
+        odrv = BatchDriver(tsl, torch, oseqs, Kd, [K] * S, warm, dev)
+        ores = time_steps(odrv, a.warmup, a.frame_route_steps, stream, torch, f"{other} route")
+        ophase = [0.0] * tsl.N_PHASES
+        ot = ores["t"]
+        for _ in range(a.phase_steps):
+            ophase = tsl.step_many_timed(oseqs, odrv.frames_for(ot), ophase, stream)
+            ot += 1
+        other_leg = {"route": other, "frames_per_s": S * 1000.0 / ores["ms_per_step"],
+                     "ms_per_step": ores["ms_per_step"],
+                     "phases_ms": {name: ophase[i] / a.phase_steps for i, name in enumerate(tsl.PHASES)}}
+        bad += [q for q in oseqs if q.status() != 0]
+        for q in oseqs:
+            q.close()
+        print(f"[bench] {other} route {other_leg['frames_per_s']:.0f} frames/s", file=sys.stderr, flush=True)
 
     # ------------------------------------------------------------------ plain
     q = open_seq(0)
@@ -372,6 +400,7 @@ def main():
                         f"= one frame of every sequence through the whole step incl. the next-row draw",
             "sequences": S, "n1": n, "n2": n, "r": r, "lambda": lam, "K": K,
             "precision": "complex FP32 frame path, FP64 RxR statistics and solve",
+            "line_route": a.route,
         },
         "latency_ms": {"batched_p50": pct(step_ms, 50), "batched_p99": pct(step_ms, 99),
                        "plain_p50": pct(plain_ms, 50), "plain_p99": pct(plain_ms, 99),
@@ -381,6 +410,8 @@ def main():
                            "served_plain_p99": served["loads"][0]["plain"]["latency_p99_ms"]}
                           if served else {})},
         "plain": {"frames_per_s": plain_fps, "ms_per_frame": 1e3 / plain_fps},
+        "route": a.route,
+        "other_route": other_leg,
         "mixed": mixed,
         "serving": served,
         "batched_over_plain": value / plain_fps,

@@ -72,6 +72,20 @@ enum {
 
 enum { TSL_STEP_MM = 0, TSL_STEP_CONST = 1 };
 
+/* How a line-mask frame evaluates the residual and the back-projected
+   gradients (Sec. IV-B; point masks always take the frame route).
+   TSL_ROUTE_KSPACE: on the sampled rows only.  With the separable transform
+   F(X) = F_l X F_r^T, the k-space prediction at the samples is
+   Ahat_S diag(gamma) Bhat^T (Ahat = F_l A, Bhat = F_r B), and Theta =
+   F^{-1}(Xi) = sum over samples of e_l times the conjugate sampling matrix,
+   so Theta conj(B) = F_l^H [rows S: E conj(Bhat)] and Theta^T conj(A) =
+   F_r^H (E^T conj(Ahat_S)), E the |S| x n2 residual.  Same quantities as the
+   frame route up to rounding, without frame-sized intermediates.
+   TSL_ROUTE_FRAME: synthesis A diag(gamma) B^T, the 2-D transform, the masked
+   residual, the inverse 2-D transform Theta, and Theta's contractions with
+   conj(B) and conj(A), all frame-sized. */
+enum { TSL_ROUTE_KSPACE = 0, TSL_ROUTE_FRAME = 1 };
+
 typedef struct {
     int      step_mode;      /* TSL_STEP_MM: mu_t = 1/alpha_bar_t, the recursion of
                                 eq. (6) (default).  TSL_STEP_CONST: mu_t = mu.       */
@@ -79,10 +93,11 @@ typedef struct {
     int      allow_lambda0;  /* accept lambda == 0 (tests of exact recovery)          */
     uint64_t seed;           /* sampler key word 0 (Philox4x64-10)                    */
     uint64_t stream_id;      /* sampler key word 1                                    */
+    int      line_route;     /* TSL_ROUTE_KSPACE (default) or TSL_ROUTE_FRAME          */
 } tsl_opts;
 
 /* Number of timed phases reported by tsl_step_many_timed. */
-#define TSL_N_PHASES 8
+#define TSL_N_PHASES 9
 
 /* One frame of one sequence, for tsl_push_frame and tsl_step_many.  `mask`
    non-NULL selects a point mask (see tsl_push_points); otherwise the sample
@@ -181,8 +196,10 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
 /* Profiling form of tsl_step_many: runs the same kernels without a graph,
    brackets each of the TSL_N_PHASES phases (partial Grams; solve and step
    size; synthesis + row transform; column transform + residual + column
-   inverse; row inverse + A gradient; A update + F_l A; B gradient + update +
-   F_r B beside the row draw; output synthesis) with HIP events on `stream`, waits, and
+   inverse; row inverse + A gradient [these three: frame route]; k-space
+   residual + gradient contractions [k-space route]; A update + F_l A; B
+   gradient + update + F_r B beside the row draw; output synthesis) with HIP
+   events on `stream`, waits, and
    ADDS each phase's elapsed milliseconds to phase_ms[TSL_N_PHASES] (host). */
 int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, double* phase_ms,
                         void* stream);

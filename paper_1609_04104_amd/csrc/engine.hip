@@ -37,7 +37,7 @@ int hip_fail(hipError_t e, const char* what) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, part, hpart, total;
+    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, wpart, part, hpart, total;
 };
 
 Layout layout_for(int n1, int n2, int r) {
@@ -54,6 +54,7 @@ Layout layout_for(int n1, int n2, int r) {
     L.frame = take(size_t(n1) * n2 * sizeof(float2));
     L.Wb = take(size_t(n2) * r * sizeof(float2));
     L.GA = take(size_t(n1) * r * sizeof(float2));
+    L.wpart = take(size_t(tsl::n_qparts(n1)) * n2 * r * sizeof(float2));
     L.part = take(size_t(tsl::n_parts(n1, n2)) * r * r * sizeof(double2));
     L.hpart = take(size_t(tsl::n_hparts(n1, n2)) * r * sizeof(double2));
     L.total = o;
@@ -88,6 +89,7 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     tsl::FrameArgs a{};
     a.n1 = s->n1; a.n2 = s->n2; a.r = s->r;
     a.mode = fr.mask ? tsl::MODE_POINTS : tsl::MODE_LINES;
+    a.kspace = (!fr.mask && s->opts.line_route == TSL_ROUTE_KSPACE) ? 1 : 0;
     a.lambda = s->lambda; a.mu_const = s->opts.mu; a.step_mode = s->opts.step_mode;
     a.n_rows = fr.mask ? 0 : fr.n_rows;
     a.A = s->at<float2>(s->lay.A); a.B = s->at<float2>(s->lay.B);
@@ -95,6 +97,7 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     a.dev = s->at<tsl::SeqDev>(s->lay.dev);
     a.gamma64 = s->at<double2>(s->lay.g64); a.gamma32 = s->at<float2>(s->lay.g32);
     a.frame = s->at<float2>(s->lay.frame); a.Wb = s->at<float2>(s->lay.Wb); a.GA = s->at<float2>(s->lay.GA);
+    a.wpart = s->at<float2>(s->lay.wpart);
     a.part = s->at<double2>(s->lay.part); a.hpart = s->at<double2>(s->lay.hpart);
     a.rows = fr.rows; a.n_rows_dev = fr.mask ? nullptr : fr.n_rows_dev; a.y_full = fr.y_full ? 1 : 0;
     a.mask = fr.mask; a.y = reinterpret_cast<const float2*>(fr.y);
@@ -108,7 +111,8 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
 }
 
 // The phases of one step (Algorithm 3 with one coil; Algorithm 4's draw of the
-// next rows runs inside the B-update launch).
+// next rows runs inside the B-update launch).  A group runs either the three
+// frame-route phases or the k-space one; the other launchers return at once.
 using PhaseFn = hipError_t (*)(const tsl::Batch&, hipStream_t);
 struct Phase {
     PhaseFn fn;
@@ -120,6 +124,7 @@ const Phase kPhases[TSL_N_PHASES] = {
     {tsl::launch_synth_rowfft, "synthesis + row pass"},    // a4, a5 (rows)
     {tsl::launch_col_resid, "column pass + residual"},     // a5 (columns), a6, a7 (columns)
     {tsl::launch_row_inv_grad, "row inverse + A grad"},    // a7 (rows), a9
+    {tsl::launch_kres, "k-space residual + gradients"},    // a4-a7 and a9's contractions on the samples
     {tsl::launch_update_a, "A update + F_l A"},            // a9, a1
     {tsl::launch_update_b, "B update + F_r B + row draw"}, // a9, a1; a11 in one more block per frame
     {tsl::launch_synth_out, "output synthesis"},           // a10
@@ -167,7 +172,7 @@ int set_dev(const tsl_seq* s) {
 // -------------------------------------------------------------- batched step state
 struct GroupKey {
     int n1, n2, mode, count, r_max, rows_cap;
-    bool want_x, want_sample;
+    bool kspace, want_x, want_sample;
 };
 
 struct Composition {
@@ -251,7 +256,7 @@ std::vector<tsl::Batch> group_batches(const Composition& c, const tsl::FrameArgs
         b.table = table + c.group_start[g];
         b.count = k.count;
         b.n1 = k.n1; b.n2 = k.n2; b.r_max = k.r_max; b.rows_max = k.rows_cap;
-        b.mode = k.mode; b.want_x = k.want_x; b.want_sample = k.want_sample;
+        b.mode = k.mode; b.kspace = k.kspace; b.want_x = k.want_x; b.want_sample = k.want_sample;
         out.push_back(b);
     }
     return out;
@@ -273,11 +278,18 @@ int compose(tsl_seq* const* seqs, int n, const tsl_frame* frames, Composition& c
         c.wants[i] = (frames[i].X_out ? 1 : 0) | (frames[i].mask ? 16 : 0) | (frames[i].K_next > 0 ? 32 : 0);
         c.caps[i] = frames[i].mask ? s->n1 : std::min(std::max(frames[i].n_rows, 0), s->n1);
     }
+    // kind: 0 line mask, k-space route; 1 point mask; 2 line mask, frame route
+    auto kind = [&](int i) {
+        if (c.wants[i] & 16) return 1;
+        return seqs[i]->opts.line_route == TSL_ROUTE_KSPACE ? 0 : 2;
+    };
     std::map<std::tuple<int, int, int>, std::vector<int>> by;
-    for (int i = 0; i < n; ++i) by[{seqs[i]->n1, seqs[i]->n2, (c.wants[i] & 16) ? 1 : 0}].push_back(i);
+    for (int i = 0; i < n; ++i) by[{seqs[i]->n1, seqs[i]->n2, kind(i)}].push_back(i);
     for (auto& kv : by) {
         GroupKey k{};
-        k.n1 = std::get<0>(kv.first); k.n2 = std::get<1>(kv.first); k.mode = std::get<2>(kv.first);
+        k.n1 = std::get<0>(kv.first); k.n2 = std::get<1>(kv.first);
+        k.mode = std::get<2>(kv.first) == 1 ? tsl::MODE_POINTS : tsl::MODE_LINES;
+        k.kspace = std::get<2>(kv.first) == 0;
         k.count = int(kv.second.size());
         for (int i : kv.second) {
             k.r_max = std::max(k.r_max, seqs[i]->r);
@@ -322,6 +334,7 @@ void tsl_opts_default(tsl_opts* o) {
     o->step_mode = TSL_STEP_MM;
     o->mu = 0.0;
     o->allow_lambda0 = 0;
+    o->line_route = TSL_ROUTE_KSPACE;
 }
 
 int tsl_size_supported(int n) { return tsl::size_supported(n) ? 1 : 0; }
@@ -355,6 +368,7 @@ static int open_impl(tsl_pool* pool, tsl_seq** out, int n1, int n2, int r, doubl
     if (!std::isfinite(lambda) || lambda < 0.0) return fail(TSL_EINVAL, "lambda must be finite and >= 0");
     if (lambda == 0.0 && !o.allow_lambda0) return fail(TSL_EINVAL, "lambda == 0 needs allow_lambda0");
     if (o.step_mode != TSL_STEP_MM && o.step_mode != TSL_STEP_CONST) return fail(TSL_EINVAL, "bad step_mode");
+    if (o.line_route != TSL_ROUTE_KSPACE && o.line_route != TSL_ROUTE_FRAME) return fail(TSL_EINVAL, "bad line_route");
     if (o.step_mode == TSL_STEP_CONST && !(o.mu > 0.0 && std::isfinite(o.mu)))
         return fail(TSL_EINVAL, "constant step needs a finite mu > 0");
     if (!A0 || !B0) return fail(TSL_EINVAL, "null A0 or B0");
@@ -448,7 +462,7 @@ int tsl_push_frame(tsl_seq* s, const tsl_frame* frame, void* stream) {
     b.one = &a;
     b.table = nullptr;
     b.count = 1;
-    b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r; b.mode = a.mode;
+    b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r; b.mode = a.mode; b.kspace = a.kspace != 0;
     b.rows_max = frame->mask ? s->n1 : std::min(std::max(frame->n_rows, 0), s->n1);
     b.want_x = frame->X_out != nullptr;
     b.want_sample = a.K_next > 0;
@@ -626,7 +640,7 @@ int tsl_get_state(tsl_seq* s, void* host_blob, size_t* nbytes) {
     TSL_HIP(hipMemcpy(&d, s->at<void>(s->lay.dev), sizeof(d), hipMemcpyDeviceToHost));
     BlobHeader h{};
     std::memcpy(h.magic, "TSLSTAT", 8);
-    h.version = 1; h.n1 = s->n1; h.n2 = s->n2; h.r = s->r; h.lambda = s->lambda; h.opts = s->opts;
+    h.version = 2; h.n1 = s->n1; h.n2 = s->n2; h.r = s->r; h.lambda = s->lambda; h.opts = s->opts;
     h.abar = d.abar; h.t = d.t;
     char* p = static_cast<char*>(host_blob);
     std::memcpy(p, &h, sizeof(h));
@@ -646,7 +660,7 @@ int tsl_set_state(tsl_seq* s, const void* host_blob, size_t nbytes) {
     BlobHeader h{};
     std::memcpy(&h, host_blob, sizeof(h));
     const size_t a = size_t(s->n1) * s->r * sizeof(float2), b = size_t(s->n2) * s->r * sizeof(float2);
-    if (std::memcmp(h.magic, "TSLSTAT", 8) != 0 || h.version != 1 || h.n1 != s->n1 || h.n2 != s->n2 ||
+    if (std::memcmp(h.magic, "TSLSTAT", 8) != 0 || h.version != 2 || h.n1 != s->n1 || h.n2 != s->n2 ||
         h.r != s->r || nbytes < sizeof(BlobHeader) + 2 * a + 2 * b)
         return fail(TSL_EINVAL, "blob does not match this sequence");
     if ((rc = set_dev(s)) != TSL_OK) return rc;

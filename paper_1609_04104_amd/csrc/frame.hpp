@@ -32,6 +32,7 @@ constexpr int kGRows = 64;      // rows of F_l A or F_r B per factor-Gram partia
 constexpr int kSRows = 32;      // sampled rows per (Gram, rhs) partial, line masks
 constexpr int kPRows = 32;      // mask rows per (Gram, rhs) partial, point masks
 constexpr int kJCH = 32;        // readout samples per right-hand-side partial, line masks
+constexpr int kKQ = 16;         // sampled rows per block of the k-space residual (partials of E^T conj(Ahat_S))
 
 __host__ __device__ constexpr inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ inline int n_gparts(int n) { return cdiv(n, kGRows); }
@@ -39,6 +40,7 @@ __host__ __device__ inline int n_sparts(int n1) { return cdiv(n1, kPRows); }   /
 __host__ __device__ inline int n_jparts(int n2) { return cdiv(n2, kJCH); }
 __host__ __device__ inline int n_parts(int n1, int n2) { return n_gparts(n1) + n_gparts(n2) + n_sparts(n1); }
 __host__ __device__ inline int n_hparts(int n1, int n2) { return n_sparts(n1) * n_jparts(n2); }
+__host__ __device__ inline int n_qparts(int n1) { return cdiv(n1, kKQ); }
 
 // Pointer types of a frame descriptor.  The host fills descriptors with plain
 // pointers; device code reads the same bits as pointers into the global address
@@ -56,6 +58,7 @@ template <class T> using GlobalPtr = T*;
 template <template <class> class P>
 struct FrameArgsT {
     int n1, n2, r, mode;
+    int kspace;           // line mask on the k-space route (GA holds E conj(Bhat) on the sampled rows, W in wpart)
     double lambda, mu_const;
     int step_mode, n_rows;
     // resident state
@@ -65,8 +68,9 @@ struct FrameArgsT {
     P<float2> gamma32;
     // workspace
     P<float2> frame;      // [n1][n2]: row-transformed synthesis, then the column-back-projected residual
-    P<float2> Wb;         // [n2][r]: Z^T conj(A), Z the column-back-projected residual
-    P<float2> GA;         // [n1][r]: Theta conj(B)
+    P<float2> Wb;         // [n2][r]: Z^T conj(A), Z the column-back-projected residual (= E^T conj(Ahat_S))
+    P<float2> GA;         // [n1][r]: Theta conj(B) (frame route); E conj(Bhat) on the sampled rows, else 0 (k-space route)
+    P<float2> wpart;      // [n_qparts(n1)][n2][r]: E^T conj(Ahat_S) per chunk of kKQ sampled rows (k-space route)
     P<double2> part;      // [n_parts][r][r] partial Grams
     P<double2> hpart;     // [n_hparts][r] partial right-hand sides
     // inputs of the frame

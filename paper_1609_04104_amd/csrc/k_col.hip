@@ -97,24 +97,14 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
 
     if (!src.live()) return;
     const DevFrame f = src.get();
-    if (!block_frame_ok(f.dev, true)) return;
     const int n2 = f.n2, R = f.r;
     const int tid = threadIdx.x, c = tid % kTW, s = tid / kTW;
     const int col = src.bx() * kTW + c;
     const bool cv = col < n2;
-    load_tw<N1>(s_tw);
-    if (tid == 0) s_bad = 0;
-    if (f.mode == MODE_LINES) {
-        for (int k = tid; k < N1; k += blockDim.x) s_map[k] = -1;
-        __syncthreads();
-        const int nr = frame_rows(f);
-        for (int q = tid; q < nr; q += blockDim.x) {
-            const int k = f.rows[q];
-            if (k >= 0 && k < N1) s_map[k] = q;
-        }
-    }
-    __syncthreads();
-
+    const bool lines = f.mode == MODE_LINES;
+    // Loads that depend on nothing but the descriptor go out before the status
+    // check (they read inside the frame's own buffers either way): the block's
+    // columns of the row-transformed frame, the sampled-row count and indices.
     float2 v[T];
     zero(v);
     if (s < Q && cv) {
@@ -123,28 +113,70 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
             v[n1c] = f.frame[size_t(Q * n1c + s) * n2 + col];
         });
     }
+    const int cap = lines ? frame_rows_cap(f) : 0;
+    const int nd = (lines && f.n_rows_dev) ? *f.n_rows_dev : cap;
+    const int my_row = tid < cap ? f.rows[tid] : -1;
+    for (int k = tid; k < N1; k += blockDim.x) s_map[k] = -1;
+    if (tid == 0) s_bad = 0;
+    load_tw<N1>(s_tw);
+    if (!block_frame_ok(f.dev, true)) return;   // its barriers also order s_map's reset
+    if (lines) {
+        const int nr = nd < 0 ? 0 : (nd > cap ? cap : nd);
+        if (tid < nr && my_row >= 0 && my_row < N1) s_map[my_row] = tid;
+        for (int q = tid + int(blockDim.x); q < nr; q += blockDim.x) {
+            const int k = f.rows[q];
+            if (k >= 0 && k < N1) s_map[k] = q;
+        }
+    }
+    __syncthreads();
+    // The samples this thread's residual entries need (k = s + P k2 after the
+    // forward transform), loaded now so that they arrive during the transform.
+    float2 ys[Q];
+    unsigned on = 0;                               // bit k2: entry k2 is sampled
+    sfor<Q>([&](auto kk) {
+        constexpr int k2 = decltype(kk)::value;
+        const int k = s + P * k2;
+        ys[k2] = float2{0.f, 0.f};
+        if (s < P && cv) {
+            if (lines) {
+                const int q = s_map[k];
+                if (q >= 0) {
+                    on |= 1u << k2;
+                    ys[k2] = line_samples(f, q, k)[col];
+                }
+            } else {
+                if (f.mask[size_t(k) * n2 + col]) on |= 1u << k2;
+                ys[k2] = f.y[size_t(k) * n2 + col];
+            }
+        }
+    });
     if (s < Q) dft_twiddle<N1, P, false>(v, s, s_tw);
     col_swap_nk<N1>(v, s_u, c, s);
     if (s < P) {
         dft_only<Q, false>(v);
-        const bool lines = f.mode == MODE_LINES;
         sfor<Q>([&](auto kk) {
             constexpr int k2 = decltype(kk)::value;
-            const int k = s + P * k2;
             const float2 K = cscale(v[k2], InvSqrt<N1>::value);
-            float2 e{0.f, 0.f};
-            if (cv) {
-                if (lines) {
-                    const int q = s_map[k];
-                    if (q >= 0) e = csub(line_samples(f, q, k)[col], K);
-                } else if (f.mask[size_t(k) * n2 + col]) {
-                    e = csub(f.y[size_t(k) * n2 + col], K);
-                }
-            }
-            v[k2] = e;
+            v[k2] = (on >> k2) & 1u ? csub(ys[k2], K) : float2{0.f, 0.f};
         });
         dft_twiddle<N1, Q, true>(v, s, s_tw);
     }
+    // The factor rows of the W contraction below, issued before the inverse
+    // transform so that they arrive while it runs (first rank pass).
+    const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64), n = lane % 16;
+    float2 av[P][WNT];
+    auto load_a = [&](int n0) {
+        sfor<P>([&](auto mc) {
+            constexpr int m2 = decltype(mc)::value;
+            const int i = s + Q * m2;
+#pragma unroll
+            for (int u = 0; u < WNT; ++u) {
+                const int r = n0 + 16 * u + n;
+                av[m2][u] = (s < Q && r < R) ? float2(f.A[size_t(i) * R + r]) : float2{0.f, 0.f};
+            }
+        });
+    };
+    load_a(0);
     col_swap_kn<N1>(v, s_u, c, s);
     if (s < Q) {
         dft_only<P, true>(v);
@@ -162,22 +194,12 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
     // their rows meet in LDS and are added in wavefront order.
     static_assert(kTW == 16, "one MFMA row per column of the tile");
     float2* s_w = s_u;                                   // [wave][c][WNT * 16]
-    const int lane = tid % 64, wave = tid / 64, n = lane % 16;
     bool bad = false;
     for (int n0 = 0; n0 < R; n0 += WNT * 16) {
         f32x4 accr[WNT], acci[WNT];
 #pragma unroll
         for (int u = 0; u < WNT; ++u) accr[u] = acci[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-        float2 av[P][WNT];                               // all factor operands in flight at once
-        sfor<P>([&](auto mc) {
-            constexpr int m2 = decltype(mc)::value;
-            const int i = s + Q * m2;
-#pragma unroll
-            for (int u = 0; u < WNT; ++u) {
-                const int r = n0 + 16 * u + n;
-                av[m2][u] = (s < Q && r < R) ? float2(f.A[size_t(i) * R + r]) : float2{0.f, 0.f};
-            }
-        });
+        if (n0 > 0) load_a(n0);                          // all factor operands in flight at once
         sfor<P>([&](auto mc) {
             constexpr int m2 = decltype(mc)::value;
             const float2 z = (s < Q) ? v[m2] : float2{0.f, 0.f};
@@ -239,6 +261,51 @@ __global__ void __launch_bounds__(512) k_update_a(Src src) {
     }
     float2 v[T];
     zero(v);
+    if (f.kspace) {
+        // k-space route: Theta conj(B) = F_l^H M with M = E conj(Bhat) on the
+        // sampled rows and zero elsewhere (as the k-space residual kernel left GA);
+        // then the update in the transform's output layout and F_l A of the new
+        // A, as in the B update.
+        if (s < Q && rv) {
+            sfor<P>([&](auto qc) {
+                constexpr int n1c = decltype(qc)::value;
+                v[n1c] = f.GA[size_t(Q * n1c + s) * R + r];
+            });
+        }
+        __syncthreads();
+        if (s < Q) dft_twiddle<N1, P, true>(v, s, s_tw);
+        col_swap_nk<N1>(v, s_x, c, s);
+        if (s < P) {
+            dft_only<Q, true>(v);
+            sfor<Q>([&](auto k) {
+                constexpr int k2 = decltype(k)::value;
+                const float2 ga = cscale(v[k2], InvSqrt<N1>::value);
+                float2 an{0.f, 0.f};
+                if (rv) {
+                    const size_t at = size_t(s + P * k2) * R + r;
+                    const float2 a = f.A[at];
+                    const double gr = double(ga.x) * g.x + double(ga.y) * g.y;
+                    const double gi = double(ga.y) * g.x - double(ga.x) * g.y;
+                    an = float2{float(sh * a.x + mu * gr), float(sh * a.y + mu * gi)};
+                    f.A[at] = an;
+                    if (f.A_out) f.A_out[at] = an;
+                }
+                v[k2] = an;
+            });
+            dft_twiddle<N1, Q, false>(v, s, s_tw);
+        }
+        col_swap_kn<N1>(v, s_x, c, s);
+        if (s < Q) {
+            dft_only<P, false>(v);
+            if (rv) {
+                sfor<P>([&](auto m) {
+                    constexpr int m2 = decltype(m)::value;
+                    f.Ahat[size_t(s + Q * m2) * R + r] = cscale(v[m2], InvSqrt<N1>::value);
+                });
+            }
+        }
+        return;
+    }
     if (s < Q && rv) {
         sfor<P>([&](auto q) {
             constexpr int n1c = decltype(q)::value;
@@ -298,10 +365,30 @@ __global__ void __launch_bounds__(512) k_update_b(Src src, int gb) {
     float2 v[T];
     zero(v);
     if (s < Q && rv) {
-        sfor<P>([&](auto q) {
-            constexpr int n1c = decltype(q)::value;
-            v[n1c] = f.Wb[size_t(Q * n1c + s) * R + r];
-        });
+        if (f.kspace) {
+            // W = sum over the chunks of sampled rows of E^T conj(Ahat_S), in chunk
+            // order, two chunks' loads in flight at a time
+            const int nqc = cdiv(frame_rows(f), kKQ);
+            for (int c0 = 0; c0 < nqc; c0 += 2) {
+                float2 w0[P], w1[P];
+                sfor<P>([&](auto q) {
+                    constexpr int n1c = decltype(q)::value;
+                    const size_t at = size_t(Q * n1c + s) * R + r;
+                    w0[n1c] = f.wpart[size_t(c0) * N2 * R + at];
+                    w1[n1c] = c0 + 1 < nqc ? float2(f.wpart[size_t(c0 + 1) * N2 * R + at]) : float2{0.f, 0.f};
+                });
+                sfor<P>([&](auto q) {
+                    constexpr int n1c = decltype(q)::value;
+                    v[n1c] = cadd(v[n1c], w0[n1c]);
+                    if (c0 + 1 < nqc) v[n1c] = cadd(v[n1c], w1[n1c]);
+                });
+            }
+        } else {
+            sfor<P>([&](auto q) {
+                constexpr int n1c = decltype(q)::value;
+                v[n1c] = f.Wb[size_t(Q * n1c + s) * R + r];
+            });
+        }
     }
     __syncthreads();
     // Theta^T conj(A) = F_r^H W: inverse transform along the row index of W.
@@ -415,6 +502,7 @@ hipError_t launch_colfft_n(int ncols, int ld, int batch, size_t bstride, const f
 }  // namespace
 
 hipError_t launch_col_resid(const Batch& b, hipStream_t st) {
+    if (b.kspace) return hipSuccess;   // frame route only
     switch (b.n1) {
 #define TSL_X(N) case N: return launch_k2_n<N>(b, st);
         TSL_FOR_EACH_N(TSL_X)

@@ -1,0 +1,255 @@
+// k-space route of a line-mask step (Sec. IV-B with one coil).
+//
+// With the separable transform F(X) = F_l X F_r^T and the k-space factors
+// Ahat = F_l A, Bhat = F_r B, the prediction at the sampled rows S is
+// K_S = Ahat_S diag(gamma) Bhat^T, so the residual of Algorithm 3 on the
+// samples is E = Y_S - Ahat_S diag(gamma) Bhat^T (|S| x n2).  The inverse
+// transform of the zero-filled residual, Theta = F_l^H Xi conj(F_r), is the sum
+// over samples of e_l times the conjugate sampling matrix, so its contractions
+// with the factors reduce to the samples:
+//     Theta conj(B)    = F_l^H (rows S: E conj(Bhat), zero elsewhere),
+//     Theta^T conj(A)  = F_r^H (E^T conj(Ahat_S)).
+// k_kres forms E, M = E conj(Bhat) (scattered to the rows of S in GA, the other
+// rows zeroed) and W = E^T conj(Ahat_S) per chunk of sampled rows (in wpart);
+// the A update applies F_l^H to GA (k_update_a), the B update adds the W
+// partials in chunk order and applies F_r^H (k_update_b).
+//
+// A block (sixteen wavefronts) owns kKQ sampled rows of one frame and runs over
+// the readout samples in chunks of up to 256 columns (fewer at large ranks, so
+// that the chunk of Bhat fits in LDS), wavefront w taking columns
+// [16 w, 16 w + 16) of a chunk.  Per chunk, on FP32 matrix cores with the
+// complex products split over K = (index, re/im) as in the synthesis:
+//   E tile [q][j]  = y - sum_r (Ahat_S gamma)[q][r] Bhat[j][r]   (K = ranks)
+//   M     [q][r] += sum_j E[q][j] conj(Bhat[j][r])               (K = the wavefront's columns)
+//   W tile [j][r]  = sum_q E[q][j] conj(Ahat_S[q][r])            (K = the block's rows)
+// A wavefront's E tile goes through its own LDS area (one wavefront's LDS
+// accesses complete in order).  At the end the wavefronts' M sums are added
+// in wavefront order.
+#include <algorithm>
+
+#include "kernels.hpp"
+#include "mfma.hpp"
+#include "tsl.h"
+
+namespace tsl {
+namespace {
+
+constexpr int kKT = 1024;           // threads per block (sixteen wavefronts)
+constexpr int kKW = kKT / 64;       // wavefronts; wavefront w takes columns [16 w, 16 w + 16) of a chunk
+constexpr int kEP = 17;             // LDS pitch of a wavefront's E tile (float2)
+constexpr size_t kBBudget = 96 * 1024;   // LDS for the Bhat chunk
+static_assert(kKQ == 16, "one matrix-core row tile of sampled rows per block");
+
+// Columns per chunk: all sixteen wavefronts' tiles, fewer when the Bhat chunk
+// [cols][R + 1] would not fit the budget (large ranks).
+inline __host__ __device__ int kres_cols(int R) {
+    const int fit = int(kBBudget / (size_t(R + 1) * sizeof(float2))) / 16 * 16;
+    return fit < 16 * kKW ? fit : 16 * kKW;
+}
+constexpr int kYL = kKQ * 16 * kKW / kKT;                   // sample loads per thread
+
+// Dynamic LDS: s_b [cols][R + 1] (Bhat chunk; at the end the wavefronts' M
+// sums [kKW][16][R]), s_a [16][R + 1] (Ahat rows), s_e [kKW][16][kEP] (E tiles).
+size_t kres_lds(int R) {
+    return (size_t(kres_cols(R)) * (R + 1) + size_t(kKQ) * (R + 1) + size_t(kKW) * 16 * kEP) * sizeof(float2);
+}
+
+template <int RT, class Src>
+__global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
+    extern __shared__ float2 s_dyn[];
+    __shared__ float2 s_g[TSL_MAX_R];
+    __shared__ int s_row[kKQ];
+    __shared__ unsigned char s_on[kMaxN];
+    __shared__ int s_bad;
+    if (!src.live()) return;
+    const DevFrame f = src.get();
+    if (!block_frame_ok(f.dev, true)) return;
+    const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x, RP = R + 1;
+    const int JC = kres_cols(R);
+    float2* s_b = s_dyn;
+    float2* s_a = s_b + JC * RP;
+    float2* s_e = s_a + kKQ * RP;
+    const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int m = lane % 16, g4 = lane / 16;
+    const bool pim = g4 & 1;                         // which part this lane's K entry takes
+    const int S = frame_rows(f), qc = src.bx(), q0 = qc * kKQ;
+    const int nq = max(0, min(kKQ, S - q0));
+    for (int r = tid; r < R; r += kKT) s_g[r] = f.gamma32[r];
+    for (int i = tid; i < n1; i += kKT) s_on[i] = 0;
+    if (tid == 0) s_bad = 0;
+    if (tid < kKQ) {
+        const int row = tid < nq ? f.rows[q0 + tid] : -1;
+        s_row[tid] = (row >= 0 && row < n1) ? row : -1;
+    }
+    __syncthreads();
+    for (int q = tid; q < S; q += kKT) {
+        const int row = f.rows[q];
+        if (row >= 0 && row < n1) s_on[row] = 1;
+    }
+    // Ahat rows of the block
+    for (int e = tid; e < kKQ * R; e += kKT) {
+        const int q = e / R, c = e % R, row = s_row[q];
+        s_a[q * RP + c] = row >= 0 ? float2(f.Ahat[size_t(row) * R + c]) : float2{0.f, 0.f};
+    }
+    __syncthreads();
+    // rows of GA that this block zeroes: the unsampled rows i with i mod nblk = qc
+    for (int e = tid; e < n1 * R; e += kKT) {
+        const int i = e / R;
+        if (i % nblk == qc && !s_on[i]) f.GA[e] = float2{0.f, 0.f};
+    }
+    if (nq == 0) return;                             // uniform
+
+    bool bad = false;
+    f32x4 mr[RT], mi[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) mr[t] = mi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float2* s_ew = s_e + wave * 16 * kEP;            // this wavefront's E tile [q][j]
+    for (int j0 = 0; j0 < n2; j0 += JC) {
+        __syncthreads();                             // the previous chunk's reads of s_b are done
+        {   // the samples and the chunk of Bhat, four loads per thread in flight per round
+            float2 yv[kYL];
+#pragma unroll
+            for (int u = 0; u < kYL; ++u) {
+                const int e = tid + u * kKT, q = e / (16 * kKW), j = e % (16 * kKW), row = s_row[q];
+                yv[u] = (row >= 0 && j < JC && j0 + j < n2) ? float2(line_samples(f, q0 + q, row)[j0 + j])
+                                                             : float2{0.f, 0.f};
+            }
+            for (int e0 = 0; e0 < JC * R; e0 += 4 * kKT) {
+                float2 bv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + tid + u * kKT, j = e / R;
+                    bv[u] = (e < JC * R && j0 + j < n2) ? float2(f.Bhat[size_t(j0) * R + e]) : float2{0.f, 0.f};
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + tid + u * kKT;
+                    if (e < JC * R) s_b[(e / R) * RP + e % R] = bv[u];
+                }
+            }
+            // samples, to the wavefront that owns their columns
+#pragma unroll
+            for (int u = 0; u < kYL; ++u) {
+                const int e = tid + u * kKT, q = e / (16 * kKW), j = e % (16 * kKW);
+                s_e[(j / 16) * 16 * kEP + q * kEP + j % 16] = yv[u];
+            }
+        }
+        __syncthreads();
+        const int jt0 = j0 + 16 * wave;              // first column of this wavefront's tile
+        if (16 * wave < JC && jt0 < n2) {            // uniform
+            // E tile: prediction on the matrix cores, then y - prediction
+            f32x4 er{0.f, 0.f, 0.f, 0.f}, ei{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+            for (int k = 0; k < cdiv(R, 2); ++k) {
+                const int c = min(2 * k + g4 / 2, R - 1);
+                const bool cv = 2 * k + g4 / 2 < R;
+                const float2 a = s_a[m * RP + c], gm = s_g[c];
+                const float2 ag = cv ? cmul(a, gm) : float2{0.f, 0.f};
+                const float2 b = s_b[(16 * wave + m) * RP + c];
+                const float bq = pim ? b.y : b.x;
+                er = mfma_16x16x4(pim ? -ag.y : ag.x, bq, er);
+                ei = mfma_16x16x4(pim ? ag.x : ag.y, bq, ei);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q = 4 * g4 + i, j = m;
+                const float2 yq = s_ew[q * kEP + j];
+                const bool live = q < nq && jt0 + j < n2;
+                const float2 e = live ? float2{yq.x - er[i], yq.y - ei[i]} : float2{0.f, 0.f};
+                bad |= live && !finite2(yq);
+                s_ew[q * kEP + j] = e;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // M += E conj(Bhat) over the tile's columns; W tile = E^T conj(Ahat_S)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                if (16 * t >= R) break;              // uniform
+                const int rc = min(16 * t + m, R - 1);
+                const bool rv = 16 * t + m < R;
+                f32x4 wr{0.f, 0.f, 0.f, 0.f}, wi{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+                for (int k = 0; k < 8; ++k) {
+                    const int kk = 2 * k + g4 / 2;
+                    const float2 em = s_ew[m * kEP + kk];         // E[q = m][j = kk]
+                    const float2 et = s_ew[kk * kEP + m];         // E[q = kk][j = m]
+                    const float2 b = s_b[(16 * wave + kk) * RP + rc];
+                    const float2 a = s_a[kk * RP + rc];
+                    const float bq = rv ? (pim ? b.y : b.x) : 0.f;
+                    const float aq = rv ? (pim ? a.y : a.x) : 0.f;
+                    mr[t] = mfma_16x16x4(pim ? em.y : em.x, bq, mr[t]);    // Re: er br + ei bi
+                    mi[t] = mfma_16x16x4(pim ? -em.x : em.y, bq, mi[t]);   // Im: ei br - er bi
+                    wr = mfma_16x16x4(pim ? et.y : et.x, aq, wr);
+                    wi = mfma_16x16x4(pim ? -et.x : et.y, aq, wi);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int j = jt0 + 4 * g4 + i, r = 16 * t + m;
+                    if (j < n2 && r < R) {
+                        const float2 w{wr[i], wi[i]};
+                        bad |= !finite2(w);
+                        f.wpart[(size_t(qc) * n2 + j) * R + r] = w;
+                    }
+                }
+            }
+        }
+    }
+    // the wavefronts' M sums meet in LDS (over the Bhat chunk) and are added in order
+    const int nw = min(kKW, cdiv(min(JC, n2), 16));  // wavefronts that took columns
+    __syncthreads();
+    float2* s_m = s_b;                               // [wave][q][r]
+    if (wave < nw) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            if (16 * t >= R) break;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q = 4 * g4 + i, r = 16 * t + m;
+                if (r < R) s_m[(wave * kKQ + q) * R + r] = float2{mr[t][i], mi[t][i]};
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < nq * R; e += kKT) {
+        const int q = e / R, r = e % R, row = s_row[q];
+        float2 acc = s_m[q * R + r];
+        for (int w = 1; w < nw; ++w) acc = cadd(acc, s_m[(w * kKQ + q) * R + r]);
+        bad |= !finite2(acc);
+        if (row >= 0) f.GA[size_t(row) * R + r] = acc;
+    }
+    if (bad) s_bad = 1;
+    __syncthreads();
+    if (tid == 0 && s_bad) latch(f.dev, ST_ENONFINITE);
+}
+
+}  // namespace
+
+void kres_attributes() {
+    const int ms = int(kres_lds(TSL_MAX_R));
+    auto set = [&](const void* k) { hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, ms); };
+    set(reinterpret_cast<const void*>(&k_kres<2, FrameTable>));
+    set(reinterpret_cast<const void*>(&k_kres<2, OneFrame>));
+    set(reinterpret_cast<const void*>(&k_kres<4, FrameTable>));
+    set(reinterpret_cast<const void*>(&k_kres<4, OneFrame>));
+    set(reinterpret_cast<const void*>(&k_kres<8, FrameTable>));
+    set(reinterpret_cast<const void*>(&k_kres<8, OneFrame>));
+}
+
+template <int RT> void launch_kres_rt(const Batch& b, hipStream_t st) {
+    const int gx = std::max(1, n_qparts(b.rows_max));
+    const dim3 grid = frame_grid(b, gx);
+    const size_t lds = kres_lds(b.r_max);
+    if (b.table) k_kres<RT, FrameTable><<<grid, kKT, lds, st>>>(FrameTable{b.table, gx, b.count}, gx);
+    else k_kres<RT, OneFrame><<<grid, kKT, lds, st>>>(OneFrame{*b.one}, gx);
+}
+
+hipError_t launch_kres(const Batch& b, hipStream_t st) {
+    if (!b.kspace) return hipSuccess;             // k-space route only
+    if (b.r_max <= 32) launch_kres_rt<2>(b, st);
+    else if (b.r_max <= 64) launch_kres_rt<4>(b, st);
+    else launch_kres_rt<8>(b, st);
+    return hipGetLastError();
+}
+
+}  // namespace tsl

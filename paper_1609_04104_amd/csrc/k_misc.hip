@@ -37,6 +37,21 @@ __device__ __forceinline__ double2 dcmulc(double2 a, double2 b) {   // a conj(b)
 }
 __device__ __forceinline__ double dabs(double2 a) { return sqrt(a.x * a.x + a.y * a.y); }
 
+// Cholesky pivot of a positive d: ip = 1/sqrt(d) from the hardware estimate and
+// two Newton steps y <- y + (y/2)(1 - d y^2) (each roughly doubles the correct
+// bits), and p = d ip = sqrt(d).  Eight dependent operations instead of a
+// square root followed by a division, on the solve's serial path.
+__device__ __forceinline__ void pivot(double d, double& p, double& ip) {
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-d * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    ip = y;
+    p = d * y;
+}
+
 // ---------------------------------------------------------------- Gram statistics
 // Blocks of kSB threads.  A Gram is accumulated from rows staged in LDS as FP64
 // (products of FP32 values are exact there).  Every block writes its own
@@ -451,7 +466,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
             if (tid == 0) s_fail = ST_ENOTPD;
             break;
         }
-        const double p = sqrt(dd), ip = 1.0 / p;
+        double p, ip;
+        pivot(dd, p, ip);
         __syncthreads();
         if (tid == 0) {
             L[pk(k, k)] = double2{p, 0.0};
@@ -757,7 +773,8 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
             if (fail) return;
             const double dkk = readlane_d(g[km].x, k + ko * RB);
             if (!(dkk > 0.0) || !isfinite(dkk)) { fail = true; return; }
-            const double p = sqrt(dkk), ip = 1.0 / p;
+            double p, ip;
+            pivot(dkk, p, ip);
             if (k < R) { piv_lo = fmin(piv_lo, p); piv_hi = fmax(piv_hi, p); }
             if (i == k) dinv = ip;
             if (h == ko) g[km] = i == k ? double2{p, 0.0} : double2{g[km].x * ip, g[km].y * ip};
@@ -956,6 +973,7 @@ size_t solve_lds(int R) { return size_t(R * (R + 1) / 2 + R) * sizeof(double2) +
 void init_kernel_attributes() {
     static std::once_flag once;
     std::call_once(once, [] {
+        kres_attributes();
         const int ms = int(size_t(kPStage) * TSL_MAX_R * sizeof(double2));
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pstats<FrameTable>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, ms);

@@ -355,6 +355,7 @@ template <int N2> hipError_t launch_rowfft_n(int nrows, const float2* in, float2
 }  // namespace
 
 hipError_t launch_synth_rowfft(const Batch& b, hipStream_t st) {
+    if (b.kspace) return hipSuccess;   // frame route only
     switch (b.n2) {
 #define TSL_X(N) case N: return launch_k1_n<N>(b, st);
         TSL_FOR_EACH_N(TSL_X)
@@ -364,6 +365,7 @@ hipError_t launch_synth_rowfft(const Batch& b, hipStream_t st) {
 }
 
 hipError_t launch_row_inv_grad(const Batch& b, hipStream_t st) {
+    if (b.kspace) return hipSuccess;   // frame route only
     switch (b.n2) {
 #define TSL_X(N) case N: return launch_k3_n<N>(b, st);
         TSL_FOR_EACH_N(TSL_X)

@@ -15,6 +15,7 @@ struct Batch {
     int r_max;                   // largest rank in the group
     int rows_max;                // largest n_rows (line masks)
     int mode;                    // MODE_LINES or MODE_POINTS (shared)
+    bool kspace;                 // line masks on the k-space route (shared)
     bool want_x;                 // some frame asks for X_t
     bool want_sample;            // some frame draws its next rows
 };
@@ -48,6 +49,11 @@ hipError_t launch_factor_fft(int n, int r, const float2* in, float2* out, bool i
 hipError_t launch_stats(const Batch& b, hipStream_t st);
 hipError_t launch_solve(const Batch& b, hipStream_t st);
 hipError_t launch_synth_out(const Batch& b, hipStream_t st);
+
+// k-space route of line masks: residual at the sampled rows and its two
+// gradient contractions (csrc/k_kspace.hip).
+hipError_t launch_kres(const Batch& b, hipStream_t st);
+void kres_attributes();   // dynamic-LDS limit of the k-space residual kernel
 hipError_t launch_sample(const Batch& b, hipStream_t st);
 
 // Raises the dynamic-LDS limit of the kernels that need more than the default

@@ -24,14 +24,16 @@ constexpr int kUPre = 256;            // uniforms computed beside the prefix sum
 constexpr int kChunk = 2048;          // factor entries (or row terms) per staged chunk of rows (16 KiB)
 constexpr int kChunkLoads = kChunk / kSampleThreads;   // loads per thread that cover one chunk
 constexpr int kBatch = 8;             // LDS loads a sequential sum keeps one batch ahead
+constexpr int kResident = 4;          // chunks of F_l A held in registers at a time
+constexpr int kPB = 32;               // prefix values one thread holds per batch
 // The staging area is padded so that every load and store of a chunk can be
 // unconditional: a row-term chunk at pitch R | 1 ends before 3 kChunk / 2, and
 // the column sums read at most one batch of rows past a chunk; the prefix
-// reads and writes at most two batches past n1.
+// reads and writes at most kPB values past n1.
 constexpr int kBuf = (3 * kChunk / 2 > kChunk + kBatch * TSL_MAX_R) ? 3 * kChunk / 2 : kChunk + kBatch * TSL_MAX_R;
 
 struct alignas(16) SampleLds {
-    double pref[kMaxN + 2 * kBatch];  // weights, then their inclusive prefix (padded)
+    double pref[kMaxN + kPB];         // weights, then their inclusive prefix (padded)
     double c[TSL_MAX_R];              // column energies
     double u[kUPre];                  // u_k for k < kUPre
     double buf[kBuf];                 // a chunk of energies E_ir, then of row terms
@@ -71,6 +73,70 @@ __device__ __forceinline__ double energy(float2 a) {
     return ax * ax + ay * ay;
 }
 
+// acc += buf[i R + r] for i = 0, 1, ..., nb - 1 in order (one or two columns
+// per lane), with the LDS loads of the next batch of rows in flight while the
+// current one is added; two register sets alternate, so no copies are needed.
+template <bool TWO>
+__device__ __forceinline__ void column_chain(const double* buf, int R, int r0, int r1, int nb, double& acc0,
+                                             double& acc1) {
+#pragma clang fp contract(off)
+    double a0[kBatch], a1[kBatch], b0[kBatch], b1[kBatch];
+    auto load = [&](double (&x0)[kBatch], double (&x1)[kBatch], int i0) {
+#pragma unroll
+        for (int w = 0; w < kBatch; ++w) {
+            x0[w] = buf[(i0 + w) * R + r0];
+            if constexpr (TWO) x1[w] = buf[(i0 + w) * R + r1];
+        }
+    };
+    auto add = [&](const double (&x0)[kBatch], const double (&x1)[kBatch]) {
+#pragma unroll
+        for (int w = 0; w < kBatch; ++w) {
+            acc0 = acc0 + x0[w];
+            if constexpr (TWO) acc1 = acc1 + x1[w];
+        }
+    };
+    load(a0, a1, 0);
+    for (int il = 0; il < nb; il += 2 * kBatch) {
+        const bool more = il + kBatch < nb;
+        if (more) load(b0, b1, il + kBatch);
+        add(a0, a1);
+        if (more) {
+            if (il + 2 * kBatch < nb) load(a0, a1, il + 2 * kBatch);
+            add(b0, b1);
+        }
+    }
+}
+
+// p[0] + p[1] + ... + p[n - 1] in order, starting from +0, with the same
+// alternating register sets.
+__device__ __forceinline__ double row_chain(const double* p, int n) {
+#pragma clang fp contract(off)
+    double q = 0.0, a[kBatch], b[kBatch];
+    const int nf = n / kBatch * kBatch;
+    auto load = [&](double (&x)[kBatch], int i0) {
+#pragma unroll
+        for (int w = 0; w < kBatch; ++w) x[w] = p[i0 + w];
+    };
+    auto add = [&](const double (&x)[kBatch]) {
+#pragma unroll
+        for (int w = 0; w < kBatch; ++w) q = q + x[w];
+    };
+    if (nf > 0) {
+        load(a, 0);
+        for (int i = 0; i < nf; i += 2 * kBatch) {
+            const bool more = i + kBatch < nf;
+            if (more) load(b, i + kBatch);
+            add(a);
+            if (more) {
+                if (i + 2 * kBatch < nf) load(a, i + 2 * kBatch);
+                add(b);
+            }
+        }
+    }
+    for (int i = nf; i < n; ++i) q = q + p[i];
+    return q;
+}
+
 __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
 #pragma clang fp contract(off)
     const int K = f.K_next;
@@ -80,56 +146,58 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
     GlobalPtr<const float2> Ah = f.Ahat;
     const uint64_t t_next = uint64_t(f.dev->t + 1);
 
-    // Rows of F_l A come in chunks of ck rows: coalesced loads into registers
-    // (the index clamped into the factor, zero past the end), then LDS.  The
-    // next chunk's loads are in flight while the current one is consumed.
-    float2 a[kChunkLoads];
-    auto load_chunk = [&](int i0, int ck) {
-        const int ne = min(ck, n1 - i0) * R;
+    // Rows of F_l A come in chunks of ck rows (a multiple of kBatch, ck R <=
+    // kChunk), kResident chunks at a time held in registers across the block:
+    // coalesced loads at indices clamped into the factor, zero past the end.
+    // When the whole factor fits (n1 R <= kResident kChunk, e.g. 256 x 32),
+    // F_l A is read from memory once for both passes.
+    const int ck = min((kChunk / R) / kBatch * kBatch, cdiv(n1, kBatch) * kBatch);
+    const int span = kResident * ck;                 // rows held at a time
+    float2 a[kResident][kChunkLoads];
+    auto load_span = [&](int I0) {
+        sfor<kResident>([&](auto sc) {
+            constexpr int sub = decltype(sc)::value;
+            const int i0 = I0 + sub * ck;
+            const int ne = max(min(ck, n1 - i0), 0) * R;
 #pragma unroll
-        for (int u = 0; u < kChunkLoads; ++u) {
-            const int e = tid + u * kSampleThreads;
-            const float2 v = Ah[size_t(i0) * R + min(e, ne - 1)];
-            a[u] = e < ne ? v : float2{0.f, 0.f};
-        }
+            for (int u = 0; u < kChunkLoads; ++u) {
+                const int e = tid + u * kSampleThreads;
+                const float2 v = Ah[min(size_t(i0) * R + e, size_t(n1) * R - 1)];
+                a[sub][u] = e < ne ? v : float2{0.f, 0.f};
+            }
+        });
     };
 
-    // 1. Column energies c_r = sum_i E_ir in row order, one column per lane of
-    //    wavefront 0 (64 columns per sweep).  The whole block computes a
-    //    chunk's energies into LDS, so the summing wavefront only loads and
-    //    adds.  A chunk holds a multiple of kBatch rows; rows past n1 are zero,
-    //    and adding +0 leaves a nonnegative sum unchanged.
+    // 1. Column energies c_r = sum_i E_ir in row order: the block writes a
+    //    chunk's energies E_ir = |Ahat_ir|^2 (FP64) to LDS, then wavefront 0
+    //    adds them up, lane l owning columns l and l + 64.  Rows past n1 are
+    //    zero, and adding +0 leaves a nonnegative sum unchanged.
     {
-        const int ck = min((kChunk / R) / kBatch * kBatch, cdiv(n1, kBatch) * kBatch);
-        for (int r0 = 0; r0 < R; r0 += 64) {
-            const int r = min(r0 + tid, R - 1);
-            double acc = 0.0;
-            if (worker) load_chunk(0, ck);
-            for (int i0 = 0; i0 < n1; i0 += ck) {
-                if (worker) {
+        const int r0 = min(tid, R - 1), r1 = min(tid + 64, R - 1);
+        const bool two = R > 64;
+        double acc0 = 0.0, acc1 = 0.0;
+        for (int I0 = 0; I0 < n1; I0 += span) {
+            if (worker) load_span(I0);
+            sfor<kResident>([&](auto sc) {
+                constexpr int sub = decltype(sc)::value;
+                const int i0 = I0 + sub * ck;
+                if (i0 < n1) {
+                    if (worker) {
 #pragma unroll
-                    for (int u = 0; u < kChunkLoads; ++u) L.buf[tid + u * kSampleThreads] = energy(a[u]);
-                }
-                __syncthreads();
-                if (worker && i0 + ck < n1) load_chunk(i0 + ck, ck);
-                if (tid < 64) {
-                    const int nb = min(ck, n1 - i0);
-                    double cur[kBatch], nxt[kBatch];
-#pragma unroll
-                    for (int w = 0; w < kBatch; ++w) cur[w] = L.buf[w * R + r];
-                    for (int il = 0; il < nb; il += kBatch) {
-#pragma unroll
-                        for (int w = 0; w < kBatch; ++w) nxt[w] = L.buf[(il + kBatch + w) * R + r];
-#pragma unroll
-                        for (int w = 0; w < kBatch; ++w) acc = acc + cur[w];
-#pragma unroll
-                        for (int w = 0; w < kBatch; ++w) cur[w] = nxt[w];
+                        for (int u = 0; u < kChunkLoads; ++u) L.buf[tid + u * kSampleThreads] = energy(a[sub][u]);
                     }
+                    __syncthreads();
+                    if (tid < 64) {
+                        const int nb = cdiv(min(ck, n1 - i0), kBatch) * kBatch;   // rows past n1 are zero
+                        if (two) column_chain<true>(L.buf, R, r0, r1, nb, acc0, acc1);
+                        else column_chain<false>(L.buf, R, r0, r1, nb, acc0, acc1);
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
-            }
-            if (tid < 64 && r0 + tid < R) L.c[r0 + tid] = acc;
+            });
         }
+        if (tid < 64 && tid < R) L.c[tid] = acc0;
+        if (tid < 64 && tid + 64 < R) L.c[tid + 64] = acc1;
     }
     for (int i = tid; i < n1; i += nt) L.mark[i] = 0;
     __syncthreads();
@@ -140,38 +208,32 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
     //    its terms up in order.
     {
         const int pitch = R | 1;
-        const int ck = min(kChunk / R, n1);
-        if (worker) load_chunk(0, ck);
-        for (int i0 = 0; i0 < n1; i0 += ck) {
-            const int ni = min(ck, n1 - i0);
-            if (worker) {
+        for (int I0 = 0; I0 < n1; I0 += span) {
+            if (worker && span < n1) load_span(I0);
+            sfor<kResident>([&](auto sc) {
+                constexpr int sub = decltype(sc)::value;
+                const int i0 = I0 + sub * ck;
+                if (i0 < n1) {
+                    const int ni = min(ck, n1 - i0);
+                    if (worker) {
 #pragma unroll
-                for (int u = 0; u < kChunkLoads; ++u) {
-                    const int e = tid + u * kSampleThreads, r = e % R;
-                    const double c = L.c[r];
-                    const double q = energy(a[u]) / (c > 0.0 ? c : 1.0);
-                    L.buf[(e / R) * pitch + r] = c > 0.0 ? q : 0.0;
+                        for (int u = 0; u < kChunkLoads; ++u) {
+                            const int e = tid + u * kSampleThreads, r = e % R;
+                            const double c = L.c[r];
+                            const double q = energy(a[sub][u]) / (c > 0.0 ? c : 1.0);
+                            L.buf[(e / R) * pitch + r] = c > 0.0 ? q : 0.0;
+                        }
+                    }
+                    __syncthreads();
+                    for (int il = tid; il < ni; il += nt) {
+                        const double q = row_chain(L.buf + il * pitch, R);
+                        double w = double(n2) * q;
+                        w = w + double(R);
+                        L.pref[i0 + il] = w;
+                    }
+                    __syncthreads();
                 }
-            }
-            __syncthreads();
-            if (worker && i0 + ck < n1) load_chunk(i0 + ck, ck);
-            for (int il = tid; il < ni; il += nt) {
-                const double* tr = L.buf + il * pitch;
-                double q = 0.0;
-                int r = 0;
-                for (; r + kBatch <= R; r += kBatch) {
-                    double v[kBatch];
-#pragma unroll
-                    for (int w = 0; w < kBatch; ++w) v[w] = tr[r + w];
-#pragma unroll
-                    for (int w = 0; w < kBatch; ++w) q = q + v[w];
-                }
-                for (; r < R; ++r) q = q + tr[r];
-                double w = double(n2) * q;
-                w = w + double(R);
-                L.pref[i0 + il] = w;
-            }
-            __syncthreads();
+            });
         }
     }
 
@@ -184,25 +246,21 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
     }
     if (tid == 0) {
         double2* p2 = reinterpret_cast<double2*>(L.pref);
-        constexpr int kH = kBatch / 2;
+        constexpr int kH = kPB / 2;
         double run = 0.0;
-        double2 cur[kH], nxt[kH];
-#pragma unroll
-        for (int w = 0; w < kH; ++w) cur[w] = p2[w];
         for (int h0 = 0; h0 < cdiv(n1, 2); h0 += kH) {
+            double2 v[kH];
 #pragma unroll
-            for (int w = 0; w < kH; ++w) nxt[w] = p2[h0 + kH + w];
+            for (int w = 0; w < kH; ++w) v[w] = p2[h0 + w];
 #pragma unroll
             for (int w = 0; w < kH; ++w) {
-                run = run + cur[w].x;
-                cur[w].x = run;
-                run = run + cur[w].y;
-                cur[w].y = run;
+                run = run + v[w].x;
+                v[w].x = run;
+                run = run + v[w].y;
+                v[w].y = run;
             }
 #pragma unroll
-            for (int w = 0; w < kH; ++w) p2[h0 + w] = cur[w];
-#pragma unroll
-            for (int w = 0; w < kH; ++w) cur[w] = nxt[w];
+            for (int w = 0; w < kH; ++w) p2[h0 + w] = v[w];
         }
     }
     __syncthreads();

@@ -38,12 +38,14 @@ class TslError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("step_mode", ctypes.c_int), ("mu", ctypes.c_double), ("allow_lambda0", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64), ("line_route", ctypes.c_int)]
 
 
-N_PHASES = 8
+N_PHASES = 9
 PHASES = ["partial Grams", "ridge solve + step size", "synthesis + row pass", "column pass + residual",
-          "row inverse + A grad", "A update + F_l A", "B update + F_r B + row draw", "output synthesis"]
+          "row inverse + A grad", "k-space residual + gradients", "A update + F_l A",
+          "B update + F_r B + row draw", "output synthesis"]
+ROUTE_KSPACE, ROUTE_FRAME = 0, 1
 
 
 class Frame(ctypes.Structure):
@@ -140,9 +142,10 @@ def selftest_codelets():
     return float(lib().tsl_selftest_codelets())
 
 
-def make_opts(step_mode="mm", mu=0.0, allow_lambda0=False, seed=0, stream_id=0):
+def make_opts(step_mode="mm", mu=0.0, allow_lambda0=False, seed=0, stream_id=0, route="kspace"):
     o = Opts()
     lib().tsl_opts_default(ctypes.byref(o))
+    o.line_route = {"kspace": ROUTE_KSPACE, "frame": ROUTE_FRAME}[route]
     o.step_mode = {"mm": STEP_MM, "const": STEP_CONST}[step_mode]
     o.mu = float(mu)
     o.allow_lambda0 = int(bool(allow_lambda0))
@@ -174,9 +177,9 @@ class Sequence:
     """One scan's resident state (tsl_open ... tsl_close)."""
 
     def __init__(self, n1, n2, r, lam, A0, B0, step_mode="mm", mu=0.0, allow_lambda0=False,
-                 seed=0, stream_id=0, pool=None, stream=None):
+                 seed=0, stream_id=0, pool=None, stream=None, route="kspace"):
         self.n1, self.n2, self.r = int(n1), int(n2), int(r)
-        self.opts = make_opts(step_mode, mu, allow_lambda0, seed, stream_id)
+        self.opts = make_opts(step_mode, mu, allow_lambda0, seed, stream_id, route)
         a = _dev(A0, torch.complex64, (n1, r), "A0")
         b = _dev(B0, torch.complex64, (n2, r), "B0")
         h = ctypes.c_void_p()

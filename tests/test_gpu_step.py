@@ -101,14 +101,15 @@ def _random_state(n1, n2, r, seed):
 @pytest.mark.parametrize("n1,n2,r,nrows", [(64, 64, 8, 20), (256, 256, 32, 32), (120, 200, 5, 37),
                                            (192, 160, 16, 1), (128, 128, 64, 128), (160, 320, 24, 11),
                                            (384, 96, 48, 200), (16, 8, 3, 16)])
-def test_one_line_step_matches_oracle(T, n1, n2, r, nrows):
-    print(f"one step lines {n1}x{n2} r={r} rows={nrows}", flush=True)
+@pytest.mark.parametrize("route", ["kspace", "frame"])
+def test_one_line_step_matches_oracle(T, n1, n2, r, nrows, route):
+    print(f"one step lines {n1}x{n2} r={r} rows={nrows} route={route}", flush=True)
     rng, A0, B0 = _random_state(n1, n2, r, n1 + 7 * n2 + r)
     rows = np.sort(rng.choice(n1, nrows, replace=False)).astype(np.int32)
     Y = cn(rng, (nrows, n2), 1.0 / (n1 * n2) * 50).astype(np.complex64)
     lam = 0.05
     ora = oracle.TslOracle(n1, n2, r, lam, A0, B0)
-    seq = T.Sequence(n1, n2, r, lam, dev(A0), dev(B0))
+    seq = T.Sequence(n1, n2, r, lam, dev(A0), dev(B0), route=route)
     o = Outs(n1, n2, r)
     for t in range(3):
         s = ora.push_lines(rows, Y)
@@ -174,12 +175,13 @@ def test_config1_exact_recovery(T):
 
 
 @pytest.mark.parametrize("T_frames", [60])
-def test_config2_trajectory_lines(T, T_frames):
-    print(f"config 2 trajectory T={T_frames}", flush=True)
+@pytest.mark.parametrize("route", ["kspace", "frame"])
+def test_config2_trajectory_lines(T, T_frames, route):
+    print(f"config 2 trajectory T={T_frames} route={route}", flush=True)
     c = I.config2(T=T_frames)
     n1, n2, r = c["n1"], c["n2"], c["r"]
     ora = oracle.TslOracle(n1, n2, r, 0.05, c["A0"], c["B0"])
-    seq = T.Sequence(n1, n2, r, 0.05, dev(c["A0"]), dev(c["B0"]))
+    seq = T.Sequence(n1, n2, r, 0.05, dev(c["A0"]), dev(c["B0"]), route=route)
     o = Outs(n1, n2, r)
     worst = {}
     for t, fr in enumerate(c["frames"]):
@@ -188,7 +190,7 @@ def test_config2_trajectory_lines(T, T_frames):
         e = compare_step(o, s, f"t={t + 1}")
         for k, v in e.items():
             worst[k] = max(worst.get(k, 0), v)
-    print("config 2 worst NRMSE", worst, flush=True)
+    print(f"config 2 ({route}) worst NRMSE", worst, flush=True)
     seq.close()
 
 
@@ -312,8 +314,9 @@ def test_step_many_equals_single_pushes_and_oracle(T):
     seqs, solo, oras, outs, outs_solo = [], [], [], [], []
     for k, (n1, n2, r) in enumerate(specs):
         _, A0, B0 = _random_state(n1, n2, r, 500 + k)
-        seqs.append(T.Sequence(n1, n2, r, 0.05, dev(A0), dev(B0)))
-        solo.append(T.Sequence(n1, n2, r, 0.05, dev(A0), dev(B0)))
+        route = "frame" if k % 2 else "kspace"     # both routes, and one shape on both (own groups)
+        seqs.append(T.Sequence(n1, n2, r, 0.05, dev(A0), dev(B0), route=route))
+        solo.append(T.Sequence(n1, n2, r, 0.05, dev(A0), dev(B0), route=route))
         oras.append(oracle.TslOracle(n1, n2, r, 0.05, A0, B0))
         outs.append(Outs(n1, n2, r))
         outs_solo.append(Outs(n1, n2, r))
