@@ -106,9 +106,9 @@ def phase_work(n1, n2, r, rows, K, kspace=True):
         "row inverse + A grad": (c * (P + a + b), f2 + 8 * P * r, "mfma"),
         "k-space residual + gradients": (c * (rows * n2 + 2 * rows * r + 2 * b) + 4 * rows,
                                          3 * 8 * rows * n2 * r, "mfma"),
-        "A update + F_l A": (c * 4 * a, (10 if kspace else 5) * a * math.log2(n1) + 8 * a, "fp32"),
-        "B update + F_r B + row draw": (c * 4 * b + c * a + 4 * K, 10 * b * math.log2(n2) + 8 * b + 6 * a, "fp32"),
-        "output synthesis": (c * (P + a + b), 8 * P * r, "mfma"),
+        "factor updates + F_l A, F_r B": (c * 4 * (a + b), (10 if kspace else 5) * a * math.log2(n1) + 8 * a
+                                          + 10 * b * math.log2(n2) + 8 * b, "fp32"),
+        "output synthesis + row draw": (c * (P + a + b) + c * a + 4 * K, 8 * P * r + 6 * a, "mfma"),
     }
 
 
@@ -122,9 +122,8 @@ PHASE_KERNELS = {   # kernel of each phase in a table launch of n x n frames
     "column pass + residual": "void k_col_resid<{n}, FrameTable>",
     "row inverse + A grad": "void k_row_inv_grad<{n}, FrameTable>",
     "k-space residual + gradients": "void k_kres<FrameTable>",
-    "A update + F_l A": "void k_update_a<{n}, FrameTable>",
-    "B update + F_r B + row draw": "void k_update_b<{n}, FrameTable>",
-    "output synthesis": "void k_synth_out<FrameTable>",
+    "factor updates + F_l A, F_r B": "void k_update_ab<{n}, FrameTable>",
+    "output synthesis + row draw": "void k_synth_out<FrameTable>",
 }
 COUNTERS = os.path.join(ROOT, "profiles", "step_64x256sq_r32_counters.json")
 

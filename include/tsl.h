@@ -97,7 +97,7 @@ typedef struct {
 } tsl_opts;
 
 /* Number of timed phases reported by tsl_step_many_timed. */
-#define TSL_N_PHASES 9
+#define TSL_N_PHASES 8
 
 /* One frame of one sequence, for tsl_push_frame and tsl_step_many.  `mask`
    non-NULL selects a point mask (see tsl_push_points); otherwise the sample
@@ -197,9 +197,9 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
    brackets each of the TSL_N_PHASES phases (partial Grams; solve and step
    size; synthesis + row transform; column transform + residual + column
    inverse; row inverse + A gradient [these three: frame route]; k-space
-   residual + gradient contractions [k-space route]; A update + F_l A; B
-   gradient + update + F_r B beside the row draw; output synthesis) with HIP
-   events on `stream`, waits, and
+   residual + gradient contractions [k-space route]; factor updates with
+   F_l A and F_r B of the new factors; output synthesis beside the row draw)
+   with HIP events on `stream`, waits, and
    ADDS each phase's elapsed milliseconds to phase_ms[TSL_N_PHASES] (host). */
 int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, double* phase_ms,
                         void* stream);

@@ -110,8 +110,13 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     return a;
 }
 
+hipError_t launch_updates(const tsl::Batch& b, hipStream_t st) {
+    hipError_t e = tsl::launch_update_a(b, st);
+    return e != hipSuccess ? e : tsl::launch_update_b(b, st);
+}
+
 // The phases of one step (Algorithm 3 with one coil; Algorithm 4's draw of the
-// next rows runs inside the B-update launch).  A group runs either the three
+// next rows runs inside the output launch, beside the output tiles).  A group runs either the three
 // frame-route phases or the k-space one; the other launchers return at once.
 using PhaseFn = hipError_t (*)(const tsl::Batch&, hipStream_t);
 struct Phase {
@@ -125,9 +130,8 @@ const Phase kPhases[TSL_N_PHASES] = {
     {tsl::launch_col_resid, "column pass + residual"},     // a5 (columns), a6, a7 (columns)
     {tsl::launch_row_inv_grad, "row inverse + A grad"},    // a7 (rows), a9
     {tsl::launch_kres, "k-space residual + gradients"},    // a4-a7 and a9's contractions on the samples
-    {tsl::launch_update_a, "A update + F_l A"},            // a9, a1
-    {tsl::launch_update_b, "B update + F_r B + row draw"}, // a9, a1; a11 in one more block per frame
-    {tsl::launch_synth_out, "output synthesis"},           // a10
+    {launch_updates, "factor updates + F_l A, F_r B"},     // a9, a1 (one launch when n1 == n2)
+    {tsl::launch_synth_out, "output synthesis + row draw"},  // a10; a11 in one more block per frame
 };
 
 // Launches every phase for every group, phase by phase; with `ev` non-null,

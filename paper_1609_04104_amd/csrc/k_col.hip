@@ -19,7 +19,6 @@
 #include "fft_engine.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
-#include "sampler.hpp"
 
 namespace tsl {
 namespace {
@@ -237,41 +236,58 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
 }
 
 // ---------------------------------------------------------------- K4 (A)
-template <int N1, class Src>
-__global__ void __launch_bounds__(512) k_update_a(Src src) {
+// Block bx of the A update of one frame (ranks [kTW bx, kTW bx + kTW)); s_tw
+// holds N1 twiddles, s_x the exchange area of ColShape<N1>.
+template <int N1>
+__device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2* s_tw, float2* s_x) {
     using S = ColShape<N1>;
     constexpr int P = S::P, Q = S::Q, T = S::T;
-    __shared__ float2 s_tw[N1];
-    __shared__ float2 s_x[S::XSIZE];
-    if (!src.live()) return;
-    const DevFrame f = src.get();
-    if (!block_frame_ok(f.dev, true)) return;
     const int R = f.r;
-    if (src.bx() * kTW >= R) return;
-    SeqDev* d = f.dev;
-    const double mu = d->mu, sh = d->shrink;
+    if (bx * kTW >= R) return;
     const int tid = threadIdx.x, c = tid % kTW, s = tid / kTW;
-    const int r = src.bx() * kTW + c;
+    const int r = bx * kTW + c;
     const bool rv = r < R;
-    const double2 g = rv ? f.gamma64[r] : double2{0.0, 0.0};
+    // Loads that need only the descriptor go out before the status check (inside
+    // the frame's own buffers): twiddles, gamma, GA and A (k-space route: A at
+    // the update's layout after the transform; frame route: both in row order).
     load_tw<N1>(s_tw);
-    if (src.bx() == 0 && tid == 0) {
-        d->abar = d->abar_new;
-        d->t = d->t_new;
-    }
-    float2 v[T];
+    const double2 g = rv ? f.gamma64[r] : double2{0.0, 0.0};
+    float2 v[T], apre[T];
     zero(v);
+    zero(apre);
     if (f.kspace) {
-        // k-space route: Theta conj(B) = F_l^H M with M = E conj(Bhat) on the
-        // sampled rows and zero elsewhere (as the k-space residual kernel left GA);
-        // then the update in the transform's output layout and F_l A of the new
-        // A, as in the B update.
         if (s < Q && rv) {
             sfor<P>([&](auto qc) {
                 constexpr int n1c = decltype(qc)::value;
                 v[n1c] = f.GA[size_t(Q * n1c + s) * R + r];
             });
         }
+        if (s < P && rv) {
+            sfor<Q>([&](auto k) {
+                constexpr int k2 = decltype(k)::value;
+                apre[k2] = f.A[size_t(s + P * k2) * R + r];
+            });
+        }
+    } else if (s < Q && rv) {
+        sfor<P>([&](auto q) {
+            constexpr int n1c = decltype(q)::value;
+            const size_t at = size_t(Q * n1c + s) * R + r;
+            apre[n1c] = f.A[at];
+            v[n1c] = f.GA[at];
+        });
+    }
+    if (!block_frame_ok(f.dev, true)) return;
+    SeqDev* d = f.dev;
+    const double mu = d->mu, sh = d->shrink;
+    if (bx == 0 && tid == 0) {
+        d->abar = d->abar_new;
+        d->t = d->t_new;
+    }
+    if (f.kspace) {
+        // k-space route: Theta conj(B) = F_l^H M with M = E conj(Bhat) on the
+        // sampled rows and zero elsewhere (as the k-space residual kernel left GA);
+        // then the update in the transform's output layout and F_l A of the new
+        // A, as in the B update.
         __syncthreads();
         if (s < Q) dft_twiddle<N1, P, true>(v, s, s_tw);
         col_swap_nk<N1>(v, s_x, c, s);
@@ -283,7 +299,7 @@ __global__ void __launch_bounds__(512) k_update_a(Src src) {
                 float2 an{0.f, 0.f};
                 if (rv) {
                     const size_t at = size_t(s + P * k2) * R + r;
-                    const float2 a = f.A[at];
+                    const float2 a = apre[k2];
                     const double gr = double(ga.x) * g.x + double(ga.y) * g.y;
                     const double gi = double(ga.y) * g.x - double(ga.x) * g.y;
                     an = float2{float(sh * a.x + mu * gr), float(sh * a.y + mu * gi)};
@@ -310,7 +326,7 @@ __global__ void __launch_bounds__(512) k_update_a(Src src) {
         sfor<P>([&](auto q) {
             constexpr int n1c = decltype(q)::value;
             const size_t at = size_t(Q * n1c + s) * R + r;
-            const float2 a = f.A[at], ga = f.GA[at];
+            const float2 a = apre[n1c], ga = v[n1c];
             // ga * conj(gamma) in double
             const double gr = double(ga.x) * g.x + double(ga.y) * g.y;
             const double gi = double(ga.y) * g.x - double(ga.x) * g.y;
@@ -334,59 +350,66 @@ __global__ void __launch_bounds__(512) k_update_a(Src src) {
     }
 }
 
+template <int N1, class Src>
+__global__ void __launch_bounds__(512) k_update_a(Src src) {
+    __shared__ float2 s_tw[N1];
+    __shared__ float2 s_x[ColShape<N1>::XSIZE];
+    if (!src.live()) return;
+    update_a_body<N1>(src.get(), src.bx(), s_tw, s_x);
+}
+
 // ---------------------------------------------------------------- K4 (B)
-// Blocks [0, gb) of a frame update B; block gb, when present, draws the frame's
-// next rows (Algorithm 4), which needs only F_l A of the new A and so runs
-// beside the B update.  The two roles share one LDS area.
-template <int N2, class Src>
-__global__ void __launch_bounds__(512) k_update_b(Src src, int gb) {
+// Block bx of the B update of one frame, as the A update above.
+template <int N2>
+__device__ __forceinline__ void update_b_body(const DevFrame& f, int bx, float2* s_tw, float2* s_x) {
     using S = ColShape<N2>;
     constexpr int P = S::P, Q = S::Q, T = S::T;
-    constexpr size_t kUB = (size_t(N2) + S::XSIZE) * sizeof(float2);
-    __shared__ __align__(16) unsigned char s_raw[kUB > sizeof(SampleLds) ? kUB : sizeof(SampleLds)];
-    if (!src.live()) return;
-    const DevFrame f = src.get();
-    if (src.bx() >= gb) {
-        draw_rows(f, *reinterpret_cast<SampleLds*>(s_raw));
-        return;
-    }
-    float2* s_tw = reinterpret_cast<float2*>(s_raw);
-    float2* s_x = s_tw + N2;
-    if (!block_frame_ok(f.dev, true)) return;
     const int R = f.r;
-    if (src.bx() * kTW >= R) return;
-    const SeqDev* d = f.dev;
-    const double mu = d->mu, sh = d->shrink;
+    if (bx * kTW >= R) return;
     const int tid = threadIdx.x, c = tid % kTW, s = tid / kTW;
-    const int r = src.bx() * kTW + c;
+    const int r = bx * kTW + c;
     const bool rv = r < R;
-    const double2 g = rv ? f.gamma64[r] : double2{0.0, 0.0};
+    // Loads that need only the descriptor go out before the status check (inside
+    // the frame's own buffers): twiddles, gamma, W (on the k-space route the
+    // first chunk's partial), B at the update's layout and the row count.
     load_tw<N2>(s_tw);
+    const double2 g = rv ? f.gamma64[r] : double2{0.0, 0.0};
     float2 v[T];
     zero(v);
     if (s < Q && rv) {
-        if (f.kspace) {
-            // W = sum over the chunks of sampled rows of E^T conj(Ahat_S), in chunk
-            // order, two chunks' loads in flight at a time
-            const int nqc = cdiv(frame_rows(f), kKQ);
-            for (int c0 = 0; c0 < nqc; c0 += 2) {
-                float2 w0[P], w1[P];
-                sfor<P>([&](auto q) {
-                    constexpr int n1c = decltype(q)::value;
-                    const size_t at = size_t(Q * n1c + s) * R + r;
-                    w0[n1c] = f.wpart[size_t(c0) * N2 * R + at];
-                    w1[n1c] = c0 + 1 < nqc ? float2(f.wpart[size_t(c0 + 1) * N2 * R + at]) : float2{0.f, 0.f};
-                });
-                sfor<P>([&](auto q) {
-                    constexpr int n1c = decltype(q)::value;
-                    v[n1c] = cadd(v[n1c], w0[n1c]);
-                    if (c0 + 1 < nqc) v[n1c] = cadd(v[n1c], w1[n1c]);
-                });
-            }
-        } else {
+        sfor<P>([&](auto q) {
+            constexpr int n1c = decltype(q)::value;
+            const size_t at = size_t(Q * n1c + s) * R + r;
+            v[n1c] = f.kspace ? f.wpart[at] : f.Wb[at];
+        });
+    }
+    float2 bpre[Q];
+    sfor<Q>([&](auto k) {
+        constexpr int k2 = decltype(k)::value;
+        bpre[k2] = (s < P && rv) ? float2(f.B[size_t(s + P * k2) * R + r]) : float2{0.f, 0.f};
+    });
+    const int cap = frame_rows_cap(f);
+    const int nd = (f.kspace && f.n_rows_dev) ? *f.n_rows_dev : cap;
+    if (!block_frame_ok(f.dev, true)) return;
+    const SeqDev* d = f.dev;
+    const double mu = d->mu, sh = d->shrink;
+    if (f.kspace && s < Q && rv) {
+        // W = sum over the chunks of sampled rows of E^T conj(Ahat_S), in chunk
+        // order (the first is already in v), two chunks' loads in flight at a time
+        const int nqc = cdiv(nd < 0 ? 0 : (nd > cap ? cap : nd), kKQ);
+        if (nqc == 0) zero(v);
+        for (int c0 = 1; c0 < nqc; c0 += 2) {
+            float2 w0[P], w1[P];
             sfor<P>([&](auto q) {
                 constexpr int n1c = decltype(q)::value;
-                v[n1c] = f.Wb[size_t(Q * n1c + s) * R + r];
+                const size_t at = size_t(Q * n1c + s) * R + r;
+                w0[n1c] = f.wpart[size_t(c0) * N2 * R + at];
+                w1[n1c] = c0 + 1 < nqc ? float2(f.wpart[size_t(c0 + 1) * N2 * R + at]) : float2{0.f, 0.f};
+            });
+            sfor<P>([&](auto q) {
+                constexpr int n1c = decltype(q)::value;
+                v[n1c] = cadd(v[n1c], w0[n1c]);
+                if (c0 + 1 < nqc) v[n1c] = cadd(v[n1c], w1[n1c]);
             });
         }
     }
@@ -402,7 +425,7 @@ __global__ void __launch_bounds__(512) k_update_b(Src src, int gb) {
             float2 bn{0.f, 0.f};
             if (rv) {
                 const size_t at = size_t(s + P * k2) * R + r;
-                const float2 b = f.B[at];
+                const float2 b = bpre[k2];
                 const double gr = double(gb.x) * g.x + double(gb.y) * g.y;
                 const double gi = double(gb.y) * g.x - double(gb.x) * g.y;
                 bn = float2{float(sh * b.x + mu * gr), float(sh * b.y + mu * gi)};
@@ -424,6 +447,26 @@ __global__ void __launch_bounds__(512) k_update_b(Src src, int gb) {
             });
         }
     }
+}
+
+template <int N2, class Src>
+__global__ void __launch_bounds__(512) k_update_b(Src src) {
+    __shared__ float2 s_tw[N2];
+    __shared__ float2 s_x[ColShape<N2>::XSIZE];
+    if (!src.live()) return;
+    update_b_body<N2>(src.get(), src.bx(), s_tw, s_x);
+}
+
+// Both updates in one launch for square frames (they are independent: each
+// uses the factors of frame t - 1): blocks [0, ga) update A, the rest B.
+template <int N, class Src>
+__global__ void __launch_bounds__(512) k_update_ab(Src src, int ga) {
+    __shared__ float2 s_tw[N];
+    __shared__ float2 s_x[ColShape<N>::XSIZE];
+    if (!src.live()) return;
+    const DevFrame f = src.get();
+    if (src.bx() < ga) update_a_body<N>(f, src.bx(), s_tw, s_x);
+    else update_b_body<N>(f, src.bx() - ga, s_tw, s_x);
 }
 
 // ---------------------------------------------------------------- standalone column pass
@@ -473,20 +516,25 @@ template <int N1> hipError_t launch_k2_n(const Batch& b, hipStream_t st) {
 }
 template <int N1> hipError_t launch_k4a_n(const Batch& b, hipStream_t st) {
     using S = ColShape<N1>;
-    const int gx = cdiv(b.r_max, kTW);
-    const dim3 grid = frame_grid(b, gx);
-    if (b.table) k_update_a<N1, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table, gx, b.count});
+    const int ga = cdiv(b.r_max, kTW);
+    if (b.n1 == b.n2) {                       // both updates in one launch
+        const int gx = 2 * ga;
+        const dim3 grid = frame_grid(b, gx);
+        if (b.table) k_update_ab<N1, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table, gx, b.count}, ga);
+        else k_update_ab<N1, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one}, ga);
+        return hipGetLastError();
+    }
+    const dim3 grid = frame_grid(b, ga);
+    if (b.table) k_update_a<N1, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table, ga, b.count});
     else k_update_a<N1, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 template <int N2> hipError_t launch_k4b_n(const Batch& b, hipStream_t st) {
     using S = ColShape<N2>;
     const int gb = cdiv(b.r_max, kTW);
-    const int gx = gb + (b.want_sample ? 1 : 0);
-    const int threads = b.want_sample ? std::max(S::THREADS64, kSampleThreads) : S::THREADS;
-    const dim3 grid = frame_grid(b, gx);
-    if (b.table) k_update_b<N2, FrameTable><<<grid, threads, 0, st>>>(FrameTable{b.table, gx, b.count}, gb);
-    else k_update_b<N2, OneFrame><<<grid, threads, 0, st>>>(OneFrame{*b.one}, gb);
+    const dim3 grid = frame_grid(b, gb);
+    if (b.table) k_update_b<N2, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table, gb, b.count});
+    else k_update_b<N2, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 template <int N1>
@@ -521,6 +569,7 @@ hipError_t launch_update_a(const Batch& b, hipStream_t st) {
 }
 
 hipError_t launch_update_b(const Batch& b, hipStream_t st) {
+    if (b.n1 == b.n2) return hipSuccess;      // launched with the A update
     switch (b.n2) {
 #define TSL_X(N) case N: return launch_k4b_n<N>(b, st);
         TSL_FOR_EACH_N(TSL_X)

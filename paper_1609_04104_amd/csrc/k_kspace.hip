@@ -63,7 +63,6 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
     __shared__ int s_bad;
     if (!src.live()) return;
     const DevFrame f = src.get();
-    if (!block_frame_ok(f.dev, true)) return;
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x, RP = R + 1;
     const int JC = kres_cols(R);
     float2* s_b = s_dyn;
@@ -72,30 +71,45 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
     const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const int m = lane % 16, g4 = lane / 16;
     const bool pim = g4 & 1;                         // which part this lane's K entry takes
-    const int S = frame_rows(f), qc = src.bx(), q0 = qc * kKQ;
-    const int nq = max(0, min(kKQ, S - q0));
-    for (int r = tid; r < R; r += kKT) s_g[r] = f.gamma32[r];
+    const int qc = src.bx(), q0 = qc * kKQ;
+    // Loads that need nothing but the descriptor go out before the status check
+    // (all inside the frame's own buffers): the row count, the row list, gamma
+    // and the first round of the first chunk of Bhat.
+    const int cap = frame_rows_cap(f);
+    const int nd = f.n_rows_dev ? *f.n_rows_dev : cap;
+    const int row_mine = (tid < kKQ && q0 + tid < cap) ? f.rows[q0 + tid] : -1;
+    const int row_list = tid < cap ? f.rows[tid] : -1;
+    const float2 gam = tid < R ? float2(f.gamma32[tid]) : float2{0.f, 0.f};
+    float2 b0[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + u * kKT, j = e / R;
+        b0[u] = (e < JC * R && j < n2) ? float2(f.Bhat[e]) : float2{0.f, 0.f};
+    }
     for (int i = tid; i < n1; i += kKT) s_on[i] = 0;
     if (tid == 0) s_bad = 0;
-    if (tid < kKQ) {
-        const int row = tid < nq ? f.rows[q0 + tid] : -1;
-        s_row[tid] = (row >= 0 && row < n1) ? row : -1;
-    }
-    __syncthreads();
-    for (int q = tid; q < S; q += kKT) {
+    if (!block_frame_ok(f.dev, true)) return;        // its barriers also order the resets above
+    const int S = nd < 0 ? 0 : (nd > cap ? cap : nd);
+    const int nq = max(0, min(kKQ, S - q0));
+    if (tid < R) s_g[tid] = gam;
+    for (int r = tid + kKT; r < R; r += kKT) s_g[r] = f.gamma32[r];
+    if (tid < kKQ) s_row[tid] = (tid < nq && row_mine >= 0 && row_mine < n1) ? row_mine : -1;
+    if (tid < S && row_list >= 0 && row_list < n1) s_on[row_list] = 1;
+    for (int q = tid + kKT; q < S; q += kKT) {
         const int row = f.rows[q];
         if (row >= 0 && row < n1) s_on[row] = 1;
     }
+    __syncthreads();
     // Ahat rows of the block
     for (int e = tid; e < kKQ * R; e += kKT) {
         const int q = e / R, c = e % R, row = s_row[q];
         s_a[q * RP + c] = row >= 0 ? float2(f.Ahat[size_t(row) * R + c]) : float2{0.f, 0.f};
     }
-    __syncthreads();
     // rows of GA that this block zeroes: the unsampled rows i with i mod nblk = qc
-    for (int e = tid; e < n1 * R; e += kKT) {
-        const int i = e / R;
-        if (i % nblk == qc && !s_on[i]) f.GA[e] = float2{0.f, 0.f};
+    const int nown = qc < n1 ? cdiv(n1 - qc, nblk) : 0;
+    for (int e = tid; e < nown * R; e += kKT) {
+        const int i = qc + (e / R) * nblk;
+        if (!s_on[i]) f.GA[size_t(i) * R + e % R] = float2{0.f, 0.f};
     }
     if (nq == 0) return;                             // uniform
 
@@ -119,7 +133,8 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int e = e0 + tid + u * kKT, j = e / R;
-                    bv[u] = (e < JC * R && j0 + j < n2) ? float2(f.Bhat[size_t(j0) * R + e]) : float2{0.f, 0.f};
+                    bv[u] = (j0 == 0 && e0 == 0) ? b0[u]
+                          : (e < JC * R && j0 + j < n2) ? float2(f.Bhat[size_t(j0) * R + e]) : float2{0.f, 0.f};
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {

@@ -96,13 +96,29 @@ __device__ void gram_staged(const double2* s_x, int nq, int R, double2* out) {
 
 // Factor-Gram block b: rows [kGRows b, kGRows (b+1)) of F_l A for b < n_gparts(n1),
 // else the corresponding rows of F_r B; the partial goes to slot b.
-__device__ void factor_gram_block(const DevFrame& f, int b, double2* s_x) {
+// With check, the frame's status is read after the first round of loads is in
+// flight (the loads stay inside the factor either way).
+__device__ void factor_gram_block(const DevFrame& f, int b, double2* s_x, bool check) {
     const int gA = n_gparts(f.n1), R = f.r;
     const bool isA = b < gA;
     const int n = isA ? f.n1 : f.n2, q0 = (isA ? b : b - gA) * kGRows, nq = min(kGRows, n - q0);
     GlobalPtr<const float2> X = (isA ? f.Ahat : f.Bhat) + size_t(q0) * R;
-    stage_copy<8, float2>(nq * R, [&](int e) { return X[e]; },
-                          [&](int e, float2 v) { s_x[e] = double2{v.x, v.y}; });
+    constexpr int kFL = 8;
+    const int ne = nq * R;
+    for (int e0 = 0; e0 < ne; e0 += kFL * kSB) {
+        float2 v[kFL];
+#pragma unroll
+        for (int u = 0; u < kFL; ++u) {
+            const int e = e0 + int(threadIdx.x) + u * kSB;
+            v[u] = e < ne ? float2(X[e]) : float2{0.f, 0.f};
+        }
+        if (e0 == 0 && check && !block_frame_ok(f.dev, false)) return;   // uniform
+#pragma unroll
+        for (int u = 0; u < kFL; ++u) {
+            const int e = e0 + int(threadIdx.x) + u * kSB;
+            if (e < ne) s_x[e] = double2{v[u].x, v[u].y};
+        }
+    }
     __syncthreads();
     gram_staged(s_x, nq, R, f.part + size_t(b) * R * R);
 }
@@ -121,46 +137,52 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     __shared__ int s_row[kSRows];
     if (!src.live()) return;
     const DevFrame f = src.get();
-    if (!block_frame_ok(f.dev, false)) return;
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
     const int gAB = n_gparts(n1) + n_gparts(n2);
     if (src.bx() < gAB) {
-        factor_gram_block(f, src.bx(), s_dyn);
+        factor_gram_block(f, src.bx(), s_dyn, true);
         return;
     }
     const int nJ = n_jparts(n2);
     const int k = (src.bx() - gAB) / nJ, c = (src.bx() - gAB) % nJ;
-    if (tid == 0) s_err = 0;
-    __syncthreads();
-    const int n_rows = frame_rows(f);
-    if (k == 0 && c == 0 && tid == 0 && f.n_rows_dev) {
-        const int nd = *f.n_rows_dev;
-        if (nd < 0 || nd > frame_rows_cap(f)) latch(f.dev, ST_EINVAL);
-    }
     const int q0 = k * kSRows;
-    if (q0 >= n_rows) return;
-    const int nq = min(n_rows, q0 + kSRows) - q0;
-    double2* s_x = s_dyn;                     // [kSRows][R]  sampled rows of F_l A
-    double2* s_b = s_x + kSRows * R;          // [kJCH][R]    rows of F_r B in the readout chunk
-    double2* s_y = s_b + kJCH * R;            // [kSRows][kJCH] samples
     const int j0 = c * kJCH, nj = min(kJCH, n2 - j0);
-    // Staging in two rounds of loads: the readout chunk of F_r B goes out with
-    // the row indices; the sampled rows of F_l A and their samples follow once
-    // the indices are in LDS.
+    // Loads that need nothing but the descriptor go out before the status check
+    // (inside the frame's own buffers): the row count, the block's row indices
+    // (and each next one, for the ascending check) and the readout chunk of F_r B.
+    const int cap = frame_rows_cap(f);
+    const int nd = f.n_rows_dev ? *f.n_rows_dev : cap;
+    const int row_raw = (tid < kSRows && q0 + tid < cap) ? f.rows[q0 + tid] : -1;
+    const int next_raw = (c == 0 && tid < kSRows && q0 + tid + 1 < cap) ? f.rows[q0 + tid + 1] : -1;
     constexpr int kBL = cdiv(kJCH * TSL_MAX_R, kSB), kXL = cdiv(kSRows * TSL_MAX_R, kSB);
     constexpr int kYL = cdiv(kSRows * kJCH, kSB);
-    const int nb = nj * R, nx = nq * R, ny = nq * kJCH;
+    const int nb = nj * R;
     float2 bv[kBL];
 #pragma unroll
     for (int u = 0; u < kBL; ++u) {
         const int e = tid + u * kSB;
         bv[u] = e < nb ? float2(f.Bhat[size_t(j0) * R + e]) : float2{0.f, 0.f};
     }
+    if (tid == 0) s_err = 0;
+    if (!block_frame_ok(f.dev, false)) return;      // its barriers also order s_err's reset
+    const int n_rows = nd < 0 ? 0 : (nd > cap ? cap : nd);
+    if (k == 0 && c == 0 && tid == 0 && f.n_rows_dev && (nd < 0 || nd > cap)) latch(f.dev, ST_EINVAL);
+    if (q0 >= n_rows) return;
+    const int nq = min(n_rows, q0 + kSRows) - q0;
+    double2* s_x = s_dyn;                     // [kSRows][R]  sampled rows of F_l A
+    // the readout chunk of F_r B and the samples stay complex64 in LDS (widened
+    // when read), which keeps a block at 32 KiB at R = 32
+    float2* s_b = reinterpret_cast<float2*>(s_x + kSRows * R);   // [kJCH][R]
+    float2* s_y = s_b + kJCH * R;                                 // [kSRows][kJCH]
+    // Staging in two rounds of loads: the readout chunk of F_r B went out with
+    // the row indices; the sampled rows of F_l A and their samples follow once
+    // the indices are in LDS.
+    const int nx = nq * R, ny = nq * kJCH;
     if (tid < nq) {                           // rows inside [0, n1), strictly ascending
-        const int q = q0 + tid, row = f.rows[q];
+        const int q = q0 + tid, row = row_raw;
         bool ok = row >= 0 && row < n1;
         if (c == 0) {
-            if (q + 1 < n_rows) ok = ok && f.rows[q + 1] > row;
+            if (q + 1 < n_rows) ok = ok && next_raw > row;
             if (!ok) atomicCAS(&s_err, 0, ST_EINVAL);
         }
         s_row[tid] = (row >= 0 && row < n1) ? row : -1;
@@ -183,7 +205,7 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
 #pragma unroll
     for (int u = 0; u < kBL; ++u) {
         const int e = tid + u * kSB;
-        if (e < nb) s_b[e] = double2{bv[u].x, bv[u].y};
+        if (e < nb) s_b[e] = bv[u];
     }
 #pragma unroll
     for (int u = 0; u < kXL; ++u) {
@@ -195,7 +217,7 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
         const int e = tid + u * kSB;
         if (e < ny) {
             fin = fin && finite2(yv[u]);
-            s_y[e] = double2{yv[u].x, yv[u].y};
+            s_y[e] = yv[u];
         }
     }
     __syncthreads();
@@ -218,7 +240,8 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
             const int tile = wave + (kSB / 64) * u;
             if (tile >= nzt) break;
             const int q = 16 * (tile / TMr) + m, r = 16 * (tile % TMr) + m, jc = min(j, nj - 1);
-            const double2 yv0 = s_y[min(q, nq - 1) * kJCH + jc], bv0 = s_b[jc * R + min(r, R - 1)];
+            const float2 yf = s_y[min(q, nq - 1) * kJCH + jc], bf = s_b[jc * R + min(r, R - 1)];
+            const double2 yv0{yf.x, yf.y}, bv0{bf.x, bf.y};
             const double2 yv = (q < nq && j < nj) ? yv0 : double2{0.0, 0.0};
             const double2 bv = (r < R && j < nj) ? bv0 : double2{0.0, 0.0};
             const double bb = p ? bv.y : bv.x;
@@ -226,8 +249,8 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
             zim[u] = mfma_16x16x4_f64(p ? -yv.x : yv.y, bb, zim[u]);
         }
     }
-    __syncthreads();                          // s_b is reused for the products below
-    double2* s_p = s_b;                       // [nq][R]: z[q][r] conj(Ahat_{row_q, r})
+    __syncthreads();                          // s_b and s_y are reused for the products below
+    double2* s_p = reinterpret_cast<double2*>(s_b);   // [nq][R]: z[q][r] conj(Ahat_{row_q, r})
 #pragma unroll
     for (int u = 0; u < kZT; ++u) {
         const int tile = wave + (kSB / 64) * u;
@@ -249,7 +272,15 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     if (tid == 0 && s_err) latch(f.dev, s_err);
 }
 
-size_t lstats_lds(int R) { return (size_t(kSRows + kJCH) * R + size_t(kSRows) * kJCH) * sizeof(double2); }
+// a factor-Gram block, or a sampled block: rows of F_l A (FP64), then the
+// complex64 chunk of F_r B and samples, later overlaid by the FP64 products
+size_t lstats_lds(int R) {
+    const size_t gram = size_t(kGRows) * R * sizeof(double2);
+    const size_t staged = size_t(kJCH * R + kSRows * kJCH) * sizeof(float2);
+    const size_t prod = size_t(kSRows) * R * sizeof(double2);
+    const size_t samp = size_t(kSRows) * R * sizeof(double2) + (staged > prod ? staged : prod);
+    return gram > samp ? gram : samp;
+}
 
 constexpr int kPW = 32;        // sampled entries staged per window of a point-mask Gram
 constexpr int kMaxAcc = 8;     // Gram entries one thread accumulates per pass (point masks)
@@ -269,7 +300,7 @@ __global__ void __launch_bounds__(kSB) k_pstats(Src src) {
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
     const int gAB = n_gparts(n1) + n_gparts(n2);
     if (src.bx() < gAB) {
-        factor_gram_block(f, src.bx(), s_dyn);
+        factor_gram_block(f, src.bx(), s_dyn, false);
         return;
     }
     const int k = src.bx() - gAB;
@@ -814,21 +845,16 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     }
     __syncthreads();
     if (wave == 0 && !s_fail) {
-        double2 lcol[RB];                         // lcol[k] = L_{k, lane}
-        sfor<RB>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            lcol[k] = lane < RB ? s_g[k * RB + lane] : double2{0.0, 0.0};
-        });
+        const int lr = lane % RB;
         sfor<RB>([&](auto kc) {
             constexpr int k = RB - 1 - decltype(kc)::value;
+            const double2 lk = s_g[k * RB + lr];      // L_{k, lane}
             const double2 zk = readlane_d2(hv, k);
             const double ik = readlane_d(dinv, k);
             const double2 gk{zk.x * ik, zk.y * ik};
-            if (lane == k) hv = gk;
-            else if (lane < k) {
-                hv.x = fma(-lcol[k].x, gk.x, fma(-lcol[k].y, gk.y, hv.x));   // - conj(L_{k,lane}) gamma_k
-                hv.y = fma(-lcol[k].x, gk.y, fma(lcol[k].y, gk.x, hv.y));
-            }
+            const double2 hu{fma(-lk.x, gk.x, fma(-lk.y, gk.y, hv.x)),    // - conj(L_{k,lane}) gamma_k
+                             fma(-lk.x, gk.y, fma(lk.y, gk.x, hv.y))};
+            hv = lane == k ? gk : (lane < k ? hu : hv);
         });
         const bool live = lane < R;
         const bool nonfinite = __any(live && (!isfinite(hv.x) || !isfinite(hv.y)));
@@ -904,39 +930,55 @@ constexpr int kOutTile = 64;                 // block tile edge
 constexpr int kOutRC = 32;                   // ranks staged per pass
 constexpr int kOutPitch = kOutRC + 1;        // LDS row pitch (float2): conflict-free column reads
 
+// With ds = 1, block 0 of each frame draws the frame's next rows (Algorithm 4,
+// which needs only F_l A of the new A) beside the output tiles; the two roles
+// share one LDS area.
+constexpr size_t kOutLds = 2 * kOutTile * kOutPitch * sizeof(float2);
 template <class Src>
-__global__ void __launch_bounds__(256) k_synth_out(Src src) {
-    __shared__ float2 s_ag[kOutTile * kOutPitch];   // [row][c] = A[i0 + row][r0 + c] gamma[r0 + c]
-    __shared__ float2 s_b[kOutTile * kOutPitch];    // [row][c] = B[j0 + row][r0 + c]
+__global__ void __launch_bounds__(256) k_synth_out(Src src, int ds) {
+    __shared__ __align__(16) unsigned char s_raw[kOutLds > sizeof(SampleLds) ? kOutLds : sizeof(SampleLds)];
     if (!src.live()) return;
     const DevFrame f = src.get();
+    if (src.bx() < ds) {
+        draw_rows(f, *reinterpret_cast<SampleLds*>(s_raw));
+        return;
+    }
+    float2* s_ag = reinterpret_cast<float2*>(s_raw);   // [row][c] = A[i0 + row][r0 + c] gamma[r0 + c]
+    float2* s_b = s_ag + kOutTile * kOutPitch;         // [row][c] = B[j0 + row][r0 + c]
     if (f.X_out == nullptr) return;
-    if (!block_frame_ok(f.dev, true)) return;
-    const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
+    const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x, tile = src.bx() - ds;
     const int lane = tid % 64, w = tid / 64;
     const int tiles_x = cdiv(n2, kOutTile);
-    const int bi = (src.bx() / tiles_x) * kOutTile, bj = (src.bx() % tiles_x) * kOutTile;
+    const int bi = (tile / tiles_x) * kOutTile, bj = (tile % tiles_x) * kOutTile;
     const int wi = 32 * (w / 2), wj = 32 * (w % 2);    // wavefront tile inside the block tile
     const int m = lane % 32, h = lane / 32;
+    // A, gamma and B of a rank pass, all loads in flight together; the first
+    // pass goes out before the status check (it reads the frame's own factors)
+    constexpr int kOL = kOutTile * kOutRC / 256;
+    float2 la[kOL], lg[kOL], lb[kOL];
+    auto load_pass = [&](int r0) {
+        const int nr = min(kOutRC, R - r0);
+#pragma unroll
+        for (int u = 0; u < kOL; ++u) {
+            const int e = tid + u * 256, row = e / kOutRC, c = e % kOutRC, i = bi + row, j = bj + row;
+            la[u] = (i < n1 && c < nr) ? float2(f.A[size_t(i) * R + r0 + c]) : float2{0.f, 0.f};
+            lg[u] = c < nr ? float2(f.gamma32[r0 + c]) : float2{0.f, 0.f};
+            lb[u] = (j < n2 && c < nr) ? float2(f.B[size_t(j) * R + r0 + c]) : float2{0.f, 0.f};
+        }
+    };
+    load_pass(0);
+    if (!block_frame_ok(f.dev, true)) return;
     f32x16 accr = {}, acci = {};
     for (int r0 = 0; r0 < R; r0 += kOutRC) {
         const int nr = min(kOutRC, R - r0);
         __syncthreads();
-        stage_copy<8, float2>(
-            kOutTile * kOutRC,
-            [&](int e) {
-                const int row = e / kOutRC, c = e % kOutRC, i = bi + row;
-                return (i < n1 && c < nr) ? cmul(float2(f.A[size_t(i) * R + r0 + c]), float2(f.gamma32[r0 + c]))
-                                          : float2{0.f, 0.f};
-            },
-            [&](int e, float2 v) { s_ag[(e / kOutRC) * kOutPitch + e % kOutRC] = v; });
-        stage_copy<8, float2>(
-            kOutTile * kOutRC,
-            [&](int e) {
-                const int row = e / kOutRC, c = e % kOutRC, j = bj + row;
-                return (j < n2 && c < nr) ? float2(f.B[size_t(j) * R + r0 + c]) : float2{0.f, 0.f};
-            },
-            [&](int e, float2 v) { s_b[(e / kOutRC) * kOutPitch + e % kOutRC] = v; });
+        if (r0 > 0) load_pass(r0);
+#pragma unroll
+        for (int u = 0; u < kOL; ++u) {
+            const int e = tid + u * 256, at = (e / kOutRC) * kOutPitch + e % kOutRC;
+            s_ag[at] = cmul(la[u], lg[u]);
+            s_b[at] = lb[u];
+        }
         __syncthreads();
         const float2* pa = s_ag + (wi + m) * kOutPitch;
         const float2* pb = s_b + (wj + m) * kOutPitch;
@@ -957,7 +999,7 @@ __global__ void __launch_bounds__(256) k_synth_out(Src src) {
 }
 
 // ---------------------------------------------------------------- sampler
-// The draw on its own (tsl_sample_lines); a step draws inside the B-update launch.
+// The draw on its own (tsl_sample_lines); a step draws inside the output launch.
 template <class Src>
 __global__ void __launch_bounds__(kSampleThreads) k_sample(Src src) {
     __shared__ SampleLds s_l;
@@ -1030,11 +1072,12 @@ hipError_t launch_solve(const Batch& b, hipStream_t st) {
 }
 
 hipError_t launch_synth_out(const Batch& b, hipStream_t st) {
-    if (!b.want_x) return hipSuccess;
-    const int gx = cdiv(b.n1, kOutTile) * cdiv(b.n2, kOutTile);
+    const int ds = b.want_sample ? 1 : 0;
+    const int gx = ds + (b.want_x ? cdiv(b.n1, kOutTile) * cdiv(b.n2, kOutTile) : 0);
+    if (gx == 0) return hipSuccess;
     const dim3 grid = frame_grid(b, gx);
-    if (b.table) k_synth_out<FrameTable><<<grid, kBlock, 0, st>>>(FrameTable{b.table, gx, b.count});
-    else k_synth_out<OneFrame><<<grid, kBlock, 0, st>>>(OneFrame{*b.one});
+    if (b.table) k_synth_out<FrameTable><<<grid, kBlock, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
+    else k_synth_out<OneFrame><<<grid, kBlock, 0, st>>>(OneFrame{*b.one}, ds);
     return hipGetLastError();
 }
 

@@ -41,10 +41,10 @@ class Opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64), ("line_route", ctypes.c_int)]
 
 
-N_PHASES = 9
+N_PHASES = 8
 PHASES = ["partial Grams", "ridge solve + step size", "synthesis + row pass", "column pass + residual",
-          "row inverse + A grad", "k-space residual + gradients", "A update + F_l A",
-          "B update + F_r B + row draw", "output synthesis"]
+          "row inverse + A grad", "k-space residual + gradients", "factor updates + F_l A, F_r B",
+          "output synthesis + row draw"]
 ROUTE_KSPACE, ROUTE_FRAME = 0, 1
 
 
