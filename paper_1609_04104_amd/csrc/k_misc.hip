@@ -845,16 +845,21 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     }
     __syncthreads();
     if (wave == 0 && !s_fail) {
-        const int lr = lane % RB;
+        double2 lcol[RB];                         // lcol[k] = L_{k, lane}
+        sfor<RB>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            lcol[k] = lane < RB ? s_g[k * RB + lane] : double2{0.0, 0.0};
+        });
         sfor<RB>([&](auto kc) {
             constexpr int k = RB - 1 - decltype(kc)::value;
-            const double2 lk = s_g[k * RB + lr];      // L_{k, lane}
             const double2 zk = readlane_d2(hv, k);
             const double ik = readlane_d(dinv, k);
             const double2 gk{zk.x * ik, zk.y * ik};
-            const double2 hu{fma(-lk.x, gk.x, fma(-lk.y, gk.y, hv.x)),    // - conj(L_{k,lane}) gamma_k
-                             fma(-lk.x, gk.y, fma(lk.y, gk.x, hv.y))};
-            hv = lane == k ? gk : (lane < k ? hu : hv);
+            if (lane == k) hv = gk;
+            else if (lane < k) {
+                hv.x = fma(-lcol[k].x, gk.x, fma(-lcol[k].y, gk.y, hv.x));   // - conj(L_{k,lane}) gamma_k
+                hv.y = fma(-lcol[k].x, gk.y, fma(lcol[k].y, gk.x, hv.y));
+            }
         });
         const bool live = lane < R;
         const bool nonfinite = __any(live && (!isfinite(hv.x) || !isfinite(hv.y)));
@@ -923,19 +928,21 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
 // ones with the rank index split into (r, re/im): with P_re = [Re AG, -Im AG],
 // P_im = [Im AG, Re AG] and Q = [Re B; Im B] (AG = A diag(gamma)),
 // Re X = P_re Q^T and Im X = P_im Q^T, so each rank is one K = 2 step of a
-// 32x32x2 FP32 MFMA for each of the two parts.  A block owns a 64 x 64 tile of
-// X (four 32 x 32 wavefront tiles); the 64 rows of AG and of B it needs are
+// 32x32x2 FP32 MFMA for each of the two parts.  A block owns a 128 x 64 tile of
+// X (eight 32 x 32 wavefront tiles); the rows of AG and of B it needs are
 // staged in LDS with coalesced loads, kOutRC ranks at a time.
-constexpr int kOutTile = 64;                 // block tile edge
+constexpr int kOutTM = 128;                  // block tile rows (i)
+constexpr int kOutTN = 64;                   // block tile columns (j)
+constexpr int kOutThreads = 512;             // eight wavefronts, a 32 x 32 tile each
 constexpr int kOutRC = 32;                   // ranks staged per pass
 constexpr int kOutPitch = kOutRC + 1;        // LDS row pitch (float2): conflict-free column reads
 
 // With ds = 1, block 0 of each frame draws the frame's next rows (Algorithm 4,
 // which needs only F_l A of the new A) beside the output tiles; the two roles
 // share one LDS area.
-constexpr size_t kOutLds = 2 * kOutTile * kOutPitch * sizeof(float2);
+constexpr size_t kOutLds = size_t(kOutTM + kOutTN) * kOutPitch * sizeof(float2);
 template <class Src>
-__global__ void __launch_bounds__(256) k_synth_out(Src src, int ds) {
+__global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     __shared__ __align__(16) unsigned char s_raw[kOutLds > sizeof(SampleLds) ? kOutLds : sizeof(SampleLds)];
     if (!src.live()) return;
     const DevFrame f = src.get();
@@ -944,25 +951,29 @@ __global__ void __launch_bounds__(256) k_synth_out(Src src, int ds) {
         return;
     }
     float2* s_ag = reinterpret_cast<float2*>(s_raw);   // [row][c] = A[i0 + row][r0 + c] gamma[r0 + c]
-    float2* s_b = s_ag + kOutTile * kOutPitch;         // [row][c] = B[j0 + row][r0 + c]
+    float2* s_b = s_ag + kOutTM * kOutPitch;           // [row][c] = B[j0 + row][r0 + c]
     if (f.X_out == nullptr) return;
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x, tile = src.bx() - ds;
     const int lane = tid % 64, w = tid / 64;
-    const int tiles_x = cdiv(n2, kOutTile);
-    const int bi = (tile / tiles_x) * kOutTile, bj = (tile % tiles_x) * kOutTile;
+    const int tiles_x = cdiv(n2, kOutTN);
+    const int bi = (tile / tiles_x) * kOutTM, bj = (tile % tiles_x) * kOutTN;
     const int wi = 32 * (w / 2), wj = 32 * (w % 2);    // wavefront tile inside the block tile
     const int m = lane % 32, h = lane / 32;
     // A, gamma and B of a rank pass, all loads in flight together; the first
     // pass goes out before the status check (it reads the frame's own factors)
-    constexpr int kOL = kOutTile * kOutRC / 256;
-    float2 la[kOL], lg[kOL], lb[kOL];
+    constexpr int kLA = kOutTM * kOutRC / kOutThreads, kLB = kOutTN * kOutRC / kOutThreads;
+    float2 la[kLA], lg[kLA], lb[kLB];
     auto load_pass = [&](int r0) {
         const int nr = min(kOutRC, R - r0);
 #pragma unroll
-        for (int u = 0; u < kOL; ++u) {
-            const int e = tid + u * 256, row = e / kOutRC, c = e % kOutRC, i = bi + row, j = bj + row;
+        for (int u = 0; u < kLA; ++u) {
+            const int e = tid + u * kOutThreads, row = e / kOutRC, c = e % kOutRC, i = bi + row;
             la[u] = (i < n1 && c < nr) ? float2(f.A[size_t(i) * R + r0 + c]) : float2{0.f, 0.f};
             lg[u] = c < nr ? float2(f.gamma32[r0 + c]) : float2{0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+            const int e = tid + u * kOutThreads, row = e / kOutRC, c = e % kOutRC, j = bj + row;
             lb[u] = (j < n2 && c < nr) ? float2(f.B[size_t(j) * R + r0 + c]) : float2{0.f, 0.f};
         }
     };
@@ -974,10 +985,14 @@ __global__ void __launch_bounds__(256) k_synth_out(Src src, int ds) {
         __syncthreads();
         if (r0 > 0) load_pass(r0);
 #pragma unroll
-        for (int u = 0; u < kOL; ++u) {
-            const int e = tid + u * 256, at = (e / kOutRC) * kOutPitch + e % kOutRC;
-            s_ag[at] = cmul(la[u], lg[u]);
-            s_b[at] = lb[u];
+        for (int u = 0; u < kLA; ++u) {
+            const int e = tid + u * kOutThreads;
+            s_ag[(e / kOutRC) * kOutPitch + e % kOutRC] = cmul(la[u], lg[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+            const int e = tid + u * kOutThreads;
+            s_b[(e / kOutRC) * kOutPitch + e % kOutRC] = lb[u];
         }
         __syncthreads();
         const float2* pa = s_ag + (wi + m) * kOutPitch;
@@ -1073,11 +1088,11 @@ hipError_t launch_solve(const Batch& b, hipStream_t st) {
 
 hipError_t launch_synth_out(const Batch& b, hipStream_t st) {
     const int ds = b.want_sample ? 1 : 0;
-    const int gx = ds + (b.want_x ? cdiv(b.n1, kOutTile) * cdiv(b.n2, kOutTile) : 0);
+    const int gx = ds + (b.want_x ? cdiv(b.n1, kOutTM) * cdiv(b.n2, kOutTN) : 0);
     if (gx == 0) return hipSuccess;
     const dim3 grid = frame_grid(b, gx);
-    if (b.table) k_synth_out<FrameTable><<<grid, kBlock, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
-    else k_synth_out<OneFrame><<<grid, kBlock, 0, st>>>(OneFrame{*b.one}, ds);
+    if (b.table) k_synth_out<FrameTable><<<grid, kOutThreads, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
+    else k_synth_out<OneFrame><<<grid, kOutThreads, 0, st>>>(OneFrame{*b.one}, ds);
     return hipGetLastError();
 }
 

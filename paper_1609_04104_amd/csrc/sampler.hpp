@@ -21,22 +21,17 @@ namespace tsl {
 
 constexpr int kSampleThreads = 256;   // threads that work on a draw (a bigger block idles the rest)
 constexpr int kUPre = 256;            // uniforms computed beside the prefix sum
-constexpr int kChunk = 2048;          // factor entries (or row terms) per staged chunk of rows (16 KiB)
+constexpr int kChunk = 2048;          // factor entries per staged chunk of rows (16 KiB)
 constexpr int kChunkLoads = kChunk / kSampleThreads;   // loads per thread that cover one chunk
 constexpr int kBatch = 8;             // LDS loads a sequential sum keeps one batch ahead
-constexpr int kResident = 4;          // chunks of F_l A held in registers at a time
-constexpr int kPB = 32;               // prefix values one thread holds per batch
-// The staging area is padded so that every load and store of a chunk can be
-// unconditional: a row-term chunk at pitch R | 1 ends before 3 kChunk / 2, and
-// the column sums read at most one batch of rows past a chunk; the prefix
-// reads and writes at most kPB values past n1.
-constexpr int kBuf = (3 * kChunk / 2 > kChunk + kBatch * TSL_MAX_R) ? 3 * kChunk / 2 : kChunk + kBatch * TSL_MAX_R;
-
+constexpr int kResident = 2;          // chunks of F_l A held in registers at a time
+constexpr int kPB = 16;               // prefix values one thread holds per batch
 struct alignas(16) SampleLds {
-    double pref[kMaxN + kPB];         // weights, then their inclusive prefix (padded)
+    double pref[kMaxN + kPB];         // weights, then their inclusive prefix (padded: the prefix
+                                      // reads and writes up to kPB values past n1, never used)
     double c[TSL_MAX_R];              // column energies
     double u[kUPre];                  // u_k for k < kUPre
-    double buf[kBuf];                 // a chunk of energies E_ir, then of row terms
+    double buf[kChunk];               // a chunk of energies E_ir
     int mark[kMaxN];
     int wcount[kMaxN / 64];
 };
@@ -80,61 +75,32 @@ template <bool TWO>
 __device__ __forceinline__ void column_chain(const double* buf, int R, int r0, int r1, int nb, double& acc0,
                                              double& acc1) {
 #pragma clang fp contract(off)
-    double a0[kBatch], a1[kBatch], b0[kBatch], b1[kBatch];
-    auto load = [&](double (&x0)[kBatch], double (&x1)[kBatch], int i0) {
+    constexpr int B = TWO ? kBatch / 2 : kBatch;      // rows per register set (nb is a multiple of kBatch)
+    double a0[B], a1[B], b0[B], b1[B];
+    auto load = [&](double (&x0)[B], double (&x1)[B], int i0) {
 #pragma unroll
-        for (int w = 0; w < kBatch; ++w) {
+        for (int w = 0; w < B; ++w) {
             x0[w] = buf[(i0 + w) * R + r0];
             if constexpr (TWO) x1[w] = buf[(i0 + w) * R + r1];
         }
     };
-    auto add = [&](const double (&x0)[kBatch], const double (&x1)[kBatch]) {
+    auto add = [&](const double (&x0)[B], const double (&x1)[B]) {
 #pragma unroll
-        for (int w = 0; w < kBatch; ++w) {
+        for (int w = 0; w < B; ++w) {
             acc0 = acc0 + x0[w];
             if constexpr (TWO) acc1 = acc1 + x1[w];
         }
     };
     load(a0, a1, 0);
-    for (int il = 0; il < nb; il += 2 * kBatch) {
-        const bool more = il + kBatch < nb;
-        if (more) load(b0, b1, il + kBatch);
+    for (int il = 0; il < nb; il += 2 * B) {
+        const bool more = il + B < nb;
+        if (more) load(b0, b1, il + B);
         add(a0, a1);
         if (more) {
-            if (il + 2 * kBatch < nb) load(a0, a1, il + 2 * kBatch);
+            if (il + 2 * B < nb) load(a0, a1, il + 2 * B);
             add(b0, b1);
         }
     }
-}
-
-// p[0] + p[1] + ... + p[n - 1] in order, starting from +0, with the same
-// alternating register sets.
-__device__ __forceinline__ double row_chain(const double* p, int n) {
-#pragma clang fp contract(off)
-    double q = 0.0, a[kBatch], b[kBatch];
-    const int nf = n / kBatch * kBatch;
-    auto load = [&](double (&x)[kBatch], int i0) {
-#pragma unroll
-        for (int w = 0; w < kBatch; ++w) x[w] = p[i0 + w];
-    };
-    auto add = [&](const double (&x)[kBatch]) {
-#pragma unroll
-        for (int w = 0; w < kBatch; ++w) q = q + x[w];
-    };
-    if (nf > 0) {
-        load(a, 0);
-        for (int i = 0; i < nf; i += 2 * kBatch) {
-            const bool more = i + kBatch < nf;
-            if (more) load(b, i + kBatch);
-            add(a);
-            if (more) {
-                if (i + 2 * kBatch < nf) load(a, i + 2 * kBatch);
-                add(b);
-            }
-        }
-    }
-    for (int i = nf; i < n; ++i) q = q + p[i];
-    return q;
 }
 
 __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
@@ -146,11 +112,10 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
     GlobalPtr<const float2> Ah = f.Ahat;
     const uint64_t t_next = uint64_t(f.dev->t + 1);
 
-    // Rows of F_l A come in chunks of ck rows (a multiple of kBatch, ck R <=
-    // kChunk), kResident chunks at a time held in registers across the block:
-    // coalesced loads at indices clamped into the factor, zero past the end.
-    // When the whole factor fits (n1 R <= kResident kChunk, e.g. 256 x 32),
-    // F_l A is read from memory once for both passes.
+    // For the column energies, rows of F_l A come in chunks of ck rows (a
+    // multiple of kBatch, ck R <= kChunk), kResident chunks at a time held in
+    // registers across the block: coalesced loads at indices clamped into the
+    // factor, zero past the end.
     const int ck = min((kChunk / R) / kBatch * kBatch, cdiv(n1, kBatch) * kBatch);
     const int span = kResident * ck;                 // rows held at a time
     float2 a[kResident][kChunkLoads];
@@ -202,40 +167,29 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
     for (int i = tid; i < n1; i += nt) L.mark[i] = 0;
     __syncthreads();
 
-    // 2. w_i = N2 q_i + R with q_i = sum_r E_ir / c_r in column order: the block
-    //    turns a chunk into terms (zero for a zero column, which leaves q
-    //    unchanged) at an odd row pitch in LDS, then one thread per row adds
-    //    its terms up in order.
-    {
-        const int pitch = R | 1;
-        for (int I0 = 0; I0 < n1; I0 += span) {
-            if (worker && span < n1) load_span(I0);
-            sfor<kResident>([&](auto sc) {
-                constexpr int sub = decltype(sc)::value;
-                const int i0 = I0 + sub * ck;
-                if (i0 < n1) {
-                    const int ni = min(ck, n1 - i0);
-                    if (worker) {
+    // 2. w_i = N2 q_i + R with q_i = sum_r E_ir / c_r in column order, one thread
+    //    per row: the thread reads its row of F_l A (just read above, so mostly
+    //    from cache) eight entries at a time and adds its terms in order (a
+    //    zero column's term is 0, which leaves q unchanged).
+    for (int i = tid; i < n1; i += nt) {
+        const size_t row0 = size_t(i) * R;
+        double q = 0.0;
+        for (int r0 = 0; r0 < R; r0 += 8) {
+            float2 v[8];
 #pragma unroll
-                        for (int u = 0; u < kChunkLoads; ++u) {
-                            const int e = tid + u * kSampleThreads, r = e % R;
-                            const double c = L.c[r];
-                            const double q = energy(a[sub][u]) / (c > 0.0 ? c : 1.0);
-                            L.buf[(e / R) * pitch + r] = c > 0.0 ? q : 0.0;
-                        }
-                    }
-                    __syncthreads();
-                    for (int il = tid; il < ni; il += nt) {
-                        const double q = row_chain(L.buf + il * pitch, R);
-                        double w = double(n2) * q;
-                        w = w + double(R);
-                        L.pref[i0 + il] = w;
-                    }
-                    __syncthreads();
-                }
-            });
+            for (int w = 0; w < 8; ++w) v[w] = Ah[row0 + min(r0 + w, R - 1)];
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+                const double c = L.c[min(r0 + w, R - 1)];
+                const double t = energy(v[w]) / (c > 0.0 ? c : 1.0);
+                q = q + ((r0 + w < R && c > 0.0) ? t : 0.0);
+            }
         }
+        double w = double(n2) * q;
+        w = w + double(R);
+        L.pref[i] = w;
     }
+    __syncthreads();
 
     // 3. Inclusive prefix in row order (one thread, loads a batch ahead; the
     //    padded tail is read and written but never used); meanwhile the other
