@@ -57,6 +57,7 @@ extern "C" {
 
 typedef struct tsl_seq tsl_seq;
 typedef struct tsl_pool tsl_pool;
+typedef struct tsl_batch tsl_batch;
 typedef struct { float re, im; } tsl_c32;
 
 enum {
@@ -203,6 +204,36 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
    ADDS each phase's elapsed milliseconds to phase_ms[TSL_N_PHASES] (host). */
 int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, double* phase_ms,
                         void* stream);
+
+/* A batched step fixed once and replayed: the same work as
+   tsl_step_many(seqs, n, frames, stream) (one step of Algorithm 3 per frame,
+   with Algorithm 4's draw where K_next > 0), with the validation and the
+   frame descriptors (uploaded once to device memory owned by the batch) done
+   at creation, so that tsl_batch_launch only launches kernels.  Made for loops
+   that cycle through a fixed set of steps (steady-state serving of a fixed
+   batch; each step's device buffers -- rows, row counts, y, outputs -- are
+   fixed at creation, their contents are read at launch).  flags:
+   0 -- each launch issues the kernels on the stream directly (one launch per
+        phase and shape group; the cheaper form for a few groups);
+   TSL_BATCH_GRAPH -- the launches are captured once in a HIP graph and each
+        launch replays it (one call whatever the number of groups).
+   The sequences must be distinct and on the current device; every pointer in
+   `frames` must stay valid while the batch lives.  *out receives the handle,
+   or NULL on error (TSL_EINVAL on bad arguments, TSL_EDEVICE on a HIP
+   failure; tsl_last_error tells which).  Closing one of the sequences
+   invalidates the batch: launching it then returns TSL_EINVAL. */
+enum { TSL_BATCH_GRAPH = 1 };
+int tsl_batch_create(tsl_seq* const* seqs, int n, const tsl_frame* frames, int flags, tsl_batch** out);
+
+/* Enqueues the batch's step on `stream` (NULL: the default stream).  Stream
+   order is the only ordering: launches of batches that share a sequence must
+   go to one stream.  Returns TSL_EINVAL for a NULL or invalidated batch or a
+   current device other than the batch's. */
+int tsl_batch_launch(tsl_batch* b, void* stream);
+
+/* Waits for the batch's last launch and frees its descriptors and graph
+   (NULL: no-op). */
+int tsl_batch_destroy(tsl_batch* b);
 
 /* Synchronises the sequence's last stream and returns its latched device
    status (TSL_OK or a negative code); clears it if clear != 0. */

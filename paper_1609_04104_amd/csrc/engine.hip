@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -212,6 +213,29 @@ struct BatchEngine {
 };
 
 BatchEngine g_batch;
+
+}  // namespace
+
+// A step fixed at creation: its descriptors live in device memory of its own,
+// and its launches are either issued directly or replayed from a graph of its own.
+struct tsl_batch {
+    int device = -1;
+    bool dead = false;                    // one of its sequences was closed
+    bool launched = false;
+    std::vector<tsl_seq*> seqs;
+    std::vector<tsl::Batch> groups;       // launch groups over `table`
+    tsl::FrameArgs* table = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last = nullptr;
+    ~tsl_batch() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (table) hipFree(table);
+    }
+};
+
+namespace {
+
+std::vector<tsl_batch*> g_live_batches;   // guarded by g_graph_mu
 
 void drop_graph(BatchEngine& be) {
     if (be.exec) hipGraphExecDestroy(be.exec);
@@ -440,6 +464,9 @@ int tsl_close(tsl_seq* s) {
         std::lock_guard<std::mutex> lk(g_graph_mu);
         for (const tsl_seq* q : g_batch.comp.seqs)
             if (q == s) { drop_graph(g_batch); break; }
+        for (tsl_batch* b : g_live_batches)
+            for (const tsl_seq* q : b->seqs)
+                if (q == s) b->dead = true;
     }
     hipSetDevice(s->device);
     hipError_t e = hipStreamSynchronize(s->last);
@@ -585,6 +612,81 @@ int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, do
     }
     for (auto& e : ev) hipEventDestroy(e);
     return rc;
+}
+
+int tsl_batch_create(tsl_seq* const* seqs, int n, const tsl_frame* frames, int flags, tsl_batch** out) {
+    if (!out) return fail(TSL_EINVAL, "null batch handle pointer");
+    *out = nullptr;
+    if (n <= 0 || !seqs || !frames) return fail(TSL_EINVAL, "bad batch arguments");
+    if (flags & ~TSL_BATCH_GRAPH) return fail(TSL_EINVAL, "unknown batch flags");
+    Composition c;
+    int rc = compose(seqs, n, frames, c);
+    if (rc != TSL_OK) return rc;
+    int dev = 0;
+    TSL_HIP(hipGetDevice(&dev));
+    for (int i = 0; i < n; ++i)
+        if (seqs[i]->device != dev) return fail(TSL_EINVAL, "a sequence of the batch is not on the current device");
+    std::unique_ptr<tsl_batch> b(new tsl_batch);
+    b->device = dev;
+    b->seqs.assign(seqs, seqs + n);
+    std::vector<tsl::FrameArgs> host(static_cast<size_t>(n));
+    for (int p = 0; p < n; ++p) host[p] = frame_args(seqs[c.order[p]], frames[c.order[p]]);
+    TSL_HIP(hipMalloc(&b->table, size_t(n) * sizeof(tsl::FrameArgs)));
+    TSL_HIP(hipMemcpy(b->table, host.data(), size_t(n) * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice));
+    b->groups = group_batches(c, b->table);
+    if (flags & TSL_BATCH_GRAPH) {
+        hipStream_t cap = nullptr;
+        TSL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipError_t eb = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        int lrc = eb == hipSuccess ? run_groups(b->groups, cap) : TSL_OK;
+        hipError_t ec = eb == hipSuccess ? hipStreamEndCapture(cap, &graph) : eb;
+        hipStreamDestroy(cap);
+        if (lrc != TSL_OK || ec != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return lrc != TSL_OK ? lrc : hip_fail(ec, "stream capture");
+        }
+        hipError_t ei = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            b->exec = nullptr;
+            return hip_fail(ei, "hipGraphInstantiate");
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    g_live_batches.push_back(b.get());
+    *out = b.release();
+    return TSL_OK;
+}
+
+int tsl_batch_launch(tsl_batch* b, void* stream) {
+    if (!b) return fail(TSL_EINVAL, "null batch");
+    if (b->dead) return fail(TSL_EINVAL, "a sequence of the batch has been closed");
+    int dev = 0;
+    TSL_HIP(hipGetDevice(&dev));
+    if (dev != b->device) return fail(TSL_EINVAL, "batch launched on another device than its own");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    for (tsl_seq* s : b->seqs) s->last = st;
+    b->last = st;
+    b->launched = true;
+    if (b->exec) {
+        TSL_HIP(hipGraphLaunch(b->exec, st));
+        return TSL_OK;
+    }
+    return run_groups(b->groups, st);
+}
+
+int tsl_batch_destroy(tsl_batch* b) {
+    if (!b) return TSL_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        g_live_batches.erase(std::remove(g_live_batches.begin(), g_live_batches.end(), b), g_live_batches.end());
+    }
+    hipSetDevice(b->device);
+    hipError_t e = b->launched ? hipStreamSynchronize(b->last) : hipSuccess;
+    delete b;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return TSL_OK;
 }
 
 int tsl_status(tsl_seq* s, int clear) {

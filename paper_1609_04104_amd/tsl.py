@@ -23,7 +23,7 @@ _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOTPD: "ENOTP
 EXPORTS = [
     "tsl_opts_default", "tsl_size_supported", "tsl_footprint", "tsl_open", "tsl_close",
     "tsl_push_lines", "tsl_push_points", "tsl_push_frame", "tsl_sample_lines", "tsl_step_many",
-    "tsl_step_many_timed", "tsl_status",
+    "tsl_step_many_timed", "tsl_batch_create", "tsl_batch_launch", "tsl_batch_destroy", "tsl_status",
     "tsl_get_factors", "tsl_get_state", "tsl_set_state", "tsl_shape", "tsl_fft2",
     "tsl_pool_create", "tsl_pool_destroy", "tsl_pool_used", "tsl_open_in_pool",
     "tsl_last_error", "tsl_selftest_codelets",
@@ -46,6 +46,7 @@ PHASES = ["partial Grams", "ridge solve + step size", "synthesis + row pass", "c
           "row inverse + A grad", "k-space residual + gradients", "factor updates + F_l A, F_r B",
           "output synthesis + row draw"]
 ROUTE_KSPACE, ROUTE_FRAME = 0, 1
+BATCH_GRAPH = 1
 
 
 class Frame(ctypes.Structure):
@@ -80,6 +81,9 @@ def lib():
             "tsl_push_frame": (i, [vp, P(Frame), vp]),
             "tsl_step_many": (i, [P(vp), i, P(Frame), vp]),
             "tsl_step_many_timed": (i, [P(vp), i, P(Frame), P(d), vp]),
+            "tsl_batch_create": (i, [P(vp), i, P(Frame), i, P(vp)]),
+            "tsl_batch_launch": (i, [vp, vp]),
+            "tsl_batch_destroy": (i, [vp]),
             "tsl_status": (i, [vp, i]),
             "tsl_get_factors": (i, [vp, vp, vp, vp, vp, vp]),
             "tsl_get_state": (i, [vp, vp, P(sz)]),
@@ -290,17 +294,38 @@ def step_many(seqs, frames, stream=None):
 
 
 class PreparedStep:
-    """A batched step whose handle and frame arrays are built once, so that
-    launching it again costs one C call (the frames' tensors must stay alive)."""
+    """A batched step fixed once (tsl_batch_create): validated and its
+    descriptors uploaded at construction, so that a launch only launches
+    kernels -- directly (default), or by replaying a HIP graph captured at
+    construction (graph=True).  The sequences and the frames' tensors must stay
+    alive; closing one of the sequences makes launch() raise."""
 
-    def __init__(self, seqs, frames):
-        self.n = len(seqs)
-        self.hs = (ctypes.c_void_p * self.n)(*[s.h for s in seqs])
-        self.fs = (Frame * self.n)(*frames)
+    def __init__(self, seqs, frames, graph=False):
+        n = len(seqs)
+        hs = (ctypes.c_void_p * n)(*[s.h for s in seqs])
+        fs = (Frame * n)(*frames)
+        h = ctypes.c_void_p()
+        _check(lib().tsl_batch_create(hs, n, fs, BATCH_GRAPH if graph else 0, ctypes.byref(h)))
+        self.h = h
+        self.n = n
         self._keep = (list(seqs), list(frames))
 
     def launch(self, stream=None):
-        _check(lib().tsl_step_many(self.hs, self.n, self.fs, _stream(stream)))
+        if self.h is None:
+            raise TslError(EINVAL, "prepared step has been closed")
+        _check(lib().tsl_batch_launch(self.h, _stream(stream)))
+
+    def close(self):
+        """Waits for the last launch and frees the descriptors and the graph."""
+        h, self.h = self.h, None
+        if h is not None:
+            _check(lib().tsl_batch_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def step_many_timed(seqs, frames, phase_ms=None, stream=None):

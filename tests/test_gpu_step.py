@@ -467,6 +467,69 @@ def test_step_many_with_draws_equals_push_frame(T):
         s.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_prepared_batch_replays_equal_step_many(T, graph):
+    """Prepared batches (descriptors fixed at creation; launched directly or
+    replayed from a graph) run in a cycle give bit-identical outputs and draws
+    to tsl_step_many on twin sequences; closing a sequence invalidates the
+    batches that hold it."""
+    print(f"prepared batch replays, graph={graph}", flush=True)
+    specs = [(128, 128, 16, "kspace"), (256, 256, 32, "kspace"), (128, 128, 8, "frame"),
+             (192, 160, 24, "kspace")]
+    rng = np.random.default_rng(11)
+    P_seqs, M_seqs, data = [], [], []
+    for k, (n1, n2, r, route) in enumerate(specs):
+        _, A0, B0 = _random_state(n1, n2, r, 950 + k)
+        P_seqs.append(T.Sequence(n1, n2, r, 0.05, dev(A0), dev(B0), seed=7, stream_id=k, route=route))
+        M_seqs.append(T.Sequence(n1, n2, r, 0.05, dev(A0), dev(B0), seed=7, stream_id=k, route=route))
+        data.append(dev(cn(rng, (3, n1, n2), 1e-3).astype(np.complex64)))
+    bufs = {}
+    for side in ("prep", "many"):
+        bufs[side] = [dict(rows=[torch.zeros(n1 // 8, dtype=torch.int32, device="cuda") for _ in range(2)],
+                           cnt=[torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(2)],
+                           out=Outs(n1, n2, r)) for (n1, n2, r, _) in specs]
+    full = {n1: torch.arange(n1, dtype=torch.int32, device="cuda") for (n1, _, _, _) in specs}
+
+    def frames_for(side, seqs, t):
+        fr = []
+        for k, (n1, n2, r, _) in enumerate(specs):
+            b = bufs[side][k]
+            nxt = dict(K_next=n1 // 8, rows_next=b["rows"][(t + 1) % 2], n_next=b["cnt"][(t + 1) % 2])
+            y = data[k][t % 3]
+            if t == 0:
+                fr.append(seqs[k].frame(rows=full[n1], y=y, y_full=True, **b["out"].kw(), **nxt))
+            else:
+                fr.append(seqs[k].frame(rows=b["rows"][t % 2], n_rows_dev=b["cnt"][t % 2], y=y, y_full=True,
+                                        **b["out"].kw(), **nxt))
+        return fr
+
+    # step 0 (all rows), then a cycle of 6 steps (row-buffer parity x data frame)
+    prepared = {key: T.PreparedStep(P_seqs, frames_for("prep", P_seqs, key), graph=graph) for key in range(7)}
+    for t in range(14):
+        key = t if t < 7 else 1 + (t - 1) % 6
+        prepared[key].launch()
+        T.step_many(M_seqs, frames_for("many", M_seqs, key))
+        for k in range(len(specs)):
+            bp, bm = bufs["prep"][k], bufs["many"][k]
+            for name in ("X", "A", "B", "g"):
+                assert np.array_equal(host(getattr(bp["out"], name)), host(getattr(bm["out"], name))), (t, k, name)
+            cp, cm = host(bp["cnt"][(t + 1) % 2]), host(bm["cnt"][(t + 1) % 2])
+            assert np.array_equal(cp, cm), (t, k)
+            n_ = int(cp[0])
+            assert np.array_equal(host(bp["rows"][(t + 1) % 2])[:n_], host(bm["rows"][(t + 1) % 2])[:n_])
+    for s in P_seqs + M_seqs:
+        assert s.status() == 0
+    P_seqs[2].close()
+    with pytest.raises(T.TslError) as ei:
+        prepared[3].launch()
+    assert ei.value.code == T.EINVAL
+    for p in prepared.values():
+        p.close()
+        p.close()
+    for s in P_seqs[:2] + P_seqs[3:] + M_seqs:
+        s.close()
+
+
 def test_device_row_count_out_of_range_latches(T):
     n1, n2, r = 64, 64, 4
     _, A0, B0 = _random_state(n1, n2, r, 8)
