@@ -121,7 +121,7 @@ PHASE_KERNELS = {   # kernel of each phase in a table launch of n x n frames
     "synthesis + row pass": "void k_synth_rowfft<{n}, FrameTable>",
     "column pass + residual": "void k_col_resid<{n}, FrameTable>",
     "row inverse + A grad": "void k_row_inv_grad<{n}, FrameTable>",
-    "k-space residual + gradients": "void k_kres<FrameTable>",
+    "k-space residual + gradients": "void k_kres<",
     "factor updates + F_l A, F_r B": "void k_update_ab<{n}, FrameTable>",
     "output synthesis + row draw": "void k_synth_out<FrameTable>",
 }
@@ -147,7 +147,9 @@ def counter_traffic(phase, n, grid=None):
         return None
     if phase == "partial Grams" and grid is not None:           # warm and informative launches differ
         hits = [v for k, v in rec["kernels"].items() if k.startswith(want) and f"[grid {grid}]" in k] or hits
-    v = max(hits, key=lambda v: v["dispatches"])
+    # kernels whose grid follows the sampled rows: the steady state is the smallest grid
+    v = min(hits, key=lambda v: v.get("grid", 0)) if all("grid" in v for v in hits) else \
+        max(hits, key=lambda v: v["dispatches"])
     return v["fetch_bytes"] + v["write_bytes"]
 
 
@@ -201,7 +203,9 @@ class BatchDriver:
 
 
 def time_steps(drv, warmup, steps, stream, torch, label):
-    """Runs `warmup` untimed steps, then times `steps` steps between HIP events."""
+    """Runs `warmup` untimed steps, times `steps` steps between two HIP events
+    (nothing else enqueued in between), then runs `steps` more with an event
+    after each for the per-step latency spread (not part of the throughput)."""
     for t in range(drv.warm + drv.period):          # every descriptor set built once, untimed
         drv.prepare(t)
     t = 0
@@ -209,29 +213,36 @@ def time_steps(drv, warmup, steps, stream, torch, label):
         drv.step(t, stream)
         t += 1
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     # a full collection of Python's cyclic garbage inside the loop stalls the
     # host for milliseconds; collect now and exempt everything alive from it
     gc.collect()
     gc.freeze()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     host_us = []
     w0 = time.perf_counter()
-    ev[0].record(stream)
+    e0.record(stream)
     for k in range(steps):
         h0 = time.perf_counter()
         drv.step(t, stream)
         host_us.append((time.perf_counter() - h0) * 1e6)
         t += 1
-        ev[k + 1].record(stream)
+    e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
+    ms_per_step = max(wall * 1e3, e0.elapsed_time(e1)) / steps
+    # latency spread: the same steps with an event between consecutive ones
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for k in range(steps):
+        drv.step(t, stream)
+        t += 1
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
     step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
     slow = sorted(range(steps), key=lambda k: -step_ms[k])[:5]
-    gpu_ms = ev[0].elapsed_time(ev[-1])
-    ms_per_step = max(wall * 1e3, gpu_ms) / steps
-    print(f"[bench] {label}: {ms_per_step:.3f} ms/step, {len(drv.seqs) * 1000.0 / ms_per_step:.0f} frames/s; "
-          f"host launch us p50 {pct(host_us, 50):.1f} max {max(host_us):.1f}; slowest steps "
-          + ", ".join(f"#{k}: {step_ms[k]:.3f} ms (host {host_us[k]:.0f} us)" for k in slow),
+    print(f"[bench] {label}: {ms_per_step:.4f} ms/step, {len(drv.seqs) * 1000.0 / ms_per_step:.0f} frames/s; "
+          f"host launch us p50 {pct(host_us, 50):.1f} max {max(host_us):.1f}; evented steps p50 "
+          f"{pct(step_ms, 50):.4f} ms, slowest " + ", ".join(f"#{k}: {step_ms[k]:.3f} ms" for k in slow),
           file=sys.stderr, flush=True)
     return {"ms_per_step": ms_per_step, "step_ms": step_ms, "t": t}
 

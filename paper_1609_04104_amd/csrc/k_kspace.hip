@@ -80,11 +80,15 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
     const int row_mine = (tid < kKQ && q0 + tid < cap) ? f.rows[q0 + tid] : -1;
     const int row_list = tid < cap ? f.rows[tid] : -1;
     const float2 gam = tid < R ? float2(f.gamma32[tid]) : float2{0.f, 0.f};
+    // (staging loads read at indices clamped into range and select the values
+    // past it away, so that they go out back to back with no branch between)
     float2 b0[4];
+    const int nb0 = min(JC, n2) * R;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const int e = tid + u * kKT, j = e / R;
-        b0[u] = (e < JC * R && j < n2) ? float2(f.Bhat[e]) : float2{0.f, 0.f};
+        const int e = tid + u * kKT;
+        const float2 v = f.Bhat[min(e, nb0 - 1)];
+        b0[u] = e < nb0 ? v : float2{0.f, 0.f};
     }
     for (int i = tid; i < n1; i += kKT) s_on[i] = 0;
     if (tid == 0) s_bad = 0;
@@ -103,7 +107,8 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
     // Ahat rows of the block
     for (int e = tid; e < kKQ * R; e += kKT) {
         const int q = e / R, c = e % R, row = s_row[q];
-        s_a[q * RP + c] = row >= 0 ? float2(f.Ahat[size_t(row) * R + c]) : float2{0.f, 0.f};
+        const float2 v = f.Ahat[size_t(max(row, 0)) * R + c];
+        s_a[q * RP + c] = row >= 0 ? v : float2{0.f, 0.f};
     }
     // rows of GA that this block zeroes: the unsampled rows i with i mod nblk = qc
     const int nown = qc < n1 ? cdiv(n1 - qc, nblk) : 0;
@@ -119,22 +124,29 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
     for (int t = 0; t < RT; ++t) mr[t] = mi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     float2* s_ew = s_e + wave * 16 * kEP;            // this wavefront's E tile [q][j]
     for (int j0 = 0; j0 < n2; j0 += JC) {
+        const int njc = min(JC, n2 - j0), nbc = njc * R;   // columns and Bhat entries of the chunk
         __syncthreads();                             // the previous chunk's reads of s_b are done
         {   // the samples and the chunk of Bhat, four loads per thread in flight per round
             float2 yv[kYL];
 #pragma unroll
             for (int u = 0; u < kYL; ++u) {
                 const int e = tid + u * kKT, q = e / (16 * kKW), j = e % (16 * kKW), row = s_row[q];
-                yv[u] = (row >= 0 && j < JC && j0 + j < n2) ? float2(line_samples(f, q0 + q, row)[j0 + j])
-                                                             : float2{0.f, 0.f};
+                // a row that is not live reads the block's first row (q0 < S here)
+                const float2 v = line_samples(f, q0 + (row >= 0 ? q : 0), max(row, 0))[j0 + min(j, njc - 1)];
+                yv[u] = (row >= 0 && j < njc) ? v : float2{0.f, 0.f};
             }
             for (int e0 = 0; e0 < JC * R; e0 += 4 * kKT) {
                 float2 bv[4];
+                if (j0 == 0 && e0 == 0) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int e = e0 + tid + u * kKT, j = e / R;
-                    bv[u] = (j0 == 0 && e0 == 0) ? b0[u]
-                          : (e < JC * R && j0 + j < n2) ? float2(f.Bhat[size_t(j0) * R + e]) : float2{0.f, 0.f};
+                    for (int u = 0; u < 4; ++u) bv[u] = b0[u];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = e0 + tid + u * kKT;
+                        const float2 v = f.Bhat[size_t(j0) * R + min(e, nbc - 1)];
+                        bv[u] = e < nbc ? v : float2{0.f, 0.f};
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {

@@ -108,10 +108,8 @@ __device__ void factor_gram_block(const DevFrame& f, int b, double2* s_x, bool c
     for (int e0 = 0; e0 < ne; e0 += kFL * kSB) {
         float2 v[kFL];
 #pragma unroll
-        for (int u = 0; u < kFL; ++u) {
-            const int e = e0 + int(threadIdx.x) + u * kSB;
-            v[u] = e < ne ? float2(X[e]) : float2{0.f, 0.f};
-        }
+        for (int u = 0; u < kFL; ++u)     // clamped index: no branch between the loads
+            v[u] = float2(X[min(e0 + int(threadIdx.x) + u * kSB, ne - 1)]);
         if (e0 == 0 && check && !block_frame_ok(f.dev, false)) return;   // uniform
 #pragma unroll
         for (int u = 0; u < kFL; ++u) {
@@ -149,20 +147,23 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     const int j0 = c * kJCH, nj = min(kJCH, n2 - j0);
     // Loads that need nothing but the descriptor go out before the status check
     // (inside the frame's own buffers): the row count, the block's row indices
-    // (and each next one, for the ascending check) and the readout chunk of F_r B.
+    // (and each next one, for the ascending check) and the first round of the
+    // readout chunk of F_r B.
     const int cap = frame_rows_cap(f);
     const int nd = f.n_rows_dev ? *f.n_rows_dev : cap;
     const int row_raw = (tid < kSRows && q0 + tid < cap) ? f.rows[q0 + tid] : -1;
     const int next_raw = (c == 0 && tid < kSRows && q0 + tid + 1 < cap) ? f.rows[q0 + tid + 1] : -1;
-    constexpr int kBL = cdiv(kJCH * TSL_MAX_R, kSB), kXL = cdiv(kSRows * TSL_MAX_R, kSB);
-    constexpr int kYL = cdiv(kSRows * kJCH, kSB);
+    // Every staging load reads a valid address (indices clamped into range) and
+    // only the LDS store is predicated, so the loads of a round go out back to
+    // back; kLU loads per thread per round.
+    constexpr int kLU = 4;
     const int nb = nj * R;
-    float2 bv[kBL];
+    float2 bv[kLU];
+    auto load_b = [&](int e0) {
 #pragma unroll
-    for (int u = 0; u < kBL; ++u) {
-        const int e = tid + u * kSB;
-        bv[u] = e < nb ? float2(f.Bhat[size_t(j0) * R + e]) : float2{0.f, 0.f};
-    }
+        for (int u = 0; u < kLU; ++u) bv[u] = float2(f.Bhat[size_t(j0) * R + min(e0 + tid + u * kSB, nb - 1)]);
+    };
+    load_b(0);
     if (tid == 0) s_err = 0;
     if (!block_frame_ok(f.dev, false)) return;      // its barriers also order s_err's reset
     const int n_rows = nd < 0 ? 0 : (nd > cap ? cap : nd);
@@ -174,9 +175,18 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     // when read), which keeps a block at 32 KiB at R = 32
     float2* s_b = reinterpret_cast<float2*>(s_x + kSRows * R);   // [kJCH][R]
     float2* s_y = s_b + kJCH * R;                                 // [kSRows][kJCH]
-    // Staging in two rounds of loads: the readout chunk of F_r B went out with
-    // the row indices; the sampled rows of F_l A and their samples follow once
-    // the indices are in LDS.
+    for (int e0 = 0;;) {
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+            const int e = e0 + tid + u * kSB;
+            if (e < nb) s_b[e] = bv[u];
+        }
+        e0 += kLU * kSB;
+        if (e0 >= nb) break;
+        load_b(e0);
+    }
+    // Then the sampled rows of F_l A and their samples, once the row indices
+    // are in LDS.
     const int nx = nq * R, ny = nq * kJCH;
     if (tid < nq) {                           // rows inside [0, n1), strictly ascending
         const int q = q0 + tid, row = row_raw;
@@ -188,36 +198,29 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
         s_row[tid] = (row >= 0 && row < n1) ? row : -1;
     }
     __syncthreads();
-    float2 xv[kXL], yv[kYL];
-#pragma unroll
-    for (int u = 0; u < kXL; ++u) {
-        const int e = tid + u * kSB;
-        const int row = e < nx ? s_row[e / R] : -1;
-        xv[u] = row >= 0 ? float2(f.Ahat[size_t(row) * R + e % R]) : float2{0.f, 0.f};
-    }
-#pragma unroll
-    for (int u = 0; u < kYL; ++u) {
-        const int e = tid + u * kSB, q = e / kJCH, jj = e % kJCH;
-        const int row = e < ny ? s_row[q] : -1;
-        yv[u] = (row >= 0 && jj < nj) ? float2(line_samples(f, q0 + q, row)[j0 + jj]) : float2{0.f, 0.f};
-    }
     bool fin = true;
+    for (int e0 = 0; e0 < max(nx, ny); e0 += kLU * kSB) {
+        float2 xv[kLU], yv[kLU];
+        int xr[kLU], yr[kLU];
 #pragma unroll
-    for (int u = 0; u < kBL; ++u) {
-        const int e = tid + u * kSB;
-        if (e < nb) s_b[e] = bv[u];
-    }
+        for (int u = 0; u < kLU; ++u) {
+            const int ex = min(e0 + tid + u * kSB, nx - 1), ey = min(e0 + tid + u * kSB, ny - 1);
+            const int q = ey / kJCH, jj = min(ey % kJCH, nj - 1);
+            xr[u] = s_row[ex / R];
+            yr[u] = s_row[q];
+            xv[u] = float2(f.Ahat[size_t(max(xr[u], 0)) * R + ex % R]);
+            yv[u] = float2(line_samples(f, q0 + q, max(yr[u], 0))[j0 + jj]);
+        }
 #pragma unroll
-    for (int u = 0; u < kXL; ++u) {
-        const int e = tid + u * kSB;
-        if (e < nx) s_x[e] = double2{xv[u].x, xv[u].y};
-    }
-#pragma unroll
-    for (int u = 0; u < kYL; ++u) {
-        const int e = tid + u * kSB;
-        if (e < ny) {
-            fin = fin && finite2(yv[u]);
-            s_y[e] = yv[u];
+        for (int u = 0; u < kLU; ++u) {
+            const int e = e0 + tid + u * kSB;
+            if (e < nx) s_x[e] = xr[u] >= 0 ? double2{xv[u].x, xv[u].y} : double2{0.0, 0.0};
+            if (e < ny) {
+                const bool live = yr[u] >= 0 && e % kJCH < nj;
+                const float2 y = live ? yv[u] : float2{0.f, 0.f};
+                fin = fin && finite2(y);
+                s_y[e] = y;
+            }
         }
     }
     __syncthreads();
@@ -644,12 +647,14 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
 // ---------------------------------------------------------------- register solve (R <= 32)
 // A block of kRegBlk threads per sequence.  The whole block first gathers G, h
 // and the magnitudes of the two factor Grams into LDS with all of its loads in
-// flight at once.  Wavefront 0 then factors G = L L^H with lane i keeping row i
-// in registers (column k goes lane to lane by readlane at step k) and runs the
-// forward substitution L z = h inside the same sweep; the back substitution
-// L^H gamma = z reads the columns of L back through LDS.  Rows R..RB-1 are
-// padded with the identity and a zero right-hand side, which leaves gamma
-// unchanged.  The Gershgorin sums of the step size use the whole block.
+// flight at once (issued before the frame's status is known, over the row
+// capacity of the descriptor; the device row count only selects which sampled
+// slots are added).  Wavefront 0 then factors G = L D L^H (unit lower L) with
+// lane i keeping row i in registers and runs the forward substitution L z = h
+// inside the same sweep; gamma = L^{-H} D^{-1} z follows with the columns of L
+// read back through LDS.  Rows R..RB-1 are padded with the identity and a zero
+// right-hand side, which leaves gamma unchanged.  The Gershgorin sums of the
+// step size use the whole block.
 __device__ __forceinline__ double readlane_d(double v, int lane) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane(int(b), lane);
@@ -659,6 +664,13 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 __device__ __forceinline__ double2 readlane_d2(double2 v, int lane) {
     return double2{readlane_d(v.x, lane), readlane_d(v.y, lane)};
 }
+// 1 / d for d > 0: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double recip(double d) {
+    double y = __builtin_amdgcn_rcp(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = fma(y, fma(-d, y, 1.0), y);
+    return y;
+}
 
 constexpr int kRegBlk = 256;
 constexpr int kGatherPF = 4;   // partial slots of each statistic loaded per round
@@ -666,12 +678,12 @@ constexpr int kGatherPF = 4;   // partial slots of each statistic loaded per rou
 template <int RB, class Src>
 __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     static_assert(RB <= 64 && kRegBlk % RB == 0 && (kRegBlk / RB) <= 64, "row groups must sit inside a wavefront");
-    constexpr int U = (RB * RB + kRegBlk - 1) / kRegBlk;   // entries of G per thread
     constexpr int TPR = kRegBlk / RB;                       // threads per row in the Gershgorin sums
-    __shared__ double2 s_g[RB * RB];       // G row-major, then L row-major
+    __shared__ double2 s_g[RB * RB];       // G row-major, then L below the diagonal
     __shared__ double s_m[2][RB * RB];     // |(F_l A)^H F_l A|, |(F_r B)^H F_r B|
-    __shared__ double2 s_h[RB];            // h, then gamma
-    __shared__ double2 s_col[64 / RB][RB]; // column k of L during step k, one copy per column group
+    __shared__ double2 s_h[RB];            // gamma
+    __shared__ double2 s_hp[kRegBlk];      // the first kRegBlk right-hand-side partial entries
+    __shared__ double2 s_c[2][RB];         // column k of the partly reduced G during step k (two buffers)
     __shared__ double s_ag[RB];            // |gamma|
     __shared__ double s_best[kRegBlk / 64];
     __shared__ double s_kappa;
@@ -679,15 +691,14 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     if (!src.live()) return;
     const DevFrame f = src.get();
     SeqDev* d = f.dev;
-    if (!block_frame_ok(d, false)) {
-        if (threadIdx.x == 0) d->frame_ok = 0;
-        return;
-    }
     const int R = f.r, tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const bool lines = f.mode == MODE_LINES;
-    const int ns = lines ? cdiv(frame_rows(f), kSRows) : cdiv(f.n1, kPRows);
+    // slot counts over the capacity (loads) and over the rows of this frame (sums)
+    const int ns_cap = lines ? cdiv(frame_rows_cap(f), kSRows) : cdiv(f.n1, kPRows);
+    const int ns = lines ? cdiv(frame_rows(f), kSRows) : ns_cap;
     const int gA = n_gparts(f.n1), gB = n_gparts(f.n2), gAB = gA + gB;
-    const int nh = ns * (lines ? n_jparts(f.n2) : 1);
+    const int hper = lines ? n_jparts(f.n2) : 1;
+    const int nh_cap = ns_cap * hper, nh = ns * hper;
     const size_t RR = size_t(R) * R;
     const double2* pa = f.part;               // slots of (F_l A)^H F_l A
     const double2* pb = f.part + gA * RR;     // slots of (F_r B)^H F_r B
@@ -697,150 +708,167 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     // Gather.  A slot holds the upper triangle: entry (r, c), r <= c, is G_rc.
     // Each thread takes upper entries (packed by rows) and writes both (i, j)
     // and its conjugate mirror (j, i).
-    {
-        constexpr int NU = RB * (RB + 1) / 2;
-        constexpr int U = (NU + kRegBlk - 1) / kRegBlk;   // upper entries per thread
-        size_t up[U];
-        bool ok[U];
-        int ui[U], uj[U];
+    constexpr int NU = RB * (RB + 1) / 2;
+    constexpr int U = (NU + kRegBlk - 1) / kRegBlk;   // upper entries per thread
+    size_t up[U];
+    bool ok[U];
+    int ui[U], uj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            int e = tid + u * kRegBlk, i = 0;
-            if (e < NU)
-                while (e >= RB - i) { e -= RB - i; ++i; }
-            ui[u] = i;
-            uj[u] = i + e;
-            ok[u] = tid + u * kRegBlk < NU && uj[u] < R;
-            up[u] = ok[u] ? size_t(ui[u]) * R + uj[u] : 0;
-        }
-        // the right-hand side's partials and all three slot ranges of every entry
-        // are loaded together (kGatherPF slots of each at a time), then added in
-        // slot order
-        constexpr int kHPF = 16;
-        double2 hw[kHPF];
-        const bool hlive = tid < R;
+    for (int u = 0; u < U; ++u) {
+        int e = tid + u * kRegBlk, i = 0;
+        if (e < NU)
+            while (e >= RB - i) { e -= RB - i; ++i; }
+        ui[u] = i;
+        uj[u] = i + e;
+        ok[u] = tid + u * kRegBlk < NU && uj[u] < R;
+        up[u] = ok[u] ? size_t(ui[u]) * R + uj[u] : 0;
+    }
+    // one right-hand-side partial entry per thread (entry q R + r is slot q of
+    // h_r) and the first kGatherPF slots of all three statistics are in flight
+    // before the status check
+    // (every load reads a valid address -- slot indices are clamped into the
+    // statistic's range -- and a select drops what lies past the count, so that
+    // the loads are issued back to back with no branch between them)
+    const double2 hpe0 = f.hpart[min(tid, max(nh_cap * R - 1, 0))];
+    const double2 hpe = tid < nh_cap * R ? hpe0 : double2{0.0, 0.0};
+    double2 g[U], ma[U], mb[U];
 #pragma unroll
-        for (int q = 0; q < kHPF; ++q)
-            hw[q] = (hlive && q < nh) ? f.hpart[size_t(q) * R + tid] : double2{0.0, 0.0};
-        double2 g[U], ma[U], mb[U];
+    for (int u = 0; u < U; ++u) g[u] = ma[u] = mb[u] = double2{0.0, 0.0};
+    const int nmax = max(gA, max(gB, ns_cap));
+    double2 wa[U][kGatherPF], wb[U][kGatherPF], ws[U][kGatherPF];
+    auto load_round = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) g[u] = ma[u] = mb[u] = double2{0.0, 0.0};
-        const int nmax = max(gA, max(gB, ns));
-        for (int k0 = 0; k0 < nmax; k0 += kGatherPF) {
-            double2 wa[U][kGatherPF], wb[U][kGatherPF], ws[U][kGatherPF];
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int q = 0; q < kGatherPF; ++q) {
-                    const size_t o = size_t(k0 + q) * RR + up[u];
-                    wa[u][q] = (ok[u] && k0 + q < gA) ? pa[o] : double2{0.0, 0.0};
-                    wb[u][q] = (ok[u] && k0 + q < gB) ? pb[o] : double2{0.0, 0.0};
-                    ws[u][q] = (ok[u] && k0 + q < ns) ? ps[o] : double2{0.0, 0.0};
-                }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int q = 0; q < kGatherPF; ++q) {
-                    ma[u].x += wa[u][q].x; ma[u].y += wa[u][q].y;
-                    mb[u].x += wb[u][q].x; mb[u].y += wb[u][q].y;
-                    g[u].x += ws[u][q].x; g[u].y += ws[u][q].y;
-                }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (tid + u * kRegBlk >= NU) continue;
-            const int i = ui[u], j = uj[u];
-            double2 v{0.0, 0.0};
-            if (ok[u]) {
-                v = lines ? dcmul(g[u], mb[u]) : g[u];
-                if (i == j) v = double2{v.x + lam, 0.0};
+            for (int q = 0; q < kGatherPF; ++q) {
+                const int k = k0 + q;
+                const double2 va = pa[size_t(min(k, gA - 1)) * RR + up[u]];
+                const double2 vb = pb[size_t(min(k, gB - 1)) * RR + up[u]];
+                const double2 vs = ps[size_t(min(k, max(ns_cap - 1, 0))) * RR + up[u]];
+                wa[u][q] = (ok[u] && k < gA) ? va : double2{0.0, 0.0};
+                wb[u][q] = (ok[u] && k < gB) ? vb : double2{0.0, 0.0};
+                ws[u][q] = (ok[u] && k < ns_cap) ? vs : double2{0.0, 0.0};
             }
-            const double am = dabs(ma[u]), bm = dabs(mb[u]);
-            s_g[i * RB + j] = v;
-            s_m[0][i * RB + j] = am;
-            s_m[1][i * RB + j] = bm;
-            if (i != j) {
-                s_g[j * RB + i] = double2{v.x, -v.y};
-                s_m[0][j * RB + i] = am;
-                s_m[1][j * RB + i] = bm;
-            }
-        }
-        if (tid < RB) {
-            double2 hv{0.0, 0.0};
+    };
+    auto add_round = [&](int k0) {
 #pragma unroll
-            for (int q = 0; q < kHPF; ++q) { hv.x += hw[q].x; hv.y += hw[q].y; }
-            for (int q = kHPF; q < nh && hlive; ++q) { hv.x += f.hpart[size_t(q) * R + tid].x; hv.y += f.hpart[size_t(q) * R + tid].y; }
-            s_h[tid] = hv;
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < kGatherPF; ++q) {
+                ma[u].x += wa[u][q].x; ma[u].y += wa[u][q].y;
+                mb[u].x += wb[u][q].x; mb[u].y += wb[u][q].y;
+                if (k0 + q < ns) { g[u].x += ws[u][q].x; g[u].y += ws[u][q].y; }
+            }
+    };
+    load_round(0);
+    if (!block_frame_ok(d, false)) {
+        if (tid == 0) d->frame_ok = 0;
+        return;
+    }
+    s_hp[tid] = hpe;
+    add_round(0);
+    for (int k0 = kGatherPF; k0 < nmax; k0 += kGatherPF) {
+        load_round(k0);
+        add_round(k0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (tid + u * kRegBlk >= NU) continue;
+        const int i = ui[u], j = uj[u];
+        double2 v{0.0, 0.0};
+        if (ok[u]) {
+            v = lines ? dcmul(g[u], mb[u]) : g[u];
+            if (i == j) v = double2{v.x + lam, 0.0};
+        } else if (i == j) {
+            v = double2{1.0, 0.0};                    // identity padding
+        }
+        const double am = dabs(ma[u]), bm = dabs(mb[u]);
+        s_g[i * RB + j] = v;
+        s_m[0][i * RB + j] = am;
+        s_m[1][i * RB + j] = bm;
+        if (i != j) {
+            s_g[j * RB + i] = double2{v.x, -v.y};
+            s_m[0][j * RB + i] = am;
+            s_m[1][j * RB + i] = bm;
         }
     }
     __syncthreads();
 
-    // Wavefront 0: right-looking Cholesky with the forward substitution fused in
-    // (z_k = h_k / L_kk once h_k has received every earlier column).  Lane l
-    // holds row l % RB of the columns j = NG m + l / RB (NG = 64 / RB column
-    // groups, so all 64 lanes work).  At step k the owner group scales column k
-    // and puts it in LDS; every lane then reads L_ik of its row and L_jk of its
-    // columns from there (a wavefront's LDS accesses complete in order, so no
-    // barrier is needed).  The pivot is the same in every lane, so `fail` is
-    // uniform.  Entries above the diagonal are updated too (never read).
+    // Wavefront 0: right-looking L D L^H, one column ahead.  Lane l holds row
+    // i = l % RB of the columns j = NG m + l / RB (NG = 64 / RB column groups,
+    // so all 64 lanes work).  Step k reads the unscaled column c = G[:, k]
+    // from LDS and applies G_ij -= c_i conj(c_j) / D_k; the column k+1 is
+    // reduced first, so its pivot's reciprocal and its copy into LDS run
+    // beside the rest of the update.  Entries above the diagonal and of
+    // finished columns receive updates too (never read).  A wavefront's LDS
+    // accesses complete in order, so the fences only keep the compiler from
+    // moving them.  The sweep has no branches: a pivot that is not positive and
+    // finite sets `fail` (the same in every lane) and is replaced by 1 so that
+    // the remaining steps stay finite; the frame is then rejected.
     constexpr int NG = 64 / RB, CPL = RB / NG;    // column groups, columns per lane
-    double2 g[CPL];
+    double2 gr[CPL];
     double2 hv{0.0, 0.0};
-    double dinv = 0.0;                            // 1 / L_{i,i}
+    double dinv = 0.0;                            // 1 / D_ii of the lane's row
     if (wave == 0) {
         const int i = lane % RB, h = lane / RB;
-        const bool live = i < R;
         sfor<CPL>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            const int j = NG * m + h;
-            g[m] = live ? s_g[i * RB + j] : double2{j == i ? 1.0 : 0.0, 0.0};
+            gr[m] = s_g[i * RB + NG * m + h];
         });
-        hv = s_h[i];
-        bool fail = false;
-        double piv_lo = 1e308, piv_hi = 0.0;
+        // h_i = sum of its slots in slot order
+        if (i < R)
+            for (int q = 0; q < nh; ++q) {
+                const int e = q * R + i;
+                const double2 v = e < kRegBlk ? s_hp[e] : f.hpart[e];
+                hv.x += v.x;
+                hv.y += v.y;
+            }
+        if (h == 0) s_c[0][i] = gr[0];
+        double dk = readlane_d(gr[0].x, 0);
+        bool fail = !(dk > 0.0) || !isfinite(dk);
+        double ik = recip(fail ? 1.0 : dk);
+        double d_lo = 1e308, d_hi = 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         sfor<RB>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            constexpr int ko = k % NG, km = k / NG;
-            if (fail) return;
-            const double dkk = readlane_d(g[km].x, k + ko * RB);
-            if (!(dkk > 0.0) || !isfinite(dkk)) { fail = true; return; }
-            double p, ip;
-            pivot(dkk, p, ip);
-            if (k < R) { piv_lo = fmin(piv_lo, p); piv_hi = fmax(piv_hi, p); }
-            if (i == k) dinv = ip;
-            if (h == ko) g[km] = i == k ? double2{p, 0.0} : double2{g[km].x * ip, g[km].y * ip};
-            s_col[h][i] = g[km];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const double2 lik = s_col[ko][i];             // L_ik
-            const double2 hk = readlane_d2(hv, k);
-            const double2 zk{hk.x * ip, hk.y * ip};
-            if (i == k) hv = zk;
-            else if (i > k) {
-                hv.x = fma(-lik.x, zk.x, fma(lik.y, zk.y, hv.x));
-                hv.y = fma(-lik.x, zk.y, fma(-lik.y, zk.x, hv.y));
+            if (k < R) { d_lo = fmin(d_lo, dk); d_hi = fmax(d_hi, dk); }
+            if (i == k) dinv = ik;
+            const double2 ci = s_c[k % 2][i];                   // G_ik
+            const double2 li{ci.x * ik, ci.y * ik};             // L_ik
+            if (h == 0 && i > k) s_g[i * RB + k] = li;
+            const double2 zk = readlane_d2(hv, k);              // z_k
+            if (i > k) {
+                hv.x = fma(-li.x, zk.x, fma(li.y, zk.y, hv.x));
+                hv.y = fma(-li.x, zk.y, fma(-li.y, zk.x, hv.y));
             }
-            sfor<CPL>([&](auto mc) {
-                constexpr int m = decltype(mc)::value;
-                if constexpr (NG * m + NG - 1 > k) {
-                    const int j = NG * m + h;
-                    const double2 ljk = s_col[ko][j];     // L_jk
-                    const double2 upd{fma(-lik.x, ljk.x, fma(-lik.y, ljk.y, g[m].x)),
-                                      fma(-lik.y, ljk.x, fma(lik.x, ljk.y, g[m].y))};   // - L_ik conj(L_jk)
-                    if constexpr (NG * m > k) g[m] = upd;
-                    else if (j > k) g[m] = upd;
-                }
-            });
-        });
-        sfor<CPL>([&](auto mc) {
-            constexpr int m = decltype(mc)::value;
-            const int j = NG * m + h;
-            s_g[i * RB + j] = j <= i ? g[m] : double2{0.0, 0.0};
+            // G_ij -= L_ik conj(c_j)
+            auto upd = [&](double2& v, double2 cj) {
+                v = double2{fma(-li.x, cj.x, fma(-li.y, cj.y, v.x)), fma(-li.y, cj.x, fma(li.x, cj.y, v.y))};
+            };
+            if constexpr (k + 1 < RB) {
+                constexpr int k1 = k + 1, ko1 = k1 % NG, km1 = k1 / NG;
+                upd(gr[km1], s_c[k % 2][NG * km1 + h]);
+                if (h == ko1) s_c[k1 % 2][i] = gr[km1];
+                const double dn = readlane_d(gr[km1].x, k1 + ko1 * RB);
+                const bool fn = !(dn > 0.0) || !isfinite(dn);
+                const double in = recip(fn ? 1.0 : dn);
+                sfor<CPL>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+                    if constexpr (m != km1 && NG * m + NG - 1 > k) upd(gr[m], s_c[k % 2][NG * m + h]);
+                });
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                dk = dn;
+                ik = in;
+                fail = fail || fn;
+            }
         });
         if (lane == 0) {
             s_fail = fail ? ST_ENOTPD : 0;
-            s_kappa = (piv_hi / piv_lo) * (piv_hi / piv_lo);
+            s_kappa = d_hi / d_lo;
         }
     }
     __syncthreads();
@@ -850,13 +878,12 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
             constexpr int k = decltype(kc)::value;
             lcol[k] = lane < RB ? s_g[k * RB + lane] : double2{0.0, 0.0};
         });
+        // y = D^{-1} z, then L^H gamma = y from the last row up
+        hv = double2{hv.x * dinv, hv.y * dinv};
         sfor<RB>([&](auto kc) {
             constexpr int k = RB - 1 - decltype(kc)::value;
-            const double2 zk = readlane_d2(hv, k);
-            const double ik = readlane_d(dinv, k);
-            const double2 gk{zk.x * ik, zk.y * ik};
-            if (lane == k) hv = gk;
-            else if (lane < k) {
+            const double2 gk = readlane_d2(hv, k);
+            if (lane < k) {
                 hv.x = fma(-lcol[k].x, gk.x, fma(-lcol[k].y, gk.y, hv.x));   // - conj(L_{k,lane}) gamma_k
                 hv.y = fma(-lcol[k].x, gk.y, fma(lcol[k].y, gk.x, hv.y));
             }
@@ -963,18 +990,23 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     // pass goes out before the status check (it reads the frame's own factors)
     constexpr int kLA = kOutTM * kOutRC / kOutThreads, kLB = kOutTN * kOutRC / kOutThreads;
     float2 la[kLA], lg[kLA], lb[kLB];
+    // (indices clamped into range and the values past it selected away, so the
+    // loads go out back to back)
     auto load_pass = [&](int r0) {
         const int nr = min(kOutRC, R - r0);
 #pragma unroll
         for (int u = 0; u < kLA; ++u) {
             const int e = tid + u * kOutThreads, row = e / kOutRC, c = e % kOutRC, i = bi + row;
-            la[u] = (i < n1 && c < nr) ? float2(f.A[size_t(i) * R + r0 + c]) : float2{0.f, 0.f};
-            lg[u] = c < nr ? float2(f.gamma32[r0 + c]) : float2{0.f, 0.f};
+            const int cc = r0 + min(c, nr - 1);
+            const float2 a = f.A[size_t(min(i, n1 - 1)) * R + cc], g = f.gamma32[cc];
+            la[u] = (i < n1 && c < nr) ? a : float2{0.f, 0.f};
+            lg[u] = c < nr ? g : float2{0.f, 0.f};
         }
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
             const int e = tid + u * kOutThreads, row = e / kOutRC, c = e % kOutRC, j = bj + row;
-            lb[u] = (j < n2 && c < nr) ? float2(f.B[size_t(j) * R + r0 + c]) : float2{0.f, 0.f};
+            const float2 b = f.B[size_t(min(j, n2 - 1)) * R + r0 + min(c, nr - 1)];
+            lb[u] = (j < n2 && c < nr) ? b : float2{0.f, 0.f};
         }
     };
     load_pass(0);

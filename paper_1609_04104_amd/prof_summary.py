@@ -86,7 +86,8 @@ def _per_dispatch(path, counter):
             key = f"{key} [grid {r['Grid_Size']}]"
             acc[key] += float(r["Counter_Value"])
             disp[key].add(r["Dispatch_Id"])
-    return {k: acc[k] / len(disp[k]) for k in acc}, {k: len(disp[k]) for k in acc}
+            grid[key] = int(r["Grid_Size"])
+    return {k: acc[k] / len(disp[k]) for k in acc}, {k: len(disp[k]) for k in acc}, grid
 
 
 def counters(fetch_csv, write_csv, copy_mib, out):
@@ -95,8 +96,8 @@ def counters(fetch_csv, write_csv, copy_mib, out):
     reads for the reference copy of copy_mib MiB (the copyBuffer dispatch of
     that size) so that the figures are true bytes."""
     import json
-    fetch, nf = _per_dispatch(fetch_csv, "FETCH_SIZE")
-    write, _ = _per_dispatch(write_csv, "WRITE_SIZE")
+    fetch, nf, grid = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write, _, _ = _per_dispatch(write_csv, "WRITE_SIZE")
     kib = copy_mib * 1024.0
     ref = [k for k in write if "copyBuffer" in k and abs(write[k] - kib) < 0.02 * kib]
     if not ref:
@@ -109,7 +110,7 @@ def counters(fetch_csv, write_csv, copy_mib, out):
         if k not in write:
             continue
         rec["kernels"][k] = {"fetch_bytes": fetch[k] * 1024.0 * fscale, "write_bytes": write[k] * 1024.0 * wscale,
-                             "dispatches": nf[k]}
+                             "dispatches": nf[k], "grid": grid[k]}
     with open(out, "w") as f:
         json.dump(rec, f, indent=1, sort_keys=True)
     print(f"fetch scale {fscale:.3f}, write scale {wscale:.3f}, {len(rec['kernels'])} kernels -> {out}")
