@@ -15,13 +15,48 @@ Readings:
   first word of Philox4x64-10 at counter (t, k, 0, 0) and key (seed, stream id);
 * the row drawn is the first i whose inclusive weight prefix exceeds u_k W,
   W being the computed weight total (clamped to the last row);
-* every sum runs sequentially in index order in float64 with no fused
-  multiply-add, so identical inputs give identical rows on any IEEE machine.
+* the paper fixes no order for the sums behind the weights; every sum of n
+  terms here runs in float64, with no fused multiply-add, as sequential sums
+  over consecutive blocks of SUM_BLOCK terms (each started from 0.0) whose
+  results are then added sequentially in block order (again from 0.0); the
+  inclusive prefix is the matching blocked scan: prefix_i = (the blocks before
+  i's block, added in order) + (i's block up to i, added in order).  Identical
+  inputs therefore give identical rows on any IEEE machine that follows the
+  same order.
 """
 
 import numpy as np
 
 from .philox import philox4x64_10
+
+SUM_BLOCK = 16     # terms per block of the blocked sums
+
+
+def blocked_sum(terms):
+    """Sum over the leading axis of ``terms`` in the blocked order: sequential
+    inside consecutive blocks of SUM_BLOCK, then the block sums in order."""
+    terms = np.asarray(terms, dtype=np.float64)
+    total = np.zeros(terms.shape[1:])
+    for b0 in range(0, terms.shape[0], SUM_BLOCK):
+        part = np.zeros(terms.shape[1:])
+        for i in range(b0, min(b0 + SUM_BLOCK, terms.shape[0])):
+            part = part + terms[i]
+        total = total + part
+    return total
+
+
+def blocked_prefix(w):
+    """Inclusive prefix of ``w`` in the blocked order of blocked_sum."""
+    w = np.asarray(w, dtype=np.float64)
+    out = np.empty(w.size)
+    before = 0.0                               # the blocks before this one, added in order
+    for b0 in range(0, w.size, SUM_BLOCK):
+        run = 0.0
+        for i in range(b0, min(b0 + SUM_BLOCK, w.size)):
+            run = run + w[i]
+            out[i] = before + run
+        before = before + run
+    return out
 
 
 def line_weights_prefix(Ahat, n2):
@@ -34,21 +69,16 @@ def line_weights_prefix(Ahat, n2):
     im = Ahat.imag.astype(np.float64)
     E = re * re + im * im                      # |Ahat_ir|^2
     n1, R = E.shape
-    c = np.zeros(R)
-    for i in range(n1):                        # column energies ||ahat_r||^2
-        c = c + E[i]
-    q = np.zeros(n1)
-    for r in range(R):                         # ||abar_i||^2 after normalisation
+    c = blocked_sum(E)                         # column energies ||ahat_r||^2, a sum over rows
+    # ||abar_i||^2 after normalisation, a sum over columns (a zero column's term is 0)
+    T = np.zeros((R, n1))
+    for r in range(R):
         if c[r] > 0.0:
-            q = q + E[:, r] / c[r]
+            T[r] = E[:, r] / c[r]
+    q = blocked_sum(T)
     w = float(n2) * q
     w = w + float(R)
-    prefix = np.empty(n1)
-    acc = 0.0
-    for i in range(n1):
-        acc = acc + w[i]
-        prefix[i] = acc
-    return w, prefix
+    return w, blocked_prefix(w)
 
 
 def line_scores(Ahat, n2):

@@ -974,7 +974,7 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     if (!src.live()) return;
     const DevFrame f = src.get();
     if (src.bx() < ds) {
-        draw_rows(f, *reinterpret_cast<SampleLds*>(s_raw));
+        draw_rows<kOutThreads>(f, *reinterpret_cast<SampleLds*>(s_raw));
         return;
     }
     float2* s_ag = reinterpret_cast<float2*>(s_raw);   // [row][c] = A[i0 + row][r0 + c] gamma[r0 + c]
@@ -989,18 +989,19 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     // A, gamma and B of a rank pass, all loads in flight together; the first
     // pass goes out before the status check (it reads the frame's own factors)
     constexpr int kLA = kOutTM * kOutRC / kOutThreads, kLB = kOutTN * kOutRC / kOutThreads;
-    float2 la[kLA], lg[kLA], lb[kLB];
+    static_assert(kOutThreads % kOutRC == 0, "a thread stages one rank column");
+    float2 la[kLA], lg, lb[kLB];
     // (indices clamped into range and the values past it selected away, so the
     // loads go out back to back)
     auto load_pass = [&](int r0) {
-        const int nr = min(kOutRC, R - r0);
+        const int nr = min(kOutRC, R - r0), c = tid % kOutRC, cc = r0 + min(c, nr - 1);   // the thread's rank
+        const float2 g = f.gamma32[cc];
+        lg = c < nr ? g : float2{0.f, 0.f};
 #pragma unroll
         for (int u = 0; u < kLA; ++u) {
-            const int e = tid + u * kOutThreads, row = e / kOutRC, c = e % kOutRC, i = bi + row;
-            const int cc = r0 + min(c, nr - 1);
-            const float2 a = f.A[size_t(min(i, n1 - 1)) * R + cc], g = f.gamma32[cc];
+            const int e = tid + u * kOutThreads, row = e / kOutRC, i = bi + row;
+            const float2 a = f.A[size_t(min(i, n1 - 1)) * R + cc];
             la[u] = (i < n1 && c < nr) ? a : float2{0.f, 0.f};
-            lg[u] = c < nr ? g : float2{0.f, 0.f};
         }
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
@@ -1019,7 +1020,7 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
 #pragma unroll
         for (int u = 0; u < kLA; ++u) {
             const int e = tid + u * kOutThreads;
-            s_ag[(e / kOutRC) * kOutPitch + e % kOutRC] = cmul(la[u], lg[u]);
+            s_ag[(e / kOutRC) * kOutPitch + e % kOutRC] = cmul(la[u], lg);
         }
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
@@ -1051,7 +1052,7 @@ template <class Src>
 __global__ void __launch_bounds__(kSampleThreads) k_sample(Src src) {
     __shared__ SampleLds s_l;
     if (!src.live()) return;
-    draw_rows(src.get(), s_l);
+    draw_rows<kSampleThreads>(src.get(), s_l);
 }
 
 // packed factor, right-hand side / gamma, then 1/L_kk and |gamma_r| (R doubles each)

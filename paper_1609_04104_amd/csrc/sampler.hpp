@@ -9,9 +9,13 @@
 // trials with replacement, trial k taking u_k = (first Philox4x64-10 word at
 // counter (t+1, k, 0, 0), key (seed, stream id)) >> 11, times 2^-53, and
 // drawing the first row whose inclusive weight prefix exceeds u_k W (W the
-// computed total, the last row if none).  Every sum runs in index order in
-// FP64 without fused multiply-adds, so the rows drawn match any IEEE
-// implementation of the same order bit for bit.
+// computed total, the last row if none).  The paper fixes no order for these
+// sums; every one of them runs in FP64 without fused multiply-adds as
+// sequential sums over consecutive blocks of kSumBlock terms (each from 0),
+// then the block sums in block order (from 0), and the prefix is the matching
+// blocked scan, so the rows drawn match any IEEE implementation of the same
+// order bit for bit while no dependent chain is longer than about
+// 2 sqrt(terms).
 #pragma once
 
 #include "frame.hpp"
@@ -19,19 +23,17 @@
 
 namespace tsl {
 
-constexpr int kSampleThreads = 256;   // threads that work on a draw (a bigger block idles the rest)
+constexpr int kSampleThreads = 256;   // block size of the standalone draw kernel
 constexpr int kUPre = 256;            // uniforms computed beside the prefix sum
-constexpr int kChunk = 2048;          // factor entries per staged chunk of rows (16 KiB)
-constexpr int kChunkLoads = kChunk / kSampleThreads;   // loads per thread that cover one chunk
-constexpr int kBatch = 8;             // LDS loads a sequential sum keeps one batch ahead
-constexpr int kResident = 2;          // chunks of F_l A held in registers at a time
-constexpr int kPB = 16;               // prefix values one thread holds per batch
+constexpr int kSumBlock = 16;         // terms per block of the blocked sums
+constexpr int kMaxBlk = kMaxN / kSumBlock;
+static_assert(TSL_MAX_R % kSumBlock == 0, "column blocks tile the widest rank");
 struct alignas(16) SampleLds {
-    double pref[kMaxN + kPB];         // weights, then their inclusive prefix (padded: the prefix
-                                      // reads and writes up to kPB values past n1, never used)
+    double pref[kMaxN];               // weights, then their inclusive prefix
     double c[TSL_MAX_R];              // column energies
     double u[kUPre];                  // u_k for k < kUPre
-    double buf[kChunk];               // a chunk of energies E_ir
+    double part[kMaxBlk * TSL_MAX_R]; // block sums: [row block][column], then [row][column block]
+    double tot[kMaxBlk];              // the prefix's block totals, then the blocks before each
     int mark[kMaxN];
     int wcount[kMaxN / 64];
 };
@@ -68,160 +70,108 @@ __device__ __forceinline__ double energy(float2 a) {
     return ax * ax + ay * ay;
 }
 
-// acc += buf[i R + r] for i = 0, 1, ..., nb - 1 in order (one or two columns
-// per lane), with the LDS loads of the next batch of rows in flight while the
-// current one is added; two register sets alternate, so no copies are needed.
-template <bool TWO>
-__device__ __forceinline__ void column_chain(const double* buf, int R, int r0, int r1, int nb, double& acc0,
-                                             double& acc1) {
-#pragma clang fp contract(off)
-    constexpr int B = TWO ? kBatch / 2 : kBatch;      // rows per register set (nb is a multiple of kBatch)
-    double a0[B], a1[B], b0[B], b1[B];
-    auto load = [&](double (&x0)[B], double (&x1)[B], int i0) {
-#pragma unroll
-        for (int w = 0; w < B; ++w) {
-            x0[w] = buf[(i0 + w) * R + r0];
-            if constexpr (TWO) x1[w] = buf[(i0 + w) * R + r1];
-        }
-    };
-    auto add = [&](const double (&x0)[B], const double (&x1)[B]) {
-#pragma unroll
-        for (int w = 0; w < B; ++w) {
-            acc0 = acc0 + x0[w];
-            if constexpr (TWO) acc1 = acc1 + x1[w];
-        }
-    };
-    load(a0, a1, 0);
-    for (int il = 0; il < nb; il += 2 * B) {
-        const bool more = il + B < nb;
-        if (more) load(b0, b1, il + B);
-        add(a0, a1);
-        if (more) {
-            if (il + 2 * B < nb) load(a0, a1, il + 2 * B);
-            add(b0, b1);
-        }
-    }
-}
-
+template <int NT>
 __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
 #pragma clang fp contract(off)
+    static_assert(NT % 64 == 0 && NT >= TSL_MAX_R && NT >= kMaxBlk, "block shape");
     const int K = f.K_next;
     if (K <= 0) return;
-    const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x, nt = blockDim.x;
-    const bool worker = tid < kSampleThreads;        // whole wavefronts
+    const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
     GlobalPtr<const float2> Ah = f.Ahat;
     const uint64_t t_next = uint64_t(f.dev->t + 1);
+    const int nblk = cdiv(n1, kSumBlock), ncb = cdiv(R, kSumBlock);
+    const size_t last = size_t(n1) * R - 1;
 
-    // For the column energies, rows of F_l A come in chunks of ck rows (a
-    // multiple of kBatch, ck R <= kChunk), kResident chunks at a time held in
-    // registers across the block: coalesced loads at indices clamped into the
-    // factor, zero past the end.
-    const int ck = min((kChunk / R) / kBatch * kBatch, cdiv(n1, kBatch) * kBatch);
-    const int span = kResident * ck;                 // rows held at a time
-    float2 a[kResident][kChunkLoads];
-    auto load_span = [&](int I0) {
-        sfor<kResident>([&](auto sc) {
-            constexpr int sub = decltype(sc)::value;
-            const int i0 = I0 + sub * ck;
-            const int ne = max(min(ck, n1 - i0), 0) * R;
+    // 1. Column energies c_r = sum over rows of E_ir = |Ahat_ir|^2 (FP64): thread
+    //    (b, r) adds rows [kSumBlock b, kSumBlock (b + 1)) of column r with all of
+    //    its loads in flight (coalesced over r, indices clamped into the factor,
+    //    rows past n1 adding +0, which leaves a nonnegative sum unchanged); the
+    //    block sums meet in LDS and thread r adds them in block order.
+    for (int p0 = 0; p0 < nblk * R; p0 += NT) {
+        const int p = p0 + tid, b = p / R, r = p % R;
+        float2 v[kSumBlock];
 #pragma unroll
-            for (int u = 0; u < kChunkLoads; ++u) {
-                const int e = tid + u * kSampleThreads;
-                const float2 v = Ah[min(size_t(i0) * R + e, size_t(n1) * R - 1)];
-                a[sub][u] = e < ne ? v : float2{0.f, 0.f};
-            }
-        });
-    };
-
-    // 1. Column energies c_r = sum_i E_ir in row order: the block writes a
-    //    chunk's energies E_ir = |Ahat_ir|^2 (FP64) to LDS, then wavefront 0
-    //    adds them up, lane l owning columns l and l + 64.  Rows past n1 are
-    //    zero, and adding +0 leaves a nonnegative sum unchanged.
-    {
-        const int r0 = min(tid, R - 1), r1 = min(tid + 64, R - 1);
-        const bool two = R > 64;
-        double acc0 = 0.0, acc1 = 0.0;
-        for (int I0 = 0; I0 < n1; I0 += span) {
-            if (worker) load_span(I0);
-            sfor<kResident>([&](auto sc) {
-                constexpr int sub = decltype(sc)::value;
-                const int i0 = I0 + sub * ck;
-                if (i0 < n1) {
-                    if (worker) {
+        for (int j = 0; j < kSumBlock; ++j) v[j] = Ah[min(size_t(b * kSumBlock + j) * R + r, last)];
+        double part = 0.0;
 #pragma unroll
-                        for (int u = 0; u < kChunkLoads; ++u) L.buf[tid + u * kSampleThreads] = energy(a[sub][u]);
-                    }
-                    __syncthreads();
-                    if (tid < 64) {
-                        const int nb = cdiv(min(ck, n1 - i0), kBatch) * kBatch;   // rows past n1 are zero
-                        if (two) column_chain<true>(L.buf, R, r0, r1, nb, acc0, acc1);
-                        else column_chain<false>(L.buf, R, r0, r1, nb, acc0, acc1);
-                    }
-                    __syncthreads();
-                }
-            });
+        for (int j = 0; j < kSumBlock; ++j) {
+            const double e = energy(v[j]);
+            part = part + (b * kSumBlock + j < n1 ? e : 0.0);
         }
-        if (tid < 64 && tid < R) L.c[tid] = acc0;
-        if (tid < 64 && tid + 64 < R) L.c[tid + 64] = acc1;
+        if (p < nblk * R) L.part[p] = part;
     }
-    for (int i = tid; i < n1; i += nt) L.mark[i] = 0;
+    for (int i = tid; i < n1; i += NT) L.mark[i] = 0;
+    __syncthreads();
+    if (tid < R) {
+        double c = 0.0;
+        for (int b = 0; b < nblk; ++b) c = c + L.part[b * R + tid];
+        L.c[tid] = c;
+    }
     __syncthreads();
 
-    // 2. w_i = N2 q_i + R with q_i = sum_r E_ir / c_r in column order, one thread
-    //    per row: the thread reads its row of F_l A (just read above, so mostly
-    //    from cache) eight entries at a time and adds its terms in order (a
-    //    zero column's term is 0, which leaves q unchanged).
-    for (int i = tid; i < n1; i += nt) {
+    // 2. w_i = N2 q_i + R with q_i = sum over columns of E_ir / c_r (a zero
+    //    column's term is 0): thread (i, k) adds the terms of column block k of
+    //    row i (loads and divisions side by side), the block sums meet in LDS
+    //    and thread i adds them in block order.
+    for (int p0 = 0; p0 < n1 * ncb; p0 += NT) {
+        const int p = p0 + tid, i = min(p / ncb, n1 - 1), k = p % ncb;
         const size_t row0 = size_t(i) * R;
-        double q = 0.0;
-        for (int r0 = 0; r0 < R; r0 += 8) {
-            float2 v[8];
+        float2 v[kSumBlock];
 #pragma unroll
-            for (int w = 0; w < 8; ++w) v[w] = Ah[row0 + min(r0 + w, R - 1)];
+        for (int j = 0; j < kSumBlock; ++j) v[j] = Ah[row0 + min(k * kSumBlock + j, R - 1)];
+        double part = 0.0;
 #pragma unroll
-            for (int w = 0; w < 8; ++w) {
-                const double c = L.c[min(r0 + w, R - 1)];
-                const double t = energy(v[w]) / (c > 0.0 ? c : 1.0);
-                q = q + ((r0 + w < R && c > 0.0) ? t : 0.0);
-            }
+        for (int j = 0; j < kSumBlock; ++j) {
+            const int r = k * kSumBlock + j;
+            const double c = L.c[min(r, R - 1)];
+            const double t = energy(v[j]) / (c > 0.0 ? c : 1.0);
+            part = part + ((r < R && c > 0.0) ? t : 0.0);
         }
+        if (p < n1 * ncb) L.part[p] = part;
+    }
+    __syncthreads();
+    for (int i = tid; i < n1; i += NT) {
+        double q = 0.0;
+        for (int k = 0; k < ncb; ++k) q = q + L.part[i * ncb + k];
         double w = double(n2) * q;
         w = w + double(R);
         L.pref[i] = w;
     }
     __syncthreads();
 
-    // 3. Inclusive prefix in row order (one thread, loads a batch ahead; the
-    //    padded tail is read and written but never used); meanwhile the other
-    //    wavefronts draw the first kUPre uniforms.
+    // 3. Inclusive prefix, blocked: thread b scans its block of rows in order
+    //    and keeps the block total, thread 0 adds the totals in block order
+    //    (the sum of the blocks before each), and every row adds its block's
+    //    offset; meanwhile the other wavefronts draw the first kUPre uniforms.
     if (tid >= 64) {
         const int kp = min(K, kUPre);
-        for (int k = tid - 64; k < kp; k += nt - 64) L.u[k] = uniform_trial(t_next, k, f.seed, f.sid);
+        for (int k = tid - 64; k < kp; k += NT - 64) L.u[k] = uniform_trial(t_next, k, f.seed, f.sid);
     }
-    if (tid == 0) {
-        double2* p2 = reinterpret_cast<double2*>(L.pref);
-        constexpr int kH = kPB / 2;
+    if (tid < nblk) {
+        const int i0 = tid * kSumBlock, ni = min(kSumBlock, n1 - i0);
         double run = 0.0;
-        for (int h0 = 0; h0 < cdiv(n1, 2); h0 += kH) {
-            double2 v[kH];
-#pragma unroll
-            for (int w = 0; w < kH; ++w) v[w] = p2[h0 + w];
-#pragma unroll
-            for (int w = 0; w < kH; ++w) {
-                run = run + v[w].x;
-                v[w].x = run;
-                run = run + v[w].y;
-                v[w].y = run;
-            }
-#pragma unroll
-            for (int w = 0; w < kH; ++w) p2[h0 + w] = v[w];
+        for (int j = 0; j < ni; ++j) {
+            run = run + L.pref[i0 + j];
+            L.pref[i0 + j] = run;
+        }
+        L.tot[tid] = run;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double before = 0.0;
+        for (int b = 0; b < nblk; ++b) {
+            const double t = L.tot[b];
+            L.tot[b] = before;
+            before = before + t;
         }
     }
+    __syncthreads();
+    for (int i = tid; i < n1; i += NT) L.pref[i] = L.tot[i / kSumBlock] + L.pref[i];
     __syncthreads();
 
     // 4. Trials: first row whose prefix exceeds u_k W.
     const double W = L.pref[n1 - 1];
-    for (int k = tid; k < K; k += nt) {
+    for (int k = tid; k < K; k += NT) {
         const double u = k < kUPre ? L.u[k] : uniform_trial(t_next, k, f.seed, f.sid);
         const double target = u * W;
         int lo = 0, hi = n1;
@@ -239,13 +189,13 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
     //    population count gives the word's offset, the lane's rank inside the
     //    word its position (integers, so the result is exact).
     const int nw = cdiv(n1, 64), lane = tid % 64;
-    for (int wd = tid / 64; wd < nw; wd += nt / 64) {
+    for (int wd = tid / 64; wd < nw; wd += NT / 64) {
         const int i = wd * 64 + lane;
         const unsigned long long m = __ballot(i < n1 && L.mark[i]);
         if (lane == 0) L.wcount[wd] = __popcll(m);
     }
     __syncthreads();
-    for (int wd = tid / 64; wd < nw; wd += nt / 64) {
+    for (int wd = tid / 64; wd < nw; wd += NT / 64) {
         const int i = wd * 64 + lane;
         const bool on = i < n1 && L.mark[i];
         const unsigned long long m = __ballot(on);
@@ -259,7 +209,7 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
         f.n_next[0] = total;
     }
     if (f.prefix_next)
-        for (int i = tid; i < n1; i += nt) f.prefix_next[i] = L.pref[i];
+        for (int i = tid; i < n1; i += NT) f.prefix_next[i] = L.pref[i];
 }
 
 }  // namespace tsl

@@ -410,3 +410,35 @@ def test_oracle_matches_its_committed_fixture():
         g = np.array(gold["gamma"][t][0]) + 1j * np.array(gold["gamma"][t][1])
         assert _nr(s.gamma, g) < 1e-12
         assert abs(s.alpha_bar - gold["alpha_bar"][t]) < 1e-9 * gold["alpha_bar"][t]
+
+
+def test_blocked_sums_follow_the_stated_order():
+    from oracle.sampler import SUM_BLOCK, blocked_prefix, blocked_sum
+    assert SUM_BLOCK == 16
+    # integer-valued terms: every order is exact, so the sum and the prefix are the exact ones
+    rng = _rng(19)
+    x = rng.integers(0, 1000, size=77).astype(np.float64)
+    assert blocked_sum(x) == float(x.sum())
+    assert np.array_equal(blocked_prefix(x), np.cumsum(x))
+    # an order-sensitive case: 1 followed by 31 terms of 2^-53.  Added one by one
+    # each small term is lost against 1; in blocks of 16 the second block's
+    # sixteen terms meet first (2^-49) and survive
+    y = np.array([1.0] + [2.0 ** -53] * 31)
+    seq = 0.0
+    for v in y:
+        seq = seq + v
+    assert seq == 1.0
+    assert blocked_sum(y) == 1.0 + 2.0 ** -49
+    p = blocked_prefix(y)
+    assert p[15] == 1.0 and p[16] == 1.0 and p[31] == 1.0 + 2.0 ** -49
+    assert p[-1] == blocked_sum(y)
+    # within one block the prefix is the sequential one
+    z = rng.random(SUM_BLOCK)
+    seq_p, run = [], 0.0
+    for v in z:
+        run = run + v
+        seq_p.append(run)
+    assert np.array_equal(blocked_prefix(z), np.array(seq_p))
+    # the sum over columns of a 2-D array goes along the leading axis
+    m = rng.random((40, 3))
+    assert np.array_equal(blocked_sum(m), np.array([blocked_sum(m[:, j]) for j in range(3)]))
