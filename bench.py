@@ -123,7 +123,7 @@ PHASE_KERNELS = {   # kernel of each phase in a table launch of n x n frames
     "row inverse + A grad": "void k_row_inv_grad<{n}, FrameTable>",
     "k-space residual + gradients": "void k_kres<",
     "factor updates + F_l A, F_r B": "void k_update_ab<{n}, FrameTable>",
-    "output synthesis + row draw": "void k_synth_out<FrameTable>",
+    "output synthesis + row draw": "void k_synth_out<",
 }
 COUNTERS = os.path.join(ROOT, "profiles", "step_64x256sq_r32_counters.json")
 

@@ -968,7 +968,9 @@ constexpr int kOutPitch = kOutRC + 1;        // LDS row pitch (float2): conflict
 // which needs only F_l A of the new A) beside the output tiles; the two roles
 // share one LDS area.
 constexpr size_t kOutLds = size_t(kOutTM + kOutTN) * kOutPitch * sizeof(float2);
-template <class Src>
+// ONE: every rank fits one pass (R <= kOutRC), so no staging load is in
+// flight beside the accumulators and the kernel needs fewer registers.
+template <bool ONE, class Src>
 __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     __shared__ __align__(16) unsigned char s_raw[kOutLds > sizeof(SampleLds) ? kOutLds : sizeof(SampleLds)];
     if (!src.live()) return;
@@ -993,6 +995,9 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     float2 la[kLA], lg, lb[kLB];
     // (indices clamped into range and the values past it selected away, so the
     // loads go out back to back)
+    // (32-bit byte offsets from the frame's factor bases: one register per load address)
+    const GlobalPtr<const char> Ab = reinterpret_cast<GlobalPtr<const char>>(f.A);
+    const GlobalPtr<const char> Bb = reinterpret_cast<GlobalPtr<const char>>(f.B);
     auto load_pass = [&](int r0) {
         const int nr = min(kOutRC, R - r0), c = tid % kOutRC, cc = r0 + min(c, nr - 1);   // the thread's rank
         const float2 g = f.gamma32[cc];
@@ -1000,23 +1005,27 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
 #pragma unroll
         for (int u = 0; u < kLA; ++u) {
             const int e = tid + u * kOutThreads, row = e / kOutRC, i = bi + row;
-            const float2 a = f.A[size_t(min(i, n1 - 1)) * R + cc];
+            const unsigned off = unsigned(min(i, n1 - 1) * R + cc) * 8u;
+            const float2 a = *reinterpret_cast<GlobalPtr<const float2>>(Ab + off);
             la[u] = (i < n1 && c < nr) ? a : float2{0.f, 0.f};
         }
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
             const int e = tid + u * kOutThreads, row = e / kOutRC, c = e % kOutRC, j = bj + row;
-            const float2 b = f.B[size_t(min(j, n2 - 1)) * R + r0 + min(c, nr - 1)];
+            const unsigned off = unsigned(min(j, n2 - 1) * R + r0 + min(c, nr - 1)) * 8u;
+            const float2 b = *reinterpret_cast<GlobalPtr<const float2>>(Bb + off);
             lb[u] = (j < n2 && c < nr) ? b : float2{0.f, 0.f};
         }
     };
     load_pass(0);
     if (!block_frame_ok(f.dev, true)) return;
     f32x16 accr = {}, acci = {};
-    for (int r0 = 0; r0 < R; r0 += kOutRC) {
+    for (int r0 = 0; r0 < (ONE ? 1 : R); r0 += kOutRC) {
         const int nr = min(kOutRC, R - r0);
-        __syncthreads();
-        if (r0 > 0) load_pass(r0);
+        if (!ONE) {
+            __syncthreads();
+            if (r0 > 0) load_pass(r0);
+        }
 #pragma unroll
         for (int u = 0; u < kLA; ++u) {
             const int e = tid + u * kOutThreads;
@@ -1124,8 +1133,13 @@ hipError_t launch_synth_out(const Batch& b, hipStream_t st) {
     const int gx = ds + (b.want_x ? cdiv(b.n1, kOutTM) * cdiv(b.n2, kOutTN) : 0);
     if (gx == 0) return hipSuccess;
     const dim3 grid = frame_grid(b, gx);
-    if (b.table) k_synth_out<FrameTable><<<grid, kOutThreads, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
-    else k_synth_out<OneFrame><<<grid, kOutThreads, 0, st>>>(OneFrame{*b.one}, ds);
+    if (b.r_max <= kOutRC) {
+        if (b.table) k_synth_out<true, FrameTable><<<grid, kOutThreads, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
+        else k_synth_out<true, OneFrame><<<grid, kOutThreads, 0, st>>>(OneFrame{*b.one}, ds);
+    } else {
+        if (b.table) k_synth_out<false, FrameTable><<<grid, kOutThreads, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
+        else k_synth_out<false, OneFrame><<<grid, kOutThreads, 0, st>>>(OneFrame{*b.one}, ds);
+    }
     return hipGetLastError();
 }
 
