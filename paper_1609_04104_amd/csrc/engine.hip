@@ -38,7 +38,7 @@ int hip_fail(hipError_t e, const char* what) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, wpart, part, hpart, total;
+    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, wpart, mpart, part, hpart, total;
 };
 
 Layout layout_for(int n1, int n2, int r) {
@@ -56,6 +56,7 @@ Layout layout_for(int n1, int n2, int r) {
     L.Wb = take(size_t(n2) * r * sizeof(float2));
     L.GA = take(size_t(n1) * r * sizeof(float2));
     L.wpart = take(size_t(tsl::n_qparts(n1)) * n2 * r * sizeof(float2));
+    L.mpart = take(size_t(tsl::n_cparts(n2)) * n1 * r * sizeof(float2));
     L.part = take(size_t(tsl::n_parts(n1, n2)) * r * r * sizeof(double2));
     L.hpart = take(size_t(tsl::n_hparts(n1, n2)) * r * sizeof(double2));
     L.total = o;
@@ -99,6 +100,7 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     a.gamma64 = s->at<double2>(s->lay.g64); a.gamma32 = s->at<float2>(s->lay.g32);
     a.frame = s->at<float2>(s->lay.frame); a.Wb = s->at<float2>(s->lay.Wb); a.GA = s->at<float2>(s->lay.GA);
     a.wpart = s->at<float2>(s->lay.wpart);
+    a.mpart = s->at<float2>(s->lay.mpart);
     a.part = s->at<double2>(s->lay.part); a.hpart = s->at<double2>(s->lay.hpart);
     a.rows = fr.rows; a.n_rows_dev = fr.mask ? nullptr : fr.n_rows_dev; a.y_full = fr.y_full ? 1 : 0;
     a.mask = fr.mask; a.y = reinterpret_cast<const float2*>(fr.y);

@@ -33,6 +33,7 @@ constexpr int kSRows = 32;      // sampled rows per (Gram, rhs) partial, line ma
 constexpr int kPRows = 32;      // mask rows per (Gram, rhs) partial, point masks
 constexpr int kJCH = 32;        // readout samples per right-hand-side partial, line masks
 constexpr int kKQ = 16;         // sampled rows per block of the k-space residual (partials of E^T conj(Ahat_S))
+constexpr int kKCols = 128;     // readout samples per block of the k-space residual (partials of E conj(Bhat))
 
 __host__ __device__ constexpr inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ inline int n_gparts(int n) { return cdiv(n, kGRows); }
@@ -41,6 +42,7 @@ __host__ __device__ inline int n_jparts(int n2) { return cdiv(n2, kJCH); }
 __host__ __device__ inline int n_parts(int n1, int n2) { return n_gparts(n1) + n_gparts(n2) + n_sparts(n1); }
 __host__ __device__ inline int n_hparts(int n1, int n2) { return n_sparts(n1) * n_jparts(n2); }
 __host__ __device__ inline int n_qparts(int n1) { return cdiv(n1, kKQ); }
+__host__ __device__ inline int n_cparts(int n2) { return cdiv(n2, kKCols); }
 
 // Pointer types of a frame descriptor.  The host fills descriptors with plain
 // pointers; device code reads the same bits as pointers into the global address
@@ -71,6 +73,8 @@ struct FrameArgsT {
     P<float2> Wb;         // [n2][r]: Z^T conj(A), Z the column-back-projected residual (= E^T conj(Ahat_S))
     P<float2> GA;         // [n1][r]: Theta conj(B) (frame route); E conj(Bhat) on the sampled rows, else 0 (k-space route)
     P<float2> wpart;      // [n_qparts(n1)][n2][r]: E^T conj(Ahat_S) per chunk of kKQ sampled rows (k-space route)
+    P<float2> mpart;      // [n_cparts(n2)][n1][r]: slab p >= 1 holds the part of E conj(Bhat) over samples
+                          // [kKCols p, kKCols (p + 1)) on the sampled rows, 0 elsewhere; GA holds part 0 (k-space route)
     P<double2> part;      // [n_parts][r][r] partial Grams
     P<double2> hpart;     // [n_hparts][r] partial right-hand sides
     // inputs of the frame

@@ -252,14 +252,16 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
     // the update's layout after the transform; frame route: both in row order).
     load_tw<N1>(s_tw);
     const double2 g = rv ? f.gamma64[r] : double2{0.0, 0.0};
-    float2 v[T], apre[T];
+    float2 v[T], apre[T], w1[P];
     zero(v);
     zero(apre);
+    const int ncp = f.kspace ? n_cparts(f.n2) : 1;   // slabs of E conj(Bhat): GA, then mpart 1..
     if (f.kspace) {
         if (s < Q && rv) {
             sfor<P>([&](auto qc) {
                 constexpr int n1c = decltype(qc)::value;
                 v[n1c] = f.GA[size_t(Q * n1c + s) * R + r];
+                w1[n1c] = ncp > 1 ? float2(f.mpart[(size_t(N1) + Q * n1c + s) * R + r]) : float2{0.f, 0.f};
             });
         }
         if (s < P && rv) {
@@ -284,8 +286,20 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
         d->t = d->t_new;
     }
     if (f.kspace) {
+        // M = the slabs added in order (the first two were loaded above)
+        if (s < Q && rv) {
+            sfor<P>([&](auto qc) {
+                constexpr int n1c = decltype(qc)::value;
+                if (ncp > 1) v[n1c] = cadd(v[n1c], w1[n1c]);
+            });
+            for (int p = 2; p < ncp; ++p)
+                sfor<P>([&](auto qc) {
+                    constexpr int n1c = decltype(qc)::value;
+                    v[n1c] = cadd(v[n1c], float2(f.mpart[(size_t(p) * N1 + Q * n1c + s) * R + r]));
+                });
+        }
         // k-space route: Theta conj(B) = F_l^H M with M = E conj(Bhat) on the
-        // sampled rows and zero elsewhere (as the k-space residual kernel left GA);
+        // sampled rows and zero elsewhere (as the k-space residual kernel left the slabs);
         // then the update in the transform's output layout and F_l A of the new
         // A, as in the B update.
         __syncthreads();

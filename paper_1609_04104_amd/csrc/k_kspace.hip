@@ -14,11 +14,14 @@
 // the A update applies F_l^H to GA (k_update_a), the B update adds the W
 // partials in chunk order and applies F_r^H (k_update_b).
 //
-// A block (sixteen wavefronts) owns kKQ sampled rows of one frame and runs over
-// the readout samples in chunks of up to 256 columns (fewer at large ranks, so
-// that the chunk of Bhat fits in LDS), wavefront w taking columns
-// [16 w, 16 w + 16) of a chunk.  Per chunk, on FP32 matrix cores with the
-// complex products split over K = (index, re/im) as in the synthesis:
+// A block (eight wavefronts) owns kKQ sampled rows and kKCols readout samples of
+// one frame and runs over them in chunks of up to 128 columns (fewer at large
+// ranks, so that the chunk of Bhat fits in LDS), wavefront w taking columns
+// [16 w, 16 w + 16) of a chunk.  Its M covers its samples only: the block of
+// samples p writes it to slab p (GA for p = 0, mpart for p >= 1) at the sampled
+// rows, every slab holds 0 on the other rows, and the A update adds the slabs
+// in order.  Per chunk, on FP32 matrix cores with the complex products split
+// over K = (index, re/im) as in the synthesis:
 //   E tile [q][j]  = y - sum_r (Ahat_S gamma)[q][r] Bhat[j][r]   (K = ranks)
 //   M     [q][r] += sum_j E[q][j] conj(Bhat[j][r])               (K = the wavefront's columns)
 //   W tile [j][r]  = sum_q E[q][j] conj(Ahat_S[q][r])            (K = the block's rows)
@@ -34,13 +37,14 @@
 namespace tsl {
 namespace {
 
-constexpr int kKT = 1024;           // threads per block (sixteen wavefronts)
+constexpr int kKT = 512;            // threads per block (eight wavefronts)
 constexpr int kKW = kKT / 64;       // wavefronts; wavefront w takes columns [16 w, 16 w + 16) of a chunk
 constexpr int kEP = 17;             // LDS pitch of a wavefront's E tile (float2)
-constexpr size_t kBBudget = 96 * 1024;   // LDS for the Bhat chunk
+constexpr size_t kBBudget = 48 * 1024;   // LDS for the Bhat chunk
 static_assert(kKQ == 16, "one matrix-core row tile of sampled rows per block");
+static_assert(kKCols == 16 * kKW, "a block's samples are one chunk of all its wavefronts' tiles");
 
-// Columns per chunk: all sixteen wavefronts' tiles, fewer when the Bhat chunk
+// Columns per chunk: all eight wavefronts' tiles, fewer when the Bhat chunk
 // [cols][R + 1] would not fit the budget (large ranks).
 inline __host__ __device__ int kres_cols(int R) {
     const int fit = int(kBBudget / (size_t(R + 1) * sizeof(float2))) / 16 * 16;
@@ -71,7 +75,8 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
     const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const int m = lane % 16, g4 = lane / 16;
     const bool pim = g4 & 1;                         // which part this lane's K entry takes
-    const int qc = src.bx(), q0 = qc * kKQ;
+    const int ncp = n_cparts(n2), bx = src.bx(), qc = bx / ncp, cp = bx % ncp, q0 = qc * kKQ;
+    const int c0 = cp * kKCols, c1 = min(n2, c0 + kKCols);   // the block's samples
     // Loads that need nothing but the descriptor go out before the status check
     // (all inside the frame's own buffers): the row count, the row list, gamma
     // and the first round of the first chunk of Bhat.
@@ -83,11 +88,11 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
     // (staging loads read at indices clamped into range and select the values
     // past it away, so that they go out back to back with no branch between)
     float2 b0[4];
-    const int nb0 = min(JC, n2) * R;
+    const int nb0 = min(JC, c1 - c0) * R;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int e = tid + u * kKT;
-        const float2 v = f.Bhat[min(e, nb0 - 1)];
+        const float2 v = f.Bhat[size_t(c0) * R + min(e, nb0 - 1)];
         b0[u] = e < nb0 ? v : float2{0.f, 0.f};
     }
     for (int i = tid; i < n1; i += kKT) s_on[i] = 0;
@@ -110,11 +115,14 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
         const float2 v = f.Ahat[size_t(max(row, 0)) * R + c];
         s_a[q * RP + c] = row >= 0 ? v : float2{0.f, 0.f};
     }
-    // rows of GA that this block zeroes: the unsampled rows i with i mod nblk = qc
-    const int nown = qc < n1 ? cdiv(n1 - qc, nblk) : 0;
+    // rows that this block zeroes in every slab: the unsampled rows i with i mod nblk = bx
+    const int nown = bx < n1 ? cdiv(n1 - bx, nblk) : 0;
     for (int e = tid; e < nown * R; e += kKT) {
-        const int i = qc + (e / R) * nblk;
-        if (!s_on[i]) f.GA[size_t(i) * R + e % R] = float2{0.f, 0.f};
+        const int i = bx + (e / R) * nblk;
+        if (!s_on[i]) {
+            f.GA[size_t(i) * R + e % R] = float2{0.f, 0.f};
+            for (int p = 1; p < ncp; ++p) f.mpart[(size_t(p) * n1 + i) * R + e % R] = float2{0.f, 0.f};
+        }
     }
     if (nq == 0) return;                             // uniform
 
@@ -123,8 +131,8 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
 #pragma unroll
     for (int t = 0; t < RT; ++t) mr[t] = mi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     float2* s_ew = s_e + wave * 16 * kEP;            // this wavefront's E tile [q][j]
-    for (int j0 = 0; j0 < n2; j0 += JC) {
-        const int njc = min(JC, n2 - j0), nbc = njc * R;   // columns and Bhat entries of the chunk
+    for (int j0 = c0; j0 < c1; j0 += JC) {
+        const int njc = min(JC, c1 - j0), nbc = njc * R;   // columns and Bhat entries of the chunk
         __syncthreads();                             // the previous chunk's reads of s_b are done
         {   // the samples and the chunk of Bhat, four loads per thread in flight per round
             float2 yv[kYL];
@@ -137,7 +145,7 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
             }
             for (int e0 = 0; e0 < JC * R; e0 += 4 * kKT) {
                 float2 bv[4];
-                if (j0 == 0 && e0 == 0) {
+                if (j0 == c0 && e0 == 0) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) bv[u] = b0[u];
                 } else {
@@ -163,7 +171,7 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
         }
         __syncthreads();
         const int jt0 = j0 + 16 * wave;              // first column of this wavefront's tile
-        if (16 * wave < JC && jt0 < n2) {            // uniform
+        if (16 * wave < JC && jt0 < c1) {            // uniform
             // E tile: prediction on the matrix cores, then y - prediction
             f32x4 er{0.f, 0.f, 0.f, 0.f}, ei{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
@@ -181,7 +189,7 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
             for (int i = 0; i < 4; ++i) {
                 const int q = 4 * g4 + i, j = m;
                 const float2 yq = s_ew[q * kEP + j];
-                const bool live = q < nq && jt0 + j < n2;
+                const bool live = q < nq && jt0 + j < c1;
                 const float2 e = live ? float2{yq.x - er[i], yq.y - ei[i]} : float2{0.f, 0.f};
                 bad |= live && !finite2(yq);
                 s_ew[q * kEP + j] = e;
@@ -223,7 +231,7 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
         }
     }
     // the wavefronts' M sums meet in LDS (over the Bhat chunk) and are added in order
-    const int nw = min(kKW, cdiv(min(JC, n2), 16));  // wavefronts that took columns
+    const int nw = min(kKW, cdiv(min(JC, c1 - c0), 16));   // wavefronts that took columns
     __syncthreads();
     float2* s_m = s_b;                               // [wave][q][r]
     if (wave < nw) {
@@ -238,12 +246,13 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
         }
     }
     __syncthreads();
+    const GlobalPtr<float2> slab = cp == 0 ? f.GA : f.mpart + size_t(cp) * n1 * R;
     for (int e = tid; e < nq * R; e += kKT) {
         const int q = e / R, r = e % R, row = s_row[q];
         float2 acc = s_m[q * R + r];
         for (int w = 1; w < nw; ++w) acc = cadd(acc, s_m[(w * kKQ + q) * R + r]);
         bad |= !finite2(acc);
-        if (row >= 0) f.GA[size_t(row) * R + r] = acc;
+        if (row >= 0) slab[size_t(row) * R + r] = acc;
     }
     if (bad) s_bad = 1;
     __syncthreads();
@@ -264,7 +273,7 @@ void kres_attributes() {
 }
 
 template <int RT> void launch_kres_rt(const Batch& b, hipStream_t st) {
-    const int gx = std::max(1, n_qparts(b.rows_max));
+    const int gx = std::max(1, n_qparts(b.rows_max)) * n_cparts(b.n2);
     const dim3 grid = frame_grid(b, gx);
     const size_t lds = kres_lds(b.r_max);
     if (b.table) k_kres<RT, FrameTable><<<grid, kKT, lds, st>>>(FrameTable{b.table, gx, b.count}, gx);
