@@ -684,6 +684,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     __shared__ double2 s_h[RB];            // gamma
     __shared__ double2 s_hp[kRegBlk];      // the first kRegBlk right-hand-side partial entries
     __shared__ double2 s_c[2][RB];         // column k of the partly reduced G during step k (two buffers)
+    __shared__ double s_piv[2];            // its pivot D_k (two buffers; four-wavefront sweep)
     __shared__ double s_ag[RB];            // |gamma|
     __shared__ double s_best[kRegBlk / 64];
     __shared__ double s_kappa;
@@ -794,6 +795,87 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     }
     __syncthreads();
 
+    double2 hv{0.0, 0.0};
+    double dinv = 0.0;                            // 1 / D_ii of the lane's row (wavefront 0)
+    // h_i = sum of its slots in slot order (wavefront 0, both halves)
+    auto gather_h = [&](int i) {
+        if (i < R)
+            for (int q = 0; q < nh; ++q) {
+                const int e = q * R + i;
+                const double2 v = e < kRegBlk ? s_hp[e] : f.hpart[e];
+                hv.x += v.x;
+                hv.y += v.y;
+            }
+    };
+    if constexpr (RB == 32) {
+        // Right-looking L D L^H shared by the four wavefronts, one barrier per
+        // step.  Lane l of wavefront w holds row i = l % 32 of the columns
+        // j = 8 m + g, g = 2 w + l / 32.  Step k reads the unscaled column
+        // c = G[:, k] and its pivot D_k from LDS (every wavefront forms 1/D_k)
+        // and applies G_ij -= c_i conj(c_j) / D_k to its columns; the lane group
+        // that holds column k+1 reduces it first and puts it and its pivot in
+        // the other LDS buffer for the next step.  Wavefront 0 also keeps L
+        // (into s_g), 1/D and the forward substitution L z = h.  Entries above
+        // the diagonal and of finished columns receive updates too (never
+        // read).  No branches on the pivots: one that is not positive and
+        // finite sets `fail` (read from LDS, so the same everywhere) and is
+        // replaced by 1; the frame is then rejected.
+        constexpr int NG = 8, CPL = RB / NG;      // column groups in the block, columns per lane
+        const int i = lane % RB, g = 2 * wave + lane / RB;
+        double2 gr[CPL];
+        sfor<CPL>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            gr[m] = s_g[i * RB + NG * m + g];
+        });
+        if (wave == 0) gather_h(i);
+        if (g == 0) s_c[0][i] = gr[0];
+        if (g == 0 && i == 0) s_piv[0] = gr[0].x;
+        __syncthreads();
+        bool fail = false;
+        double d_lo = 1e308, d_hi = 0.0;
+        sfor<RB>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const double dk = s_piv[k % 2];
+            const bool fk = !(dk > 0.0) || !isfinite(dk);
+            fail = fail || fk;
+            const double ik = recip(fk ? 1.0 : dk);
+            if (k < R) { d_lo = fmin(d_lo, dk); d_hi = fmax(d_hi, dk); }
+            const double2 ci = s_c[k % 2][i];                   // G_ik
+            const double2 li{ci.x * ik, ci.y * ik};             // L_ik
+            if (wave == 0) {
+                if (i == k) dinv = ik;
+                if (lane < RB && i > k) s_g[i * RB + k] = li;
+                const double2 zk = readlane_d2(hv, k);          // z_k
+                if (i > k) {
+                    hv.x = fma(-li.x, zk.x, fma(li.y, zk.y, hv.x));
+                    hv.y = fma(-li.x, zk.y, fma(-li.y, zk.x, hv.y));
+                }
+            }
+            // G_ij -= L_ik conj(c_j)
+            auto upd = [&](double2& v, double2 cj) {
+                v = double2{fma(-li.x, cj.x, fma(-li.y, cj.y, v.x)), fma(-li.y, cj.x, fma(li.x, cj.y, v.y))};
+            };
+            if constexpr (k + 1 < RB) {
+                constexpr int k1 = k + 1, g1 = k1 % NG, m1 = k1 / NG;
+                const bool own = g == g1;                        // this lane group holds column k+1
+                if (own) {
+                    upd(gr[m1], s_c[k % 2][k1]);
+                    s_c[k1 % 2][i] = gr[m1];
+                    if (i == k1) s_piv[k1 % 2] = gr[m1].x;
+                }
+                sfor<CPL>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+                    if constexpr (NG * m + NG - 1 > k)
+                        if (m != m1 || !own) upd(gr[m], s_c[k % 2][NG * m + g]);
+                });
+                __syncthreads();
+            }
+        });
+        if (wave == 0 && lane == 0) {
+            s_fail = fail ? ST_ENOTPD : 0;
+            s_kappa = d_hi / d_lo;
+        }
+    } else {
     // Wavefront 0: right-looking L D L^H, one column ahead.  Lane l holds row
     // i = l % RB of the columns j = NG m + l / RB (NG = 64 / RB column groups,
     // so all 64 lanes work).  Step k reads the unscaled column c = G[:, k]
@@ -807,22 +889,13 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     // the remaining steps stay finite; the frame is then rejected.
     constexpr int NG = 64 / RB, CPL = RB / NG;    // column groups, columns per lane
     double2 gr[CPL];
-    double2 hv{0.0, 0.0};
-    double dinv = 0.0;                            // 1 / D_ii of the lane's row
     if (wave == 0) {
         const int i = lane % RB, h = lane / RB;
         sfor<CPL>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
             gr[m] = s_g[i * RB + NG * m + h];
         });
-        // h_i = sum of its slots in slot order
-        if (i < R)
-            for (int q = 0; q < nh; ++q) {
-                const int e = q * R + i;
-                const double2 v = e < kRegBlk ? s_hp[e] : f.hpart[e];
-                hv.x += v.x;
-                hv.y += v.y;
-            }
+        gather_h(i);
         if (h == 0) s_c[0][i] = gr[0];
         double dk = readlane_d(gr[0].x, 0);
         bool fail = !(dk > 0.0) || !isfinite(dk);
@@ -870,6 +943,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
             s_fail = fail ? ST_ENOTPD : 0;
             s_kappa = d_hi / d_lo;
         }
+    }
     }
     __syncthreads();
     if (wave == 0 && !s_fail) {
