@@ -116,7 +116,7 @@ PEAK_TFS = {"fp64": 78.6, "mfma": 157.3, "fp32": 157.3}   # MI355X published: FP
 
 
 PHASE_KERNELS = {   # kernel of each phase in a table launch of n x n frames
-    "partial Grams": "void k_lstats<FrameTable>",
+    "partial Grams": "void k_lstats<",
     "ridge solve + step size": "void k_solve",
     "synthesis + row pass": "void k_synth_rowfft<{n}, FrameTable>",
     "column pass + residual": "void k_col_resid<{n}, FrameTable>",
@@ -315,7 +315,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": dbytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    gx = (-(-n // 64)) * 2 + (-(-K // 32)) * (-(-n // 32))          # statistics blocks per frame
+    gx = (-(-n // 64)) * 2 + (-(-K // 32)) * (1 + (-(-n // 32)))    # statistics blocks per frame
     roof["traffic"] = counter_traffic(dname, n, grid=gx * 256 * (-(-S // 8) * 8))
     roof["kernel"] = dname
     roof["algorithmic_bytes_per_launch"] = dbytes

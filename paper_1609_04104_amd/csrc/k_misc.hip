@@ -60,12 +60,16 @@ __device__ __forceinline__ void pivot(double d, double& p, double& ip) {
 constexpr int kSB = 256;
 static_assert(kJCH >= kSRows, "the rhs products reuse the readout-chunk staging area");
 
-// Upper entries (r <= s) of sum_q conj(x_qr) x_qs over the nq rows of s_x ([nq][R])
-// on FP64 matrix cores (products of FP32 values are exact in FP64).  With the K
+// Upper entries (r <= s) of sum_q conj(x_qr) x_qs over the nq rows of s_x ([nq][R],
+// complex64 or complex128, widened when read) on FP64 matrix cores (products of
+// FP32 values are exact in FP64).  With the K
 // index over (row, re/im), Re = sum Xr_r Xr_s + Xi_r Xi_s and
 // Im = sum Xr_r Xi_s - Xi_r Xr_s are each one 16x16x4 step per two rows; the
 // wavefronts take the 16 x 16 tiles on and above the diagonal.
-__device__ void gram_staged(const double2* s_x, int nq, int R, double2* out) {
+__device__ __forceinline__ double2 widen(float2 v) { return double2{v.x, v.y}; }
+__device__ __forceinline__ double2 widen(double2 v) { return v; }
+template <class T>
+__device__ void gram_staged(const T* s_x, int nq, int R, double2* out) {
     // wavefront index in a scalar register: uniform tile loops, full exec masks
     // around the matrix-core steps; operands are read at clamped indices and masked
     const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), nw = blockDim.x / 64;
@@ -80,7 +84,7 @@ __device__ void gram_staged(const double2* s_x, int nq, int R, double2* out) {
         f64x4 are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
         for (int q0 = 0; q0 < nq; q0 += 2) {
             const int q = q0 + g / 2, qc = min(q, nq - 1);
-            const double2 xa0 = s_x[qc * R + min(ra, R - 1)], xb0 = s_x[qc * R + min(sb, R - 1)];
+            const double2 xa0 = widen(s_x[qc * R + min(ra, R - 1)]), xb0 = widen(s_x[qc * R + min(sb, R - 1)]);
             const double2 xa = (q < nq && ra < R) ? xa0 : double2{0.0, 0.0};
             const double2 xb = (q < nq && sb < R) ? xb0 : double2{0.0, 0.0};
             are = mfma_16x16x4_f64(p ? xa.y : xa.x, p ? xb.y : xb.x, are);
@@ -98,7 +102,7 @@ __device__ void gram_staged(const double2* s_x, int nq, int R, double2* out) {
 // else the corresponding rows of F_r B; the partial goes to slot b.
 // With check, the frame's status is read after the first round of loads is in
 // flight (the loads stay inside the factor either way).
-__device__ void factor_gram_block(const DevFrame& f, int b, double2* s_x, bool check) {
+__device__ void factor_gram_block(const DevFrame& f, int b, float2* s_x, bool check) {
     const int gA = n_gparts(f.n1), R = f.r;
     const bool isA = b < gA;
     const int n = isA ? f.n1 : f.n2, q0 = (isA ? b : b - gA) * kGRows, nq = min(kGRows, n - q0);
@@ -114,7 +118,7 @@ __device__ void factor_gram_block(const DevFrame& f, int b, double2* s_x, bool c
 #pragma unroll
         for (int u = 0; u < kFL; ++u) {
             const int e = e0 + int(threadIdx.x) + u * kSB;
-            if (e < ne) s_x[e] = double2{v[u].x, v[u].y};
+            if (e < ne) s_x[e] = v[u];
         }
     }
     __syncthreads();
@@ -123,13 +127,16 @@ __device__ void factor_gram_block(const DevFrame& f, int b, double2* s_x, bool c
 
 // Line masks, one launch for all of S1's statistics.  Blocks [0, gAB) are the
 // factor-Gram partials (gAB = n_gparts(n1) + n_gparts(n2)); block gAB + k nJ + c
-// covers sampled rows [kSRows k, kSRows (k+1)) and readout samples
-// [kJCH c, kJCH (c+1)): for c = 0 it validates those rows and writes the Gram of
-// the sampled rows of F_l A to slot gAB + k; every such block writes the
-// right-hand-side partial h_r = sum_q conj(Ahat_{row_q, r}) sum_j y_qj conj(Bhat_jr)
-// (Phi^H y restricted to the block's samples) to hpart[k nJ + c].
-template <class Src>
-__global__ void __launch_bounds__(kSB) k_lstats(Src src) {
+// gAB + k (k < nsg, the launch's chunks of kSRows sampled rows) validates the
+// rows [kSRows k, kSRows (k+1)) of the row list and writes the Gram of those rows
+// of F_l A to slot gAB + k; block gAB + nsg + k nJ + c writes the right-hand-side
+// partial h_r = sum_q conj(Ahat_{row_q, r}) sum_j y_qj conj(Bhat_jr) over the same
+// rows and readout samples [kJCH c, kJCH (c+1)) (Phi^H y restricted to the
+// block's samples) to hpart[k nJ + c].  (A block doing both kept the launch
+// waiting on its Gram.)
+// RT: rank tiles of 16 the readout products are sized for (R <= 16 RT).
+template <int RT, class Src>
+__global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
     extern __shared__ double2 s_dyn[];
     __shared__ int s_err;
     __shared__ int s_row[kSRows];
@@ -138,13 +145,15 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
     const int gAB = n_gparts(n1) + n_gparts(n2);
     if (src.bx() < gAB) {
-        factor_gram_block(f, src.bx(), s_dyn, true);
+        factor_gram_block(f, src.bx(), reinterpret_cast<float2*>(s_dyn), true);
         return;
     }
     const int nJ = n_jparts(n2);
-    const int k = (src.bx() - gAB) / nJ, c = (src.bx() - gAB) % nJ;
+    const bool gram_role = src.bx() < gAB + nsg;    // the Gram of one chunk of sampled rows
+    const int k = gram_role ? src.bx() - gAB : (src.bx() - gAB - nsg) / nJ;
+    const int c = gram_role ? 0 : (src.bx() - gAB - nsg) % nJ;
     const int q0 = k * kSRows;
-    const int j0 = c * kJCH, nj = min(kJCH, n2 - j0);
+    const int j0 = c * kJCH, nj = gram_role ? 0 : min(kJCH, n2 - j0);
     // Loads that need nothing but the descriptor go out before the status check
     // (inside the frame's own buffers): the row count, the block's row indices
     // (and each next one, for the ascending check) and the first round of the
@@ -152,7 +161,7 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     const int cap = frame_rows_cap(f);
     const int nd = f.n_rows_dev ? *f.n_rows_dev : cap;
     const int row_raw = (tid < kSRows && q0 + tid < cap) ? f.rows[q0 + tid] : -1;
-    const int next_raw = (c == 0 && tid < kSRows && q0 + tid + 1 < cap) ? f.rows[q0 + tid + 1] : -1;
+    const int next_raw = (gram_role && tid < kSRows && q0 + tid + 1 < cap) ? f.rows[q0 + tid + 1] : -1;
     // Every staging load reads a valid address (indices clamped into range) and
     // only the LDS store is predicated, so the loads of a round go out back to
     // back; kLU loads per thread per round.
@@ -163,19 +172,19 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
 #pragma unroll
         for (int u = 0; u < kLU; ++u) bv[u] = float2(f.Bhat[size_t(j0) * R + min(e0 + tid + u * kSB, nb - 1)]);
     };
-    load_b(0);
+    if (!gram_role) load_b(0);
     if (tid == 0) s_err = 0;
     if (!block_frame_ok(f.dev, false)) return;      // its barriers also order s_err's reset
     const int n_rows = nd < 0 ? 0 : (nd > cap ? cap : nd);
-    if (k == 0 && c == 0 && tid == 0 && f.n_rows_dev && (nd < 0 || nd > cap)) latch(f.dev, ST_EINVAL);
+    if (k == 0 && gram_role && tid == 0 && f.n_rows_dev && (nd < 0 || nd > cap)) latch(f.dev, ST_EINVAL);
     if (q0 >= n_rows) return;
     const int nq = min(n_rows, q0 + kSRows) - q0;
-    double2* s_x = s_dyn;                     // [kSRows][R]  sampled rows of F_l A
+    float2* s_x = reinterpret_cast<float2*>(s_dyn);   // [kSRows][R]  sampled rows of F_l A (complex64)
     // the readout chunk of F_r B and the samples stay complex64 in LDS (widened
     // when read), which keeps a block at 32 KiB at R = 32
-    float2* s_b = reinterpret_cast<float2*>(s_x + kSRows * R);   // [kJCH][R]
+    float2* s_b = s_x + kSRows * R;                               // [kJCH][R]
     float2* s_y = s_b + kJCH * R;                                 // [kSRows][kJCH]
-    for (int e0 = 0;;) {
+    for (int e0 = 0; e0 < nb;) {
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             const int e = e0 + tid + u * kSB;
@@ -187,11 +196,11 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
     }
     // Then the sampled rows of F_l A and their samples, once the row indices
     // are in LDS.
-    const int nx = nq * R, ny = nq * kJCH;
+    const int nx = nq * R, ny = gram_role ? 0 : nq * kJCH;
     if (tid < nq) {                           // rows inside [0, n1), strictly ascending
         const int q = q0 + tid, row = row_raw;
         bool ok = row >= 0 && row < n1;
-        if (c == 0) {
+        if (gram_role) {
             if (q + 1 < n_rows) ok = ok && next_raw > row;
             if (!ok) atomicCAS(&s_err, 0, ST_EINVAL);
         }
@@ -204,17 +213,20 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
         int xr[kLU], yr[kLU];
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
-            const int ex = min(e0 + tid + u * kSB, nx - 1), ey = min(e0 + tid + u * kSB, ny - 1);
-            const int q = ey / kJCH, jj = min(ey % kJCH, nj - 1);
+            const int ex = min(e0 + tid + u * kSB, nx - 1);
             xr[u] = s_row[ex / R];
-            yr[u] = s_row[q];
             xv[u] = float2(f.Ahat[size_t(max(xr[u], 0)) * R + ex % R]);
-            yv[u] = float2(line_samples(f, q0 + q, max(yr[u], 0))[j0 + jj]);
+            if (!gram_role) {                 // uniform; the Gram role stages no samples (ny = 0)
+                const int ey = min(e0 + tid + u * kSB, ny - 1);
+                const int q = ey / kJCH, jj = min(ey % kJCH, nj - 1);
+                yr[u] = s_row[q];
+                yv[u] = float2(line_samples(f, q0 + q, max(yr[u], 0))[j0 + jj]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             const int e = e0 + tid + u * kSB;
-            if (e < nx) s_x[e] = xr[u] >= 0 ? double2{xv[u].x, xv[u].y} : double2{0.0, 0.0};
+            if (e < nx) s_x[e] = xr[u] >= 0 ? xv[u] : float2{0.f, 0.f};
             if (e < ny) {
                 const bool live = yr[u] >= 0 && e % kJCH < nj;
                 const float2 y = live ? yv[u] : float2{0.f, 0.f};
@@ -224,15 +236,16 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
         }
     }
     __syncthreads();
-    if (c == 0) gram_staged(s_x, nq, R, f.part + size_t(gAB + k) * R * R);
-
+    if (gram_role) {
+        gram_staged(s_x, nq, R, f.part + size_t(gAB + k) * R * R);
+    } else {
     // z[q][r] = sum_j y_qj conj(Bhat_jr) over the chunk on FP64 matrix cores: M = the
     // sampled rows, N = ranks, K = (sample, re/im); Re z = sum yr br + yi bi and
     // Im z = sum yi br - yr bi share the B operand [Re B; Im B].
     const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64), m = lane % 16, g = lane / 16;
     const bool p = g & 1;
     const int TMq = (nq + 15) / 16, TMr = (R + 15) / 16, nzt = TMq * TMr;
-    constexpr int kZT = ((kSRows + 15) / 16 * ((TSL_MAX_R + 15) / 16) + kSB / 64 - 1) / (kSB / 64);
+    constexpr int kZT = ((kSRows + 15) / 16 * RT + kSB / 64 - 1) / (kSB / 64);
     f64x4 zre[kZT], zim[kZT];
 #pragma unroll
     for (int u = 0; u < kZT; ++u) zre[u] = zim[u] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -261,7 +274,7 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int q = 16 * (tile / TMr) + 4 * i + g, r = 16 * (tile % TMr) + m;
-            if (q < nq && r < R) s_p[q * R + r] = dcmulc(double2{zre[u][i], zim[u][i]}, s_x[q * R + r]);
+            if (q < nq && r < R) s_p[q * R + r] = dcmulc(double2{zre[u][i], zim[u][i]}, widen(s_x[q * R + r]));
         }
     }
     __syncthreads();
@@ -270,6 +283,7 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
         for (int q = 0; q < nq; ++q) { h.x += s_p[q * R + tid].x; h.y += s_p[q * R + tid].y; }
         f.hpart[size_t(k * nJ + c) * R + tid] = h;
     }
+    }
     if (!fin) atomicCAS(&s_err, 0, ST_ENONFINITE);
     __syncthreads();
     if (tid == 0 && s_err) latch(f.dev, s_err);
@@ -277,11 +291,14 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src) {
 
 // a factor-Gram block, or a sampled block: rows of F_l A (FP64), then the
 // complex64 chunk of F_r B and samples, later overlaid by the FP64 products
+// (Factor rows and sampled rows are staged as complex64 and widened when read:
+// at R = 32 a block then takes 24 KiB, so six share a compute unit and a full
+// batch of statistics blocks goes out in one round.)
 size_t lstats_lds(int R) {
-    const size_t gram = size_t(kGRows) * R * sizeof(double2);
+    const size_t gram = size_t(kGRows) * R * sizeof(float2);
     const size_t staged = size_t(kJCH * R + kSRows * kJCH) * sizeof(float2);
     const size_t prod = size_t(kSRows) * R * sizeof(double2);
-    const size_t samp = size_t(kSRows) * R * sizeof(double2) + (staged > prod ? staged : prod);
+    const size_t samp = size_t(kSRows) * R * sizeof(float2) + (staged > prod ? staged : prod);
     return gram > samp ? gram : samp;
 }
 
@@ -303,7 +320,7 @@ __global__ void __launch_bounds__(kSB) k_pstats(Src src) {
     const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
     const int gAB = n_gparts(n1) + n_gparts(n2);
     if (src.bx() < gAB) {
-        factor_gram_block(f, src.bx(), s_dyn, false);
+        factor_gram_block(f, src.bx(), reinterpret_cast<float2*>(s_dyn), false);
         return;
     }
     const int k = src.bx() - gAB;
@@ -1153,10 +1170,13 @@ void init_kernel_attributes() {
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pstats<OneFrame>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, ms);
         const int ml = int(lstats_lds(TSL_MAX_R));
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lstats<FrameTable>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, ml);
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lstats<OneFrame>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, ml);
+        for (const void* k : {reinterpret_cast<const void*>(&k_lstats<2, FrameTable>),
+                              reinterpret_cast<const void*>(&k_lstats<2, OneFrame>),
+                              reinterpret_cast<const void*>(&k_lstats<4, FrameTable>),
+                              reinterpret_cast<const void*>(&k_lstats<4, OneFrame>),
+                              reinterpret_cast<const void*>(&k_lstats<8, FrameTable>),
+                              reinterpret_cast<const void*>(&k_lstats<8, OneFrame>)})
+            hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, ml);
         const int mv = int(solve_lds(TSL_MAX_R));
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve<FrameTable>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, mv);
@@ -1168,11 +1188,18 @@ void init_kernel_attributes() {
 hipError_t launch_stats(const Batch& b, hipStream_t st) {
     const int gAB = n_gparts(b.n1) + n_gparts(b.n2);
     if (b.mode == MODE_LINES) {
-        const int gx = gAB + cdiv(b.rows_max > 0 ? b.rows_max : 1, kSRows) * n_jparts(b.n2);
+        const int nsg = cdiv(b.rows_max > 0 ? b.rows_max : 1, kSRows);   // chunks of sampled rows
+        const int gx = gAB + nsg * (1 + n_jparts(b.n2));
         const dim3 grid = frame_grid(b, gx);
         const size_t lds = lstats_lds(b.r_max);
-        if (b.table) k_lstats<FrameTable><<<grid, kSB, lds, st>>>(FrameTable{b.table, gx, b.count});
-        else k_lstats<OneFrame><<<grid, kSB, lds, st>>>(OneFrame{*b.one});
+        auto go = [&](auto rt) {
+            constexpr int RT = decltype(rt)::value;
+            if (b.table) k_lstats<RT, FrameTable><<<grid, kSB, lds, st>>>(FrameTable{b.table, gx, b.count}, nsg);
+            else k_lstats<RT, OneFrame><<<grid, kSB, lds, st>>>(OneFrame{*b.one}, nsg);
+        };
+        if (b.r_max <= 32) go(std::integral_constant<int, 2>{});
+        else if (b.r_max <= 64) go(std::integral_constant<int, 4>{});
+        else go(std::integral_constant<int, 8>{});
     } else {
         const size_t lds = size_t(kPStage) * b.r_max * sizeof(double2);
         const int gx = gAB + n_sparts(b.n1);

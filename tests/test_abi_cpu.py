@@ -68,3 +68,20 @@ def test_pool_accounting_on_host():
     p = tsl.Pool(1 << 20)
     assert p.used() == (0, 1 << 20)
     p.destroy()
+
+
+def test_prepared_batch_argument_errors_on_host():
+    """The prepared-batch calls reject bad arguments before any device call."""
+    from paper_1609_04104_amd import tsl
+    L = tsl.lib()
+    out = ctypes.c_void_p(1)
+    assert L.tsl_batch_create(None, 1, None, 0, ctypes.byref(out)) == tsl.EINVAL
+    assert out.value is None                         # *out is cleared on error
+    assert L.tsl_batch_create(None, 0, None, 0, ctypes.byref(out)) == tsl.EINVAL
+    assert L.tsl_batch_create(None, 1, None, 0, None) == tsl.EINVAL
+    hs = (ctypes.c_void_p * 1)(None)
+    fs = (tsl.Frame * 1)()
+    assert L.tsl_batch_create(hs, 1, fs, 0, ctypes.byref(out)) == tsl.EINVAL     # null sequence
+    assert L.tsl_batch_create(hs, 1, fs, 0x80, ctypes.byref(out)) == tsl.EINVAL  # unknown flag
+    assert L.tsl_batch_launch(None, None) == tsl.EINVAL
+    assert L.tsl_batch_destroy(None) == tsl.OK
