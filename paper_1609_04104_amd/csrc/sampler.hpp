@@ -1,8 +1,8 @@
 // Informative line sampling (Algorithm 4 on rows, with the row score of
-// Sec. VI-C) for one frame, run by one block of at least kSampleThreads threads.
-// Used by the standalone draw kernel and by the extra block per frame of the
-// B-update launch, which runs beside the B update (the draw reads F_l A of
-// the new A only).
+// Sec. VI-C) for one frame, run by one block of NT threads.  Used by the
+// standalone draw kernel and by the first block of each frame of the output
+// launch, which runs beside the output tiles (the draw reads F_l A of the new
+// A only).
 //
 // Row weight w_i = N2 ||abar_i||^2 + R where abar_i is row i of F_l A with
 // every column of nonzero norm normalised (a zero column is left out); K
