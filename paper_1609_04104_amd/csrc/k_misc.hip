@@ -1043,11 +1043,11 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
 }
 
 // ---------------------------------------------------------------- output synthesis
-// X_t = A diag(gamma) B^T on the matrix cores.  A complex product is two real
-// ones with the rank index split into (r, re/im): with P_re = [Re AG, -Im AG],
-// P_im = [Im AG, Re AG] and Q = [Re B; Im B] (AG = A diag(gamma)),
-// Re X = P_re Q^T and Im X = P_im Q^T, so each rank is one K = 2 step of a
-// 32x32x2 FP32 MFMA for each of the two parts.  A block owns a 128 x 64 tile of
+// X_t = A diag(gamma) B^T on the matrix cores in Gauss's three-multiplication
+// form: with AG = A diag(gamma), P1 = sum_r Re AG Re B, P2 = sum_r Im AG Im B and
+// P3 = sum_r (Re AG + Im AG)(Re B + Im B), Re X = P1 - P2 and
+// Im X = P3 - P1 - P2; a 32x32x2 FP32 MFMA step takes two ranks (K over ranks),
+// so a rank pair costs three steps instead of four.  A block owns a 128 x 64 tile of
 // X (eight 32 x 32 wavefront tiles); the rows of AG and of B it needs are
 // staged in LDS with coalesced loads, kOutRC ranks at a time.
 constexpr int kOutTM = 128;                  // block tile rows (i)
@@ -1111,7 +1111,7 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     };
     load_pass(0);
     if (!block_frame_ok(f.dev, true)) return;
-    f32x16 accr = {}, acci = {};
+    f32x16 p1 = {}, p2 = {}, p3 = {};        // sum ar br, sum ai bi, sum (ar + ai)(br + bi)
     for (int r0 = 0; r0 < (ONE ? 1 : R); r0 += kOutRC) {
         const int nr = min(kOutRC, R - r0);
         if (!ONE) {
@@ -1131,11 +1131,16 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
         __syncthreads();
         const float2* pa = s_ag + (wi + m) * kOutPitch;
         const float2* pb = s_b + (wj + m) * kOutPitch;
-        for (int c = 0; c < nr; ++c) {
-            const float2 ag = pa[c], bb = pb[c];
-            const float bv = h ? bb.y : bb.x;
-            accr = mfma_32x32x2(h ? -ag.y : ag.x, bv, accr);
-            acci = mfma_32x32x2(h ? ag.x : ag.y, bv, acci);
+        // two ranks per step (K = 2: lane half h takes rank c0 + h), three real
+        // products per complex one: Re = P1 - P2, Im = P3 - P1 - P2
+        for (int c0 = 0; c0 < nr; c0 += 2) {
+            const int c = min(c0 + h, nr - 1);
+            const bool cv = c0 + h < nr;
+            const float2 ag0 = pa[c], bb0 = pb[c];
+            const float2 ag = cv ? ag0 : float2{0.f, 0.f}, bb = cv ? bb0 : float2{0.f, 0.f};
+            p1 = mfma_32x32x2(ag.x, bb.x, p1);
+            p2 = mfma_32x32x2(ag.y, bb.y, p2);
+            p3 = mfma_32x32x2(ag.x + ag.y, bb.x + bb.y, p3);
         }
     }
     const int i0 = bi + wi, j = bj + wj + m;
@@ -1143,7 +1148,7 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int row = i0 + mfma32_row(v, lane);
-        if (row < n1) f.X_out[size_t(row) * n2 + j] = float2{accr[v], acci[v]};
+        if (row < n1) f.X_out[size_t(row) * n2 + j] = float2{p1[v] - p2[v], p3[v] - p1[v] - p2[v]};
     }
 }
 
