@@ -61,39 +61,40 @@ constexpr int kSB = 256;
 static_assert(kJCH >= kSRows, "the rhs products reuse the readout-chunk staging area");
 
 // Upper entries (r <= s) of sum_q conj(x_qr) x_qs over the nq rows of s_x ([nq][R],
-// complex64 or complex128, widened when read) on FP64 matrix cores (products of
-// FP32 values are exact in FP64).  With the K
-// index over (row, re/im), Re = sum Xr_r Xr_s + Xi_r Xi_s and
-// Im = sum Xr_r Xi_s - Xi_r Xr_s are each one 16x16x4 step per two rows; the
-// wavefronts take the 16 x 16 tiles on and above the diagonal.
+// complex64 or complex128, widened when read) on FP64 matrix cores, three
+// 16x16x4 steps per four rows (below); the wavefronts take the 16 x 16 tiles on
+// and above the diagonal.
 __device__ __forceinline__ double2 widen(float2 v) { return double2{v.x, v.y}; }
 __device__ __forceinline__ double2 widen(double2 v) { return v; }
 template <class T>
 __device__ void gram_staged(const T* s_x, int nq, int R, double2* out) {
     // wavefront index in a scalar register: uniform tile loops, full exec masks
-    // around the matrix-core steps; operands are read at clamped indices and masked
+    // around the matrix-core steps; operands are read at clamped indices and
+    // masked.  Gauss's three-multiplication form over K = four rows per step:
+    // with a = conj(x_r), b = x_s, P1 = sum ar br, P2 = sum ai bi,
+    // P3 = sum (ar + ai)(br + bi), Re = P1 - P2 and Im = P3 - P1 - P2.
     const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), nw = blockDim.x / 64;
     const int m = lane % 16, g = lane / 16;
-    const bool p = g & 1;
     const int TM = (R + 15) / 16, ntiles = TM * (TM + 1) / 2;
     for (int tile = wave; tile < ntiles; tile += nw) {
         int mi = 0, t = tile;
         while (t >= TM - mi) { t -= TM - mi; ++mi; }
         const int ni = mi + t;
         const int ra = 16 * mi + m, sb = 16 * ni + m;
-        f64x4 are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
-        for (int q0 = 0; q0 < nq; q0 += 2) {
-            const int q = q0 + g / 2, qc = min(q, nq - 1);
+        f64x4 p1 = {0.0, 0.0, 0.0, 0.0}, p2 = {0.0, 0.0, 0.0, 0.0}, p3 = {0.0, 0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 < nq; q0 += 4) {
+            const int q = q0 + g, qc = min(q, nq - 1);
             const double2 xa0 = widen(s_x[qc * R + min(ra, R - 1)]), xb0 = widen(s_x[qc * R + min(sb, R - 1)]);
             const double2 xa = (q < nq && ra < R) ? xa0 : double2{0.0, 0.0};
             const double2 xb = (q < nq && sb < R) ? xb0 : double2{0.0, 0.0};
-            are = mfma_16x16x4_f64(p ? xa.y : xa.x, p ? xb.y : xb.x, are);
-            aim = mfma_16x16x4_f64(p ? -xa.y : xa.x, p ? xb.x : xb.y, aim);
+            p1 = mfma_16x16x4_f64(xa.x, xb.x, p1);
+            p2 = mfma_16x16x4_f64(-xa.y, xb.y, p2);
+            p3 = mfma_16x16x4_f64(xa.x - xa.y, xb.x + xb.y, p3);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int rr = 16 * mi + 4 * i + g, ss = 16 * ni + m;
-            if (rr < R && ss < R && rr <= ss) out[size_t(rr) * R + ss] = double2{are[i], aim[i]};
+            if (rr < R && ss < R && rr <= ss) out[size_t(rr) * R + ss] = double2{p1[i] - p2[i], p3[i] - p1[i] - p2[i]};
         }
     }
 }
@@ -239,18 +240,18 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
     if (gram_role) {
         gram_staged(s_x, nq, R, f.part + size_t(gAB + k) * R * R);
     } else {
-    // z[q][r] = sum_j y_qj conj(Bhat_jr) over the chunk on FP64 matrix cores: M = the
-    // sampled rows, N = ranks, K = (sample, re/im); Re z = sum yr br + yi bi and
-    // Im z = sum yi br - yr bi share the B operand [Re B; Im B].
+    // z[q][r] = sum_j y_qj conj(Bhat_jr) over the chunk on FP64 matrix cores
+    // (M = the sampled rows, N = ranks, K = four samples per step) in Gauss's
+    // three-multiplication form: P1 = sum yr br, P2 = sum yi (-bi),
+    // P3 = sum (yr + yi)(br - bi), Re z = P1 - P2, Im z = P3 - P1 - P2.
     const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64), m = lane % 16, g = lane / 16;
-    const bool p = g & 1;
     const int TMq = (nq + 15) / 16, TMr = (R + 15) / 16, nzt = TMq * TMr;
     constexpr int kZT = ((kSRows + 15) / 16 * RT + kSB / 64 - 1) / (kSB / 64);
-    f64x4 zre[kZT], zim[kZT];
+    f64x4 zp1[kZT], zp2[kZT], zp3[kZT];
 #pragma unroll
-    for (int u = 0; u < kZT; ++u) zre[u] = zim[u] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int j0 = 0; j0 < nj; j0 += 2) {
-        const int j = j0 + g / 2;
+    for (int u = 0; u < kZT; ++u) zp1[u] = zp2[u] = zp3[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j0 = 0; j0 < nj; j0 += 4) {
+        const int j = j0 + g;
 #pragma unroll
         for (int u = 0; u < kZT; ++u) {
             const int tile = wave + (kSB / 64) * u;
@@ -260,9 +261,9 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
             const double2 yv0{yf.x, yf.y}, bv0{bf.x, bf.y};
             const double2 yv = (q < nq && j < nj) ? yv0 : double2{0.0, 0.0};
             const double2 bv = (r < R && j < nj) ? bv0 : double2{0.0, 0.0};
-            const double bb = p ? bv.y : bv.x;
-            zre[u] = mfma_16x16x4_f64(p ? yv.y : yv.x, bb, zre[u]);
-            zim[u] = mfma_16x16x4_f64(p ? -yv.x : yv.y, bb, zim[u]);
+            zp1[u] = mfma_16x16x4_f64(yv.x, bv.x, zp1[u]);
+            zp2[u] = mfma_16x16x4_f64(yv.y, -bv.y, zp2[u]);
+            zp3[u] = mfma_16x16x4_f64(yv.x + yv.y, bv.x - bv.y, zp3[u]);
         }
     }
     __syncthreads();                          // s_b and s_y are reused for the products below
@@ -274,7 +275,8 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int q = 16 * (tile / TMr) + 4 * i + g, r = 16 * (tile % TMr) + m;
-            if (q < nq && r < R) s_p[q * R + r] = dcmulc(double2{zre[u][i], zim[u][i]}, widen(s_x[q * R + r]));
+            const double2 z{zp1[u][i] - zp2[u][i], zp3[u][i] - zp1[u][i] - zp2[u][i]};
+            if (q < nq && r < R) s_p[q * R + r] = dcmulc(z, widen(s_x[q * R + r]));
         }
     }
     __syncthreads();
