@@ -74,7 +74,6 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
     float2* s_e = s_a + kKQ * RP;
     const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const int m = lane % 16, g4 = lane / 16;
-    const bool pim = g4 & 1;                         // which part this lane's K entry takes
     const int ncp = n_cparts(n2), bx = src.bx(), qc = bx / ncp, cp = bx % ncp, q0 = qc * kKQ;
     const int c0 = cp * kKCols, c1 = min(n2, c0 + kKCols);   // the block's samples
     // Loads that need nothing but the descriptor go out before the status check
@@ -172,18 +171,27 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
         __syncthreads();
         const int jt0 = j0 + 16 * wave;              // first column of this wavefront's tile
         if (16 * wave < JC && jt0 < c1) {            // uniform
-            // E tile: prediction on the matrix cores, then y - prediction
-            f32x4 er{0.f, 0.f, 0.f, 0.f}, ei{0.f, 0.f, 0.f, 0.f};
+            // E tile: prediction on the matrix cores in Gauss's three-product form
+            // (lane K entry g4 takes rank 4 k + g4: P1 = sum ag.x b.x, P2 = sum
+            // ag.y b.y, P3 = sum (ag.x + ag.y)(b.x + b.y), Re = P1 - P2,
+            // Im = P3 - P1 - P2), then y - prediction
+            f32x4 p1{0.f, 0.f, 0.f, 0.f}, p2{0.f, 0.f, 0.f, 0.f}, p3{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-            for (int k = 0; k < cdiv(R, 2); ++k) {
-                const int c = min(2 * k + g4 / 2, R - 1);
-                const bool cv = 2 * k + g4 / 2 < R;
+            for (int k = 0; k < cdiv(R, 4); ++k) {
+                const int c = min(4 * k + g4, R - 1);
+                const bool cv = 4 * k + g4 < R;
                 const float2 a = s_a[m * RP + c], gm = s_g[c];
                 const float2 ag = cv ? cmul(a, gm) : float2{0.f, 0.f};
                 const float2 b = s_b[(16 * wave + m) * RP + c];
-                const float bq = pim ? b.y : b.x;
-                er = mfma_16x16x4(pim ? -ag.y : ag.x, bq, er);
-                ei = mfma_16x16x4(pim ? ag.x : ag.y, bq, ei);
+                p1 = mfma_16x16x4(ag.x, b.x, p1);
+                p2 = mfma_16x16x4(ag.y, b.y, p2);
+                p3 = mfma_16x16x4(ag.x + ag.y, b.x + b.y, p3);
+            }
+            f32x4 er, ei;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                er[i] = p1[i] - p2[i];
+                ei[i] = p3[i] - p1[i] - p2[i];
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -197,26 +205,60 @@ __global__ void __launch_bounds__(kKT) k_kres(Src src, int nblk) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // M += E conj(Bhat) over the tile's columns; W tile = E^T conj(Ahat_S)
+            // M += E conj(Bhat) over the tile's columns; W tile = E^T conj(Ahat_S);
+            // up to rank 32 both in the three-product form with the conjugate's
+            // sign on the factor (lane K entry g4 takes tile column or sample 4 k + g4)
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 if (16 * t >= R) break;              // uniform
                 const int rc = min(16 * t + m, R - 1);
                 const bool rv = 16 * t + m < R;
-                f32x4 wr{0.f, 0.f, 0.f, 0.f}, wi{0.f, 0.f, 0.f, 0.f};
+                f32x4 wr, wi;
+                if constexpr (RT <= 2) {
+                    f32x4 m1{0.f, 0.f, 0.f, 0.f}, m2{0.f, 0.f, 0.f, 0.f};
+                    f32x4 w1{0.f, 0.f, 0.f, 0.f}, w2{0.f, 0.f, 0.f, 0.f}, w3{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-                for (int k = 0; k < 8; ++k) {
-                    const int kk = 2 * k + g4 / 2;
-                    const float2 em = s_ew[m * kEP + kk];         // E[q = m][j = kk]
-                    const float2 et = s_ew[kk * kEP + m];         // E[q = kk][j = m]
-                    const float2 b = s_b[(16 * wave + kk) * RP + rc];
-                    const float2 a = s_a[kk * RP + rc];
-                    const float bq = rv ? (pim ? b.y : b.x) : 0.f;
-                    const float aq = rv ? (pim ? a.y : a.x) : 0.f;
-                    mr[t] = mfma_16x16x4(pim ? em.y : em.x, bq, mr[t]);    // Re: er br + ei bi
-                    mi[t] = mfma_16x16x4(pim ? -em.x : em.y, bq, mi[t]);   // Im: ei br - er bi
-                    wr = mfma_16x16x4(pim ? et.y : et.x, aq, wr);
-                    wi = mfma_16x16x4(pim ? -et.x : et.y, aq, wi);
+                    for (int k = 0; k < 4; ++k) {
+                        const int kk = 4 * k + g4;
+                        const float2 em = s_ew[m * kEP + kk];         // E[q = m][j = kk]
+                        const float2 et = s_ew[kk * kEP + m];         // E[q = kk][j = m]
+                        const float2 bl = s_b[(16 * wave + kk) * RP + rc];
+                        const float2 al = s_a[kk * RP + rc];
+                        const float2 b = rv ? float2{bl.x, -bl.y} : float2{0.f, 0.f};   // conj(Bhat)
+                        const float2 a = rv ? float2{al.x, -al.y} : float2{0.f, 0.f};   // conj(Ahat)
+                        m1 = mfma_16x16x4(em.x, b.x, m1);
+                        m2 = mfma_16x16x4(em.y, b.y, m2);
+                        mi[t] = mfma_16x16x4(em.x + em.y, b.x + b.y, mi[t]);
+                        w1 = mfma_16x16x4(et.x, a.x, w1);
+                        w2 = mfma_16x16x4(et.y, a.y, w2);
+                        w3 = mfma_16x16x4(et.x + et.y, a.x + a.y, w3);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        mr[t][i] += m1[i] - m2[i];
+                        mi[t][i] -= m1[i] + m2[i];
+                        wr[i] = w1[i] - w2[i];
+                        wi[i] = w3[i] - w1[i] - w2[i];
+                    }
+                } else {
+                    // wider ranks keep the four-product form, which needs fewer
+                    // registers (two blocks per compute unit)
+                    const bool pim = g4 & 1;             // which part this lane's K entry takes
+                    wr = wi = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+                    for (int k = 0; k < 8; ++k) {
+                        const int kk = 2 * k + g4 / 2;
+                        const float2 em = s_ew[m * kEP + kk];     // E[q = m][j = kk]
+                        const float2 et = s_ew[kk * kEP + m];     // E[q = kk][j = m]
+                        const float2 b = s_b[(16 * wave + kk) * RP + rc];
+                        const float2 a = s_a[kk * RP + rc];
+                        const float bq = rv ? (pim ? b.y : b.x) : 0.f;
+                        const float aq = rv ? (pim ? a.y : a.x) : 0.f;
+                        mr[t] = mfma_16x16x4(pim ? em.y : em.x, bq, mr[t]);   // Re: er br + ei bi
+                        mi[t] = mfma_16x16x4(pim ? -em.x : em.y, bq, mi[t]);  // Im: ei br - er bi
+                        wr = mfma_16x16x4(pim ? et.y : et.x, aq, wr);
+                        wi = mfma_16x16x4(pim ? -et.x : et.y, aq, wi);
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
