@@ -105,7 +105,8 @@ typedef struct {
    set is the rows `rows` (see tsl_push_lines).  Zero-initialise the struct
    and fill what is used. */
 typedef struct {
-    int            n_rows;     /* host: number of rows, 0..n1 (ignored if n_rows_dev)   */
+    int            n_rows;     /* host: number of rows, 0..n1; with n_rows_dev, the
+                                  capacity of `rows` (and of y's rows), 0..n1           */
     const int32_t* rows;       /* [n_rows] strictly ascending row indices, or NULL      */
     const uint8_t* mask;       /* [n1][n2] 0/1 point mask, or NULL                      */
     const tsl_c32* y;          /* [n_rows][n2] rows' samples; [n1][n2] if y_full or a
@@ -114,9 +115,10 @@ typedef struct {
     tsl_c32*       A_out;      /* [n1][r] or NULL                                       */
     tsl_c32*       B_out;      /* [n2][r] or NULL                                       */
     tsl_c32*       gamma_out;  /* [r] or NULL                                           */
-    const int32_t* n_rows_dev; /* device word holding the row count (in [0, n1]; checked
-                                  on the device, TSL_EINVAL latches otherwise), so a row
-                                  set drawn on the device needs no host round trip; or
+    const int32_t* n_rows_dev; /* device word holding the row count, so that a row set
+                                  drawn on the device needs no host round trip; it must
+                                  lie in [0, n_rows] (checked on the device: TSL_EINVAL
+                                  latches and the frame is not committed otherwise); or
                                   NULL to use n_rows                                    */
     int            y_full;     /* line masks: y is a whole [n1][n2] frame of which only
                                   the listed rows are read                              */
@@ -174,7 +176,10 @@ int tsl_push_points(tsl_seq* s, const uint8_t* mask, const tsl_c32* y,
    s(i) proportional to N2 ||abar_i||^2 + R with abar the column-normalised
    k-space factor F_l A[t]; K >= 1 draws with replacement from Philox4x64-10 at
    counter (t+1, k, 0, 0) and key (seed, stream_id); every weight and sum in
-   float64 in index order.  rows_out [K] receives the distinct rows ascending,
+   float64 without fused multiply-add, each sum of n terms in a fixed blocked
+   order (sequential inside consecutive blocks of 16 terms, then the block sums
+   in block order; the inclusive prefix is the matching blocked scan), so equal
+   inputs give equal rows on any IEEE machine that keeps that order.  rows_out [K] receives the distinct rows ascending,
    n_out [1] their count (<= K).  Optional (may be NULL): draws_out [K] int32,
    the row of each trial; prefix_out [n1] float64, the inclusive prefix of the
    unnormalised weights. */
@@ -191,7 +196,10 @@ int tsl_push_frame(tsl_seq* s, const tsl_frame* frame, void* stream);
    shape share launches; the launch sequence of a batch composition (which
    sequences, which outputs, which mask kinds, whether rows are drawn) is
    captured once in a HIP graph and replayed while the composition repeats.
-   The sequences must be distinct. */
+   The sequences must be distinct.  Calls may go to different streams: each
+   call's descriptors live in one of three slots that the library reuses only
+   after the call that last used it has finished on the device (the host waits
+   for it), so the host runs at most three calls ahead of the GPU. */
 int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* stream);
 
 /* Profiling form of tsl_step_many: runs the same kernels without a graph,
@@ -247,7 +255,10 @@ int tsl_get_factors(tsl_seq* s, tsl_c32* A, tsl_c32* B, tsl_c32* Ahat, tsl_c32* 
 /* Host-blob checkpoint of the whole state (A, B, alpha_bar, t, options).
    tsl_get_state with blob == NULL stores the size in *nbytes.  Both
    synchronise the sequence's stream.  tsl_set_state needs a blob of the same
-   shape (TSL_EINVAL otherwise) and clears the status. */
+   shape whose lambda and options pass tsl_open's checks and whose alpha_bar
+   and t are finite and >= 0 (TSL_EINVAL otherwise, nothing changed), and
+   clears the status.  If the blob's lambda or options differ from the
+   sequence's, every prepared batch that holds the sequence is invalidated. */
 int tsl_get_state(tsl_seq* s, void* host_blob, size_t* nbytes);
 int tsl_set_state(tsl_seq* s, const void* host_blob, size_t nbytes);
 

@@ -194,23 +194,29 @@ struct Composition {
     }
 };
 
+// One slot of the descriptor ring: pinned host staging, the device table the
+// kernels of a step read, the event recorded after that step's launches, and
+// the graph captured over this slot's table.  A slot is reused only after the
+// host has waited for its event, so neither its staging buffer nor its device
+// table is rewritten while a step that reads them may still run, whatever
+// stream either step was issued on.  The wait also bounds how far the host runs
+// ahead of the GPU (kRing steps); a deeper queue has been seen to stall the
+// host for milliseconds while the runtime drains it.
+struct Slot {
+    tsl::FrameArgs* host = nullptr;       // pinned staging
+    tsl::FrameArgs* table = nullptr;      // device table
+    size_t cap = 0;                       // entries of both
+    hipEvent_t done = nullptr;            // recorded after the last step that used the slot
+    Composition comp;                     // composition of `exec`
+    hipGraphExec_t exec = nullptr;
+};
+
 struct BatchEngine {
     int device = -1;
     hipStream_t cap = nullptr;            // capture stream (never executes work)
-    tsl::FrameArgs* table = nullptr;      // device table
-    size_t table_cap = 0;
-    // Descriptor ring: slot k is reused only after the step that last used it
-    // has finished on the device, which also bounds how far the host runs ahead
-    // of the GPU (kRing steps); a deeper queue has been seen to stall the host
-    // for milliseconds while the runtime drains it.
     static constexpr int kRing = 3;
-    tsl::FrameArgs* staging[kRing] = {};
-    hipEvent_t staged[kRing] = {};
-    int ring_pos = 0, cur_slot = 0;
-    size_t staging_cap = 0;
-    Composition comp;                     // composition of the captured graph
-    bool have_graph = false;
-    hipGraphExec_t exec = nullptr;
+    Slot slot[kRing];
+    int ring_pos = 0;
     Composition last;                     // composition of the previous call
 };
 
@@ -239,41 +245,55 @@ namespace {
 
 std::vector<tsl_batch*> g_live_batches;   // guarded by g_graph_mu
 
-void drop_graph(BatchEngine& be) {
-    if (be.exec) hipGraphExecDestroy(be.exec);
-    be.exec = nullptr;
-    be.have_graph = false;
-    be.comp = Composition{};
+void drop_graph(Slot& sl) {
+    if (sl.exec) hipGraphExecDestroy(sl.exec);
+    sl.exec = nullptr;
+    sl.comp = Composition{};
 }
 
-int ensure_batch_buffers(BatchEngine& be, size_t n) {
+void drop_graphs(BatchEngine& be) {
+    for (Slot& sl : be.slot) drop_graph(sl);
+}
+
+// Takes the next ring slot for a step of n frames: waits (host) for the last
+// step that used it, then grows its buffers if needed.  Returns its index.
+int take_slot(BatchEngine& be, size_t n, int* slot_out) {
     int dev = 0;
     TSL_HIP(hipGetDevice(&dev));
     if (be.device != dev) {
-        drop_graph(be);
-        be.device = dev;
-        if (be.cap) hipStreamDestroy(be.cap);
-        TSL_HIP(hipStreamCreateWithFlags(&be.cap, hipStreamNonBlocking));
-        be.table_cap = 0;
-        be.staging_cap = 0;
-    }
-    if (be.table_cap < n) {
-        drop_graph(be);
-        if (be.table) hipFree(be.table);
-        size_t cap = n < 64 ? 64 : n;
-        TSL_HIP(hipMalloc(&be.table, cap * sizeof(tsl::FrameArgs)));
-        be.table_cap = cap;
-    }
-    if (be.staging_cap < n) {
-        for (int k = 0; k < BatchEngine::kRing; ++k) {
-            if (be.staged[k]) hipEventSynchronize(be.staged[k]);
-            if (be.staging[k]) hipHostFree(be.staging[k]);
-            size_t cap = n < 64 ? 64 : n;
-            TSL_HIP(hipHostMalloc(&be.staging[k], cap * sizeof(tsl::FrameArgs), hipHostMallocDefault));
-            if (!be.staged[k]) TSL_HIP(hipEventCreateWithFlags(&be.staged[k], hipEventDisableTiming));
+        // buffers of another device: wait for their last use, then release them
+        for (Slot& sl : be.slot) {
+            if (sl.done) hipEventSynchronize(sl.done);
+            drop_graph(sl);
+            if (sl.table) hipFree(sl.table);
+            if (sl.host) hipHostFree(sl.host);
+            if (sl.done) hipEventDestroy(sl.done);
+            sl = Slot{};
         }
-        be.staging_cap = n < 64 ? 64 : n;
+        if (be.cap) hipStreamDestroy(be.cap);
+        be.cap = nullptr;
+        be.device = dev;
+        be.last = Composition{};
+        TSL_HIP(hipStreamCreateWithFlags(&be.cap, hipStreamNonBlocking));
     }
+    const int k = be.ring_pos;
+    Slot& sl = be.slot[k];
+    if (!sl.done) TSL_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    TSL_HIP(hipEventSynchronize(sl.done));
+    if (sl.cap < n) {
+        drop_graph(sl);
+        if (sl.table) hipFree(sl.table);
+        if (sl.host) hipHostFree(sl.host);
+        sl.table = nullptr;
+        sl.host = nullptr;
+        sl.cap = 0;
+        const size_t cap = n < 64 ? 64 : n;
+        TSL_HIP(hipMalloc(&sl.table, cap * sizeof(tsl::FrameArgs)));
+        TSL_HIP(hipHostMalloc(&sl.host, cap * sizeof(tsl::FrameArgs), hipHostMallocDefault));
+        sl.cap = cap;
+    }
+    be.ring_pos = (k + 1) % BatchEngine::kRing;
+    *slot_out = k;
     return TSL_OK;
 }
 
@@ -292,7 +312,16 @@ std::vector<tsl::Batch> group_batches(const Composition& c, const tsl::FrameArgs
     return out;
 }
 
-// Validates a batch and groups it by (n1, n2, mask kind), call order kept inside a group.
+// The kernels are instantiated for rank tiers (a register-resident solve up to
+// 8, 16 and 32, wider accumulators up to 64 and 128); a launch group takes the
+// tier of its largest rank, so frames are grouped by tier as well as by shape
+// and a rank-16 frame never runs the kernels sized for rank 64.
+int rank_tier(int r) {
+    return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : r <= 64 ? 64 : TSL_MAX_R;
+}
+
+// Validates a batch and groups it by (n1, n2, mask kind and route, rank tier),
+// call order kept inside a group.
 int compose(tsl_seq* const* seqs, int n, const tsl_frame* frames, Composition& c) {
     c.seqs.resize(n);
     c.wants.resize(n);
@@ -305,16 +334,17 @@ int compose(tsl_seq* const* seqs, int n, const tsl_frame* frames, Composition& c
         int rc = check_frame(s, frames[i]);
         if (rc != TSL_OK) return rc;
         c.seqs[i] = s;
-        c.wants[i] = (frames[i].X_out ? 1 : 0) | (frames[i].mask ? 16 : 0) | (frames[i].K_next > 0 ? 32 : 0);
+        c.wants[i] = (frames[i].X_out ? 1 : 0) | (frames[i].mask ? 16 : 0) | (frames[i].K_next > 0 ? 32 : 0) |
+                     (!frames[i].mask && s->opts.line_route == TSL_ROUTE_FRAME ? 64 : 0);
         c.caps[i] = frames[i].mask ? s->n1 : std::min(std::max(frames[i].n_rows, 0), s->n1);
     }
     // kind: 0 line mask, k-space route; 1 point mask; 2 line mask, frame route
     auto kind = [&](int i) {
         if (c.wants[i] & 16) return 1;
-        return seqs[i]->opts.line_route == TSL_ROUTE_KSPACE ? 0 : 2;
+        return (c.wants[i] & 64) ? 2 : 0;
     };
-    std::map<std::tuple<int, int, int>, std::vector<int>> by;
-    for (int i = 0; i < n; ++i) by[{seqs[i]->n1, seqs[i]->n2, kind(i)}].push_back(i);
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
+    for (int i = 0; i < n; ++i) by[{seqs[i]->n1, seqs[i]->n2, kind(i), rank_tier(seqs[i]->r)}].push_back(i);
     for (auto& kv : by) {
         GroupKey k{};
         k.n1 = std::get<0>(kv.first); k.n2 = std::get<1>(kv.first);
@@ -334,22 +364,17 @@ int compose(tsl_seq* const* seqs, int n, const tsl_frame* frames, Composition& c
     return TSL_OK;
 }
 
-// Writes the descriptors of a composed batch into the pinned ring and copies
-// them to the device table on `st`.
-int stage_table(BatchEngine& be, const Composition& c, tsl_seq* const* seqs, const tsl_frame* frames,
-                hipStream_t st) {
-    const int n = int(c.order.size());
-    const int slot = be.ring_pos;
-    be.ring_pos = (be.ring_pos + 1) % BatchEngine::kRing;
-    TSL_HIP(hipEventSynchronize(be.staged[slot]));
-    tsl::FrameArgs* host = be.staging[slot];
-    for (int p = 0; p < n; ++p) {
+// Writes the descriptors of a composed batch into the slot's pinned staging
+// buffer and copies them to the slot's device table on `st`.
+int stage_table(Slot& sl, const Composition& c, tsl_seq* const* seqs, const tsl_frame* frames, hipStream_t st) {
+    const size_t n = c.order.size();
+    if (n > sl.cap) return fail(TSL_EINVAL, "internal: descriptor slot too small");
+    for (size_t p = 0; p < n; ++p) {
         const int i = c.order[p];
         seqs[i]->last = st;
-        host[p] = frame_args(seqs[i], frames[i]);
+        sl.host[p] = frame_args(seqs[i], frames[i]);
     }
-    TSL_HIP(hipMemcpyAsync(be.table, host, size_t(n) * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice, st));
-    be.cur_slot = slot;
+    TSL_HIP(hipMemcpyAsync(sl.table, sl.host, n * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice, st));
     return TSL_OK;
 }
 
@@ -386,6 +411,18 @@ int tsl_footprint(int n1, int n2, int r, size_t* bytes) {
 
 const char* tsl_last_error(void) { return g_err.c_str(); }
 
+// The checks tsl_open applies to lambda and the options (also applied to a
+// checkpoint's values by tsl_set_state).
+static int validate_params(double lambda, const tsl_opts& o) {
+    if (!std::isfinite(lambda) || lambda < 0.0) return fail(TSL_EINVAL, "lambda must be finite and >= 0");
+    if (lambda == 0.0 && !o.allow_lambda0) return fail(TSL_EINVAL, "lambda == 0 needs allow_lambda0");
+    if (o.step_mode != TSL_STEP_MM && o.step_mode != TSL_STEP_CONST) return fail(TSL_EINVAL, "bad step_mode");
+    if (o.line_route != TSL_ROUTE_KSPACE && o.line_route != TSL_ROUTE_FRAME) return fail(TSL_EINVAL, "bad line_route");
+    if (o.step_mode == TSL_STEP_CONST && !(o.mu > 0.0 && std::isfinite(o.mu)))
+        return fail(TSL_EINVAL, "constant step needs a finite mu > 0");
+    return TSL_OK;
+}
+
 static int open_impl(tsl_pool* pool, tsl_seq** out, int n1, int n2, int r, double lambda, const tsl_opts* opts,
                      const tsl_c32* A0, const tsl_c32* B0, void* stream) {
     if (!out) return fail(TSL_EINVAL, "null output handle");
@@ -395,12 +432,7 @@ static int open_impl(tsl_pool* pool, tsl_seq** out, int n1, int n2, int r, doubl
     tsl_opts o;
     tsl_opts_default(&o);
     if (opts) o = *opts;
-    if (!std::isfinite(lambda) || lambda < 0.0) return fail(TSL_EINVAL, "lambda must be finite and >= 0");
-    if (lambda == 0.0 && !o.allow_lambda0) return fail(TSL_EINVAL, "lambda == 0 needs allow_lambda0");
-    if (o.step_mode != TSL_STEP_MM && o.step_mode != TSL_STEP_CONST) return fail(TSL_EINVAL, "bad step_mode");
-    if (o.line_route != TSL_ROUTE_KSPACE && o.line_route != TSL_ROUTE_FRAME) return fail(TSL_EINVAL, "bad line_route");
-    if (o.step_mode == TSL_STEP_CONST && !(o.mu > 0.0 && std::isfinite(o.mu)))
-        return fail(TSL_EINVAL, "constant step needs a finite mu > 0");
+    if ((rc = validate_params(lambda, o)) != TSL_OK) return rc;
     if (!A0 || !B0) return fail(TSL_EINVAL, "null A0 or B0");
     Layout L = layout_for(n1, n2, r);
     tsl::init_kernel_attributes();
@@ -464,8 +496,11 @@ int tsl_close(tsl_seq* s) {
     if (!s) return TSL_OK;
     {
         std::lock_guard<std::mutex> lk(g_graph_mu);
-        for (const tsl_seq* q : g_batch.comp.seqs)
-            if (q == s) { drop_graph(g_batch); break; }
+        for (Slot& sl : g_batch.slot)
+            for (const tsl_seq* q : sl.comp.seqs)
+                if (q == s) { drop_graph(sl); break; }
+        for (const tsl_seq* q : g_batch.last.seqs)
+            if (q == s) { g_batch.last = Composition{}; break; }
         for (tsl_batch* b : g_live_batches)
             for (const tsl_seq* q : b->seqs)
                 if (q == s) b->dead = true;
@@ -534,7 +569,7 @@ int tsl_sample_lines(tsl_seq* s, int K, int32_t* rows_out, int32_t* n_out, int32
     tsl::Batch b{};
     b.one = &a;
     b.count = 1;
-    b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r;
+    b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r; b.mode = a.mode; b.kspace = a.kspace != 0;
     b.want_sample = true;
     hipError_t e = tsl::launch_sample(b, st);
     if (e != hipSuccess) return hip_fail(e, "sample");
@@ -550,41 +585,45 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
     if (rc != TSL_OK) return rc;
     std::lock_guard<std::mutex> lk(g_graph_mu);
     BatchEngine& be = g_batch;
-    if ((rc = ensure_batch_buffers(be, size_t(n))) != TSL_OK) return rc;
-    if ((rc = stage_table(be, c, seqs, frames, st)) != TSL_OK) return rc;
-    const bool cached = be.have_graph && be.comp == c;
-    if (!cached && !(be.last == c)) {
+    int k = 0;
+    if ((rc = take_slot(be, size_t(n), &k)) != TSL_OK) return rc;
+    Slot& sl = be.slot[k];
+    if ((rc = stage_table(sl, c, seqs, frames, st)) != TSL_OK) return rc;
+    const bool cached = sl.exec && sl.comp == c;
+    const bool repeat = be.last == c;
+    be.last = c;
+    if (!cached && !repeat) {
         // A composition seen for the first time runs as plain launches; one that
-        // repeats (the steady state of a fixed batch) is captured and replayed.
-        be.last = c;
-        rc = run_groups(group_batches(c, be.table), st);
+        // repeats (the steady state of a fixed batch) is captured over this
+        // slot's table and replayed whenever the slot comes round again.
+        rc = run_groups(group_batches(c, sl.table), st);
+        hipError_t er = hipEventRecord(sl.done, st);
         if (rc != TSL_OK) return rc;
-        TSL_HIP(hipEventRecord(be.staged[be.cur_slot], st));
+        if (er != hipSuccess) return hip_fail(er, "hipEventRecord");
         return TSL_OK;
     }
-    be.last = c;
     if (!cached) {
-        drop_graph(be);
+        drop_graph(sl);
         hipGraph_t graph = nullptr;
-        TSL_HIP(hipStreamBeginCapture(be.cap, hipStreamCaptureModeThreadLocal));
-        int lrc = run_groups(group_batches(c, be.table), be.cap);
-        hipError_t ec = hipStreamEndCapture(be.cap, &graph);
-        if (lrc != TSL_OK) {
-            if (graph) hipGraphDestroy(graph);
-            return lrc;
+        hipError_t eb = hipStreamBeginCapture(be.cap, hipStreamCaptureModeThreadLocal);
+        int lrc = eb == hipSuccess ? run_groups(group_batches(c, sl.table), be.cap) : TSL_OK;
+        hipError_t ec = eb == hipSuccess ? hipStreamEndCapture(be.cap, &graph) : eb;
+        hipError_t ei = hipSuccess;
+        if (lrc == TSL_OK && ec == hipSuccess) ei = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
+        if (graph) hipGraphDestroy(graph);
+        if (lrc != TSL_OK || ec != hipSuccess || ei != hipSuccess) {
+            sl.exec = nullptr;
+            // the staged table is in flight on `st`: keep the slot's wait honest
+            hipEventRecord(sl.done, st);
+            if (lrc != TSL_OK) return lrc;
+            return hip_fail(ec != hipSuccess ? ec : ei, ec != hipSuccess ? "stream capture" : "hipGraphInstantiate");
         }
-        if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
-        hipError_t ei = hipGraphInstantiate(&be.exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
-        if (ei != hipSuccess) {
-            be.exec = nullptr;
-            return hip_fail(ei, "hipGraphInstantiate");
-        }
-        be.comp = c;
-        be.have_graph = true;
+        sl.comp = c;
     }
-    TSL_HIP(hipGraphLaunch(be.exec, st));
-    TSL_HIP(hipEventRecord(be.staged[be.cur_slot], st));
+    hipError_t el = hipGraphLaunch(sl.exec, st);
+    hipError_t er = hipEventRecord(sl.done, st);
+    if (el != hipSuccess) return hip_fail(el, "hipGraphLaunch");
+    if (er != hipSuccess) return hip_fail(er, "hipEventRecord");
     return TSL_OK;
 }
 
@@ -597,12 +636,22 @@ int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, do
     if (rc != TSL_OK) return rc;
     std::lock_guard<std::mutex> lk(g_graph_mu);
     BatchEngine& be = g_batch;
-    if ((rc = ensure_batch_buffers(be, size_t(n))) != TSL_OK) return rc;
-    if ((rc = stage_table(be, c, seqs, frames, st)) != TSL_OK) return rc;
+    int k = 0;
+    if ((rc = take_slot(be, size_t(n), &k)) != TSL_OK) return rc;
+    Slot& sl = be.slot[k];
+    if ((rc = stage_table(sl, c, seqs, frames, st)) != TSL_OK) return rc;
     hipEvent_t ev[TSL_N_PHASES + 1] = {};
-    for (auto& e : ev) TSL_HIP(hipEventCreate(&e));
-    rc = run_groups(group_batches(c, be.table), st, ev);
-    if (rc == TSL_OK) rc = hipEventRecord(be.staged[be.cur_slot], st) == hipSuccess ? TSL_OK : TSL_EDEVICE;
+    for (auto& e : ev) {
+        hipError_t ee = hipEventCreate(&e);
+        if (ee != hipSuccess) {
+            for (auto& x : ev) if (x) hipEventDestroy(x);
+            hipEventRecord(sl.done, st);
+            return hip_fail(ee, "hipEventCreate");
+        }
+    }
+    rc = run_groups(group_batches(c, sl.table), st, ev);
+    hipError_t er = hipEventRecord(sl.done, st);
+    if (rc == TSL_OK && er != hipSuccess) rc = hip_fail(er, "hipEventRecord");
     if (rc == TSL_OK) {
         hipError_t e = hipEventSynchronize(ev[TSL_N_PHASES]);
         for (int p = 0; p < TSL_N_PHASES && e == hipSuccess; ++p) {
@@ -771,6 +820,8 @@ int tsl_set_state(tsl_seq* s, const void* host_blob, size_t nbytes) {
     if (std::memcmp(h.magic, "TSLSTAT", 8) != 0 || h.version != 2 || h.n1 != s->n1 || h.n2 != s->n2 ||
         h.r != s->r || nbytes < sizeof(BlobHeader) + 2 * a + 2 * b)
         return fail(TSL_EINVAL, "blob does not match this sequence");
+    if ((rc = validate_params(h.lambda, h.opts)) != TSL_OK) return rc;
+    if (!std::isfinite(h.abar) || h.abar < 0.0 || h.t < 0) return fail(TSL_EINVAL, "blob holds an invalid alpha_bar or t");
     if ((rc = set_dev(s)) != TSL_OK) return rc;
     TSL_HIP(hipStreamSynchronize(s->last));
     const char* p = static_cast<const char*>(host_blob) + sizeof(h);
@@ -782,8 +833,17 @@ int tsl_set_state(tsl_seq* s, const void* host_blob, size_t nbytes) {
     d.abar = h.abar;
     d.t = h.t;
     TSL_HIP(hipMemcpy(s->at<void>(s->lay.dev), &d, sizeof(d), hipMemcpyHostToDevice));
+    const bool changed = h.lambda != s->lambda || std::memcmp(&h.opts, &s->opts, sizeof(tsl_opts)) != 0;
     s->lambda = h.lambda;
     s->opts = h.opts;
+    if (changed) {
+        // a prepared batch holds descriptors (lambda, step, route, sampler key)
+        // taken at its creation: one that holds this sequence is no longer valid
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (tsl_batch* bt : g_live_batches)
+            for (const tsl_seq* q : bt->seqs)
+                if (q == s) bt->dead = true;
+    }
     return TSL_OK;
 }
 

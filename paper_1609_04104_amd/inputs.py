@@ -206,8 +206,11 @@ class PointFrame:
         self.mask, self.y, self.truth = mask, y, truth
 
 
-def config1(T=20, n=64, r=8, count=1024, sigma=0.01, exact=False):
-    """Low-rank truth, uniformly random points (25 % of 64 x 64), noise sigma."""
+def config1(T=20, n=64, r=8, count=1024, sigma=0.01, exact=False, perturb=0.0):
+    """Low-rank truth, uniformly random points (25 % of 64 x 64), noise sigma.
+
+    exact=True: every point sampled, no noise, and the start factors are the
+    true ones, plus i.i.d. CN(0, perturb^2) noise when perturb > 0."""
     rng_truth, rng_mask, rng_noise, rng_init = (rng_for(1, 0, s) for s in range(4))
     A, B, G = lowrank_truth(n, n, r, T, rng_truth)
     frames = []
@@ -222,7 +225,12 @@ def config1(T=20, n=64, r=8, count=1024, sigma=0.01, exact=False):
             y = np.where(mask, K + cn(rng_noise, (n, n), sigma * sigma), 0.0)
         frames.append(PointFrame(mask, y.astype(np.complex64), truth=X))
     if exact:
-        A0, B0 = A.astype(np.complex64), B.astype(np.complex64)
+        A0, B0 = A, B
+        if perturb > 0:
+            rng_p = rng_for(1, 0, 4)
+            A0 = A + cn(rng_p, A.shape, perturb * perturb)
+            B0 = B + cn(rng_p, B.shape, perturb * perturb)
+        A0, B0 = A0.astype(np.complex64), B0.astype(np.complex64)
     else:
         A0, B0 = init_factors(n, n, r, rng_init)
     return dict(n1=n, n2=n, r=r, frames=frames, A0=A0, B0=B0, truth=(A, B, G))

@@ -30,12 +30,17 @@ class Scan:
     frames on the device (frame t acquires rows of bank[t % len(bank)]), the
     number of frames, arrival time (s) and frame rate (frames/s)."""
 
-    def __init__(self, sid, n, r, lam, A0, B0, bank, T, arrival, fps, t_warm=5, K=None, seed=1609):
+    def __init__(self, sid, n, r, lam, A0, B0, bank, T, arrival, fps, t_warm=5, K=None, seed=1609,
+                 record=False):
         self.sid, self.n, self.r, self.lam = sid, n, r, lam
         self.A0, self.B0, self.bank = A0, B0, bank
         self.T, self.arrival, self.fps, self.t_warm = T, arrival, fps, t_warm
         self.K = K if K else max(1, n // 8)
         self.seed = seed
+        # record=True keeps every frame's output and every drawn row set on the
+        # device (X_hist [T][n][n], rows_hist [T+1][K], cnt_hist [T+1]) instead of
+        # reusing one output and two row buffers
+        self.record = record
         self.seq = None
         self.t = 0            # frames launched
         self.done = 0         # frames completed
@@ -53,9 +58,20 @@ class Scan:
         self.cnt = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in range(2)]
         self.full = torch.arange(self.n, dtype=torch.int32, device=dev)
         self.X = torch.empty(self.n, self.n, dtype=torch.complex64, device=dev)
+        if self.record:
+            self.X_hist = torch.empty(self.T, self.n, self.n, dtype=torch.complex64, device=dev)
+            self.rows_hist = torch.zeros(self.T + 1, self.K, dtype=torch.int32, device=dev)
+            self.cnt_hist = torch.zeros(self.T + 1, 1, dtype=torch.int32, device=dev)
 
     def next_frame(self):
         t = self.t
+        if self.record:
+            y = self.bank[t % self.bank.shape[0]]
+            nxt = dict(K_next=self.K, rows_next=self.rows_hist[t + 1], n_next=self.cnt_hist[t + 1])
+            if t < self.t_warm:
+                return self.seq.frame(rows=self.full, y=y, y_full=True, X_out=self.X_hist[t], **nxt)
+            return self.seq.frame(rows=self.rows_hist[t], n_rows_dev=self.cnt_hist[t], y=y, y_full=True,
+                                  X_out=self.X_hist[t], **nxt)
         key = (t % self.bank.shape[0], t % 2, t < self.t_warm)
         f = self._frames.get(key)
         if f is None:

@@ -220,6 +220,87 @@ def test_step_alpha_bounds_the_block_hessian(seed):
     assert top <= alpha * (1 + 1e-12)
 
 
+def _orthogonal_columns(rng, n, norms):
+    """n x R matrix whose columns are orthogonal with the given Euclidean norms."""
+    Q, _ = np.linalg.qr(_cn(rng, (n, len(norms))))
+    return Q * np.asarray(norms, float)[None, :]
+
+
+def _alpha_pin_case(seed, step_alpha):
+    """Factors with orthogonal columns, every entry sampled, t = 3.
+
+    There A^H A and B^H B are diagonal, so the Gershgorin bound of eq. (8)'s
+    block Hessians is exact and alpha_t must equal the largest eigenvalue of the
+    two factor-block Hessians of f_t (eq. 5), found here by brute force from the
+    explicit linear map factor -> sampled F(A diag(gamma) B^T).  Returns
+    (alpha from `step_alpha`, brute-force top eigenvalue, closed form)."""
+    rng = _rng(40 + seed)
+    n1, n2, R = 7, 6, 3
+    A = _orthogonal_columns(rng, n1, [1.7, 0.6, 1.1])
+    B = _orthogonal_columns(rng, n2, [0.5, 1.3, 0.9])
+    gamma = _cn(rng, R)
+    lam, t = 0.9, 3
+    Fl, Fr = oracle.dft_matrix(n1), oracle.dft_matrix(n2)
+    oi, oj = np.nonzero(np.ones((n1, n2), bool))
+    top = 0.0
+    for wrt in ("A", "B"):
+        Lop = _block_operator(A, B, gamma, oi, oj, Fl, Fr, wrt)
+        H = Lop.conj().T @ Lop + (lam / t) * np.eye(Lop.shape[1])
+        top = max(top, float(np.linalg.eigvalsh(H).max()))
+    g2 = np.abs(gamma) ** 2
+    closed = lam / t + float(np.max(g2 * np.maximum(np.sum(np.abs(A) ** 2, 0), np.sum(np.abs(B) ** 2, 0))))
+    return step_alpha(A, B, gamma, lam, t), top, closed
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_step_alpha_equals_block_hessian_top_eigenvalue_when_gershgorin_is_exact(seed):
+    alpha, top, closed = _alpha_pin_case(seed, oracle.step_alpha)
+    assert abs(top - closed) <= 1e-12 * closed          # the brute force agrees with the closed form
+    assert abs(alpha - top) <= 1e-12 * top               # eq. (6)/(8) reading, fixed from above and below
+
+
+def test_step_alpha_pin_rejects_planted_mistakes():
+    """Plausible slips in the step size (planted in a copy of the oracle's
+    function, on the CPU) each move alpha off the top eigenvalue."""
+    def scaled(A, B, g, lam, t):
+        return 1.01 * oracle.step_alpha(A, B, g, lam, t)
+
+    def lam_not_over_t(A, B, g, lam, t):
+        return oracle.step_alpha(A, B, g, lam, 1)
+
+    def sum_not_max(A, B, g, lam, t):
+        Gc = np.diag(g)
+        MB = Gc.conj().T @ (B.conj().T @ B) @ Gc
+        MA = Gc.conj().T @ (A.conj().T @ A) @ Gc
+        return lam / t + oracle.gershgorin(MB) + oracle.gershgorin(MA)
+
+    for bad in (scaled, lam_not_over_t, sum_not_max):
+        alpha, top, _ = _alpha_pin_case(0, bad)
+        assert abs(alpha - top) > 1e-6 * top, bad.__name__
+
+
+def test_step_alpha_through_the_push_at_t3():
+    """The alpha a push reports is the same exact value (the push's own gamma)."""
+    rng = _rng(47)
+    n1, n2, R = 7, 6, 3
+    A = _orthogonal_columns(rng, n1, [1.7, 0.6, 1.1])
+    B = _orthogonal_columns(rng, n2, [0.5, 1.3, 0.9])
+    lam = 0.9
+    o = oracle.TslOracle(n1, n2, R, lam, A, B)
+    o.t, o.abar = 2, 5.0                                  # the state after two frames
+    s = o.push_points(np.ones((n1, n2), bool), _cn(rng, (n1, n2)))
+    assert s.t == 3
+    Fl, Fr = o.Fl, o.Fr
+    oi, oj = np.nonzero(np.ones((n1, n2), bool))
+    top = 0.0
+    for wrt in ("A", "B"):
+        Lop = _block_operator(A, B, s.gamma, oi, oj, Fl, Fr, wrt)
+        top = max(top, float(np.linalg.eigvalsh(Lop.conj().T @ Lop).max()) + lam / 3)
+    assert abs(s.alpha - top) <= 1e-12 * top
+    assert abs(s.alpha_bar - (5.0 + top)) <= 1e-12 * (5.0 + top)
+    assert abs(s.mu - 1.0 / (5.0 + top)) <= 1e-12 / (5.0 + top)
+
+
 def test_mm_majorized_cost_never_increases():
     c = I.config1(T=8)
     o = oracle.TslOracle(c["n1"], c["n2"], c["r"], 0.1, c["A0"], c["B0"])
@@ -265,6 +346,29 @@ def test_exact_recovery_noiseless_full_sampling_lambda0():
         assert np.max(np.abs(s.e)) < 1e-10
         assert _nr(s.A, A) < 1e-12 and _nr(s.B, B) < 1e-12
         assert _nr(s.X, fr.truth) < 1e-11
+
+
+def test_recovery_from_perturbed_factors_noiseless_full_sampling():
+    """Started off the truth (true factors plus CN(0, 1e-4) noise), lambda = 0,
+    every point sampled, one noiseless frame pushed repeatedly: the S2 update
+    must move the factors towards the data.  The fit residual ||y - Phi gamma||
+    after each frame's ridge solve never increases and falls at least fourfold
+    over 30 frames, and the output frame approaches the truth."""
+    c = I.config1(T=1, exact=True, perturb=1e-2)
+    o = oracle.TslOracle(c["n1"], c["n2"], c["r"], 0.0, c["A0"], c["B0"])
+    truth = c["frames"][0].truth
+    Y = np.fft.fft2(truth, norm="ortho")
+    full = np.ones((c["n1"], c["n2"]), bool)
+    res, err = [], []
+    for _ in range(30):
+        s = o.push_points(full, Y)
+        res.append(float(np.linalg.norm(s.e)))
+        err.append(_nr(s.X, truth))
+    res = np.array(res)
+    assert res[0] > 1e-3                                 # the start is really off the truth
+    assert np.all(np.diff(res) <= 1e-12 * res[0])
+    assert res[-1] < 0.25 * res[0]
+    assert err[-1] < 0.5 * err[0]
 
 
 def test_exact_data_with_lambda_gives_shrunk_closed_form():
