@@ -202,6 +202,23 @@ int tsl_push_frame(tsl_seq* s, const tsl_frame* frame, void* stream);
    for it), so the host runs at most three calls ahead of the GPU. */
 int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* stream);
 
+/* Allocation-free form of tsl_step_many, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops, harnesses
+   that forbid hipMalloc): same arguments, same kernels and results as
+   tsl_step_many.  It calls no hipMalloc, hipFree, hipHostMalloc or graph
+   instantiation: the frame descriptors go into one fixed device array of
+   TSL_STATIC_MAX_FRAMES entries compiled into the library (each GPU it runs on
+   holds its own copy, about 72 KiB, until the process ends), written by small
+   kernels on `stream`, and the phases are launched directly on `stream`.
+   n > TSL_STATIC_MAX_FRAMES returns TSL_EINVAL before anything is enqueued;
+   every sequence must be on the current device.  All calls on one GPU share
+   that array and each overwrites it: calls that can overlap on one GPU (on
+   different streams with nothing ordering them) race and must not be made;
+   calls on one stream are ordered.  The first call on a device looks up the
+   array's device address (make it outside a stream capture). */
+#define TSL_STATIC_MAX_FRAMES 256
+int tsl_step_many_noalloc(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* stream);
+
 /* Profiling form of tsl_step_many: runs the same kernels without a graph,
    brackets each of the TSL_N_PHASES phases (partial Grams; solve and step
    size; synthesis + row transform; column transform + residual + column

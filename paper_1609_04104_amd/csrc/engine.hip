@@ -12,10 +12,10 @@
 #include <tuple>
 #include <vector>
 
-#include "kernels.hpp"
-#include "tsl.h"
+#include "engine.hpp"
 
-namespace {
+namespace tsl {
+namespace eng {
 
 thread_local std::string g_err;
 
@@ -29,17 +29,9 @@ int hip_fail(hipError_t e, const char* what) {
     return TSL_EDEVICE;
 }
 
-#define TSL_HIP(call)                                       \
-    do {                                                    \
-        hipError_t e_ = (call);                             \
-        if (e_ != hipSuccess) return hip_fail(e_, #call);   \
-    } while (0)
-
+namespace {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-struct Layout {
-    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, wpart, mpart, part, hpart, total;
-};
+}  // namespace
 
 Layout layout_for(int n1, int n2, int r) {
     Layout L{};
@@ -62,29 +54,6 @@ Layout layout_for(int n1, int n2, int r) {
     L.total = o;
     return L;
 }
-
-std::mutex g_graph_mu;
-
-}  // namespace
-
-struct tsl_pool {
-    std::mutex mu;
-    size_t budget = 0, used = 0;
-};
-
-struct tsl_seq {
-    int n1 = 0, n2 = 0, r = 0, device = 0;
-    double lambda = 0;
-    tsl_opts opts{};
-    char* arena = nullptr;
-    size_t bytes = 0;
-    Layout lay{};
-    hipStream_t last = nullptr;
-    tsl_pool* pool = nullptr;
-    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(arena + off); }
-};
-
-namespace {
 
 // -------------------------------------------------------------- frame descriptors
 tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
@@ -113,6 +82,7 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     return a;
 }
 
+namespace {
 hipError_t launch_updates(const tsl::Batch& b, hipStream_t st) {
     hipError_t e = tsl::launch_update_a(b, st);
     return e != hipSuccess ? e : tsl::launch_update_b(b, st);
@@ -137,13 +107,13 @@ const Phase kPhases[TSL_N_PHASES] = {
     {tsl::launch_synth_out, "output synthesis + row draw"},  // a10; a11 in one more block per frame
 };
 
-// Launches every phase for every group, phase by phase; with `ev` non-null,
-// records ev[p] before phase p and ev[TSL_N_PHASES] after the last.
-int run_groups(const std::vector<tsl::Batch>& groups, hipStream_t st, hipEvent_t* ev = nullptr) {
+}  // namespace
+
+int run_groups(const tsl::Batch* groups, int n_groups, hipStream_t st, hipEvent_t* ev) {
     for (int p = 0; p < TSL_N_PHASES; ++p) {
         if (ev) TSL_HIP(hipEventRecord(ev[p], st));
-        for (const tsl::Batch& b : groups) {
-            hipError_t e = kPhases[p].fn(b, st);
+        for (int g = 0; g < n_groups; ++g) {
+            hipError_t e = kPhases[p].fn(groups[g], st);
             if (e != hipSuccess) return hip_fail(e, kPhases[p].name);
         }
     }
@@ -164,6 +134,23 @@ int check_frame(const tsl_seq* s, const tsl_frame& fr) {
     if (fr.K_next < 0) return fail(TSL_EINVAL, "K_next must be >= 0");
     if (fr.K_next > 0 && (!fr.rows_next || !fr.n_next)) return fail(TSL_EINVAL, "null rows_next or n_next");
     return TSL_OK;
+}
+
+int rank_tier(int r) {
+    return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : r <= 64 ? 64 : TSL_MAX_R;
+}
+
+}  // namespace eng
+}  // namespace tsl
+
+using namespace tsl::eng;
+
+namespace {
+
+std::mutex g_graph_mu;
+
+int run_groups(const std::vector<tsl::Batch>& groups, hipStream_t st, hipEvent_t* ev = nullptr) {
+    return tsl::eng::run_groups(groups.data(), int(groups.size()), st, ev);
 }
 
 int check_seq(const tsl_seq* s) {
@@ -310,14 +297,6 @@ std::vector<tsl::Batch> group_batches(const Composition& c, const tsl::FrameArgs
         out.push_back(b);
     }
     return out;
-}
-
-// The kernels are instantiated for rank tiers (a register-resident solve up to
-// 8, 16 and 32, wider accumulators up to 64 and 128); a launch group takes the
-// tier of its largest rank, so frames are grouped by tier as well as by shape
-// and a rank-16 frame never runs the kernels sized for rank 64.
-int rank_tier(int r) {
-    return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : r <= 64 ? 64 : TSL_MAX_R;
 }
 
 // Validates a batch and groups it by (n1, n2, mask kind and route, rank tier),

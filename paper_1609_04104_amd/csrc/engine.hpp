@@ -1,0 +1,68 @@
+// Internals of the host engine shared by its source files: a sequence's state
+// and workspace layout, error reporting, frame descriptors and the launch of a
+// step's phases over launch groups.
+#pragma once
+
+#include <cstddef>
+#include <mutex>
+#include <string>
+
+#include "kernels.hpp"
+#include "tsl.h"
+
+// Byte offsets of a sequence's arrays inside its one device arena.
+struct Layout {
+    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, wpart, mpart, part, hpart, total;
+};
+
+struct tsl_pool {
+    std::mutex mu;
+    size_t budget = 0, used = 0;
+};
+
+struct tsl_seq {
+    int n1 = 0, n2 = 0, r = 0, device = 0;
+    double lambda = 0;
+    tsl_opts opts{};
+    char* arena = nullptr;
+    size_t bytes = 0;
+    Layout lay{};
+    hipStream_t last = nullptr;
+    tsl_pool* pool = nullptr;
+    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(arena + off); }
+};
+
+namespace tsl {
+namespace eng {
+
+// Records the message for tsl_last_error and returns `code`.
+int fail(int code, const std::string& msg);
+// Records a HIP failure and returns TSL_EDEVICE.
+int hip_fail(hipError_t e, const char* what);
+
+#define TSL_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) return ::tsl::eng::hip_fail(e_, #call);   \
+    } while (0)
+
+Layout layout_for(int n1, int n2, int r);
+
+// The descriptor of frame `fr` of sequence `s` (plain host pointers).
+FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr);
+
+// Synchronous checks of one frame's arguments (TSL_OK or TSL_EINVAL).
+int check_frame(const tsl_seq* s, const tsl_frame& fr);
+
+// The kernels are instantiated for rank tiers (a register-resident solve up to
+// 8, 16 and 32, wider accumulators up to 64 and 128); a launch group takes the
+// tier of its largest rank, so frames are grouped by tier as well as by shape
+// and a rank-16 frame never runs the kernels sized for rank 64.
+int rank_tier(int r);
+
+// Launches every phase for every group, phase by phase; with `ev` non-null,
+// records ev[p] before phase p and ev[TSL_N_PHASES] after the last.
+int run_groups(const Batch* groups, int n_groups, hipStream_t st, hipEvent_t* ev = nullptr);
+
+}  // namespace eng
+}  // namespace tsl

@@ -23,6 +23,7 @@ _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOTPD: "ENOTP
 EXPORTS = [
     "tsl_opts_default", "tsl_size_supported", "tsl_footprint", "tsl_open", "tsl_close",
     "tsl_push_lines", "tsl_push_points", "tsl_push_frame", "tsl_sample_lines", "tsl_step_many",
+    "tsl_step_many_noalloc",
     "tsl_step_many_timed", "tsl_batch_create", "tsl_batch_launch", "tsl_batch_destroy", "tsl_status",
     "tsl_get_factors", "tsl_get_state", "tsl_set_state", "tsl_shape", "tsl_fft2",
     "tsl_pool_create", "tsl_pool_destroy", "tsl_pool_used", "tsl_open_in_pool",
@@ -80,6 +81,7 @@ def lib():
             "tsl_sample_lines": (i, [vp, i, vp, vp, vp, vp, vp]),
             "tsl_push_frame": (i, [vp, P(Frame), vp]),
             "tsl_step_many": (i, [P(vp), i, P(Frame), vp]),
+            "tsl_step_many_noalloc": (i, [P(vp), i, P(Frame), vp]),
             "tsl_step_many_timed": (i, [P(vp), i, P(Frame), P(d), vp]),
             "tsl_batch_create": (i, [P(vp), i, P(Frame), i, P(vp)]),
             "tsl_batch_launch": (i, [vp, vp]),
@@ -291,6 +293,19 @@ def step_many(seqs, frames, stream=None):
     hs = (ctypes.c_void_p * n)(*[s.h for s in seqs])
     fs = (Frame * n)(*frames)
     _check(lib().tsl_step_many(hs, n, fs, _stream(stream)))
+
+
+STATIC_MAX_FRAMES = 256
+
+
+def step_many_noalloc(seqs, frames, stream=None):
+    """tsl_step_many_noalloc: the batched step with its descriptors in the
+    library's fixed device array (no device allocation; at most
+    STATIC_MAX_FRAMES frames; calls that overlap on one GPU race)."""
+    n = len(seqs)
+    hs = (ctypes.c_void_p * n)(*[s.h for s in seqs])
+    fs = (Frame * n)(*frames)
+    _check(lib().tsl_step_many_noalloc(hs, n, fs, _stream(stream)))
 
 
 class PreparedStep:
