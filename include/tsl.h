@@ -126,6 +126,13 @@ typedef struct {
                                   tsl_sample_lines does, into rows_next / n_next        */
     int32_t*       rows_next;  /* [K_next] device, or NULL if K_next == 0               */
     int32_t*       n_next;     /* [1] device, or NULL if K_next == 0                    */
+    double*        info_out;   /* [4] device float64, or NULL: the frame's step size
+                                  alpha_t, alpha_bar_t, mu_t (eq. 6, Sec. III-A) and
+                                  the conditioning of the ridge Gram G_t = Phi^H Phi +
+                                  lambda I as max(D)/min(D) over the pivots of its
+                                  L D L^H factorisation (a lower bound on kappa_2(G_t),
+                                  equal to it for a diagonal G_t).  Written when the
+                                  ridge solve succeeds                                 */
 } tsl_frame;
 
 /* Fills *o with the defaults: MM step, lambda > 0 required, seed 0, stream 0. */

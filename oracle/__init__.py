@@ -31,7 +31,7 @@ docstrings next to the code that takes them.
 from .dft import dft_matrix, fft2_unitary, ifft2_unitary
 from .tsl import (TslOracle, KspaceOracle, regression_matrix, ridge_gamma,
                   ridge_gamma_svd, back_projection, step_alpha, gershgorin,
-                  instantaneous_cost)
+                  instantaneous_cost, gram_pivot_ratio)
 from .sampler import (line_scores, line_weights_prefix, draw_lines, uniform_draws,
                       point_scores, expected_count)
 from .philox import philox4x64_10
@@ -39,7 +39,7 @@ from .philox import philox4x64_10
 __all__ = [
     "dft_matrix", "fft2_unitary", "ifft2_unitary", "TslOracle", "KspaceOracle",
     "regression_matrix", "ridge_gamma", "ridge_gamma_svd", "back_projection",
-    "step_alpha", "gershgorin", "instantaneous_cost", "line_scores",
+    "step_alpha", "gershgorin", "instantaneous_cost", "gram_pivot_ratio", "line_scores",
     "line_weights_prefix", "draw_lines", "uniform_draws", "point_scores",
     "expected_count", "philox4x64_10",
 ]

@@ -82,6 +82,17 @@ def ridge_gamma_svd(Phi, y, lam):
     return Vh.conj().T @ ((s / (s * s + lam)) * (U.conj().T @ y))
 
 
+def gram_pivot_ratio(G):
+    """max_k D_k / min_k D_k over the pivots of G = L D L^H (D_k = |L_kk|^2 of the
+    Cholesky factor): the conditioning figure reported per frame for the ridge
+    Gram of Sec. III-A.  Every pivot is a Schur complement's diagonal entry and
+    lies in [lambda_min(G), lambda_max(G)], so the ratio never exceeds
+    kappa_2(G), and equals it when G is diagonal."""
+    L = np.linalg.cholesky(G)
+    d = np.abs(np.diag(L)) ** 2
+    return float(d.max() / d.min())
+
+
 def back_projection(Xi, Fl, Fr):
     """Theta = F^{-1}(Xi) = F_l^H Xi F_r^H (Sec. IV-B with one coil, H = ones)."""
     return Fl.conj().T @ Xi @ Fr.conj().T
@@ -198,7 +209,7 @@ class TslOracle:
         self.A, self.B, self.abar, self.t = A_new, B_new, abar, t
         return Step(t=t, gamma=gamma, G=G, h=h, e=e, Xi=Xi, Theta=Theta, alpha=alpha,
                     alpha_bar=abar, mu=mu, shrink=shrink, A=A_new, B=B_new, X=X,
-                    oi=oi, oj=oj, y=y)
+                    oi=oi, oj=oj, y=y, pivot_ratio=gram_pivot_ratio(G))
 
 
 class KspaceOracle:

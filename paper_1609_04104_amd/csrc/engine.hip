@@ -79,6 +79,7 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     a.rows_next = fr.rows_next; a.n_next = fr.n_next;
     a.draws_next = nullptr; a.prefix_next = nullptr;
     a.seed = s->opts.seed; a.sid = s->opts.stream_id;
+    a.info_out = fr.info_out;
     return a;
 }
 

@@ -17,7 +17,7 @@ struct SeqDev {
     // written by the solve kernel, read by the later kernels of the same frame
     double mu, shrink, alpha, abar_new;
     long long t_new;
-    double kappa_proxy; // max pivot^2 / min pivot^2 of the Cholesky factor
+    double kappa_proxy; // max / min pivot D_k of G = L D L^H (squared diagonal ratio of the Cholesky factor)
 };
 
 enum : int { MODE_LINES = 0, MODE_POINTS = 1 };
@@ -92,6 +92,7 @@ struct FrameArgsT {
     P<int> draws_next;         // [K_next] rows of the individual trials, or null
     P<double> prefix_next;     // [n1] weight prefix, or null
     unsigned long long seed, sid;
+    P<double> info_out;        // [4]: alpha_t, alpha_bar_t, mu_t, max/min pivot of G_t, or null
 };
 using FrameArgs = FrameArgsT<HostPtr>;
 using DevFrame = FrameArgsT<GlobalPtr>;

@@ -660,6 +660,12 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
         d->shrink = 1.0 - lam * mu / double(tn);
         d->kappa_proxy = (s_piv_hi / s_piv_lo) * (s_piv_hi / s_piv_lo);
         d->frame_ok = 1;
+        if (f.info_out) {
+            f.info_out[0] = alpha;
+            f.info_out[1] = abar;
+            f.info_out[2] = mu;
+            f.info_out[3] = d->kappa_proxy;
+        }
     }
 }
 
@@ -1041,6 +1047,12 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
         d->shrink = 1.0 - lam * mu / double(tn);
         d->kappa_proxy = s_kappa;
         d->frame_ok = 1;
+        if (f.info_out) {
+            f.info_out[0] = alpha;
+            f.info_out[1] = abar;
+            f.info_out[2] = mu;
+            f.info_out[3] = s_kappa;
+        }
     }
 }
 

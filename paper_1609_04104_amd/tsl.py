@@ -55,7 +55,7 @@ class Frame(ctypes.Structure):
                 ("y", ctypes.c_void_p), ("X_out", ctypes.c_void_p), ("A_out", ctypes.c_void_p),
                 ("B_out", ctypes.c_void_p), ("gamma_out", ctypes.c_void_p), ("n_rows_dev", ctypes.c_void_p),
                 ("y_full", ctypes.c_int), ("K_next", ctypes.c_int), ("rows_next", ctypes.c_void_p),
-                ("n_next", ctypes.c_void_p)]
+                ("n_next", ctypes.c_void_p), ("info_out", ctypes.c_void_p)]
 
 
 _lib = None
@@ -225,11 +225,13 @@ class Sequence:
                                       _stream(stream)))
 
     def frame(self, rows=None, y=None, mask=None, X_out=None, A_out=None, B_out=None, gamma_out=None,
-              n_rows_dev=None, y_full=False, K_next=0, rows_next=None, n_next=None):
+              n_rows_dev=None, y_full=False, K_next=0, rows_next=None, n_next=None, info_out=None):
         """A tsl_frame for push_frame / step_many (keeps the tensors alive on the struct).
 
         rows: int32 [n] (or a capacity-sized buffer when n_rows_dev holds the count);
-        y: [n, n2] samples, or [n1, n2] with y_full=True / a point mask."""
+        y: [n, n2] samples, or [n1, n2] with y_full=True / a point mask;
+        info_out: float64 [4] receiving alpha_t, alpha_bar_t, mu_t and the pivot
+        ratio of the ridge Gram."""
         f = Frame()
         if mask is not None:
             f.mask = _dev(mask, torch.uint8, (self.n1, self.n2), "mask")
@@ -246,7 +248,8 @@ class Sequence:
             f.K_next = int(K_next)
             f.rows_next = _dev(rows_next, torch.int32, (int(K_next),), "rows_next")
             f.n_next = _dev(n_next, torch.int32, (1,), "n_next")
-        f._keep = (rows, y, mask, X_out, A_out, B_out, gamma_out, n_rows_dev, rows_next, n_next)
+        f.info_out = _dev(info_out, torch.float64, (4,), "info_out")
+        f._keep = (rows, y, mask, X_out, A_out, B_out, gamma_out, n_rows_dev, rows_next, n_next, info_out)
         return f
 
     def push(self, frame, stream=None):

@@ -568,3 +568,37 @@ def test_device_row_count_out_of_range_latches(T):
     seq.push(seq.frame(rows=rows, n_rows_dev=cnt, y=y, y_full=True))
     assert seq.status(clear=True) == T.EINVAL
     seq.close()
+
+
+@pytest.mark.parametrize("n1,n2,r,nrows,kind", [(256, 256, 32, 32, "lines"), (128, 128, 64, 40, "lines"),
+                                                (64, 64, 8, 0, "points"), (120, 200, 5, 37, "lines")])
+def test_frame_info_matches_oracle(T, n1, n2, r, nrows, kind):
+    """info_out carries alpha_t, alpha_bar_t, mu_t and the pivot ratio of the
+    ridge Gram; each matches the oracle's to 1e-4 relative on every frame (both
+    sides in FP64, from factors that agree to the parity bar)."""
+    print(f"frame info {kind} {n1}x{n2} r={r}", flush=True)
+    rng, A0, B0 = _random_state(n1, n2, r, 4 * n1 + n2 + r)
+    ora = oracle.TslOracle(n1, n2, r, 0.05, A0, B0)
+    seq = T.Sequence(n1, n2, r, 0.05, dev(A0), dev(B0))
+    info = torch.zeros(4, dtype=torch.float64, device="cuda")
+    worst = 0.0
+    for t in range(4):
+        if kind == "lines":
+            rows = np.sort(rng.choice(n1, nrows, replace=False)).astype(np.int32)
+            Y = cn(rng, (nrows, n2), 50.0 / (n1 * n2)).astype(np.complex64)
+            s = ora.push_lines(rows, Y)
+            fr = seq.frame(rows=dev(rows), y=dev(Y), info_out=info)
+        else:
+            mask = rng.random((n1, n2)) < 0.25
+            Y = cn(rng, (n1, n2), 50.0 / (n1 * n2)).astype(np.complex64)
+            s = ora.push_points(mask, Y)
+            fr = seq.frame(mask=dev(mask.astype(np.uint8)), y=dev(Y), info_out=info)
+        seq.push(fr)
+        got = host(info)
+        want = np.array([s.alpha, s.alpha_bar, s.mu, s.pivot_ratio])
+        rel = np.abs(got - want) / np.abs(want)
+        worst = max(worst, float(rel.max()))
+        assert np.all(rel <= TOL), f"t={t + 1}: got {got}, want {want}"
+    print(f"frame info worst relative error {worst:.2e}, last pivot ratio {got[3]:.3e}", flush=True)
+    assert seq.status() == 0
+    seq.close()

@@ -546,3 +546,24 @@ def test_blocked_sums_follow_the_stated_order():
     # the sum over columns of a 2-D array goes along the leading axis
     m = rng.random((40, 3))
     assert np.array_equal(blocked_sum(m), np.array([blocked_sum(m[:, j]) for j in range(3)]))
+
+
+# ---------------------------------------------------------------------------- Gram conditioning figure
+def test_pivot_ratio_is_kappa_for_a_diagonal_gram_and_bounds_it_otherwise():
+    rng = _rng(90)
+    d = np.array([3.0, 0.25, 7.5, 1.0])
+    assert abs(oracle.gram_pivot_ratio(np.diag(d).astype(complex)) - 30.0) <= 1e-12 * 30.0
+    for _ in range(20):
+        M = _cn(rng, (6, 4))
+        G = M.conj().T @ M + 0.1 * np.eye(4)
+        ev = np.linalg.eigvalsh(G)
+        assert oracle.gram_pivot_ratio(G) <= ev[-1] / ev[0] * (1 + 1e-12)
+
+
+def test_pivot_ratio_two_by_two_closed_form():
+    """G = [[a, b], [conj(b), c]]: the pivots are a and c - |b|^2 / a."""
+    a, b, c = 2.0, 0.7 - 0.4j, 1.3
+    G = np.array([[a, b], [np.conj(b), c]])
+    d2 = c - abs(b) ** 2 / a
+    want = max(a, d2) / min(a, d2)
+    assert abs(oracle.gram_pivot_ratio(G) - want) <= 1e-12 * want
