@@ -214,8 +214,8 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
    that forbid hipMalloc): same arguments, same kernels and results as
    tsl_step_many.  It calls no hipMalloc, hipFree, hipHostMalloc or graph
    instantiation: the frame descriptors go into one fixed device array of
-   TSL_STATIC_MAX_FRAMES entries compiled into the library (each GPU it runs on
-   holds its own copy, about 72 KiB, until the process ends), written by small
+   2 x TSL_STATIC_MAX_FRAMES descriptors compiled into the library (each GPU it
+   runs on holds its own copy, about 148 KiB, until the process ends), written by small
    kernels on `stream`, and the phases are launched directly on `stream`.
    n > TSL_STATIC_MAX_FRAMES returns TSL_EINVAL before anything is enqueued;
    every sequence must be on the current device.  All calls on one GPU share

@@ -51,6 +51,7 @@ Layout layout_for(int n1, int n2, int r) {
     L.mpart = take(size_t(tsl::n_cparts(n2)) * n1 * r * sizeof(float2));
     L.part = take(size_t(tsl::n_parts(n1, n2)) * r * r * sizeof(double2));
     L.hpart = take(size_t(tsl::n_hparts(n1, n2)) * r * sizeof(double2));
+    L.wq = take(size_t(tsl::cdiv(r, 16)) * n1 * sizeof(double));
     L.total = o;
     return L;
 }
@@ -80,6 +81,7 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     a.draws_next = nullptr; a.prefix_next = nullptr;
     a.seed = s->opts.seed; a.sid = s->opts.stream_id;
     a.info_out = fr.info_out;
+    a.wq = s->at<double>(s->lay.wq);
     return a;
 }
 
@@ -141,6 +143,99 @@ int rank_tier(int r) {
     return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : r <= 64 ? 64 : TSL_MAX_R;
 }
 
+FrameFacts frame_facts(const tsl_seq* s, const tsl_frame& fr) {
+    FrameFacts x{};
+    x.n1 = s->n1; x.n2 = s->n2; x.r = s->r;
+    x.mode = fr.mask ? MODE_POINTS : MODE_LINES;
+    x.kspace = (!fr.mask && s->opts.line_route == TSL_ROUTE_KSPACE) ? 1 : 0;
+    x.cap = fr.mask ? s->n1 : std::min(std::max(fr.n_rows, 0), s->n1);
+    x.want_x = fr.X_out != nullptr;
+    x.want_sample = fr.K_next > 0;
+    return x;
+}
+
+namespace {
+
+// Rank tier of the statistics and k-space residual kernels (accumulator tiles).
+int acc_tier(int r) { return r <= 32 ? 2 : r <= 64 ? 4 : 8; }
+bool on_frame_route(const FrameFacts& a) { return a.mode == MODE_POINTS || !a.kspace; }
+
+// The phases in launch order (see kPhases) and the table order each reads.
+bool phase_reads_b(int p) { return p == 2 || p == 3 || p == 4 || p == 6; }
+
+// True if frames a and b (adjacent in the phase's table order) share one launch
+// of phase p: the same kernel instantiation and launch-wide arguments.
+bool same_launch(int p, const FrameFacts& a, const FrameFacts& b) {
+    switch (p) {
+        case 0: return a.mode == b.mode && (a.mode == MODE_POINTS || acc_tier(a.r) == acc_tier(b.r));
+        case 1: return rank_tier(a.r) == rank_tier(b.r);
+        case 2: case 3: case 4:
+            return on_frame_route(a) == on_frame_route(b) && (!on_frame_route(a) || (a.n1 == b.n1 && a.n2 == b.n2));
+        case 5: return a.kspace == b.kspace && (!a.kspace || acc_tier(a.r) == acc_tier(b.r));
+        case 6: return a.n1 == b.n1 && a.n2 == b.n2;
+        default: return (a.r <= 32) == (b.r <= 32);
+    }
+}
+
+template <class Less> void stable_order(int n, int* order, Less less) {
+    for (int i = 0; i < n; ++i) order[i] = i;
+    if (n <= 256) {                          // insertion sort: no heap use (the allocation-free path)
+        for (int i = 1; i < n; ++i) {
+            const int v = order[i];
+            int p = i;
+            while (p > 0 && less(v, order[p - 1])) { order[p] = order[p - 1]; --p; }
+            order[p] = v;
+        }
+    } else {
+        std::stable_sort(order, order + n, less);
+    }
+}
+
+}  // namespace
+
+bool table_orders(const FrameFacts* f, int n, int* order_a, int* order_b) {
+    auto key_a = [&](int i) { return std::make_tuple(rank_tier(f[i].r), f[i].mode, f[i].kspace, f[i].n1, f[i].n2); };
+    auto key_b = [&](int i) { return std::make_tuple(f[i].n1, f[i].n2, f[i].mode, f[i].kspace, rank_tier(f[i].r)); };
+    stable_order(n, order_a, [&](int a, int b) { return key_a(a) < key_a(b); });
+    stable_order(n, order_b, [&](int a, int b) { return key_b(a) < key_b(b); });
+    for (int i = 0; i < n; ++i)
+        if (order_a[i] != order_b[i]) return false;
+    return true;
+}
+
+int launch_phases(const FrameFacts* fa, const FrameArgs* ta, const FrameFacts* fb, const FrameArgs* tb, int n,
+                  hipStream_t st, hipEvent_t* ev) {
+    for (int p = 0; p < TSL_N_PHASES; ++p) {
+        if (ev) TSL_HIP(hipEventRecord(ev[p], st));
+        const bool useb = phase_reads_b(p);
+        const FrameFacts* f = useb ? fb : fa;
+        const FrameArgs* t = useb ? tb : ta;
+        for (int i = 0; i < n;) {
+            int j = i + 1;
+            while (j < n && same_launch(p, f[i], f[j])) ++j;
+            Batch b{};
+            b.one = nullptr;
+            b.table = t + i;
+            b.count = j - i;
+            b.mode = f[i].mode;
+            b.kspace = f[i].kspace != 0;
+            for (int q = i; q < j; ++q) {
+                b.n1 = std::max(b.n1, f[q].n1);
+                b.n2 = std::max(b.n2, f[q].n2);
+                b.r_max = std::max(b.r_max, f[q].r);
+                b.rows_max = std::max(b.rows_max, f[q].cap);
+                b.want_x = b.want_x || f[q].want_x;
+                b.want_sample = b.want_sample || f[q].want_sample;
+            }
+            hipError_t e = kPhases[p].fn(b, st);
+            if (e != hipSuccess) return hip_fail(e, kPhases[p].name);
+            i = j;
+        }
+    }
+    if (ev) TSL_HIP(hipEventRecord(ev[TSL_N_PHASES], st));
+    return TSL_OK;
+}
+
 }  // namespace eng
 }  // namespace tsl
 
@@ -165,18 +260,14 @@ int set_dev(const tsl_seq* s) {
 }
 
 // -------------------------------------------------------------- batched step state
-struct GroupKey {
-    int n1, n2, mode, count, r_max, rows_cap;
-    bool kspace, want_x, want_sample;
-};
-
 struct Composition {
     std::vector<const tsl_seq*> seqs;     // in the order of the call
-    std::vector<int> wants;               // per frame: bit0 X, bit4 points, bit5 row draw
+    std::vector<int> wants;               // per frame: bit0 X, bit4 points, bit5 row draw, bit6 frame route
     std::vector<int> caps;                // per frame: row capacity (sizes the statistics grid)
-    std::vector<int> order;               // frame indices sorted by group
-    std::vector<GroupKey> groups;
-    std::vector<int> group_start;         // offset into order / table
+    std::vector<int> order_a, order_b;    // frame indices in table orders A and B (table_orders)
+    std::vector<tsl::eng::FrameFacts> fa, fb;   // the facts in those orders
+    bool same = true;                     // order B == order A: the table holds n entries, else 2n
+    int entries() const { return int(seqs.size()) * (same ? 1 : 2); }
     bool operator==(const Composition& o) const {
         return seqs == o.seqs && wants == o.wants && caps == o.caps;
     }
@@ -219,7 +310,7 @@ struct tsl_batch {
     bool dead = false;                    // one of its sequences was closed
     bool launched = false;
     std::vector<tsl_seq*> seqs;
-    std::vector<tsl::Batch> groups;       // launch groups over `table`
+    Composition comp;                     // the frames' order and launch facts over `table`
     tsl::FrameArgs* table = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t last = nullptr;
@@ -285,27 +376,12 @@ int take_slot(BatchEngine& be, size_t n, int* slot_out) {
     return TSL_OK;
 }
 
-std::vector<tsl::Batch> group_batches(const Composition& c, const tsl::FrameArgs* table) {
-    std::vector<tsl::Batch> out;
-    for (size_t g = 0; g < c.groups.size(); ++g) {
-        const GroupKey& k = c.groups[g];
-        tsl::Batch b{};
-        b.one = nullptr;
-        b.table = table + c.group_start[g];
-        b.count = k.count;
-        b.n1 = k.n1; b.n2 = k.n2; b.r_max = k.r_max; b.rows_max = k.rows_cap;
-        b.mode = k.mode; b.kspace = k.kspace; b.want_x = k.want_x; b.want_sample = k.want_sample;
-        out.push_back(b);
-    }
-    return out;
-}
-
-// Validates a batch and groups it by (n1, n2, mask kind and route, rank tier),
-// call order kept inside a group.
+// Validates a batch and orders its frames (table_orders).
 int compose(tsl_seq* const* seqs, int n, const tsl_frame* frames, Composition& c) {
     c.seqs.resize(n);
     c.wants.resize(n);
     c.caps.resize(n);
+    std::vector<tsl::eng::FrameFacts> facts(n);
     for (int i = 0; i < n; ++i) {
         const tsl_seq* s = seqs[i];
         if (!s) return fail(TSL_EINVAL, "null sequence in batch");
@@ -316,45 +392,43 @@ int compose(tsl_seq* const* seqs, int n, const tsl_frame* frames, Composition& c
         c.seqs[i] = s;
         c.wants[i] = (frames[i].X_out ? 1 : 0) | (frames[i].mask ? 16 : 0) | (frames[i].K_next > 0 ? 32 : 0) |
                      (!frames[i].mask && s->opts.line_route == TSL_ROUTE_FRAME ? 64 : 0);
-        c.caps[i] = frames[i].mask ? s->n1 : std::min(std::max(frames[i].n_rows, 0), s->n1);
+        facts[i] = frame_facts(s, frames[i]);
+        c.caps[i] = facts[i].cap;
     }
-    // kind: 0 line mask, k-space route; 1 point mask; 2 line mask, frame route
-    auto kind = [&](int i) {
-        if (c.wants[i] & 16) return 1;
-        return (c.wants[i] & 64) ? 2 : 0;
-    };
-    std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
-    for (int i = 0; i < n; ++i) by[{seqs[i]->n1, seqs[i]->n2, kind(i), rank_tier(seqs[i]->r)}].push_back(i);
-    for (auto& kv : by) {
-        GroupKey k{};
-        k.n1 = std::get<0>(kv.first); k.n2 = std::get<1>(kv.first);
-        k.mode = std::get<2>(kv.first) == 1 ? tsl::MODE_POINTS : tsl::MODE_LINES;
-        k.kspace = std::get<2>(kv.first) == 0;
-        k.count = int(kv.second.size());
-        for (int i : kv.second) {
-            k.r_max = std::max(k.r_max, seqs[i]->r);
-            k.rows_cap = std::max(k.rows_cap, c.caps[i]);
-            k.want_x = k.want_x || (c.wants[i] & 1);
-            k.want_sample = k.want_sample || (c.wants[i] & 32);
-        }
-        c.group_start.push_back(int(c.order.size()));
-        for (int i : kv.second) c.order.push_back(i);
-        c.groups.push_back(k);
+    c.order_a.resize(n);
+    c.order_b.resize(n);
+    c.same = table_orders(facts.data(), n, c.order_a.data(), c.order_b.data());
+    c.fa.resize(n);
+    c.fb.resize(n);
+    for (int p = 0; p < n; ++p) {
+        c.fa[p] = facts[c.order_a[p]];
+        c.fb[p] = facts[c.order_b[p]];
     }
     return TSL_OK;
+}
+
+// The launches of a composed batch whose table starts at `table`.
+int run_composition(const Composition& c, const tsl::FrameArgs* table, hipStream_t st, hipEvent_t* ev = nullptr) {
+    const int n = int(c.seqs.size());
+    return launch_phases(c.fa.data(), table, c.fb.data(), c.same ? table : table + n, n, st, ev);
+}
+
+// Host descriptors of a composed batch: order A, then (if it differs) order B.
+void fill_descriptors(const Composition& c, tsl_seq* const* seqs, const tsl_frame* frames, tsl::FrameArgs* out) {
+    const int n = int(c.seqs.size());
+    for (int p = 0; p < n; ++p) out[p] = frame_args(seqs[c.order_a[p]], frames[c.order_a[p]]);
+    if (!c.same)
+        for (int p = 0; p < n; ++p) out[n + p] = frame_args(seqs[c.order_b[p]], frames[c.order_b[p]]);
 }
 
 // Writes the descriptors of a composed batch into the slot's pinned staging
 // buffer and copies them to the slot's device table on `st`.
 int stage_table(Slot& sl, const Composition& c, tsl_seq* const* seqs, const tsl_frame* frames, hipStream_t st) {
-    const size_t n = c.order.size();
-    if (n > sl.cap) return fail(TSL_EINVAL, "internal: descriptor slot too small");
-    for (size_t p = 0; p < n; ++p) {
-        const int i = c.order[p];
-        seqs[i]->last = st;
-        sl.host[p] = frame_args(seqs[i], frames[i]);
-    }
-    TSL_HIP(hipMemcpyAsync(sl.table, sl.host, n * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice, st));
+    const size_t m = size_t(c.entries());
+    if (m > sl.cap) return fail(TSL_EINVAL, "internal: descriptor slot too small");
+    for (const tsl_seq* q : c.seqs) const_cast<tsl_seq*>(q)->last = st;
+    fill_descriptors(c, seqs, frames, sl.host);
+    TSL_HIP(hipMemcpyAsync(sl.table, sl.host, m * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice, st));
     return TSL_OK;
 }
 
@@ -566,7 +640,7 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
     std::lock_guard<std::mutex> lk(g_graph_mu);
     BatchEngine& be = g_batch;
     int k = 0;
-    if ((rc = take_slot(be, size_t(n), &k)) != TSL_OK) return rc;
+    if ((rc = take_slot(be, size_t(c.entries()), &k)) != TSL_OK) return rc;
     Slot& sl = be.slot[k];
     if ((rc = stage_table(sl, c, seqs, frames, st)) != TSL_OK) return rc;
     const bool cached = sl.exec && sl.comp == c;
@@ -576,7 +650,7 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
         // A composition seen for the first time runs as plain launches; one that
         // repeats (the steady state of a fixed batch) is captured over this
         // slot's table and replayed whenever the slot comes round again.
-        rc = run_groups(group_batches(c, sl.table), st);
+        rc = run_composition(c, sl.table, st);
         hipError_t er = hipEventRecord(sl.done, st);
         if (rc != TSL_OK) return rc;
         if (er != hipSuccess) return hip_fail(er, "hipEventRecord");
@@ -586,7 +660,7 @@ int tsl_step_many(tsl_seq* const* seqs, int n, const tsl_frame* frames, void* st
         drop_graph(sl);
         hipGraph_t graph = nullptr;
         hipError_t eb = hipStreamBeginCapture(be.cap, hipStreamCaptureModeThreadLocal);
-        int lrc = eb == hipSuccess ? run_groups(group_batches(c, sl.table), be.cap) : TSL_OK;
+        int lrc = eb == hipSuccess ? run_composition(c, sl.table, be.cap) : TSL_OK;
         hipError_t ec = eb == hipSuccess ? hipStreamEndCapture(be.cap, &graph) : eb;
         hipError_t ei = hipSuccess;
         if (lrc == TSL_OK && ec == hipSuccess) ei = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
@@ -617,7 +691,7 @@ int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, do
     std::lock_guard<std::mutex> lk(g_graph_mu);
     BatchEngine& be = g_batch;
     int k = 0;
-    if ((rc = take_slot(be, size_t(n), &k)) != TSL_OK) return rc;
+    if ((rc = take_slot(be, size_t(c.entries()), &k)) != TSL_OK) return rc;
     Slot& sl = be.slot[k];
     if ((rc = stage_table(sl, c, seqs, frames, st)) != TSL_OK) return rc;
     hipEvent_t ev[TSL_N_PHASES + 1] = {};
@@ -629,7 +703,7 @@ int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, do
             return hip_fail(ee, "hipEventCreate");
         }
     }
-    rc = run_groups(group_batches(c, sl.table), st, ev);
+    rc = run_composition(c, sl.table, st, ev);
     hipError_t er = hipEventRecord(sl.done, st);
     if (rc == TSL_OK && er != hipSuccess) rc = hip_fail(er, "hipEventRecord");
     if (rc == TSL_OK) {
@@ -660,17 +734,18 @@ int tsl_batch_create(tsl_seq* const* seqs, int n, const tsl_frame* frames, int f
     std::unique_ptr<tsl_batch> b(new tsl_batch);
     b->device = dev;
     b->seqs.assign(seqs, seqs + n);
-    std::vector<tsl::FrameArgs> host(static_cast<size_t>(n));
-    for (int p = 0; p < n; ++p) host[p] = frame_args(seqs[c.order[p]], frames[c.order[p]]);
-    TSL_HIP(hipMalloc(&b->table, size_t(n) * sizeof(tsl::FrameArgs)));
-    TSL_HIP(hipMemcpy(b->table, host.data(), size_t(n) * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice));
-    b->groups = group_batches(c, b->table);
+    const size_t m = size_t(c.entries());
+    std::vector<tsl::FrameArgs> host(m);
+    fill_descriptors(c, seqs, frames, host.data());
+    TSL_HIP(hipMalloc(&b->table, m * sizeof(tsl::FrameArgs)));
+    TSL_HIP(hipMemcpy(b->table, host.data(), m * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice));
+    b->comp = c;
     if (flags & TSL_BATCH_GRAPH) {
         hipStream_t cap = nullptr;
         TSL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         hipError_t eb = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        int lrc = eb == hipSuccess ? run_groups(b->groups, cap) : TSL_OK;
+        int lrc = eb == hipSuccess ? run_composition(b->comp, b->table, cap) : TSL_OK;
         hipError_t ec = eb == hipSuccess ? hipStreamEndCapture(cap, &graph) : eb;
         hipStreamDestroy(cap);
         if (lrc != TSL_OK || ec != hipSuccess) {
@@ -704,7 +779,7 @@ int tsl_batch_launch(tsl_batch* b, void* stream) {
         TSL_HIP(hipGraphLaunch(b->exec, st));
         return TSL_OK;
     }
-    return run_groups(b->groups, st);
+    return run_composition(b->comp, b->table, st);
 }
 
 int tsl_batch_destroy(tsl_batch* b) {

@@ -12,7 +12,7 @@
 
 // Byte offsets of a sequence's arrays inside its one device arena.
 struct Layout {
-    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, wpart, mpart, part, hpart, total;
+    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, wpart, mpart, part, hpart, wq, total;
 };
 
 struct tsl_pool {
@@ -63,6 +63,30 @@ int rank_tier(int r);
 // Launches every phase for every group, phase by phase; with `ev` non-null,
 // records ev[p] before phase p and ev[TSL_N_PHASES] after the last.
 int run_groups(const Batch* groups, int n_groups, hipStream_t st, hipEvent_t* ev = nullptr);
+
+// What the launch plan of a batched step needs to know of one frame.
+struct FrameFacts {
+    int n1, n2, r, mode, kspace, cap, want_x, want_sample;
+};
+FrameFacts frame_facts(const tsl_seq* s, const tsl_frame& fr);
+
+// A batched step keeps its descriptors in two orders.  Order A sorts by (rank
+// tier, mask kind, route, shape): the phases whose kernels are instantiated per
+// rank tier and take any shape (statistics, solve, k-space residual, output)
+// launch once per run of adjacent frames with the same instantiation.  Order B
+// sorts by (shape, mask kind, route, rank tier) for the phases instantiated per
+// transform length (the frame-route passes and the factor updates).  Both are
+// stable (call order kept among equal keys); facts, order_a and order_b hold n
+// entries.  Returns true when the two orders coincide (one table serves both).
+bool table_orders(const FrameFacts* facts, int n, int* order_a, int* order_b);
+
+// Launches every phase of a batched step whose descriptors sit in table ta
+// (order A, facts fa) and tb (order B, facts fb), phase by phase, one launch
+// per maximal run of adjacent frames that share the phase's kernel
+// instantiation (the grid covers the largest frame of the run; the kernels
+// leave the blocks a smaller frame does not need).  `ev` as in run_groups.
+int launch_phases(const FrameFacts* fa, const FrameArgs* ta, const FrameFacts* fb, const FrameArgs* tb, int n,
+                  hipStream_t st, hipEvent_t* ev = nullptr);
 
 }  // namespace eng
 }  // namespace tsl

@@ -93,6 +93,8 @@ struct FrameArgsT {
     P<double> prefix_next;     // [n1] weight prefix, or null
     unsigned long long seed, sid;
     P<double> info_out;        // [4]: alpha_t, alpha_bar_t, mu_t, max/min pivot of G_t, or null
+    P<double> wq;              // [cdiv(r, 16)][n1]: the draw's row-weight block sums of the current F_l A,
+                               // written by the A update (valid when this frame's update committed)
 };
 using FrameArgs = FrameArgsT<HostPtr>;
 using DevFrame = FrameArgsT<GlobalPtr>;

@@ -19,6 +19,7 @@
 #include "fft_engine.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
+#include "sampler.hpp"
 
 namespace tsl {
 namespace {
@@ -235,12 +236,58 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
     if (tid == 0 && s_bad) latch(f.dev, ST_ENONFINITE);
 }
 
+// ---------------------------------------------------------------- sampler weights of the new F_l A
+// The A update block for ranks [kTW bx, kTW bx + kTW) (one column block of the
+// sampler's blocked sums, kTW == kSumBlock) also forms, from the complex64
+// values of the new F_l A it wrote (their energies E_ir in s_e[i][c]), the
+// column energies c_r and every row's block sum over its columns of E_ir / c_r
+// in the sampler's order (sampler.hpp), into wq[bx][i]; the draw of the same
+// step then only adds the block sums of each row.
+static_assert(kTW == kSumBlock, "an update block owns one column block of the sampler's sums");
+constexpr int kWeightParts = (kMaxN / kSumBlock + 1) * kTW;   // block sums, then the column energies
+template <int N1>
+__device__ __forceinline__ void row_weight_parts(const DevFrame& f, int bx, const double* s_e, double* s_cp) {
+#pragma clang fp contract(off)
+    constexpr int nblk = (N1 + kSumBlock - 1) / kSumBlock;
+    const int tid = threadIdx.x, R = f.r;
+    for (int p = tid; p < nblk * kTW; p += blockDim.x) {      // thread (b, c): rows of block b, column c
+        const int b = p / kTW, c = p % kTW;
+        double part = 0.0;
+#pragma unroll
+        for (int j = 0; j < kSumBlock; ++j) {
+            const int i = b * kSumBlock + j;
+            part = part + (i < N1 ? s_e[min(i, N1 - 1) * kTW + c] : 0.0);
+        }
+        s_cp[p] = part;
+    }
+    __syncthreads();
+    double* s_c = s_cp + nblk * kTW;
+    if (tid < kTW) {
+        double cr = 0.0;
+        for (int b = 0; b < nblk; ++b) cr = cr + s_cp[b * kTW + tid];
+        s_c[tid] = cr;
+    }
+    __syncthreads();
+    for (int i = tid; i < N1; i += blockDim.x) {
+        double part = 0.0;
+#pragma unroll
+        for (int c = 0; c < kTW; ++c) {
+            const int r = bx * kTW + c;
+            const double cc = s_c[c];
+            const double t = s_e[i * kTW + c] / (cc > 0.0 ? cc : 1.0);
+            part = part + ((r < R && cc > 0.0) ? t : 0.0);
+        }
+        f.wq[size_t(bx) * N1 + i] = part;
+    }
+}
+
 // ---------------------------------------------------------------- K4 (A)
 // Block bx of the A update of one frame (ranks [kTW bx, kTW bx + kTW)); s_tw
 // holds N1 twiddles, s_x the exchange area of ColShape<N1>.
 template <int N1>
-__device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2* s_tw, float2* s_x) {
+__device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2* s_tw, float2* s_x, double* s_cp) {
     using S = ColShape<N1>;
+    static_assert(S::XSIZE >= N1 * kTW, "the exchange area holds the energies of the block's columns");
     constexpr int P = S::P, Q = S::Q, T = S::T;
     const int R = f.r;
     if (bx * kTW >= R) return;
@@ -327,13 +374,21 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
         col_swap_kn<N1>(v, s_x, c, s);
         if (s < Q) {
             dft_only<P, false>(v);
-            if (rv) {
-                sfor<P>([&](auto m) {
-                    constexpr int m2 = decltype(m)::value;
-                    f.Ahat[size_t(s + Q * m2) * R + r] = cscale(v[m2], InvSqrt<N1>::value);
-                });
-            }
+            sfor<P>([&](auto m) {
+                constexpr int m2 = decltype(m)::value;
+                v[m2] = cscale(v[m2], InvSqrt<N1>::value);
+                if (rv) f.Ahat[size_t(s + Q * m2) * R + r] = v[m2];
+            });
         }
+        __syncthreads();                      // s_x is free: it takes the energies
+        double* s_e = reinterpret_cast<double*>(s_x);
+        if (s < Q)
+            sfor<P>([&](auto m) {
+                constexpr int m2 = decltype(m)::value;
+                s_e[(s + Q * m2) * kTW + c] = rv ? energy(v[m2]) : 0.0;
+            });
+        __syncthreads();
+        row_weight_parts<N1>(f, bx, s_e, s_cp);
         return;
     }
     if (s < Q && rv) {
@@ -355,21 +410,30 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
     col_swap_nk<N1>(v, s_x, c, s);
     if (s < P) {
         dft_only<Q, false>(v);
-        if (rv) {
-            sfor<Q>([&](auto k) {
-                constexpr int k2 = decltype(k)::value;
-                f.Ahat[size_t(s + P * k2) * R + r] = cscale(v[k2], InvSqrt<N1>::value);
-            });
-        }
+        sfor<Q>([&](auto k) {
+            constexpr int k2 = decltype(k)::value;
+            v[k2] = cscale(v[k2], InvSqrt<N1>::value);
+            if (rv) f.Ahat[size_t(s + P * k2) * R + r] = v[k2];
+        });
     }
+    __syncthreads();                          // s_x is free: it takes the energies
+    double* s_e = reinterpret_cast<double*>(s_x);
+    if (s < P)
+        sfor<Q>([&](auto k) {
+            constexpr int k2 = decltype(k)::value;
+            s_e[(s + P * k2) * kTW + c] = rv ? energy(v[k2]) : 0.0;
+        });
+    __syncthreads();
+    row_weight_parts<N1>(f, bx, s_e, s_cp);
 }
 
 template <int N1, class Src>
 __global__ void __launch_bounds__(512) k_update_a(Src src) {
     __shared__ float2 s_tw[N1];
     __shared__ float2 s_x[ColShape<N1>::XSIZE];
+    __shared__ double s_cp[kWeightParts];
     if (!src.live()) return;
-    update_a_body<N1>(src.get(), src.bx(), s_tw, s_x);
+    update_a_body<N1>(src.get(), src.bx(), s_tw, s_x, s_cp);
 }
 
 // ---------------------------------------------------------------- K4 (B)
@@ -477,9 +541,10 @@ template <int N, class Src>
 __global__ void __launch_bounds__(512) k_update_ab(Src src, int ga) {
     __shared__ float2 s_tw[N];
     __shared__ float2 s_x[ColShape<N>::XSIZE];
+    __shared__ double s_cp[kWeightParts];
     if (!src.live()) return;
     const DevFrame f = src.get();
-    if (src.bx() < ga) update_a_body<N>(f, src.bx(), s_tw, s_x);
+    if (src.bx() < ga) update_a_body<N>(f, src.bx(), s_tw, s_x, s_cp);
     else update_b_body<N>(f, src.bx() - ga, s_tw, s_x);
 }
 

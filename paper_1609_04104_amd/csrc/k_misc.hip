@@ -669,7 +669,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
     }
 }
 
-// ---------------------------------------------------------------- register solve (R <= 32)
+// ---------------------------------------------------------------- register solve (R <= 64)
 // A block of kRegBlk threads per sequence.  The whole block first gathers G, h
 // and the magnitudes of the two factor Grams into LDS with all of its loads in
 // flight at once (issued before the frame's status is known, over the row
@@ -699,7 +699,9 @@ __device__ __forceinline__ double recip(double d) {
 }
 
 constexpr int kRegBlk = 256;
-constexpr int kGatherPF = 4;   // partial slots of each statistic loaded per round
+// partial slots of each statistic loaded per round (fewer at RB = 64, where a
+// thread gathers nine upper entries)
+template <int RB> constexpr int gather_pf() { return RB <= 32 ? 4 : 1; }
 
 template <int RB, class Src>
 __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
@@ -762,6 +764,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
 #pragma unroll
     for (int u = 0; u < U; ++u) g[u] = ma[u] = mb[u] = double2{0.0, 0.0};
     const int nmax = max(gA, max(gB, ns_cap));
+    constexpr int kGatherPF = gather_pf<RB>();
     double2 wa[U][kGatherPF], wb[U][kGatherPF], ws[U][kGatherPF];
     auto load_round = [&](int k0) {
 #pragma unroll
@@ -833,10 +836,12 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
                 hv.y += v.y;
             }
     };
-    if constexpr (RB == 32) {
+    if constexpr (RB >= 32) {
         // Right-looking L D L^H shared by the four wavefronts, one barrier per
-        // step.  Lane l of wavefront w holds row i = l % 32 of the columns
-        // j = 8 m + g, g = 2 w + l / 32.  Step k reads the unscaled column
+        // step.  Thread t holds row i = t % RB of the columns j = NG m + g,
+        // g = t / RB (NG = 8 column groups of four columns at RB = 32: lane l of
+        // wavefront w in group 2 w + l / 32; NG = 4 groups of sixteen columns at
+        // RB = 64: wavefront w is group w).  Step k reads the unscaled column
         // c = G[:, k] and its pivot D_k from LDS (every wavefront forms 1/D_k)
         // and applies G_ij -= c_i conj(c_j) / D_k to its columns; the lane group
         // that holds column k+1 reduces it first and puts it and its pivot in
@@ -846,8 +851,8 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
         // read).  No branches on the pivots: one that is not positive and
         // finite sets `fail` (read from LDS, so the same everywhere) and is
         // replaced by 1; the frame is then rejected.
-        constexpr int NG = 8, CPL = RB / NG;      // column groups in the block, columns per lane
-        const int i = lane % RB, g = 2 * wave + lane / RB;
+        constexpr int NG = kRegBlk / RB, CPL = RB / NG;   // column groups in the block, columns per lane
+        const int i = tid % RB, g = tid / RB;
         double2 gr[CPL];
         sfor<CPL>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
@@ -973,20 +978,25 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     }
     __syncthreads();
     if (wave == 0 && !s_fail) {
-        double2 lcol[RB];                         // lcol[k] = L_{k, lane}
-        sfor<RB>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            lcol[k] = lane < RB ? s_g[k * RB + lane] : double2{0.0, 0.0};
-        });
-        // y = D^{-1} z, then L^H gamma = y from the last row up
+        // y = D^{-1} z, then L^H gamma = y from the last row up, the columns of
+        // L read back from LDS kBS rows at a time (lcol[k] = L_{k, lane})
+        constexpr int kBS = RB < 32 ? RB : 32;
         hv = double2{hv.x * dinv, hv.y * dinv};
-        sfor<RB>([&](auto kc) {
-            constexpr int k = RB - 1 - decltype(kc)::value;
-            const double2 gk = readlane_d2(hv, k);
-            if (lane < k) {
-                hv.x = fma(-lcol[k].x, gk.x, fma(-lcol[k].y, gk.y, hv.x));   // - conj(L_{k,lane}) gamma_k
-                hv.y = fma(-lcol[k].x, gk.y, fma(lcol[k].y, gk.x, hv.y));
-            }
+        sfor<RB / kBS>([&](auto bc) {
+            constexpr int k0 = RB - kBS * (decltype(bc)::value + 1);
+            double2 lcol[kBS];
+            sfor<kBS>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                lcol[k] = lane < RB ? s_g[(k0 + k) * RB + lane] : double2{0.0, 0.0};
+            });
+            sfor<kBS>([&](auto kc) {
+                constexpr int kk = kBS - 1 - decltype(kc)::value, k = k0 + kk;
+                const double2 gk = readlane_d2(hv, k);
+                if (lane < k) {
+                    hv.x = fma(-lcol[kk].x, gk.x, fma(-lcol[kk].y, gk.y, hv.x));   // - conj(L_{k,lane}) gamma_k
+                    hv.y = fma(-lcol[kk].x, gk.y, fma(lcol[kk].y, gk.x, hv.y));
+                }
+            });
         });
         const bool live = lane < R;
         const bool nonfinite = __any(live && (!isfinite(hv.x) || !isfinite(hv.y)));
@@ -1082,7 +1092,9 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     if (!src.live()) return;
     const DevFrame f = src.get();
     if (src.bx() < ds) {
-        draw_rows<kOutThreads>(f, *reinterpret_cast<SampleLds*>(s_raw));
+        // a committed frame's A update left the row-weight block sums
+        const bool ready = block_frame_ok(f.dev, true);
+        draw_rows<kOutThreads>(f, *reinterpret_cast<SampleLds*>(s_raw), ready);
         return;
     }
     float2* s_ag = reinterpret_cast<float2*>(s_raw);   // [row][c] = A[i0 + row][r0 + c] gamma[r0 + c]
@@ -1092,6 +1104,7 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     const int lane = tid % 64, w = tid / 64;
     const int tiles_x = cdiv(n2, kOutTN);
     const int bi = (tile / tiles_x) * kOutTM, bj = (tile % tiles_x) * kOutTN;
+    if (bi >= n1) return;                   // a launch sized for a larger frame of the run
     const int wi = 32 * (w / 2), wj = 32 * (w % 2);    // wavefront tile inside the block tile
     const int m = lane % 32, h = lane / 32;
     // A, gamma and B of a rank pass, all loads in flight together; the first
@@ -1241,6 +1254,7 @@ hipError_t launch_solve(const Batch& b, hipStream_t st) {
     if (b.r_max <= 8) { launch_solve_reg<8>(b, st); return hipGetLastError(); }
     if (b.r_max <= 16) { launch_solve_reg<16>(b, st); return hipGetLastError(); }
     if (b.r_max <= 32) { launch_solve_reg<32>(b, st); return hipGetLastError(); }
+    if (b.r_max <= 64) { launch_solve_reg<64>(b, st); return hipGetLastError(); }
     const int gx = 1;
     const dim3 grid = frame_grid(b, gx);
     const size_t lds = solve_lds(b.r_max);

@@ -70,8 +70,13 @@ __device__ __forceinline__ double energy(float2 a) {
     return ax * ax + ay * ay;
 }
 
+// With parts_ready, the A update of this frame has left every row's block sums
+// over the column blocks (wq[k][i], the terms E_ir / c_r of column block k in
+// the order of step 2 below) and steps 1-2 reduce to adding them in block order;
+// otherwise (the standalone draw, a frame that was not committed) they are
+// formed here from F_l A.  Both give the same weights bit for bit.
 template <int NT>
-__device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
+__device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L, bool parts_ready = false) {
 #pragma clang fp contract(off)
     static_assert(NT % 64 == 0 && NT >= TSL_MAX_R && NT >= kMaxBlk, "block shape");
     const int K = f.K_next;
@@ -81,6 +86,23 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
     const uint64_t t_next = uint64_t(f.dev->t + 1);
     const int nblk = cdiv(n1, kSumBlock), ncb = cdiv(R, kSumBlock);
     const size_t last = size_t(n1) * R - 1;
+    if (parts_ready) {
+        for (int i = tid; i < n1; i += NT) {
+            double part[TSL_MAX_R / kSumBlock];
+#pragma unroll
+            for (int k = 0; k < TSL_MAX_R / kSumBlock; ++k)
+                if (k < ncb) part[k] = f.wq[size_t(k) * n1 + i];
+            double q = 0.0;
+#pragma unroll
+            for (int k = 0; k < TSL_MAX_R / kSumBlock; ++k)
+                if (k < ncb) q = q + part[k];
+            double w = double(n2) * q;
+            w = w + double(R);
+            L.pref[i] = w;
+            L.mark[i] = 0;
+        }
+        __syncthreads();
+    } else {
 
     // 1. Column energies c_r = sum over rows of E_ir = |Ahat_ir|^2 (FP64): thread
     //    (b, r) adds rows [kSumBlock b, kSumBlock (b + 1)) of column r with all of
@@ -138,6 +160,7 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L) {
         L.pref[i] = w;
     }
     __syncthreads();
+    }
 
     // 3. Inclusive prefix, blocked: thread b scans its block of rows in order
     //    and keeps the block total, thread 0 adds the totals in block order

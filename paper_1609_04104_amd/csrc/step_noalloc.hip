@@ -15,11 +15,12 @@ namespace {
 
 constexpr int kStaticFrames = TSL_STATIC_MAX_FRAMES;
 
-// The descriptor array.  Each GPU the library runs on holds its own copy until
+// The descriptor array (two orders of up to kStaticFrames descriptors, see
+// table_orders).  Each GPU the library runs on holds its own copy until
 // the process ends.  Host code never names it in a kernel argument or a copy:
 // its device address comes from hipGetSymbolAddress, looked up once per device
 // with that device current (device_scratch).
-static __device__ __align__(256) unsigned char scratch[kStaticFrames * sizeof(tsl::FrameArgs)];
+static __device__ __align__(256) unsigned char scratch[2 * kStaticFrames * sizeof(tsl::FrameArgs)];
 
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
@@ -60,19 +61,16 @@ __global__ void __launch_bounds__(1024) k_put_descriptors(PutChunk c, unsigned* 
     }
 }
 
-// tsl_step_many's grouping without heap use: launch groups by (n1, n2, mask
-// kind and route, rank tier) in ascending key order, call order kept inside a
-// group.
+// The step's frame facts and table orders without heap use (table_orders
+// sorts n <= 256 frames by insertion).
 struct StaticComposition {
-    int n = 0, n_groups = 0;
-    int order[kStaticFrames];
-    int group_start[kStaticFrames];
-    tsl::Batch groups[kStaticFrames];
+    int n = 0;
+    bool same = true;
+    int order_a[kStaticFrames], order_b[kStaticFrames];
+    tsl::eng::FrameFacts facts[kStaticFrames], fa[kStaticFrames], fb[kStaticFrames];
 };
 
 int compose_static(tsl_seq* const* seqs, int n, const tsl_frame* frames, int dev, StaticComposition& c) {
-    int key[kStaticFrames][4];
-    int cap[kStaticFrames];
     for (int i = 0; i < n; ++i) {
         const tsl_seq* s = seqs[i];
         if (!s) return fail(TSL_EINVAL, "null sequence in batch");
@@ -81,41 +79,13 @@ int compose_static(tsl_seq* const* seqs, int n, const tsl_frame* frames, int dev
         if (s->device != dev) return fail(TSL_EINVAL, "a sequence of the batch is not on the current device");
         int rc = check_frame(s, frames[i]);
         if (rc != TSL_OK) return rc;
-        const int kind = frames[i].mask ? 1 : (s->opts.line_route == TSL_ROUTE_FRAME ? 2 : 0);
-        key[i][0] = s->n1; key[i][1] = s->n2; key[i][2] = kind; key[i][3] = rank_tier(s->r);
-        cap[i] = frames[i].mask ? s->n1 : std::min(std::max(frames[i].n_rows, 0), s->n1);
-    }
-    auto less = [&](int a, int b) {
-        for (int q = 0; q < 4; ++q)
-            if (key[a][q] != key[b][q]) return key[a][q] < key[b][q];
-        return false;
-    };
-    for (int i = 0; i < n; ++i) {          // stable insertion sort of the frame indices by key
-        int p = i;
-        while (p > 0 && less(i, c.order[p - 1])) {
-            c.order[p] = c.order[p - 1];
-            --p;
-        }
-        c.order[p] = i;
+        c.facts[i] = frame_facts(s, frames[i]);
     }
     c.n = n;
-    c.n_groups = 0;
+    c.same = table_orders(c.facts, n, c.order_a, c.order_b);
     for (int p = 0; p < n; ++p) {
-        const int i = c.order[p];
-        if (p == 0 || less(c.order[p - 1], i)) {
-            tsl::Batch b{};
-            b.n1 = key[i][0]; b.n2 = key[i][1];
-            b.mode = key[i][2] == 1 ? tsl::MODE_POINTS : tsl::MODE_LINES;
-            b.kspace = key[i][2] == 0;
-            c.group_start[c.n_groups] = p;
-            c.groups[c.n_groups++] = b;
-        }
-        tsl::Batch& b = c.groups[c.n_groups - 1];
-        b.count += 1;
-        b.r_max = std::max(b.r_max, seqs[i]->r);
-        b.rows_max = std::max(b.rows_max, cap[i]);
-        b.want_x = b.want_x || frames[i].X_out != nullptr;
-        b.want_sample = b.want_sample || frames[i].K_next > 0;
+        c.fa[p] = c.facts[c.order_a[p]];
+        c.fb[p] = c.facts[c.order_b[p]];
     }
     return TSL_OK;
 }
@@ -129,25 +99,27 @@ extern "C" int tsl_step_many_noalloc(tsl_seq* const* seqs, int n, const tsl_fram
     if (n == 0) return TSL_OK;
     int dev = 0;
     TSL_HIP(hipGetDevice(&dev));
-    StaticComposition c;          // about 14 KiB of stack: no heap use on this path
+    StaticComposition c;          // about 30 KiB of stack: no heap use on this path
     int rc = compose_static(seqs, n, frames, dev, c);
     if (rc != TSL_OK) return rc;
     tsl::FrameArgs* table = nullptr;
     if ((rc = device_scratch(dev, &table)) != TSL_OK) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    for (int p0 = 0; p0 < n; p0 += kPutFrames) {
-        const int m = std::min(kPutFrames, n - p0);
+    for (int i = 0; i < n; ++i) seqs[i]->last = st;
+    // order A at [0, n), order B (if it differs) at [n, 2n)
+    const int m = c.same ? n : 2 * n;
+    for (int p0 = 0; p0 < m; p0 += kPutFrames) {
+        const int cnt = std::min(kPutFrames, m - p0);
         PutChunk chunk;
         std::memset(&chunk, 0, sizeof(chunk));
-        for (int q = 0; q < m; ++q) {
-            const int i = c.order[p0 + q];
-            seqs[i]->last = st;
+        for (int q = 0; q < cnt; ++q) {
+            const int p = p0 + q;
+            const int i = p < n ? c.order_a[p] : c.order_b[p - n];
             chunk.f[q] = frame_args(seqs[i], frames[i]);
         }
-        const int words = m * int(sizeof(tsl::FrameArgs) / 4);
+        const int words = cnt * int(sizeof(tsl::FrameArgs) / 4);
         k_put_descriptors<<<1, kPutWords, 0, st>>>(chunk, reinterpret_cast<unsigned*>(table + p0), words);
         TSL_HIP(hipGetLastError());
     }
-    for (int g = 0; g < c.n_groups; ++g) c.groups[g].table = table + c.group_start[g];
-    return run_groups(c.groups, c.n_groups, st);
+    return launch_phases(c.fa, table, c.fb, c.same ? table : table + n, n, st);
 }

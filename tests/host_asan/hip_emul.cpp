@@ -95,16 +95,49 @@ void touch(const T* p, size_t n) {
 }
 
 int tier(int r) { return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : r <= 64 ? 64 : 128; }
+int acc_tier(int r) { return r <= 32 ? 2 : r <= 64 ? 4 : 8; }
 
-// What a kernel of the group reads of one descriptor.
-void check_frame(const tsl::Batch& b, const tsl::FrameArgs& a) {
+// Which launcher a group reaches (the invariants a launch relies on differ).
+enum Phase { P_STATS, P_SOLVE, P_FRAME, P_KRES, P_UPDATE, P_OUT, P_SAMPLE };
+
+// What a kernel of the launch reads of one descriptor, and the launch-wide
+// arguments it relies on: the grid covers the descriptor's shape, rank and
+// rows; kernels instantiated per transform length see only that shape;
+// kernels instantiated per rank tier see only that tier.
+void check_frame(const tsl::Batch& b, const tsl::FrameArgs& a, Phase ph) {
     ++g_groups_run;
-    if (a.n1 != b.n1 || a.n2 != b.n2) report("descriptor shape differs from its launch group");
-    if (a.r < 1 || a.r > b.r_max) report("descriptor rank outside its launch group's tier");
-    if (b.table && tier(a.r) != tier(b.r_max)) report("descriptor rank tier differs from its launch group");
-    if (a.mode != b.mode) report("descriptor mask kind differs from its launch group");
-    if (a.mode == tsl::MODE_LINES && (a.kspace != 0) != b.kspace) report("descriptor route differs from its group");
-    if (a.mode == tsl::MODE_LINES && a.n_rows > b.rows_max) report("descriptor rows above the group's capacity");
+    if (a.n1 > b.n1 || a.n2 > b.n2) report("descriptor larger than its launch");
+    if (a.r < 1 || a.r > b.r_max) report("descriptor rank above its launch's");
+    if (a.mode == tsl::MODE_LINES && a.n_rows > b.rows_max) report("descriptor rows above the launch's capacity");
+    const bool frame_route = a.mode == tsl::MODE_POINTS || !a.kspace;
+    switch (ph) {
+        case P_STATS:
+            if (a.mode != b.mode) report("statistics launch mixes mask kinds");
+            if (a.mode == tsl::MODE_LINES && b.table && acc_tier(a.r) != acc_tier(b.r_max))
+                report("statistics launch mixes accumulator tiers");
+            break;
+        case P_SOLVE:
+            if (b.table && tier(a.r) != tier(b.r_max)) report("solve launch mixes rank tiers");
+            break;
+        case P_FRAME:
+            if (a.n1 != b.n1 || a.n2 != b.n2) report("frame-route launch mixes shapes");
+            if (!frame_route) report("k-space frame in a frame-route launch");
+            break;
+        case P_KRES:
+            if (a.mode != tsl::MODE_LINES || !a.kspace) report("frame-route frame in a k-space residual launch");
+            if (b.table && acc_tier(a.r) != acc_tier(b.r_max)) report("k-space residual launch mixes tiers");
+            break;
+        case P_UPDATE:
+            if (a.n1 != b.n1 || a.n2 != b.n2) report("update launch mixes shapes");
+            break;
+        case P_OUT:
+            if ((a.r <= 32) != (b.r_max <= 32)) report("output launch mixes single- and multi-pass ranks");
+            if (a.X_out && !b.want_x) report("output frame without output tiles");
+            if (a.K_next > 0 && !b.want_sample) report("row draw without a draw block");
+            break;
+        case P_SAMPLE:
+            break;
+    }
     const size_t n1 = size_t(a.n1), n2 = size_t(a.n2), r = size_t(a.r);
     touch(a.A, n1 * r); touch(a.B, n2 * r); touch(a.Ahat, n1 * r); touch(a.Bhat, n2 * r);
     touch(a.dev, 1); touch(a.gamma64, r); touch(a.gamma32, r);
@@ -113,6 +146,7 @@ void check_frame(const tsl::Batch& b, const tsl::FrameArgs& a) {
     touch(a.mpart, size_t(tsl::n_cparts(a.n2)) * n1 * r);
     touch(a.part, size_t(tsl::n_parts(a.n1, a.n2)) * r * r);
     touch(a.hpart, size_t(tsl::n_hparts(a.n1, a.n2)) * r);
+    touch(a.wq, size_t(tsl::cdiv(a.r, 16)) * n1);
     if (a.mode == tsl::MODE_LINES) {
         touch(a.rows, size_t(a.n_rows));
         touch(a.y, (a.y_full ? n1 : size_t(a.n_rows)) * n2);
@@ -122,15 +156,16 @@ void check_frame(const tsl::Batch& b, const tsl::FrameArgs& a) {
     }
     touch(a.X_out, n1 * n2); touch(a.A_out, n1 * r); touch(a.B_out, n2 * r); touch(a.gamma_out, r);
     if (a.K_next > 0) { touch(a.rows_next, size_t(a.K_next)); touch(a.n_next, 1); }
+    if (a.info_out) touch(a.info_out, 4);
 }
 
-hipError_t run_group(const tsl::Batch& b0, hipStream_t st) {
+hipError_t run_group(const tsl::Batch& b0, hipStream_t st, Phase ph) {
     tsl::Batch b = b0;
     tsl::FrameArgs one{};
     if (b.one) one = *b.one;          // a by-value descriptor is copied at launch, as a kernel argument is
-    issue(st, [b, one]() {
-        if (b.one) { check_frame(b, one); return; }
-        for (int i = 0; i < b.count; ++i) check_frame(b, b.table[i]);
+    issue(st, [b, one, ph]() {
+        if (b.one) { check_frame(b, one, ph); return; }
+        for (int i = 0; i < b.count; ++i) check_frame(b, b.table[i], ph);
     }, false);
     return hipSuccess;
 }
@@ -146,16 +181,16 @@ extern "C" void emul_flush() { flush_all(); }
 
 // ------------------------------------------------------------ launchers
 namespace tsl {
-hipError_t launch_synth_rowfft(const Batch& b, hipStream_t st) { return b.mode == MODE_POINTS || !b.kspace ? run_group(b, st) : hipSuccess; }
-hipError_t launch_row_inv_grad(const Batch& b, hipStream_t st) { return b.mode == MODE_POINTS || !b.kspace ? run_group(b, st) : hipSuccess; }
-hipError_t launch_col_resid(const Batch& b, hipStream_t st) { return b.mode == MODE_POINTS || !b.kspace ? run_group(b, st) : hipSuccess; }
-hipError_t launch_kres(const Batch& b, hipStream_t st) { return b.mode == MODE_LINES && b.kspace ? run_group(b, st) : hipSuccess; }
-hipError_t launch_update_a(const Batch& b, hipStream_t st) { return run_group(b, st); }
-hipError_t launch_update_b(const Batch& b, hipStream_t st) { return run_group(b, st); }
-hipError_t launch_stats(const Batch& b, hipStream_t st) { return run_group(b, st); }
-hipError_t launch_solve(const Batch& b, hipStream_t st) { return run_group(b, st); }
-hipError_t launch_synth_out(const Batch& b, hipStream_t st) { return run_group(b, st); }
-hipError_t launch_sample(const Batch& b, hipStream_t st) { return run_group(b, st); }
+hipError_t launch_synth_rowfft(const Batch& b, hipStream_t st) { return b.mode == MODE_POINTS || !b.kspace ? run_group(b, st, P_FRAME) : hipSuccess; }
+hipError_t launch_row_inv_grad(const Batch& b, hipStream_t st) { return b.mode == MODE_POINTS || !b.kspace ? run_group(b, st, P_FRAME) : hipSuccess; }
+hipError_t launch_col_resid(const Batch& b, hipStream_t st) { return b.mode == MODE_POINTS || !b.kspace ? run_group(b, st, P_FRAME) : hipSuccess; }
+hipError_t launch_kres(const Batch& b, hipStream_t st) { return b.mode == MODE_LINES && b.kspace ? run_group(b, st, P_KRES) : hipSuccess; }
+hipError_t launch_update_a(const Batch& b, hipStream_t st) { return run_group(b, st, P_UPDATE); }
+hipError_t launch_update_b(const Batch& b, hipStream_t st) { return run_group(b, st, P_UPDATE); }
+hipError_t launch_stats(const Batch& b, hipStream_t st) { return run_group(b, st, P_STATS); }
+hipError_t launch_solve(const Batch& b, hipStream_t st) { return run_group(b, st, P_SOLVE); }
+hipError_t launch_synth_out(const Batch& b, hipStream_t st) { return run_group(b, st, P_OUT); }
+hipError_t launch_sample(const Batch& b, hipStream_t st) { return run_group(b, st, P_SAMPLE); }
 hipError_t launch_rowfft(int n1, int n2, int batch, const float2* in, float2* out, bool, hipStream_t st) {
     issue(st, [=]() { touch(in, size_t(batch) * n1 * n2); touch(out, size_t(batch) * n1 * n2); }, false);
     return hipSuccess;
