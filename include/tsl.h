@@ -95,7 +95,16 @@ typedef struct {
     uint64_t seed;           /* sampler key word 0 (Philox4x64-10)                    */
     uint64_t stream_id;      /* sampler key word 1                                    */
     int      line_route;     /* TSL_ROUTE_KSPACE (default) or TSL_ROUTE_FRAME          */
+    int      synth_bf16;     /* operands of the rank-R syntheses A diag(gamma) B^T (the
+                                frame route's X- and the output X_t, eq. 2) on the
+                                matrix cores: TSL_SYNTH_FP32 (default), TSL_SYNTH_BF16
+                                (BF16 operands, FP32 sums: relative error of X near
+                                3e-3, outside the 1e-4 parity bar) or TSL_SYNTH_BF16X3
+                                (each FP32 operand split into two BF16 numbers and
+                                three products summed: near 1e-5)                    */
 } tsl_opts;
+
+enum { TSL_SYNTH_FP32 = 0, TSL_SYNTH_BF16 = 1, TSL_SYNTH_BF16X3 = 2 };
 
 /* Number of timed phases reported by tsl_step_many_timed. */
 #define TSL_N_PHASES 8

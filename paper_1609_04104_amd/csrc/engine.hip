@@ -63,6 +63,7 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     a.mode = fr.mask ? tsl::MODE_POINTS : tsl::MODE_LINES;
     a.kspace = (!fr.mask && s->opts.line_route == TSL_ROUTE_KSPACE) ? 1 : 0;
     a.lambda = s->lambda; a.mu_const = s->opts.mu; a.step_mode = s->opts.step_mode;
+    a.synth_bf16 = s->opts.synth_bf16;
     a.n_rows = fr.mask ? 0 : fr.n_rows;
     a.A = s->at<float2>(s->lay.A); a.B = s->at<float2>(s->lay.B);
     a.Ahat = s->at<float2>(s->lay.Ahat); a.Bhat = s->at<float2>(s->lay.Bhat);
@@ -151,6 +152,7 @@ FrameFacts frame_facts(const tsl_seq* s, const tsl_frame& fr) {
     x.cap = fr.mask ? s->n1 : std::min(std::max(fr.n_rows, 0), s->n1);
     x.want_x = fr.X_out != nullptr;
     x.want_sample = fr.K_next > 0;
+    x.synth = s->opts.synth_bf16;
     return x;
 }
 
@@ -173,7 +175,7 @@ bool same_launch(int p, const FrameFacts& a, const FrameFacts& b) {
             return on_frame_route(a) == on_frame_route(b) && (!on_frame_route(a) || (a.n1 == b.n1 && a.n2 == b.n2));
         case 5: return a.kspace == b.kspace && (!a.kspace || acc_tier(a.r) == acc_tier(b.r));
         case 6: return a.n1 == b.n1 && a.n2 == b.n2;
-        default: return (a.r <= 32) == (b.r <= 32);
+        default: return (a.r <= 32) == (b.r <= 32) && a.synth == b.synth;
     }
 }
 
@@ -219,6 +221,7 @@ int launch_phases(const FrameFacts* fa, const FrameArgs* ta, const FrameFacts* f
             b.count = j - i;
             b.mode = f[i].mode;
             b.kspace = f[i].kspace != 0;
+            b.synth = f[i].synth;
             for (int q = i; q < j; ++q) {
                 b.n1 = std::max(b.n1, f[q].n1);
                 b.n2 = std::max(b.n2, f[q].n2);
@@ -444,6 +447,7 @@ void tsl_opts_default(tsl_opts* o) {
     o->mu = 0.0;
     o->allow_lambda0 = 0;
     o->line_route = TSL_ROUTE_KSPACE;
+    o->synth_bf16 = TSL_SYNTH_FP32;
 }
 
 int tsl_size_supported(int n) { return tsl::size_supported(n) ? 1 : 0; }
@@ -472,6 +476,8 @@ static int validate_params(double lambda, const tsl_opts& o) {
     if (lambda == 0.0 && !o.allow_lambda0) return fail(TSL_EINVAL, "lambda == 0 needs allow_lambda0");
     if (o.step_mode != TSL_STEP_MM && o.step_mode != TSL_STEP_CONST) return fail(TSL_EINVAL, "bad step_mode");
     if (o.line_route != TSL_ROUTE_KSPACE && o.line_route != TSL_ROUTE_FRAME) return fail(TSL_EINVAL, "bad line_route");
+    if (o.synth_bf16 != TSL_SYNTH_FP32 && o.synth_bf16 != TSL_SYNTH_BF16 && o.synth_bf16 != TSL_SYNTH_BF16X3)
+        return fail(TSL_EINVAL, "bad synth_bf16");
     if (o.step_mode == TSL_STEP_CONST && !(o.mu > 0.0 && std::isfinite(o.mu)))
         return fail(TSL_EINVAL, "constant step needs a finite mu > 0");
     return TSL_OK;
@@ -588,6 +594,7 @@ int tsl_push_frame(tsl_seq* s, const tsl_frame* frame, void* stream) {
     b.rows_max = frame->mask ? s->n1 : std::min(std::max(frame->n_rows, 0), s->n1);
     b.want_x = frame->X_out != nullptr;
     b.want_sample = a.K_next > 0;
+    b.synth = s->opts.synth_bf16;
     return run_groups({b}, st);
 }
 

@@ -66,7 +66,7 @@ int run_groups(const Batch* groups, int n_groups, hipStream_t st, hipEvent_t* ev
 
 // What the launch plan of a batched step needs to know of one frame.
 struct FrameFacts {
-    int n1, n2, r, mode, kspace, cap, want_x, want_sample;
+    int n1, n2, r, mode, kspace, cap, want_x, want_sample, synth;
 };
 FrameFacts frame_facts(const tsl_seq* s, const tsl_frame& fr);
 

@@ -63,6 +63,7 @@ struct FrameArgsT {
     int kspace;           // line mask on the k-space route (GA holds E conj(Bhat) on the sampled rows, W in wpart)
     double lambda, mu_const;
     int step_mode, n_rows;
+    int synth_bf16;       // SYN_FP32, SYN_BF16 or SYN_BF16X3 (mfma.hpp): operands of the syntheses
     // resident state
     P<float2> A, B, Ahat, Bhat;
     P<SeqDev> dev;

@@ -1086,7 +1086,9 @@ constexpr int kOutPitch = kOutRC + 1;        // LDS row pitch (float2): conflict
 constexpr size_t kOutLds = size_t(kOutTM + kOutTN) * kOutPitch * sizeof(float2);
 // ONE: every rank fits one pass (R <= kOutRC), so no staging load is in
 // flight beside the accumulators and the kernel needs fewer registers.
-template <bool ONE, class Src>
+// BF: SYN_FP32 (FP32 steps, two ranks each), SYN_BF16 or SYN_BF16X3 (BF16
+// steps, sixteen ranks each: lane half h takes ranks c0 + 8h + j, j < 8).
+template <bool ONE, int BF, class Src>
 __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     __shared__ __align__(16) unsigned char s_raw[kOutLds > sizeof(SampleLds) ? kOutLds : sizeof(SampleLds)];
     if (!src.live()) return;
@@ -1158,16 +1160,54 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
         __syncthreads();
         const float2* pa = s_ag + (wi + m) * kOutPitch;
         const float2* pb = s_b + (wj + m) * kOutPitch;
-        // two ranks per step (K = 2: lane half h takes rank c0 + h), three real
-        // products per complex one: Re = P1 - P2, Im = P3 - P1 - P2
-        for (int c0 = 0; c0 < nr; c0 += 2) {
-            const int c = min(c0 + h, nr - 1);
-            const bool cv = c0 + h < nr;
-            const float2 ag0 = pa[c], bb0 = pb[c];
-            const float2 ag = cv ? ag0 : float2{0.f, 0.f}, bb = cv ? bb0 : float2{0.f, 0.f};
-            p1 = mfma_32x32x2(ag.x, bb.x, p1);
-            p2 = mfma_32x32x2(ag.y, bb.y, p2);
-            p3 = mfma_32x32x2(ag.x + ag.y, bb.x + bb.y, p3);
+        // three real products per complex one: Re = P1 - P2, Im = P3 - P1 - P2
+        if constexpr (BF == SYN_FP32) {
+            // two ranks per step (K = 2: lane half h takes rank c0 + h)
+            for (int c0 = 0; c0 < nr; c0 += 2) {
+                const int c = min(c0 + h, nr - 1);
+                const bool cv = c0 + h < nr;
+                const float2 ag0 = pa[c], bb0 = pb[c];
+                const float2 ag = cv ? ag0 : float2{0.f, 0.f}, bb = cv ? bb0 : float2{0.f, 0.f};
+                p1 = mfma_32x32x2(ag.x, bb.x, p1);
+                p2 = mfma_32x32x2(ag.y, bb.y, p2);
+                p3 = mfma_32x32x2(ag.x + ag.y, bb.x + bb.y, p3);
+            }
+        } else {
+            for (int c0 = 0; c0 < nr; c0 += 16) {
+                bf16x8 ah[3], bh[3], al[3], bl[3];     // [re, im, re + im] of AG and of B
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int c = c0 + 8 * h + j;
+                    const bool cv = c < nr;
+                    const float2 ag0 = pa[min(c, nr - 1)], bb0 = pb[min(c, nr - 1)];
+                    const float2 ag = cv ? ag0 : float2{0.f, 0.f}, bb = cv ? bb0 : float2{0.f, 0.f};
+                    const float av[3] = {ag.x, ag.y, ag.x + ag.y}, bv[3] = {bb.x, bb.y, bb.x + bb.y};
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        if constexpr (BF == SYN_BF16X3) {
+                            const BfPair sa = split_bf16(av[q]), sb = split_bf16(bv[q]);
+                            ah[q][j] = sa.hi;
+                            al[q][j] = sa.lo;
+                            bh[q][j] = sb.hi;
+                            bl[q][j] = sb.lo;
+                        } else {
+                            ah[q][j] = static_cast<__bf16>(av[q]);
+                            bh[q][j] = static_cast<__bf16>(bv[q]);
+                        }
+                    }
+                }
+                p1 = mfma_32x32x16_bf16(ah[0], bh[0], p1);
+                p2 = mfma_32x32x16_bf16(ah[1], bh[1], p2);
+                p3 = mfma_32x32x16_bf16(ah[2], bh[2], p3);
+                if constexpr (BF == SYN_BF16X3) {
+                    p1 = mfma_32x32x16_bf16(ah[0], bl[0], p1);
+                    p2 = mfma_32x32x16_bf16(ah[1], bl[1], p2);
+                    p3 = mfma_32x32x16_bf16(ah[2], bl[2], p3);
+                    p1 = mfma_32x32x16_bf16(al[0], bh[0], p1);
+                    p2 = mfma_32x32x16_bf16(al[1], bh[1], p2);
+                    p3 = mfma_32x32x16_bf16(al[2], bh[2], p3);
+                }
+            }
         }
     }
     const int i0 = bi + wi, j = bj + wj + m;
@@ -1268,13 +1308,20 @@ hipError_t launch_synth_out(const Batch& b, hipStream_t st) {
     const int gx = ds + (b.want_x ? cdiv(b.n1, kOutTM) * cdiv(b.n2, kOutTN) : 0);
     if (gx == 0) return hipSuccess;
     const dim3 grid = frame_grid(b, gx);
-    if (b.r_max <= kOutRC) {
-        if (b.table) k_synth_out<true, FrameTable><<<grid, kOutThreads, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
-        else k_synth_out<true, OneFrame><<<grid, kOutThreads, 0, st>>>(OneFrame{*b.one}, ds);
-    } else {
-        if (b.table) k_synth_out<false, FrameTable><<<grid, kOutThreads, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
-        else k_synth_out<false, OneFrame><<<grid, kOutThreads, 0, st>>>(OneFrame{*b.one}, ds);
-    }
+    auto go = [&](auto one, auto bf) {
+        constexpr bool ONE = decltype(one)::value;
+        constexpr int BF = decltype(bf)::value;
+        if (b.table)
+            k_synth_out<ONE, BF, FrameTable><<<grid, kOutThreads, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
+        else k_synth_out<ONE, BF, OneFrame><<<grid, kOutThreads, 0, st>>>(OneFrame{*b.one}, ds);
+    };
+    auto with_bf = [&](auto one) {
+        if (b.synth == SYN_BF16) go(one, std::integral_constant<int, SYN_BF16>{});
+        else if (b.synth == SYN_BF16X3) go(one, std::integral_constant<int, SYN_BF16X3>{});
+        else go(one, std::integral_constant<int, SYN_FP32>{});
+    };
+    if (b.r_max <= kOutRC) with_bf(std::true_type{});
+    else with_bf(std::false_type{});
     return hipGetLastError();
 }
 

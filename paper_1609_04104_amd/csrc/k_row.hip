@@ -99,6 +99,8 @@ __global__ void __launch_bounds__(kRowBlock) k_synth_rowfft(Src src) {
 #pragma unroll
         for (int u = 0; u < RT::TPW; ++u) accr[u] = acci[u] = f32x4{0.f, 0.f, 0.f, 0.f};
         const bool im = g & 1;
+        const int bf = __builtin_amdgcn_readfirstlane(f.synth_bf16);   // uniform: scalar branch
+        static_assert(kSynRC == 8, "a BF16 step covers the 16 K entries of one pass");
         for (int r0 = 0; r0 < R; r0 += kSynRC) {
             const int nr = min(kSynRC, R - r0);
             __syncthreads();
@@ -116,19 +118,61 @@ __global__ void __launch_bounds__(kRowBlock) k_synth_rowfft(Src src) {
                                              : float2{0.f, 0.f};
             }
             __syncthreads();
+            if (bf == SYN_FP32) {
 #pragma unroll
-            for (int k = 0; k < kSynRC / 2; ++k) {
-                const int c = 2 * k + g / 2;
+                for (int k = 0; k < kSynRC / 2; ++k) {
+                    const int c = 2 * k + g / 2;
+#pragma unroll
+                    for (int u = 0; u < RT::TPW; ++u) {
+                        const int tile = wave + kRowWaves * u;
+                        if (tile >= RT::MT * RT::NT) break;
+                        const int mt = tile / RT::NT, nt = tile % RT::NT, j = 16 * nt + m;
+                        const float2 a = s_ag[(16 * mt + m) * kSynBP + c];
+                        const float2 b = s_b[(j < N2 ? j : N2 - 1) * kSynBP + c];   // clamped, then masked
+                        const float bv = j < N2 ? (im ? b.y : b.x) : 0.f;
+                        accr[u] = mfma_16x16x4(im ? -a.y : a.x, bv, accr[u]);
+                        acci[u] = mfma_16x16x4(im ? a.x : a.y, bv, acci[u]);
+                    }
+                }
+            } else {
+                // one 16x16x16 BF16 step per pass: lane (m, g) supplies K entries
+                // 4 g + e, e < 4, i.e. rank 2 g + e / 2, real part if e is even
 #pragma unroll
                 for (int u = 0; u < RT::TPW; ++u) {
                     const int tile = wave + kRowWaves * u;
                     if (tile >= RT::MT * RT::NT) break;
                     const int mt = tile / RT::NT, nt = tile % RT::NT, j = 16 * nt + m;
-                    const float2 a = s_ag[(16 * mt + m) * kSynBP + c];
-                    const float2 b = s_b[(j < N2 ? j : N2 - 1) * kSynBP + c];   // clamped, then masked
-                    const float bv = j < N2 ? (im ? b.y : b.x) : 0.f;
-                    accr[u] = mfma_16x16x4(im ? -a.y : a.x, bv, accr[u]);
-                    acci[u] = mfma_16x16x4(im ? a.x : a.y, bv, acci[u]);
+                    bf16x4 pr_h, pi_h, q_h, pr_l, pi_l, q_l;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int c = 2 * g + e / 2;
+                        const bool re = (e & 1) == 0;
+                        const float2 a = s_ag[(16 * mt + m) * kSynBP + c];
+                        const float2 b = s_b[(j < N2 ? j : N2 - 1) * kSynBP + c];
+                        const float pr = re ? a.x : -a.y, pi = re ? a.y : a.x;
+                        const float q = j < N2 ? (re ? b.x : b.y) : 0.f;
+                        if (bf == SYN_BF16X3) {
+                            const BfPair sr = split_bf16(pr), si = split_bf16(pi), sq = split_bf16(q);
+                            pr_h[e] = sr.hi;
+                            pr_l[e] = sr.lo;
+                            pi_h[e] = si.hi;
+                            pi_l[e] = si.lo;
+                            q_h[e] = sq.hi;
+                            q_l[e] = sq.lo;
+                        } else {
+                            pr_h[e] = static_cast<__bf16>(pr);
+                            pi_h[e] = static_cast<__bf16>(pi);
+                            q_h[e] = static_cast<__bf16>(q);
+                        }
+                    }
+                    accr[u] = mfma_16x16x16_bf16(pr_h, q_h, accr[u]);
+                    acci[u] = mfma_16x16x16_bf16(pi_h, q_h, acci[u]);
+                    if (bf == SYN_BF16X3) {
+                        accr[u] = mfma_16x16x16_bf16(pr_h, q_l, accr[u]);
+                        acci[u] = mfma_16x16x16_bf16(pi_h, q_l, acci[u]);
+                        accr[u] = mfma_16x16x16_bf16(pr_l, q_h, accr[u]);
+                        acci[u] = mfma_16x16x16_bf16(pi_l, q_h, acci[u]);
+                    }
                 }
             }
         }

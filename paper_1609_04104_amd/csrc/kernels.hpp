@@ -18,6 +18,7 @@ struct Batch {
     bool kspace;                 // line masks on the k-space route (shared)
     bool want_x;                 // some frame asks for X_t
     bool want_sample;            // some frame draws its next rows
+    int synth;                   // synthesis operands (SYN_*), shared by the frames of an output launch
 };
 
 // Threads per block of the kernels that are not templated on a length.

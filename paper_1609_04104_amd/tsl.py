@@ -39,7 +39,8 @@ class TslError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("step_mode", ctypes.c_int), ("mu", ctypes.c_double), ("allow_lambda0", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64), ("line_route", ctypes.c_int)]
+                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64), ("line_route", ctypes.c_int),
+                ("synth_bf16", ctypes.c_int)]
 
 
 N_PHASES = 8
@@ -148,9 +149,13 @@ def selftest_codelets():
     return float(lib().tsl_selftest_codelets())
 
 
-def make_opts(step_mode="mm", mu=0.0, allow_lambda0=False, seed=0, stream_id=0, route="kspace"):
+SYNTH = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+
+
+def make_opts(step_mode="mm", mu=0.0, allow_lambda0=False, seed=0, stream_id=0, route="kspace", synth="fp32"):
     o = Opts()
     lib().tsl_opts_default(ctypes.byref(o))
+    o.synth_bf16 = SYNTH[synth]
     o.line_route = {"kspace": ROUTE_KSPACE, "frame": ROUTE_FRAME}[route]
     o.step_mode = {"mm": STEP_MM, "const": STEP_CONST}[step_mode]
     o.mu = float(mu)
@@ -183,9 +188,9 @@ class Sequence:
     """One scan's resident state (tsl_open ... tsl_close)."""
 
     def __init__(self, n1, n2, r, lam, A0, B0, step_mode="mm", mu=0.0, allow_lambda0=False,
-                 seed=0, stream_id=0, pool=None, stream=None, route="kspace"):
+                 seed=0, stream_id=0, pool=None, stream=None, route="kspace", synth="fp32"):
         self.n1, self.n2, self.r = int(n1), int(n2), int(r)
-        self.opts = make_opts(step_mode, mu, allow_lambda0, seed, stream_id, route)
+        self.opts = make_opts(step_mode, mu, allow_lambda0, seed, stream_id, route, synth)
         a = _dev(A0, torch.complex64, (n1, r), "A0")
         b = _dev(B0, torch.complex64, (n2, r), "B0")
         h = ctypes.c_void_p()
