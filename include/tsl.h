@@ -202,6 +202,36 @@ int tsl_push_points(tsl_seq* s, const uint8_t* mask, const tsl_c32* y,
 int tsl_sample_lines(tsl_seq* s, int K, int32_t* rows_out, int32_t* n_out,
                      int32_t* draws_out, double* prefix_out, void* stream);
 
+/* Batch processing of a stored scan in several passes (Sec. VI-D): E passes
+   over the T frames frames[0..T-1], pass e visiting them in the order
+   order[e*T] .. order[e*T + T - 1] (host int32; each pass a permutation of
+   0..T-1 -- the paper may reorder the frames at random between passes, so the
+   caller draws the permutations, e.g. the time order for the first pass).  The
+   state carries over from pass to pass (the subspace learnt in one pass starts
+   the next, and t counts every visit, as the recursion of eq. (6) does).  Each
+   visit is one step of Algorithm 3 exactly as tsl_push_frame; a frame's outputs
+   are rewritten at every visit, so after the call they hold those of its last
+   visit.  The frames of a stored scan draw no rows (K_next must be 0).
+   TSL_EINVAL, with nothing enqueued, for bad arguments or an order that is not
+   a permutation. */
+int tsl_epochs(tsl_seq* s, int T, const tsl_frame* frames, int E, const int32_t* order, void* stream);
+
+/* Draws the sample set of frame t+1 as single k-space entries by Algorithm 4
+   with the score of eq. (13): s(n1, n2) = (||abar_n1||^2 + ||bbar_n2||^2) /
+   (R (N1 + N2)), abar and bbar the rows of the column-normalised k-space
+   factors F_l A[t] and F_r B[t] (a zero column left out), drawn as the exact
+   two-component mixture of eq. (13) (probability N2/(N1+N2): row from
+   ||abar||^2, column uniform; else column from ||bbar||^2, row uniform).  K >= 1
+   trials with replacement; trial k takes the first three words w0..w2 of
+   Philox4x64-10 at counter (t+1, k, 1, 0), key (seed, stream_id), u = (w >> 11)
+   2^-53: component A iff u0 (N1+N2) < N2, the weighted index the first whose
+   inclusive prefix (float64, blocked order as tsl_sample_lines) exceeds u1 W,
+   the uniform one floor(u2 N) (clamped).  mask_out [n1][n2] uint8 receives 1
+   at the distinct points drawn and 0 elsewhere (the form tsl_push_points
+   takes), n_out [1] their count (<= K); draws_out [K] int32 (may be NULL) the
+   entry n1 * N2 + n2 of each trial. */
+int tsl_sample_points(tsl_seq* s, int K, uint8_t* mask_out, int32_t* n_out, int32_t* draws_out, void* stream);
+
 /* Pushes one frame described by a tsl_frame (the general form of
    tsl_push_lines / tsl_push_points, with device-side row counts, full-frame
    sample arrays and the next frame's row draw in the same call). */

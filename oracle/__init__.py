@@ -17,9 +17,11 @@ Informative Random Sampling for Real-Time MR Imaging", arXiv 1609.04104):
                   parallel factor updates of Algorithm 3; the output frame is
                   A[t] diag(gamma_t) B[t]^T as in Sec. IV-A.  A second, independent
                   formulation runs Algorithm 2 (k-space interpolation) on the
-                  transformed factors.
-* ``sampler``  -- Algorithm 4 (random subsampling) with the row-marginal score of
-                  Sec. VI-C, draws with replacement.
+                  transformed factors.  ``epochs`` runs the batch mode of
+                  Sec. VI-D: passes over stored frames, state carried over.
+* ``sampler``  -- Algorithm 4 (random subsampling): whole rows with the
+                  row-marginal score of Sec. VI-C, and single entries with the
+                  score of eq. 13; draws with replacement.
 * ``philox``   -- the Philox4x64-10 counter-based generator (Salmon, Moraes,
                   Dror, Shaw, SC'11), which supplies the sampler's uniforms.
 
@@ -31,15 +33,17 @@ docstrings next to the code that takes them.
 from .dft import dft_matrix, fft2_unitary, ifft2_unitary
 from .tsl import (TslOracle, KspaceOracle, regression_matrix, ridge_gamma,
                   ridge_gamma_svd, back_projection, step_alpha, gershgorin,
-                  instantaneous_cost, gram_pivot_ratio)
+                  instantaneous_cost, gram_pivot_ratio, epochs)
 from .sampler import (line_scores, line_weights_prefix, draw_lines, uniform_draws,
-                      point_scores, expected_count)
+                      point_scores, expected_count, point_weights_prefix, point_draw_probabilities,
+                      draw_points)
 from .philox import philox4x64_10
 
 __all__ = [
     "dft_matrix", "fft2_unitary", "ifft2_unitary", "TslOracle", "KspaceOracle",
     "regression_matrix", "ridge_gamma", "ridge_gamma_svd", "back_projection",
-    "step_alpha", "gershgorin", "instantaneous_cost", "gram_pivot_ratio", "line_scores",
+    "step_alpha", "gershgorin", "instantaneous_cost", "gram_pivot_ratio", "epochs", "line_scores",
     "line_weights_prefix", "draw_lines", "uniform_draws", "point_scores",
-    "expected_count", "philox4x64_10",
+    "expected_count", "point_weights_prefix", "point_draw_probabilities", "draw_points",
+    "philox4x64_10",
 ]

@@ -59,24 +59,31 @@ def blocked_prefix(w):
     return out
 
 
+def row_energy_weights(F):
+    """q_i = ||fbar_i||^2 for the column-normalised factor F ([n, R]): the sum
+    over columns of |F_ir|^2 / c_r with c_r = sum over rows of |F_ir|^2 (a zero
+    column's term is 0), both sums in the blocked order, from the complex64
+    values of F widened exactly."""
+    F = np.asarray(F)
+    re = F.real.astype(np.float64)
+    im = F.imag.astype(np.float64)
+    E = re * re + im * im                      # |F_ir|^2
+    n, R = E.shape
+    c = blocked_sum(E)                         # column energies, a sum over rows
+    T = np.zeros((R, n))
+    for r in range(R):
+        if c[r] > 0.0:
+            T[r] = E[:, r] / c[r]
+    return blocked_sum(T)
+
+
 def line_weights_prefix(Ahat, n2):
     """Unnormalised row weights w_i = N2 ||abar_i||^2 + R and their inclusive prefix.
 
     ``Ahat`` is the [N1, R] k-space row factor.  Returns (w, prefix), float64.
     """
-    Ahat = np.asarray(Ahat)
-    re = Ahat.real.astype(np.float64)
-    im = Ahat.imag.astype(np.float64)
-    E = re * re + im * im                      # |Ahat_ir|^2
-    n1, R = E.shape
-    c = blocked_sum(E)                         # column energies ||ahat_r||^2, a sum over rows
-    # ||abar_i||^2 after normalisation, a sum over columns (a zero column's term is 0)
-    T = np.zeros((R, n1))
-    for r in range(R):
-        if c[r] > 0.0:
-            T[r] = E[:, r] / c[r]
-    q = blocked_sum(T)
-    w = float(n2) * q
+    R = np.asarray(Ahat).shape[1]
+    w = float(n2) * row_energy_weights(Ahat)
     w = w + float(R)
     return w, blocked_prefix(w)
 
@@ -132,3 +139,56 @@ def expected_count(scores, K):
     """E|Omega_t| = sum over candidates of 1 - (1 - s)^K (Sec. V-B)."""
     s = np.asarray(scores, dtype=np.float64)
     return float(np.sum(1.0 - (1.0 - s) ** K))
+
+
+# ---------------------------------------------------------------- points (eq. 13)
+# Reading: eq. 13 is a two-component mixture.  With a_i = ||abar_i||^2 (rows of
+# the column-normalised F_l A) and b_j = ||bbar_j||^2 (rows of F_r B), both
+# summing to R, s(i, j) = (a_i + b_j) / (R (N1 + N2))
+#   = N2/(N1+N2) * (a_i / R) * (1/N2)  +  N1/(N1+N2) * (1/N1) * (b_j / R):
+# with probability N2/(N1+N2) the row follows a and the column is uniform,
+# otherwise the column follows b and the row is uniform.  Trial k of the mask
+# for frame t takes the three first words (w0, w1, w2) of Philox4x64-10 at
+# counter (t, k, 1, 0) (the 1 keeps point trials apart from the line trials'
+# counters) and u_m = (w_m >> 11) 2^-53: component A if u0 (N1 + N2) < N2, the
+# weighted index is the first one whose inclusive blocked prefix exceeds
+# u1 W (W the computed total, clamped to the last), the uniform one is
+# floor(u2 N) (clamped to N - 1).  Draws are with replacement; Omega is the set
+# of distinct points.
+
+def point_weights_prefix(Ahat, Bhat):
+    """(qa, prefix_a, qb, prefix_b): row weights of both factors and their
+    inclusive blocked prefixes."""
+    qa = row_energy_weights(Ahat)
+    qb = row_energy_weights(Bhat)
+    return qa, blocked_prefix(qa), qb, blocked_prefix(qb)
+
+
+def point_draw_probabilities(Ahat, Bhat):
+    """The probability of each (i, j) under the mixture above, from the
+    computed weights (equal to eq. 13 when no column is zero)."""
+    qa, pa, qb, pb = point_weights_prefix(Ahat, Bhat)
+    n1, n2 = qa.size, qb.size
+    wa, wb = n2 / (n1 + n2), n1 / (n1 + n2)
+    return wa * (qa / pa[-1])[:, None] / n2 + wb * (qb / pb[-1])[None, :] / n1
+
+
+def draw_points(Ahat, Bhat, K, seed, stream, t):
+    """Algorithm 4 on entries (eq. 13): K draws with replacement.  Returns
+    (mask [N1, N2] bool of the distinct points, draws [K, 2] int32 (i, j))."""
+    _, pa, _, pb = point_weights_prefix(Ahat, Bhat)
+    n1, n2 = pa.size, pb.size
+    mask = np.zeros((n1, n2), dtype=bool)
+    draws = np.empty((K, 2), dtype=np.int32)
+    for k in range(K):
+        w = philox4x64_10((t, k, 1, 0), (seed, stream))
+        u0, u1, u2 = (float(x >> 11) * 2.0 ** -53 for x in w[:3])
+        if u0 * float(n1 + n2) < float(n2):
+            i = min(int(np.searchsorted(pa, u1 * pa[-1], side="right")), n1 - 1)
+            j = min(int(np.floor(u2 * float(n2))), n2 - 1)
+        else:
+            j = min(int(np.searchsorted(pb, u1 * pb[-1], side="right")), n2 - 1)
+            i = min(int(np.floor(u2 * float(n1))), n1 - 1)
+        draws[k] = (i, j)
+        mask[i, j] = True
+    return mask, draws

@@ -261,3 +261,23 @@ class KspaceOracle:
         Xk = al_new @ np.diag(gamma) @ be_new.T
         return Step(t=t, gamma=gamma, alpha_f=al_new, beta_f=be_new, Xk=Xk,
                     alpha=alpha, alpha_bar=abar, mu=mu)
+
+
+def epochs(ora, frames, order):
+    """Batch processing of a stored scan in several passes (Sec. VI-D).
+
+    ``frames[k]`` is ("lines", rows, Y) or ("points", mask, Y); pass e visits
+    the frames in the order ``order[e]`` (a permutation of range(T)), each visit
+    one push of ``ora`` with its state carried over from the previous visit (the
+    subspace learnt in a pass starts the next one).  Returns the step of each
+    frame's last visit."""
+    T = len(frames)
+    last = [None] * T
+    for perm in order:
+        perm = [int(v) for v in perm]
+        if sorted(perm) != list(range(T)):
+            raise ValueError("each pass must be a permutation of range(T)")
+        for v in perm:
+            kind, sel, Y = frames[v]
+            last[v] = ora.push_lines(sel, Y) if kind == "lines" else ora.push_points(sel, Y)
+    return last

@@ -598,6 +598,44 @@ int tsl_push_frame(tsl_seq* s, const tsl_frame* frame, void* stream) {
     return run_groups({b}, st);
 }
 
+int tsl_epochs(tsl_seq* s, int T, const tsl_frame* frames, int E, const int32_t* order, void* stream) {
+    int rc = check_seq(s);
+    if (rc != TSL_OK) return rc;
+    if (T <= 0 || E <= 0 || !frames || !order) return fail(TSL_EINVAL, "bad epoch arguments");
+    for (int k = 0; k < T; ++k) {
+        if ((rc = check_frame(s, frames[k])) != TSL_OK) return rc;
+        if (frames[k].K_next != 0) return fail(TSL_EINVAL, "frames of a stored scan draw no rows (K_next must be 0)");
+    }
+    std::vector<int> seen(static_cast<size_t>(T), -1);
+    for (int e = 0; e < E; ++e)
+        for (int k = 0; k < T; ++k) {
+            const int v = order[size_t(e) * T + k];
+            if (v < 0 || v >= T || seen[size_t(v)] == e) return fail(TSL_EINVAL, "each pass must be a permutation of 0..T-1");
+            seen[size_t(v)] = e;
+        }
+    if ((rc = set_dev(s)) != TSL_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    s->last = st;
+    std::vector<tsl::FrameArgs> args(static_cast<size_t>(T));
+    for (int k = 0; k < T; ++k) args[size_t(k)] = frame_args(s, frames[k]);
+    for (int e = 0; e < E; ++e)
+        for (int k = 0; k < T; ++k) {
+            const int v = order[size_t(e) * T + k];
+            const tsl_frame& fr = frames[v];
+            tsl::Batch b{};
+            b.one = &args[size_t(v)];
+            b.count = 1;
+            b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r; b.mode = args[size_t(v)].mode;
+            b.kspace = args[size_t(v)].kspace != 0;
+            b.rows_max = fr.mask ? s->n1 : std::min(std::max(fr.n_rows, 0), s->n1);
+            b.want_x = fr.X_out != nullptr;
+            b.want_sample = false;
+            b.synth = s->opts.synth_bf16;
+            if ((rc = run_groups(&b, 1, st)) != TSL_OK) return rc;
+        }
+    return TSL_OK;
+}
+
 int tsl_push_lines(tsl_seq* s, int n_rows, const int32_t* rows, const tsl_c32* y, tsl_c32* X_out, tsl_c32* A_out,
                    tsl_c32* B_out, tsl_c32* gamma_out, void* stream) {
     tsl_frame f{};
@@ -634,6 +672,21 @@ int tsl_sample_lines(tsl_seq* s, int K, int32_t* rows_out, int32_t* n_out, int32
     b.want_sample = true;
     hipError_t e = tsl::launch_sample(b, st);
     if (e != hipSuccess) return hip_fail(e, "sample");
+    return TSL_OK;
+}
+
+int tsl_sample_points(tsl_seq* s, int K, uint8_t* mask_out, int32_t* n_out, int32_t* draws_out, void* stream) {
+    int rc = check_seq(s);
+    if (rc != TSL_OK) return rc;
+    if (K < 1) return fail(TSL_EINVAL, "K must be >= 1");
+    if (!mask_out || !n_out) return fail(TSL_EINVAL, "null mask_out or n_out");
+    if ((rc = set_dev(s)) != TSL_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    s->last = st;
+    tsl_frame fr{};
+    const tsl::FrameArgs a = frame_args(s, fr);
+    hipError_t e = tsl::launch_sample_points(a, K, mask_out, n_out, draws_out, st);
+    if (e != hipSuccess) return hip_fail(e, "sample points");
     return TSL_OK;
 }
 

@@ -1228,6 +1228,14 @@ __global__ void __launch_bounds__(kSampleThreads) k_sample(Src src) {
     draw_rows<kSampleThreads>(src.get(), s_l);
 }
 
+// The point draw (tsl_sample_points), one block.
+__global__ void __launch_bounds__(kPointThreads) k_sample_points(OneFrame src, int K, unsigned char* mask, int* n_out,
+                                                                 int* draws) {
+    __shared__ PointLds s_l;
+    const DevFrame f = src.get();
+    draw_points<kPointThreads>(f, K, mask, n_out, draws, s_l);
+}
+
 // packed factor, right-hand side / gamma, then 1/L_kk and |gamma_r| (R doubles each)
 size_t solve_lds(int R) { return size_t(R * (R + 1) / 2 + R) * sizeof(double2) + 2 * size_t(R) * sizeof(double); }
 
@@ -1322,6 +1330,12 @@ hipError_t launch_synth_out(const Batch& b, hipStream_t st) {
     };
     if (b.r_max <= kOutRC) with_bf(std::true_type{});
     else with_bf(std::false_type{});
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_points(const FrameArgs& a, int K, unsigned char* mask, int* n_out, int* draws,
+                                hipStream_t st) {
+    k_sample_points<<<1, kPointThreads, 0, st>>>(OneFrame{a}, K, mask, n_out, draws);
     return hipGetLastError();
 }
 

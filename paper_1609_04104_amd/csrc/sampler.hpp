@@ -70,6 +70,61 @@ __device__ __forceinline__ double energy(float2 a) {
     return ax * ax + ay * ay;
 }
 
+// Steps 1-2 of a draw for a factor F ([n][R], complex64): column energies
+// c_r = sum over rows of E_ir = |F_ir|^2 (FP64) -- thread (b, r) adds rows
+// [kSumBlock b, kSumBlock (b + 1)) of column r with all of its loads in flight
+// (coalesced over r, indices clamped into the factor, rows past n adding +0,
+// which leaves a nonnegative sum unchanged), the block sums meet in LDS and
+// thread r adds them in block order -- then, for every row i and column block
+// k, the sum of the terms E_ir / c_r of that block (a zero column's term is 0)
+// into part[i * ncb + k]; the caller adds a row's block sums in block order.
+// Ends with the block synchronised.
+template <int NT>
+__device__ __forceinline__ void row_weight_blocks(GlobalPtr<const float2> Fm, int n, int R, double* c_lds,
+                                                  double* part) {
+#pragma clang fp contract(off)
+    const int tid = threadIdx.x;
+    const int nblk = cdiv(n, kSumBlock), ncb = cdiv(R, kSumBlock);
+    const size_t last = size_t(n) * R - 1;
+    for (int p0 = 0; p0 < nblk * R; p0 += NT) {
+        const int p = p0 + tid, b = p / R, r = p % R;
+        float2 v[kSumBlock];
+#pragma unroll
+        for (int j = 0; j < kSumBlock; ++j) v[j] = Fm[min(size_t(b * kSumBlock + j) * R + r, last)];
+        double pt = 0.0;
+#pragma unroll
+        for (int j = 0; j < kSumBlock; ++j) {
+            const double e = energy(v[j]);
+            pt = pt + (b * kSumBlock + j < n ? e : 0.0);
+        }
+        if (p < nblk * R) part[p] = pt;
+    }
+    __syncthreads();
+    if (tid < R) {
+        double cr = 0.0;
+        for (int b = 0; b < nblk; ++b) cr = cr + part[b * R + tid];
+        c_lds[tid] = cr;
+    }
+    __syncthreads();
+    for (int p0 = 0; p0 < n * ncb; p0 += NT) {
+        const int p = p0 + tid, i = min(p / ncb, n - 1), k = p % ncb;
+        const size_t row0 = size_t(i) * R;
+        float2 v[kSumBlock];
+#pragma unroll
+        for (int j = 0; j < kSumBlock; ++j) v[j] = Fm[row0 + min(k * kSumBlock + j, R - 1)];
+        double pt = 0.0;
+#pragma unroll
+        for (int j = 0; j < kSumBlock; ++j) {
+            const int r = k * kSumBlock + j;
+            const double cc = c_lds[min(r, R - 1)];
+            const double t = energy(v[j]) / (cc > 0.0 ? cc : 1.0);
+            pt = pt + ((r < R && cc > 0.0) ? t : 0.0);
+        }
+        if (p < n * ncb) part[p] = pt;
+    }
+    __syncthreads();
+}
+
 // With parts_ready, the A update of this frame has left every row's block sums
 // over the column blocks (wq[k][i], the terms E_ir / c_r of column block k in
 // the order of step 2 below) and steps 1-2 reduce to adding them in block order;
@@ -85,7 +140,6 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L, bool 
     GlobalPtr<const float2> Ah = f.Ahat;
     const uint64_t t_next = uint64_t(f.dev->t + 1);
     const int nblk = cdiv(n1, kSumBlock), ncb = cdiv(R, kSumBlock);
-    const size_t last = size_t(n1) * R - 1;
     if (parts_ready) {
         for (int i = tid; i < n1; i += NT) {
             double part[TSL_MAX_R / kSumBlock];
@@ -104,53 +158,8 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L, bool 
         __syncthreads();
     } else {
 
-    // 1. Column energies c_r = sum over rows of E_ir = |Ahat_ir|^2 (FP64): thread
-    //    (b, r) adds rows [kSumBlock b, kSumBlock (b + 1)) of column r with all of
-    //    its loads in flight (coalesced over r, indices clamped into the factor,
-    //    rows past n1 adding +0, which leaves a nonnegative sum unchanged); the
-    //    block sums meet in LDS and thread r adds them in block order.
-    for (int p0 = 0; p0 < nblk * R; p0 += NT) {
-        const int p = p0 + tid, b = p / R, r = p % R;
-        float2 v[kSumBlock];
-#pragma unroll
-        for (int j = 0; j < kSumBlock; ++j) v[j] = Ah[min(size_t(b * kSumBlock + j) * R + r, last)];
-        double part = 0.0;
-#pragma unroll
-        for (int j = 0; j < kSumBlock; ++j) {
-            const double e = energy(v[j]);
-            part = part + (b * kSumBlock + j < n1 ? e : 0.0);
-        }
-        if (p < nblk * R) L.part[p] = part;
-    }
+    row_weight_blocks<NT>(Ah, n1, R, L.c, L.part);
     for (int i = tid; i < n1; i += NT) L.mark[i] = 0;
-    __syncthreads();
-    if (tid < R) {
-        double c = 0.0;
-        for (int b = 0; b < nblk; ++b) c = c + L.part[b * R + tid];
-        L.c[tid] = c;
-    }
-    __syncthreads();
-
-    // 2. w_i = N2 q_i + R with q_i = sum over columns of E_ir / c_r (a zero
-    //    column's term is 0): thread (i, k) adds the terms of column block k of
-    //    row i (loads and divisions side by side), the block sums meet in LDS
-    //    and thread i adds them in block order.
-    for (int p0 = 0; p0 < n1 * ncb; p0 += NT) {
-        const int p = p0 + tid, i = min(p / ncb, n1 - 1), k = p % ncb;
-        const size_t row0 = size_t(i) * R;
-        float2 v[kSumBlock];
-#pragma unroll
-        for (int j = 0; j < kSumBlock; ++j) v[j] = Ah[row0 + min(k * kSumBlock + j, R - 1)];
-        double part = 0.0;
-#pragma unroll
-        for (int j = 0; j < kSumBlock; ++j) {
-            const int r = k * kSumBlock + j;
-            const double c = L.c[min(r, R - 1)];
-            const double t = energy(v[j]) / (c > 0.0 ? c : 1.0);
-            part = part + ((r < R && c > 0.0) ? t : 0.0);
-        }
-        if (p < n1 * ncb) L.part[p] = part;
-    }
     __syncthreads();
     for (int i = tid; i < n1; i += NT) {
         double q = 0.0;
@@ -233,6 +242,118 @@ __device__ __forceinline__ void draw_rows(const DevFrame& f, SampleLds& L, bool 
     }
     if (f.prefix_next)
         for (int i = tid; i < n1; i += NT) f.prefix_next[i] = L.pref[i];
+}
+
+// ---------------------------------------------------------------- points (eq. 13)
+// Algorithm 4 on entries.  With a_i = ||abar_i||^2 over the rows of the
+// column-normalised F_l A and b_j = ||bbar_j||^2 over those of F_r B (each
+// summing to R), eq. 13 is the mixture s(i, j) = N2/(N1+N2) (a_i/R)(1/N2) +
+// N1/(N1+N2) (1/N1)(b_j/R).  Trial k for frame t takes the first three Philox
+// words at counter (t, k, 1, 0), u_m = (w_m >> 11) 2^-53: component A if
+// u0 (N1 + N2) < N2, the weighted index the first whose inclusive blocked
+// prefix exceeds u1 W (clamped to the last), the other floor(u2 N) (clamped to
+// N - 1).  The distinct points are marked in an LDS bitmap; the mask is written
+// from it and their count is its population count.
+constexpr int kPointThreads = 512;
+struct alignas(16) PointLds {
+    double pa[kMaxN], pb[kMaxN];      // row weights of F_l A and F_r B, then their inclusive prefixes
+    double c[TSL_MAX_R];
+    double part[kMaxBlk * TSL_MAX_R];
+    double tot[2][kMaxBlk];
+    unsigned bits[kMaxN * kMaxN / 32];
+    int cnt[kPointThreads / 64];
+};
+
+template <int NT>
+__device__ __forceinline__ void blocked_scan(double* w, int n, double* tot) {
+#pragma clang fp contract(off)
+    const int tid = threadIdx.x, nblk = cdiv(n, kSumBlock);
+    if (tid < nblk) {
+        const int i0 = tid * kSumBlock, ni = min(kSumBlock, n - i0);
+        double run = 0.0;
+        for (int j = 0; j < ni; ++j) {
+            run = run + w[i0 + j];
+            w[i0 + j] = run;
+        }
+        tot[tid] = run;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double before = 0.0;
+        for (int b = 0; b < nblk; ++b) {
+            const double t = tot[b];
+            tot[b] = before;
+            before = before + t;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) w[i] = tot[i / kSumBlock] + w[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ int first_above(const double* pref, int n, double target) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (target < pref[mid]) hi = mid; else lo = mid + 1;
+    }
+    return lo < n ? lo : n - 1;
+}
+
+template <int NT>
+__device__ __forceinline__ void draw_points(const DevFrame& f, int K, unsigned char* __restrict__ mask,
+                                            int* __restrict__ n_out, int* __restrict__ draws, PointLds& L) {
+#pragma clang fp contract(off)
+    const int n1 = f.n1, n2 = f.n2, R = f.r, tid = threadIdx.x;
+    const int ncb = cdiv(R, kSumBlock), nbits = n1 * n2, nwords = cdiv(nbits, 32);
+    const uint64_t t_next = uint64_t(f.dev->t + 1);
+    for (int w = tid; w < nwords; w += NT) L.bits[w] = 0u;
+    GlobalPtr<const float2> facs[2] = {f.Ahat, f.Bhat};
+    double* outs[2] = {L.pa, L.pb};
+    const int ns[2] = {n1, n2};
+    for (int which = 0; which < 2; ++which) {
+        row_weight_blocks<NT>(facs[which], ns[which], R, L.c, L.part);
+        for (int i = tid; i < ns[which]; i += NT) {
+            double q = 0.0;
+            for (int k = 0; k < ncb; ++k) q = q + L.part[i * ncb + k];
+            outs[which][i] = q;
+        }
+        __syncthreads();
+        blocked_scan<NT>(outs[which], ns[which], L.tot[which]);
+    }
+    const double Wa = L.pa[n1 - 1], Wb = L.pb[n2 - 1];
+    for (int k = tid; k < K; k += NT) {
+        uint64_t x[4] = {t_next, uint64_t(k), 1ull, 0ull};
+        philox4x64_10(x, f.seed, f.sid);
+        const double u0 = double(x[0] >> 11) * 0x1.0p-53, u1 = double(x[1] >> 11) * 0x1.0p-53;
+        const double u2 = double(x[2] >> 11) * 0x1.0p-53;
+        int i, j;
+        if (u0 * double(n1 + n2) < double(n2)) {
+            i = first_above(L.pa, n1, u1 * Wa);
+            j = min(int(floor(u2 * double(n2))), n2 - 1);
+        } else {
+            j = first_above(L.pb, n2, u1 * Wb);
+            i = min(int(floor(u2 * double(n1))), n1 - 1);
+        }
+        const int e = i * n2 + j;
+        if (draws) draws[k] = e;
+        atomicOr(&L.bits[e >> 5], 1u << (e & 31));
+    }
+    __syncthreads();
+    int mine = 0;
+    for (int e = tid; e < nbits; e += NT) {
+        const unsigned on = (L.bits[e >> 5] >> (e & 31)) & 1u;
+        mask[e] = static_cast<unsigned char>(on);
+        mine += int(on);
+    }
+    for (int m = 32; m > 0; m >>= 1) mine += __shfl_xor(mine, m, 64);
+    if (tid % 64 == 0) L.cnt[tid / 64] = mine;
+    __syncthreads();
+    if (tid == 0) {
+        int total = 0;
+        for (int w = 0; w < NT / 64; ++w) total += L.cnt[w];
+        n_out[0] = total;
+    }
 }
 
 }  // namespace tsl

@@ -23,7 +23,7 @@ _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOTPD: "ENOTP
 EXPORTS = [
     "tsl_opts_default", "tsl_size_supported", "tsl_footprint", "tsl_open", "tsl_close",
     "tsl_push_lines", "tsl_push_points", "tsl_push_frame", "tsl_sample_lines", "tsl_step_many",
-    "tsl_step_many_noalloc",
+    "tsl_step_many_noalloc", "tsl_epochs", "tsl_sample_points",
     "tsl_step_many_timed", "tsl_batch_create", "tsl_batch_launch", "tsl_batch_destroy", "tsl_status",
     "tsl_get_factors", "tsl_get_state", "tsl_set_state", "tsl_shape", "tsl_fft2",
     "tsl_pool_create", "tsl_pool_destroy", "tsl_pool_used", "tsl_open_in_pool",
@@ -81,6 +81,8 @@ def lib():
             "tsl_push_points": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
             "tsl_sample_lines": (i, [vp, i, vp, vp, vp, vp, vp]),
             "tsl_push_frame": (i, [vp, P(Frame), vp]),
+            "tsl_epochs": (i, [vp, i, P(Frame), i, vp, vp]),
+            "tsl_sample_points": (i, [vp, i, vp, vp, vp, vp]),
             "tsl_step_many": (i, [P(vp), i, P(Frame), vp]),
             "tsl_step_many_noalloc": (i, [P(vp), i, P(Frame), vp]),
             "tsl_step_many_timed": (i, [P(vp), i, P(Frame), P(d), vp]),
@@ -229,6 +231,12 @@ class Sequence:
                                       _dev(prefix_out, torch.float64, (self.n1,), "prefix_out"),
                                       _stream(stream)))
 
+    def sample_points(self, K, mask_out, n_out, draws_out=None, stream=None):
+        """tsl_sample_points: the entries of frame t+1 drawn by eq. (13)."""
+        _check(lib().tsl_sample_points(self.h, int(K), _dev(mask_out, torch.uint8, (self.n1, self.n2), "mask_out"),
+                                       _dev(n_out, torch.int32, (1,), "n_out"),
+                                       _dev(draws_out, torch.int32, (K,), "draws_out"), _stream(stream)))
+
     def frame(self, rows=None, y=None, mask=None, X_out=None, A_out=None, B_out=None, gamma_out=None,
               n_rows_dev=None, y_full=False, K_next=0, rows_next=None, n_next=None, info_out=None):
         """A tsl_frame for push_frame / step_many (keeps the tensors alive on the struct).
@@ -260,6 +268,17 @@ class Sequence:
     def push(self, frame, stream=None):
         """tsl_push_frame with a Frame from self.frame(...)."""
         _check(lib().tsl_push_frame(self.h, ctypes.byref(frame), _stream(stream)))
+
+    def epochs(self, frames, order, stream=None):
+        """tsl_epochs: passes over the stored frames (Frames from self.frame(...));
+        order is an integer array [E, T], each row a permutation of range(T)."""
+        import numpy as np
+        order = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+        if order.ndim != 2 or order.shape[1] != len(frames):
+            raise ValueError("order must be [E, T] with T = len(frames)")
+        fs = (Frame * len(frames))(*frames)
+        _check(lib().tsl_epochs(self.h, len(frames), fs, order.shape[0], order.ctypes.data_as(ctypes.c_void_p),
+                                _stream(stream)))
 
     # ---------------------------------------------------------------- state
     def status(self, clear=False):

@@ -191,6 +191,15 @@ hipError_t launch_stats(const Batch& b, hipStream_t st) { return run_group(b, st
 hipError_t launch_solve(const Batch& b, hipStream_t st) { return run_group(b, st, P_SOLVE); }
 hipError_t launch_synth_out(const Batch& b, hipStream_t st) { return run_group(b, st, P_OUT); }
 hipError_t launch_sample(const Batch& b, hipStream_t st) { return run_group(b, st, P_SAMPLE); }
+hipError_t launch_sample_points(const FrameArgs& a, int K, unsigned char* mask, int* n_out, int* draws,
+                                hipStream_t st) {
+    issue(st, [a, K, mask, n_out, draws]() {
+        touch(a.Ahat, size_t(a.n1) * a.r); touch(a.Bhat, size_t(a.n2) * a.r); touch(a.dev, 1);
+        touch(mask, size_t(a.n1) * a.n2); touch(n_out, 1);
+        if (draws) touch(draws, size_t(K));
+    }, false);
+    return hipSuccess;
+}
 hipError_t launch_rowfft(int n1, int n2, int batch, const float2* in, float2* out, bool, hipStream_t st) {
     issue(st, [=]() { touch(in, size_t(batch) * n1 * n2); touch(out, size_t(batch) * n1 * n2); }, false);
     return hipSuccess;

@@ -298,3 +298,34 @@ def test_served_scans_match_oracle(T):
                 print(f"note: scan {sp['scan']} frame {t + 2}: oracle's own draw differs", flush=True)
             rows = drawn if t + 1 >= warm else np.arange(n, dtype=np.int32)
     print("served worst X NRMSE per (scan, N, R):", {k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+
+
+# ---------------------------------------------------------------------------- batch passes (Sec. VI-D)
+@pytest.mark.parametrize("route", ["kspace", "frame"])
+def test_epochs_match_oracle(T, route):
+    """Three passes over ten stored frames (time order, then two seeded
+    permutations) of a 128 x 128, R = 16 scan with variable-density lines: every
+    frame's last reconstruction and the final factors against the oracle."""
+    c = I.config2(T=10, n1=128, n2=128, r=16, seq=5)
+    n, r, lam = 128, 16, 0.05
+    rng = np.random.default_rng(8)
+    order = np.stack([np.arange(10)] + [rng.permutation(10) for _ in range(2)]).astype(np.int32)
+    dev = torch.device("cuda:0")
+    q = T.Sequence(n, n, r, lam, torch.from_numpy(c["A0"]).to(dev), torch.from_numpy(c["B0"]).to(dev), route=route)
+    Xs = [torch.empty(n, n, dtype=torch.complex64, device=dev) for _ in c["frames"]]
+    frames = [q.frame(rows=torch.from_numpy(fr.rows).to(dev), y=torch.from_numpy(fr.y).to(dev), X_out=X)
+              for fr, X in zip(c["frames"], Xs)]
+    print(f"epochs: 3 passes over 10 frames, route {route}", flush=True)
+    q.epochs(frames, order)
+    o = oracle.TslOracle(n, n, r, lam, c["A0"], c["B0"])
+    last = oracle.epochs(o, [("lines", fr.rows, fr.y) for fr in c["frames"]], order)
+    A_ = torch.empty(n, r, dtype=torch.complex64, device=dev)
+    B_ = torch.empty(n, r, dtype=torch.complex64, device=dev)
+    q.factors(A=A_, B=B_)
+    errs = [nr(host(X), s.X) for X, s in zip(Xs, last)] + [nr(host(A_), o.A), nr(host(B_), o.B)]
+    print(f"epochs worst NRMSE {max(errs):.2e}", flush=True)
+    assert max(errs) <= TOL, errs
+    with pytest.raises(T.TslError):
+        q.epochs(frames, np.array([[0] * 10], dtype=np.int32))   # not a permutation
+    assert q.status() == 0
+    q.close()

@@ -602,3 +602,60 @@ def test_frame_info_matches_oracle(T, n1, n2, r, nrows, kind):
     print(f"frame info worst relative error {worst:.2e}, last pivot ratio {got[3]:.3e}", flush=True)
     assert seq.status() == 0
     seq.close()
+
+
+# ---------------------------------------------------------------------------- point sampling (eq. 13)
+@pytest.mark.parametrize("n1,n2,r,K", [(64, 64, 8, 1024), (120, 200, 5, 500), (256, 256, 32, 8192),
+                                       (512, 64, 128, 300), (8, 16, 3, 40)])
+def test_point_sampler_bit_exact_on_device_factors(T, n1, n2, r, K):
+    """tsl_sample_points draws from the device's F_l A and F_r B exactly what
+    the oracle's point sampler draws from the same (exported) factors."""
+    print(f"point sampler {n1}x{n2} r={r} K={K}", flush=True)
+    rng, A0, B0 = _random_state(n1, n2, r, 3 * n1 + n2 + r)
+    seq = T.Sequence(n1, n2, r, 0.05, dev(A0), dev(B0), seed=2024, stream_id=r)
+    for _ in range(2):
+        mask = rng.random((n1, n2)) < 0.3
+        seq.push_points(dev(mask.astype(np.uint8)), dev(cn(rng, (n1, n2), 50.0 / (n1 * n2)).astype(np.complex64)))
+    m = torch.zeros(n1, n2, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    dr = torch.zeros(K, dtype=torch.int32, device="cuda")
+    seq.sample_points(K, m, cnt, draws_out=dr)
+    Ah = torch.zeros(n1, r, dtype=torch.complex64, device="cuda")
+    Bh = torch.zeros(n2, r, dtype=torch.complex64, device="cuda")
+    seq.factors(Ahat=Ah, Bhat=Bh)
+    want_mask, want_draws = oracle.draw_points(host(Ah), host(Bh), K, 2024, r, 3)
+    assert np.array_equal(host(dr), want_draws[:, 0] * n2 + want_draws[:, 1])
+    assert np.array_equal(host(m).astype(bool), want_mask)
+    assert int(host(cnt)[0]) == int(want_mask.sum())
+    assert seq.status() == 0
+    seq.close()
+
+
+def test_point_sampled_trajectory_matches_oracle(T):
+    """Six frames of the 64 x 64, R = 8 low-rank sequence, each acquired at the
+    entries the device drew from the previous frame's factors (the first frame
+    at a uniform 25 % mask): masks equal the oracle's draw bit for bit and the
+    outputs meet the parity bar."""
+    c = I.config1(T=6)
+    n, r, K = 64, 8, 1024
+    ora = oracle.TslOracle(n, n, r, 0.1, c["A0"], c["B0"])
+    seq = T.Sequence(n, n, r, 0.1, dev(c["A0"]), dev(c["B0"]), seed=5, stream_id=9)
+    o = Outs(n, n, r)
+    m = torch.zeros(n, n, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Ah = torch.zeros(n, r, dtype=torch.complex64, device="cuda")
+    Bh = torch.zeros(n, r, dtype=torch.complex64, device="cuda")
+    mask = c["frames"][0].mask
+    for t, fr in enumerate(c["frames"]):
+        full = np.fft.fft2(fr.truth, norm="ortho").astype(np.complex64)      # the frame's k-space
+        s = ora.push_points(mask, full)
+        seq.push_points(dev(mask.astype(np.uint8)), dev(full), **o.kw())
+        compare_step(o, s, f"t={t + 1}")
+        seq.sample_points(K, m, cnt)
+        seq.factors(Ahat=Ah, Bhat=Bh)
+        want, _ = oracle.draw_points(host(Ah), host(Bh), K, 5, 9, t + 2)
+        got = host(m).astype(bool)
+        assert np.array_equal(got, want) and int(host(cnt)[0]) == int(want.sum())
+        mask = got
+    assert seq.status() == 0
+    seq.close()

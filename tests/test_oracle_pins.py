@@ -567,3 +567,94 @@ def test_pivot_ratio_two_by_two_closed_form():
     d2 = c - abs(b) ** 2 / a
     want = max(a, d2) / min(a, d2)
     assert abs(oracle.gram_pivot_ratio(G) - want) <= 1e-12 * want
+
+
+# ---------------------------------------------------------------------------- batch passes (Sec. VI-D)
+def _epoch_case(E, lam=1e-3):
+    c = I.config1(T=6, exact=True, perturb=3e-2)
+    frames = [("points", fr.mask, fr.y) for fr in c["frames"]]
+    rng = _rng(60)
+    order = [np.arange(6)] + [rng.permutation(6) for _ in range(E - 1)]
+    o = oracle.TslOracle(c["n1"], c["n2"], c["r"], lam, c["A0"], c["B0"])
+    last = oracle.epochs(o, frames, order)
+    err = float(np.mean([_nr(s.X, fr.truth) ** 2 for s, fr in zip(last, c["frames"])]))
+    return o, last, err, order, frames, c
+
+
+def test_epochs_carry_the_subspace_from_pass_to_pass():
+    """Noiseless rank-R frames, every point sampled, started off the true
+    factors: later passes start from what earlier ones learnt, so the mean NMSE
+    of the frames' last reconstructions falls with the number of passes (a
+    restart at every pass would leave it where one pass leaves it)."""
+    errs = [_epoch_case(E)[2] for E in (1, 2, 4)]
+    assert errs[1] < 0.9 * errs[0] and errs[2] < 0.9 * errs[1], errs
+
+
+def test_epochs_are_the_pushes_in_pass_order():
+    """Two passes in one call equal the same visits pushed one by one, and t
+    counts every visit (12 after two passes over six frames)."""
+    o, last, _, order, frames, c = _epoch_case(2)
+    ref = oracle.TslOracle(c["n1"], c["n2"], c["r"], 1e-3, c["A0"], c["B0"])
+    for perm in order:
+        for v in perm:
+            s = ref.push_points(frames[v][1], frames[v][2])
+    assert o.t == 12 and ref.t == 12
+    assert np.array_equal(o.A, ref.A) and np.array_equal(o.B, ref.B) and o.abar == ref.abar
+    assert np.array_equal(last[order[-1][-1]].X, s.X)
+
+
+def test_epochs_reject_an_order_that_is_not_a_permutation():
+    c = I.config1(T=3)
+    frames = [("points", fr.mask, fr.y) for fr in c["frames"]]
+    o = oracle.TslOracle(c["n1"], c["n2"], c["r"], 0.1, c["A0"], c["B0"])
+    with pytest.raises(ValueError):
+        oracle.epochs(o, frames, [[0, 1, 1]])
+
+
+# ---------------------------------------------------------------------------- point sampling (eq. 13)
+def test_point_mixture_is_the_score_of_eq13():
+    """The two-component mixture the point draw uses assigns every entry the
+    probability eq. 13 gives it (and the probabilities sum to one); the mixture
+    weights swapped would not."""
+    rng = _rng(71)
+    Ah, Bh = _cn(rng, (9, 3)), _cn(rng, (7, 3))
+    s13 = oracle.point_scores(Ah, Bh)
+    mix = oracle.point_draw_probabilities(Ah, Bh)
+    assert abs(s13.sum() - 1.0) < 1e-13 and abs(mix.sum() - 1.0) < 1e-13
+    assert np.max(np.abs(mix - s13)) < 1e-15
+    qa, pa, qb, pb = oracle.point_weights_prefix(Ah, Bh)
+    n1, n2 = 9, 7
+    swapped = (n1 / (n1 + n2)) * (qa / pa[-1])[:, None] / n2 + (n2 / (n1 + n2)) * (qb / pb[-1])[None, :] / n1
+    assert np.max(np.abs(swapped - s13)) > 1e-3
+
+
+def test_point_draws_follow_eq13_and_expected_count():
+    rng = _rng(72)
+    n1, n2, R, K = 6, 5, 2, 12
+    Ah = _cn(rng, (n1, R)) * np.exp(-0.4 * np.arange(n1))[:, None]
+    Bh = _cn(rng, (n2, R)) * np.exp(-0.3 * np.arange(n2))[:, None]
+    s = oracle.point_scores(Ah, Bh)
+    freq, counts = np.zeros((n1, n2)), []
+    n_frames = 1500
+    for t in range(1, n_frames + 1):
+        mask, draws = oracle.draw_points(Ah, Bh, K, seed=3, stream=1, t=t)
+        counts.append(int(mask.sum()))
+        np.add.at(freq, (draws[:, 0], draws[:, 1]), 1)
+        assert set(map(tuple, draws.tolist())) == set(zip(*np.nonzero(mask)))
+    exp = s * K * n_frames
+    chi2 = float(np.sum((freq - exp) ** 2 / exp))
+    import scipy.stats
+    assert chi2 < scipy.stats.chi2.ppf(1 - 1e-4, n1 * n2 - 1)
+    counts = np.array(counts, float)
+    mean, se = counts.mean(), counts.std(ddof=1) / np.sqrt(n_frames)
+    assert abs(mean - oracle.expected_count(s, K)) < 2.58 * se + 1e-9     # E|Omega| of Sec. V-B
+
+
+def test_point_draws_skip_a_zero_column():
+    rng = _rng(73)
+    Ah, Bh = _cn(rng, (8, 3)), _cn(rng, (6, 3))
+    Ah[:, 1] = 0
+    mix = oracle.point_draw_probabilities(Ah, Bh)
+    assert np.all(np.isfinite(mix)) and abs(mix.sum() - 1.0) < 1e-13
+    mask, draws = oracle.draw_points(Ah.astype(np.complex64), Bh.astype(np.complex64), 20, 1, 2, 3)
+    assert mask.sum() >= 1 and np.all(draws >= 0) and np.all(draws[:, 0] < 8) and np.all(draws[:, 1] < 6)
