@@ -19,6 +19,8 @@ Informative Random Sampling for Real-Time MR Imaging", arXiv 1609.04104):
                   formulation runs Algorithm 2 (k-space interpolation) on the
                   transformed factors.  ``epochs`` runs the batch mode of
                   Sec. VI-D: passes over stored frames, state carried over.
+                  ``CoilOracle`` is Algorithm 3 with C coils and sensitivity
+                  maps (Sec. IV-B), line masks.
 * ``sampler``  -- Algorithm 4 (random subsampling): whole rows with the
                   row-marginal score of Sec. VI-C, and single entries with the
                   score of eq. 13; draws with replacement.
@@ -33,7 +35,8 @@ docstrings next to the code that takes them.
 from .dft import dft_matrix, fft2_unitary, ifft2_unitary
 from .tsl import (TslOracle, KspaceOracle, regression_matrix, ridge_gamma,
                   ridge_gamma_svd, back_projection, step_alpha, gershgorin,
-                  instantaneous_cost, gram_pivot_ratio, epochs)
+                  instantaneous_cost, gram_pivot_ratio, epochs, CoilOracle,
+                  coil_regression_matrix, coil_gain)
 from .sampler import (line_scores, line_weights_prefix, draw_lines, uniform_draws,
                       point_scores, expected_count, point_weights_prefix, point_draw_probabilities,
                       draw_points)
@@ -42,7 +45,8 @@ from .philox import philox4x64_10
 __all__ = [
     "dft_matrix", "fft2_unitary", "ifft2_unitary", "TslOracle", "KspaceOracle",
     "regression_matrix", "ridge_gamma", "ridge_gamma_svd", "back_projection",
-    "step_alpha", "gershgorin", "instantaneous_cost", "gram_pivot_ratio", "epochs", "line_scores",
+    "step_alpha", "gershgorin", "instantaneous_cost", "gram_pivot_ratio", "epochs", "CoilOracle",
+    "coil_regression_matrix", "coil_gain", "line_scores",
     "line_weights_prefix", "draw_lines", "uniform_draws", "point_scores",
     "expected_count", "point_weights_prefix", "point_draw_probabilities", "draw_points",
     "philox4x64_10",

@@ -281,3 +281,80 @@ def epochs(ora, frames, order):
             kind, sel, Y = frames[v]
             last[v] = ora.push_lines(sel, Y) if kind == "lines" else ora.push_points(sel, Y)
     return last
+
+
+# ---------------------------------------------------------------- several coils (Sec. IV-B)
+def coil_regression_matrix(A, B, H, rows, Fl, Fr):
+    """[Phi]_{(c, i, j), r} = [F(H_c .* (a_r b_r^T))]_{ij} for the sampled rows
+    (every column of each), coils stacked in order (Algorithm 3, S1).  H is
+    [C, N1, N2]; returns [C * len(rows) * N2, R]."""
+    C = H.shape[0]
+    R = A.shape[1]
+    out = []
+    for c in range(C):
+        cols = [(Fl @ (H[c] * np.outer(A[:, r], B[:, r])) @ Fr)[rows, :].reshape(-1) for r in range(R)]
+        out.append(np.stack(cols, axis=1))
+    return np.concatenate(out, axis=0)
+
+
+def coil_gain(H):
+    """max over pixels of sum_c |H_c|^2: the factor by which the coil-weighted
+    sampling can stretch a frame's norm (1 for a single all-ones map)."""
+    return float(np.max(np.sum(np.abs(H) ** 2, axis=0)))
+
+
+class CoilOracle:
+    """Algorithm 3 with C coils and sensitivity maps H_c (Sec. IV-B), line masks.
+
+    Per frame: Phi from F(H_c .* (a_r b_r^T)) at the sampled rows of every coil,
+    gamma the ridge solution over all coils' samples, the residual e_c per coil,
+    Theta = sum_c conj(H_c) .* F^{-1}(Xi_c) (Xi_c the zero-filled residual of
+    coil c) and the S2 updates of Algorithm 3 from the factors at t-1.  Step
+    size (reading): alpha_t = lambda/t + g max(Gersh(G^H B^H B G), Gersh(G^H A^H A G))
+    with g = max over pixels of sum_c |H_c|^2, which bounds the factor-block
+    Lipschitz constant since ||P F(H_c .* X)|| <= ||H_c .* X|| and
+    sum_c ||H_c .* X||^2 <= g ||X||^2; with one all-ones map it is the
+    single-coil rule.  Output X_t = A[t] diag(gamma_t) B[t]^T."""
+
+    def __init__(self, n1, n2, r, lam, A0, B0, H, step_mode="mm", mu=None):
+        self.n1, self.n2, self.r, self.lam = int(n1), int(n2), int(r), float(lam)
+        self.A = np.array(A0, dtype=np.complex128).reshape(n1, r)
+        self.B = np.array(B0, dtype=np.complex128).reshape(n2, r)
+        self.H = np.array(H, dtype=np.complex128).reshape(-1, n1, n2)
+        self.C = self.H.shape[0]
+        self.step_mode, self.mu_const = step_mode, mu
+        self.abar, self.t = 0.0, 0
+        self.Fl, self.Fr = dft_matrix(self.n1), dft_matrix(self.n2)
+        self.gain = coil_gain(self.H)
+
+    def kspace_factors(self):
+        return self.Fl @ self.A, self.Fr @ self.B
+
+    def push_lines(self, rows, Y):
+        """``Y`` is [C, len(rows), n2]: Y[c, s] the samples of row rows[s] at coil c."""
+        rows = _check_lines(rows, self.n1)
+        Y = np.asarray(Y).reshape(self.C, rows.size, self.n2).astype(np.complex128)
+        if not np.all(np.isfinite(Y)):
+            raise NonFinite("non-finite sample")
+        t = self.t + 1
+        A, B, lam = self.A, self.B, self.lam
+        Phi = coil_regression_matrix(A, B, self.H, rows, self.Fl, self.Fr)
+        y = Y.reshape(-1)
+        gamma, G, h = ridge_gamma(Phi, y, lam)
+        e = (y - Phi @ gamma).reshape(self.C, rows.size, self.n2)
+        Theta = np.zeros((self.n1, self.n2), dtype=np.complex128)
+        for c in range(self.C):
+            Xi = np.zeros((self.n1, self.n2), dtype=np.complex128)
+            Xi[rows, :] = e[c]
+            Theta += np.conj(self.H[c]) * back_projection(Xi, self.Fl, self.Fr)
+        alpha = lam / t + self.gain * (step_alpha(A, B, gamma, 0.0, t))
+        abar = self.abar + alpha
+        mu = 1.0 / abar if self.step_mode == "mm" else float(self.mu_const)
+        shrink = 1.0 - lam * mu / t
+        cg = np.conj(gamma)[None, :]
+        A_new = shrink * A + mu * (Theta @ np.conj(B)) * cg
+        B_new = shrink * B + mu * (Theta.T @ np.conj(A)) * cg
+        X = A_new @ np.diag(gamma) @ B_new.T
+        self.A, self.B, self.abar, self.t = A_new, B_new, abar, t
+        return Step(t=t, gamma=gamma, G=G, h=h, e=e, Theta=Theta, alpha=alpha, alpha_bar=abar, mu=mu,
+                    shrink=shrink, A=A_new, B=B_new, X=X, Phi=Phi, y=y)

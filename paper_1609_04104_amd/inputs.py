@@ -311,3 +311,50 @@ def serving_specs(n_scans=128, rate=16.0, sizes=(128, 160, 192, 256, 320, 384), 
         A0, B0 = init_factors(n, n, r, rng_for(seed_config, s, 3))
         out.append(dict(scan=s, n=n, r=r, arrival=float(arrivals[s]), A0=A0, B0=B0))
     return out
+
+
+def coil_maps(n1, n2, C, rng, width=0.8):
+    """Synthetic sensitivity maps H_c [C, n1, n2] (complex64): smooth Gaussian
+    magnitudes centred on a ring just outside the field of view, each with a
+    linear phase, normalised so that sum_c |H_c|^2 = 1 at every pixel (the
+    sum-of-squares normalisation the paper estimates its maps with)."""
+    y = (np.arange(n1) - n1 / 2) / (n1 / 2)
+    x = (np.arange(n2) - n2 / 2) / (n2 / 2)
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    off = rng.uniform(0, 2 * np.pi)
+    H = np.empty((C, n1, n2), dtype=np.complex128)
+    for c in range(C):
+        th = off + 2 * np.pi * c / C
+        cy, cx = 1.2 * np.sin(th), 1.2 * np.cos(th)
+        mag = np.exp(-((Y - cy) ** 2 + (X - cx) ** 2) / (2 * width ** 2))
+        a, b = rng.uniform(-np.pi / 2, np.pi / 2, 2)
+        H[c] = mag * np.exp(1j * (a * X + b * Y + rng.uniform(0, 2 * np.pi)))
+    H /= np.sqrt(np.sum(np.abs(H) ** 2, axis=0))[None]
+    return H.astype(np.complex64)
+
+
+class CoilFrame:
+    """One multi-coil frame: ascending rows (int32) and their samples at every
+    coil [C, rows, n2] c64."""
+
+    def __init__(self, rows, y, truth=None):
+        self.rows, self.y, self.truth = rows, y, truth
+
+
+def config_coils(T=20, n1=128, n2=128, r=16, C=8, accel=4, sigma=0.005, t_warm=2, seq=0, config=6):
+    """The phantom cine seen through C coils: y_c = [F(H_c .* X_t)] at
+    variable-density rows, plus CN(0, sigma^2) noise per coil (Sec. IV-B's
+    model); the first t_warm frames are fully sampled."""
+    rng_ph, rng_mask, rng_noise, rng_init, rng_coil = (rng_for(config, seq, s) for s in range(5))
+    spec = phantom_spec(n1, n2, rng_ph)
+    H = coil_maps(n1, n2, C, rng_coil)
+    L = int(round(n1 / accel))
+    frames = []
+    for t in range(1, T + 1):
+        img = phantom_frame(spec, t)
+        rows = np.arange(n1, dtype=np.int32) if t <= t_warm else vd_line_mask(n1, L, rng_mask)
+        Y = np.stack([kspace(H[c].astype(np.complex128) * img)[rows, :] for c in range(C)])
+        Y = Y + cn(rng_noise, Y.shape, sigma * sigma)
+        frames.append(CoilFrame(rows, Y.astype(np.complex64), truth=img))
+    A0, B0 = init_factors(n1, n2, r, rng_init)
+    return dict(n1=n1, n2=n2, r=r, C=C, H=H, frames=frames, A0=A0, B0=B0)

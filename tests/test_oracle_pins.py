@@ -658,3 +658,138 @@ def test_point_draws_skip_a_zero_column():
     assert np.all(np.isfinite(mix)) and abs(mix.sum() - 1.0) < 1e-13
     mask, draws = oracle.draw_points(Ah.astype(np.complex64), Bh.astype(np.complex64), 20, 1, 2, 3)
     assert mask.sum() >= 1 and np.all(draws >= 0) and np.all(draws[:, 0] < 8) and np.all(draws[:, 1] < 6)
+
+
+# ---------------------------------------------------------------------------- several coils (Sec. IV-B)
+def _coil_case(seed, n1=6, n2=5, R=2, C=3):
+    rng = _rng(80 + seed)
+    A, B = _cn(rng, (n1, R)), _cn(rng, (n2, R))
+    H = _cn(rng, (C, n1, n2))
+    return rng, A, B, H
+
+
+def test_one_all_ones_coil_is_the_single_coil_step():
+    c = I.config2(T=4, n1=16, n2=12, r=3, accel=2, t_warm=1)
+    a = oracle.TslOracle(16, 12, 3, 0.05, c["A0"], c["B0"])
+    b = oracle.CoilOracle(16, 12, 3, 0.05, c["A0"], c["B0"], np.ones((1, 16, 12)))
+    for fr in c["frames"]:
+        sa = a.push_lines(fr.rows, fr.y)
+        sb = b.push_lines(fr.rows, fr.y[None])
+        for k in ("gamma", "A", "B", "X"):
+            assert _nr(getattr(sb, k), getattr(sa, k)) < 1e-12, k
+        assert abs(sb.alpha - sa.alpha) < 1e-12 * sa.alpha
+
+
+def test_coil_back_projection_is_the_explicit_sketch_sum():
+    """Theta = sum_c sum_l e_c^l conj(W_c^l) with W_c^(i,j) = H_c .* F(e_i e_j^T)
+    (Sec. IV-B), summed matrix by matrix, equals sum_c conj(H_c) .* F^{-1}(Xi_c)."""
+    rng, A, B, H = _coil_case(1)
+    n1, n2, C = 6, 5, 3
+    o = oracle.CoilOracle(n1, n2, 2, 0.2, A, B, H)
+    rows = np.array([0, 2, 5], dtype=np.int32)
+    s = o.push_lines(rows, _cn(rng, (C, 3, n2)))
+    Fl, Fr = oracle.dft_matrix(n1), oracle.dft_matrix(n2)
+    Theta = np.zeros((n1, n2), complex)
+    for c in range(C):
+        for q, i in enumerate(rows):
+            for j in range(n2):
+                E = np.zeros((n1, n2)); E[i, j] = 1.0
+                W = H[c] * (Fl @ E @ Fr)
+                Theta += s.e[c, q, j] * np.conj(W)
+    assert _nr(s.Theta, Theta) < 1e-12
+
+
+def test_coil_regression_matrix_is_the_coil_weighted_synthesis():
+    """Phi gamma read at the samples equals F(H_c .* A diag(gamma) B^T) at the
+    sampled rows (linearity), coil by coil."""
+    rng, A, B, H = _coil_case(2)
+    Fl, Fr = oracle.dft_matrix(6), oracle.dft_matrix(5)
+    rows = np.array([1, 3, 4])
+    g = _cn(rng, 2)
+    Phi = oracle.coil_regression_matrix(A, B, H, rows, Fl, Fr)
+    X = A @ np.diag(g) @ B.T
+    want = np.concatenate([(Fl @ (H[c] * X) @ Fr)[rows, :].reshape(-1) for c in range(3)])
+    assert _nr(Phi @ g, want) < 1e-13
+
+
+def test_coil_update_is_the_gradient_by_finite_differences():
+    """(A[t-1] - A[t]) / mu_t is the gradient of the several-coil cost
+    1/2 sum_c ||y_c - F(H_c .* A diag(gamma) B^T)_S||^2 + lambda/(2t) ||A||^2."""
+    rng, A, B, H = _coil_case(3)
+    lam = 0.3
+    o = oracle.CoilOracle(6, 5, 2, lam, A, B, H)
+    rows = np.array([0, 1, 4], dtype=np.int32)
+    Y = _cn(rng, (3, 3, 5))
+    s = o.push_lines(rows, Y)
+    Fl, Fr = o.Fl, o.Fr
+    gA, gB = (A - s.A) / s.mu, (B - s.B) / s.mu
+
+    def cost(a, b):
+        X = a @ np.diag(s.gamma) @ b.T
+        r = np.concatenate([(Y[c] - (Fl @ (H[c] * X) @ Fr)[rows, :]).reshape(-1) for c in range(3)])
+        return 0.5 * np.vdot(r, r).real + lam / (2 * s.t) * (np.vdot(a, a).real + np.vdot(b, b).real)
+
+    h = 1e-6
+    for _ in range(3):
+        E = _cn(rng, A.shape)
+        fd = (cost(A + h * E, B) - cost(A - h * E, B)) / (2 * h)
+        assert abs(fd - np.vdot(gA, E).real) < 1e-6 * max(1.0, abs(fd))
+        E = _cn(rng, B.shape)
+        fd = (cost(A, B + h * E) - cost(A, B - h * E)) / (2 * h)
+        assert abs(fd - np.vdot(gB, E).real) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_coil_step_size_bounds_the_block_hessian_and_is_exact_for_constant_maps():
+    rng, A, B, H = _coil_case(4)
+    n1, n2, C, R = 6, 5, 3, 2
+    Fl, Fr = oracle.dft_matrix(n1), oracle.dft_matrix(n2)
+    g = _cn(rng, R)
+    lam, t = 0.4, 2
+
+    def top_eig(A, B, H, rows, wrt):
+        n = A.shape[0] if wrt == "A" else B.shape[0]
+        cols = []
+        for r in range(R):
+            for m in range(n):
+                D = np.zeros((n, R), complex); D[m, r] = 1.0
+                X = (D * g) @ B.T if wrt == "A" else (A * g) @ D.T
+                cols.append(np.concatenate([(Fl @ (H[c] * X) @ Fr)[rows, :].reshape(-1) for c in range(len(H))]))
+        L = np.array(cols).T
+        return float(np.linalg.eigvalsh(L.conj().T @ L).max())
+
+    def alpha(A, B, H):
+        return lam / t + oracle.coil_gain(H) * oracle.step_alpha(A, B, g, 0.0, t)
+
+    rows = np.array([0, 2, 3])
+    for wrt in ("A", "B"):
+        assert top_eig(A, B, H, rows, wrt) + lam / t <= alpha(A, B, H) * (1 + 1e-12)
+    # constant maps (H_c = eta_c everywhere), orthogonal factor columns, every row:
+    # the bound is the top eigenvalue of the factor-block Hessians
+    Ao = _orthogonal_columns(rng, n1, [1.4, 0.7])
+    Bo = _orthogonal_columns(rng, n2, [0.6, 1.2])
+    eta = _cn(rng, C)
+    Hc = eta[:, None, None] * np.ones((C, n1, n2))
+    full = np.arange(n1)
+    top = max(top_eig(Ao, Bo, Hc, full, w) for w in ("A", "B")) + lam / t
+    assert abs(alpha(Ao, Bo, Hc) - top) <= 1e-12 * top
+
+
+def test_coil_exact_recovery_noiseless_full_sampling_lambda0():
+    c = I.config1(T=3, n=16, r=3, exact=True)
+    A, B, G = c["truth"]
+    rng = _rng(85)
+    H = I.coil_maps(16, 16, 4, rng).astype(np.complex128)
+    o = oracle.CoilOracle(16, 16, 3, 0.0, A, B, H)
+    rows = np.arange(16)
+    for k, fr in enumerate(c["frames"]):
+        Y = np.stack([(o.Fl @ (H[q] * fr.truth) @ o.Fr) for q in range(4)])
+        s = o.push_lines(rows, Y)
+        assert _nr(s.gamma, G[k]) < 1e-11
+        assert _nr(s.X, fr.truth) < 1e-11
+        assert _nr(s.A, A) < 1e-12 and _nr(s.B, B) < 1e-12
+
+
+def test_coil_maps_are_sum_of_squares_normalised():
+    H = I.coil_maps(24, 20, 6, _rng(86)).astype(np.complex128)
+    assert np.allclose(np.sum(np.abs(H) ** 2, axis=0), 1.0, atol=1e-6)
+    assert abs(oracle.coil_gain(H) - 1.0) < 1e-6
