@@ -54,6 +54,8 @@ extern "C" {
 #endif
 
 #define TSL_MAX_R 128
+#define TSL_MAX_COILS 32       /* coils of a several-coil sequence (tsl_open_coils) */
+#define TSL_MAX_COIL_R 64      /* rank of a several-coil sequence                   */
 
 typedef struct tsl_seq tsl_seq;
 typedef struct tsl_pool tsl_pool;
@@ -162,6 +164,30 @@ int tsl_footprint(int n1, int n2, int r, size_t* bytes);
    NULL (defaults). */
 int tsl_open(tsl_seq** out, int n1, int n2, int r, double lambda, const tsl_opts* opts,
              const tsl_c32* A0, const tsl_c32* B0, void* stream);
+
+/* Opens a sequence imaged by C coils (Algorithm 3 with C coils, Sec. IV-B):
+   as tsl_open, plus H [C][n1][n2] (device, complex64, copied into the
+   sequence), H[c] the sensitivity map of coil c; coil c sees the frame
+   H_c .* X and samples F(H_c .* X).  1 <= C <= TSL_MAX_COILS, r <= TSL_MAX_COIL_R.
+   Frames go through tsl_push_coils (the single-coil pushes, batched steps and
+   tsl_epochs refuse such a sequence with TSL_EINVAL).  The step size uses
+   g = max over pixels of sum_c |H_c|^2 (1 for maps normalised to unit sum of
+   squares): alpha_t = lambda/t + g max(Gersh(G^H B^H B G), Gersh(G^H A^H A G)),
+   which bounds the factor-block Lipschitz constant of the several-coil cost. */
+int tsl_open_coils(tsl_seq** out, int n1, int n2, int r, int C, double lambda, const tsl_opts* opts,
+                   const tsl_c32* A0, const tsl_c32* B0, const tsl_c32* H, void* stream);
+
+/* Pushes frame t = t+1 of a several-coil sequence, sampled at the full
+   k-space rows `rows` (strictly ascending, in [0, n1); checked on the device)
+   of every coil: y [C][n_rows][n2], y[c][s][j] coil c's sample at
+   (rows[s], j), i.e. [F(H_c .* X_t)]_{rows[s], j} plus noise (Sec. IV-B).  One
+   step of Algorithm 3: Phi with entries [F(H_c .* (a_r b_r^T))]_{ij} over every
+   coil's samples, gamma_t = (Phi^H Phi + lambda I)^{-1} Phi^H y (FP64), the
+   residual per coil, Theta = sum_c conj(H_c) .* F^{-1}(Xi_c), and the updates
+   of A and B from the factors at t-1.  n_rows == 0 is a pure shrink.  Outputs
+   as tsl_push_lines (each may be NULL); device errors latch as there. */
+int tsl_push_coils(tsl_seq* s, int n_rows, const int32_t* rows, const tsl_c32* y, tsl_c32* X_out, tsl_c32* A_out,
+                   tsl_c32* B_out, tsl_c32* gamma_out, void* stream);
 
 /* Releases the sequence after synchronising its last stream.  NULL is a no-op. */
 int tsl_close(tsl_seq* s);

@@ -33,7 +33,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 }  // namespace
 
-Layout layout_for(int n1, int n2, int r) {
+Layout layout_for(int n1, int n2, int r, int C) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
@@ -52,6 +52,15 @@ Layout layout_for(int n1, int n2, int r) {
     L.part = take(size_t(tsl::n_parts(n1, n2)) * r * r * sizeof(double2));
     L.hpart = take(size_t(tsl::n_hparts(n1, n2)) * r * sizeof(double2));
     L.wq = take(size_t(tsl::cdiv(r, 16)) * n1 * sizeof(double));
+    if (C > 0) {
+        const size_t P = size_t(n1) * n2;
+        L.H = take(size_t(C) * P * sizeof(float2));
+        L.P = take(size_t(r) * P * sizeof(float2));
+        L.Q = take(size_t(C) * P * sizeof(float2));
+        L.gslot = take(size_t(C) * n1 * r * r * sizeof(double2));
+        L.hslot = take(size_t(C) * n1 * r * sizeof(double2));
+        L.gain = take(sizeof(double));
+    }
     L.total = o;
     return L;
 }
@@ -126,6 +135,7 @@ int run_groups(const tsl::Batch* groups, int n_groups, hipStream_t st, hipEvent_
 }
 
 int check_frame(const tsl_seq* s, const tsl_frame& fr) {
+    if (s->C > 0) return fail(TSL_EINVAL, "a several-coil sequence takes its frames through tsl_push_coils");
     if (fr.mask) {
         if (fr.rows) return fail(TSL_EINVAL, "a frame has both rows and a mask");
         if (!fr.y) return fail(TSL_EINVAL, "null y");
@@ -484,7 +494,7 @@ static int validate_params(double lambda, const tsl_opts& o) {
 }
 
 static int open_impl(tsl_pool* pool, tsl_seq** out, int n1, int n2, int r, double lambda, const tsl_opts* opts,
-                     const tsl_c32* A0, const tsl_c32* B0, void* stream) {
+                     const tsl_c32* A0, const tsl_c32* B0, void* stream, int C = 0, const tsl_c32* H = nullptr) {
     if (!out) return fail(TSL_EINVAL, "null output handle");
     *out = nullptr;
     int rc = validate_shape(n1, n2, r);
@@ -494,7 +504,8 @@ static int open_impl(tsl_pool* pool, tsl_seq** out, int n1, int n2, int r, doubl
     if (opts) o = *opts;
     if ((rc = validate_params(lambda, o)) != TSL_OK) return rc;
     if (!A0 || !B0) return fail(TSL_EINVAL, "null A0 or B0");
-    Layout L = layout_for(n1, n2, r);
+    if (C > 0 && !H) return fail(TSL_EINVAL, "null coil maps");
+    Layout L = layout_for(n1, n2, r, C);
     tsl::init_kernel_attributes();
     if (pool) {
         std::lock_guard<std::mutex> lk(pool->mu);
@@ -509,6 +520,7 @@ static int open_impl(tsl_pool* pool, tsl_seq** out, int n1, int n2, int r, doubl
     };
     tsl_seq* s = new tsl_seq();
     s->n1 = n1; s->n2 = n2; s->r = r; s->lambda = lambda; s->opts = o; s->lay = L; s->bytes = L.total;
+    s->C = C;
     s->pool = pool;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     s->last = st;
@@ -537,7 +549,67 @@ static int open_impl(tsl_pool* pool, tsl_seq** out, int n1, int n2, int r, doubl
         return bail(e, "F_l A0");
     if ((e = tsl::launch_factor_fft(n2, r, s->at<float2>(L.B), s->at<float2>(L.Bhat), false, st)) != hipSuccess)
         return bail(e, "F_r B0");
+    if (C > 0) {
+        if ((e = hipMemcpyAsync(s->at<void>(L.H), H, size_t(C) * n1 * n2 * sizeof(float2), hipMemcpyDeviceToDevice,
+                                st)) != hipSuccess)
+            return bail(e, "copy coil maps");
+        tsl::CoilArgs ca{};
+        ca.n1 = n1; ca.n2 = n2; ca.C = C;
+        ca.H = s->at<float2>(L.H);
+        ca.gain = s->at<double>(L.gain);
+        if ((e = tsl::launch_coil_gain(ca, st)) != hipSuccess) return bail(e, "coil gain");
+    }
     *out = s;
+    return TSL_OK;
+}
+
+int tsl_open_coils(tsl_seq** out, int n1, int n2, int r, int C, double lambda, const tsl_opts* opts,
+                   const tsl_c32* A0, const tsl_c32* B0, const tsl_c32* H, void* stream) {
+    if (C < 1 || C > TSL_MAX_COILS) return fail(TSL_EINVAL, "C must be in [1, TSL_MAX_COILS]");
+    if (r > TSL_MAX_COIL_R) return fail(TSL_EINVAL, "a several-coil sequence takes r <= TSL_MAX_COIL_R");
+    return open_impl(nullptr, out, n1, n2, r, lambda, opts, A0, B0, stream, C, H);
+}
+
+int tsl_push_coils(tsl_seq* s, int n_rows, const int32_t* rows, const tsl_c32* y, tsl_c32* X_out, tsl_c32* A_out,
+                   tsl_c32* B_out, tsl_c32* gamma_out, void* stream) {
+    if (!s) return fail(TSL_EINVAL, "null sequence handle");
+    if (s->C <= 0) return fail(TSL_EINVAL, "tsl_push_coils needs a sequence opened with tsl_open_coils");
+    if (n_rows < 0 || n_rows > s->n1) return fail(TSL_EINVAL, "n_rows must be in [0, n1]");
+    if (n_rows > 0 && (!rows || !y)) return fail(TSL_EINVAL, "null rows or y");
+    TSL_HIP(hipSetDevice(s->device));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    s->last = st;
+    const Layout& L = s->lay;
+    tsl::CoilArgs a{};
+    a.n1 = s->n1; a.n2 = s->n2; a.r = s->r; a.C = s->C; a.n_rows = n_rows; a.step_mode = s->opts.step_mode;
+    a.lambda = s->lambda; a.mu_const = s->opts.mu;
+    a.A = s->at<float2>(L.A); a.B = s->at<float2>(L.B); a.Ahat = s->at<float2>(L.Ahat); a.Bhat = s->at<float2>(L.Bhat);
+    a.dev = s->at<tsl::SeqDev>(L.dev);
+    a.gamma64 = s->at<double2>(L.g64); a.gamma32 = s->at<float2>(L.g32);
+    a.H = s->at<float2>(L.H); a.P = s->at<float2>(L.P); a.Q = s->at<float2>(L.Q);
+    a.theta = s->at<float2>(L.frame); a.GA = s->at<float2>(L.GA); a.GB = s->at<float2>(L.Wb);
+    a.gslot = s->at<double2>(L.gslot); a.hslot = s->at<double2>(L.hslot); a.gain = s->at<double>(L.gain);
+    a.rows = rows; a.y = reinterpret_cast<const float2*>(y);
+    a.A_out = reinterpret_cast<float2*>(A_out); a.B_out = reinterpret_cast<float2*>(B_out);
+    a.gamma_out = reinterpret_cast<float2*>(gamma_out);
+    hipError_t e = tsl::launch_coil_step(a, st);
+    if (e != hipSuccess) return hip_fail(e, "several-coil step");
+    if (X_out) {
+        // X_t = A[t] diag(gamma_t) B[t]^T, the output launch of the single-coil step
+        tsl::FrameArgs fa{};
+        fa.n1 = s->n1; fa.n2 = s->n2; fa.r = s->r; fa.mode = tsl::MODE_LINES;
+        fa.A = a.A; fa.B = a.B; fa.Ahat = a.Ahat; fa.Bhat = a.Bhat; fa.dev = a.dev;
+        fa.gamma64 = a.gamma64; fa.gamma32 = a.gamma32;
+        fa.X_out = reinterpret_cast<float2*>(X_out);
+        tsl::Batch b{};
+        b.one = &fa;
+        b.count = 1;
+        b.n1 = s->n1; b.n2 = s->n2; b.r_max = s->r; b.mode = tsl::MODE_LINES;
+        b.want_x = true;
+        b.synth = s->opts.synth_bf16;
+        e = tsl::launch_synth_out(b, st);
+        if (e != hipSuccess) return hip_fail(e, "several-coil output");
+    }
     return TSL_OK;
 }
 

@@ -12,7 +12,10 @@
 
 // Byte offsets of a sequence's arrays inside its one device arena.
 struct Layout {
-    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, wpart, mpart, part, hpart, wq, total;
+    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, wpart, mpart, part, hpart, wq;
+    // several coils (0 for a single-coil sequence)
+    size_t H, P, Q, gslot, hslot, gain;
+    size_t total;
 };
 
 struct tsl_pool {
@@ -22,6 +25,7 @@ struct tsl_pool {
 
 struct tsl_seq {
     int n1 = 0, n2 = 0, r = 0, device = 0;
+    int C = 0;                            // coils (tsl_open_coils), 0 for a single-coil sequence
     double lambda = 0;
     tsl_opts opts{};
     char* arena = nullptr;
@@ -46,7 +50,7 @@ int hip_fail(hipError_t e, const char* what);
         if (e_ != hipSuccess) return ::tsl::eng::hip_fail(e_, #call);   \
     } while (0)
 
-Layout layout_for(int n1, int n2, int r);
+Layout layout_for(int n1, int n2, int r, int C = 0);
 
 // The descriptor of frame `fr` of sequence `s` (plain host pointers).
 FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr);

@@ -60,6 +60,31 @@ hipError_t launch_sample(const Batch& b, hipStream_t st);
 hipError_t launch_sample_points(const FrameArgs& a, int K, unsigned char* mask, int* n_out, int* draws,
                                 hipStream_t st);
 
+// One frame of a sequence imaged by several coils (Algorithm 3 with C coils,
+// csrc/k_coils.hip): the sequence's state, its coil maps and workspace, the
+// frame's rows and samples.
+struct CoilArgs {
+    int n1, n2, r, C, n_rows, step_mode;
+    double lambda, mu_const;
+    float2 *A, *B, *Ahat, *Bhat;       // state (A, B updated in place; F_l A, F_r B recomputed)
+    SeqDev* dev;
+    double2* gamma64;
+    float2* gamma32;
+    const float2* H;                   // [C][n1][n2] sensitivity maps
+    float2* P;                         // [r][n1][n2] transformed rank images of one coil
+    float2* Q;                         // [C][n1][n2] coil-weighted prediction, then Xi_c, then F^{-1}(Xi_c)
+    float2* theta;                     // [n1][n2] Theta
+    float2 *GA, *GB;                   // [n1][r] Theta conj(B), [n2][r] Theta^T conj(A)
+    double2* gslot;                    // [C][n1][r][r] Gram partials per coil and sampled row (upper entries)
+    double2* hslot;                    // [C][n1][r] right-hand-side partials
+    double* gain;                      // [1] max over pixels of sum_c |H_c|^2
+    const int* rows;                   // [n_rows] ascending
+    const float2* y;                   // [C][n_rows][n2]
+    float2 *A_out, *B_out, *gamma_out;
+};
+hipError_t launch_coil_step(const CoilArgs& a, hipStream_t st);
+hipError_t launch_coil_gain(const CoilArgs& a, hipStream_t st);
+
 // Raises the dynamic-LDS limit of the kernels that need more than the default
 // (idempotent; called before any launch or graph capture).
 void init_kernel_attributes();

@@ -23,7 +23,7 @@ _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOTPD: "ENOTP
 EXPORTS = [
     "tsl_opts_default", "tsl_size_supported", "tsl_footprint", "tsl_open", "tsl_close",
     "tsl_push_lines", "tsl_push_points", "tsl_push_frame", "tsl_sample_lines", "tsl_step_many",
-    "tsl_step_many_noalloc", "tsl_epochs", "tsl_sample_points",
+    "tsl_step_many_noalloc", "tsl_epochs", "tsl_sample_points", "tsl_open_coils", "tsl_push_coils",
     "tsl_step_many_timed", "tsl_batch_create", "tsl_batch_launch", "tsl_batch_destroy", "tsl_status",
     "tsl_get_factors", "tsl_get_state", "tsl_set_state", "tsl_shape", "tsl_fft2",
     "tsl_pool_create", "tsl_pool_destroy", "tsl_pool_used", "tsl_open_in_pool",
@@ -83,6 +83,8 @@ def lib():
             "tsl_push_frame": (i, [vp, P(Frame), vp]),
             "tsl_epochs": (i, [vp, i, P(Frame), i, vp, vp]),
             "tsl_sample_points": (i, [vp, i, vp, vp, vp, vp]),
+            "tsl_open_coils": (i, [P(vp), i, i, i, i, d, P(Opts), vp, vp, vp, vp]),
+            "tsl_push_coils": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
             "tsl_step_many": (i, [P(vp), i, P(Frame), vp]),
             "tsl_step_many_noalloc": (i, [P(vp), i, P(Frame), vp]),
             "tsl_step_many_timed": (i, [P(vp), i, P(Frame), P(d), vp]),
@@ -395,3 +397,27 @@ def fft2(x, out=None, inverse=False, stream=None):
     _check(lib().tsl_fft2(n1, n2, batch, _dev(x, torch.complex64, shape, "x"),
                           _dev(out, torch.complex64, shape, "out"), int(bool(inverse)), _stream(stream)))
     return out
+
+
+class CoilSequence(Sequence):
+    """A scan imaged by C coils with sensitivity maps H [C, n1, n2] (tsl_open_coils)."""
+
+    def __init__(self, n1, n2, r, lam, A0, B0, H, step_mode="mm", mu=0.0, allow_lambda0=False, seed=0,
+                 stream_id=0, stream=None, synth="fp32"):
+        self.n1, self.n2, self.r = int(n1), int(n2), int(r)
+        self.C = int(H.shape[0])
+        self.opts = make_opts(step_mode, mu, allow_lambda0, seed, stream_id, "frame", synth)
+        a = _dev(A0, torch.complex64, (n1, r), "A0")
+        b = _dev(B0, torch.complex64, (n2, r), "B0")
+        hp = _dev(H, torch.complex64, (self.C, n1, n2), "H")
+        h = ctypes.c_void_p()
+        _check(lib().tsl_open_coils(ctypes.byref(h), n1, n2, r, self.C, float(lam), ctypes.byref(self.opts), a, b,
+                                    hp, _stream(stream)))
+        self.h = h
+
+    def push_coils(self, rows, y, X_out=None, A_out=None, B_out=None, gamma_out=None, stream=None):
+        """rows: int32 [n]; y: complex64 [C, n, n2]."""
+        n = int(rows.shape[0])
+        rp = _dev(rows, torch.int32, (n,), "rows")
+        yp = _dev(y, torch.complex64, (self.C, n, self.n2), "y")
+        _check(lib().tsl_push_coils(self.h, n, rp, yp, *self._outs(X_out, A_out, B_out, gamma_out), _stream(stream)))

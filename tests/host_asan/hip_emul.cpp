@@ -191,6 +191,25 @@ hipError_t launch_stats(const Batch& b, hipStream_t st) { return run_group(b, st
 hipError_t launch_solve(const Batch& b, hipStream_t st) { return run_group(b, st, P_SOLVE); }
 hipError_t launch_synth_out(const Batch& b, hipStream_t st) { return run_group(b, st, P_OUT); }
 hipError_t launch_sample(const Batch& b, hipStream_t st) { return run_group(b, st, P_SAMPLE); }
+hipError_t launch_coil_gain(const CoilArgs& a, hipStream_t st) {
+    issue(st, [a]() { touch(a.H, size_t(a.C) * a.n1 * a.n2); touch(a.gain, 1); }, false);
+    return hipSuccess;
+}
+hipError_t launch_coil_step(const CoilArgs& a, hipStream_t st) {
+    issue(st, [a]() {
+        const size_t P = size_t(a.n1) * a.n2, r = size_t(a.r);
+        touch(a.A, a.n1 * r); touch(a.B, a.n2 * r); touch(a.Ahat, a.n1 * r); touch(a.Bhat, a.n2 * r);
+        touch(a.dev, 1); touch(a.gamma64, r); touch(a.gamma32, r);
+        touch(a.H, size_t(a.C) * P); touch(a.P, r * P); touch(a.Q, size_t(a.C) * P); touch(a.theta, P);
+        touch(a.GA, a.n1 * r); touch(a.GB, a.n2 * r);
+        touch(a.gslot, size_t(a.C) * a.n1 * r * r); touch(a.hslot, size_t(a.C) * a.n1 * r); touch(a.gain, 1);
+        if (a.n_rows > 0) { touch(a.rows, size_t(a.n_rows)); touch(a.y, size_t(a.C) * a.n_rows * a.n2); }
+        if (a.A_out) touch(a.A_out, a.n1 * r);
+        if (a.B_out) touch(a.B_out, a.n2 * r);
+        if (a.gamma_out) touch(a.gamma_out, r);
+    }, false);
+    return hipSuccess;
+}
 hipError_t launch_sample_points(const FrameArgs& a, int K, unsigned char* mask, int* n_out, int* draws,
                                 hipStream_t st) {
     issue(st, [a, K, mask, n_out, draws]() {
