@@ -59,6 +59,9 @@ def parse():
                     help="offered-load factors: arrival rate and frame rate (30/s) both times the factor")
     ap.add_argument("--serve-limit", type=float, default=20.0, help="wall-time cap per served run (s)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--mall-seqs", type=int, default=1024,
+                    help="sequences of the leg whose frame arrays overflow the 256 MB Infinity Cache (0: skip)")
+    ap.add_argument("--mall-steps", type=int, default=10)
     ap.add_argument("--route", choices=["kspace", "frame"], default="kspace",
                     help="line-mask route of the headline measurement")
     ap.add_argument("--frame-route-steps", type=int, default=20,
@@ -339,10 +342,16 @@ def main():
         other_leg = {"route": other, "frames_per_s": S * 1000.0 / ores["ms_per_step"],
                      "ms_per_step": ores["ms_per_step"],
                      "phases_ms": {name: ophase[i] / a.phase_steps for i, name in enumerate(tsl.PHASES)}}
+        if other == "frame":
+            other_leg["roofline_passes"] = frame_pass_rooflines(
+                other_leg["phases_ms"], phase_ms, n, r, mean_rows, K, S, "frame-route passes, 64-sequence batch")
         bad += [q for q in oseqs if q.status() != 0]
         for q in oseqs:
             q.close()
         print(f"[bench] {other} route {other_leg['frames_per_s']:.0f} frames/s", file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------------ beyond the Infinity Cache
+    mall = None if a.mall_seqs <= 0 else mall_leg(a, tsl, torch, dev, stream, n, r, lam, K, warm)
 
     # ------------------------------------------------------------------ plain
     q = open_seq(0)
@@ -423,9 +432,11 @@ def main():
         "route": a.route,
         "other_route": other_leg,
         "mixed": mixed,
+        "beyond_mall": mall,
         "serving": served,
         "batched_over_plain": value / plain_fps,
         "phases_ms": {name: phase_ms[i] for i, name in enumerate(tsl.PHASES)},
+        "tuned_output_tile": {"batched": tsl.output_tile(n, n, r, S), "plain": tsl.output_tile(n, n, r, 1)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,
@@ -433,6 +444,67 @@ def main():
     }
     print(json.dumps(out))
     return 0
+
+
+def frame_pass_rooflines(phases, kspace_phases, n, r, rows, K, S, label):
+    """HBM rooflines of the frame route's three frame-sized passes from their
+    event-bracketed phase times.  A bracket adds a fixed overhead (the events
+    and the launch gap), measured on a phase that launches nothing in the same
+    run (the synthesis + row pass of the k-space route) and subtracted."""
+    overhead = kspace_phases.get("synthesis + row pass", 0.0) if isinstance(kspace_phases, dict) else \
+        kspace_phases[2]
+    work = phase_work(n, n, r, rows, K, kspace=False)
+    out = {"label": label, "bracket_overhead_ms": overhead, "passes": {}}
+    for name in ("synthesis + row pass", "column pass + residual", "row inverse + A grad"):
+        ms = phases[name]
+        net = max(ms - overhead, 1e-6)
+        b, fl = work[name][0] * S, work[name][1] * S
+        hbm = b / (net * 1e-3) / 1e9 / HBM_PEAK_GBS
+        mfma = fl / (net * 1e-3) / 1e12 / PEAK_TFS["mfma"]
+        out["passes"][name] = {"algorithmic_bytes_per_launch": b, "algorithmic_flops_per_launch": fl,
+                               "bracketed_ms": ms, "net_ms": net,
+                               "achieved_GBps": b / (net * 1e-3) / 1e9, "frac_of_hbm": hbm,
+                               "achieved_TFLOPs": fl / (net * 1e-3) / 1e12, "frac_of_fp32_matrix": mfma,
+                               "bound": "hbm" if hbm >= mfma else "mfma"}
+    return out
+
+
+def mall_leg(a, tsl, torch, dev, stream, n, r, lam, K, warm):
+    """Both routes on a batch whose frame-sized arrays exceed the 256 MB
+    Infinity Cache (1024 x 256^2: 512 MiB per frame array), so the frame
+    route's passes stream from HBM.  Inputs are CN(0, 1) k-space frames made on
+    the device (two per sequence, cycled): the work of a step does not depend
+    on their content."""
+    S = a.mall_seqs
+    g = torch.Generator(device=dev)
+    g.manual_seed(1609)
+    banks = [torch.randn(2, n, n, dtype=torch.complex64, device=dev, generator=g) for _ in range(S)]
+    out = {"workload": f"{S} sequences of {n}x{n}, R={r}, informative rows (K={K}) after {warm} full frames; "
+                       f"synthetic CN(0,1) k-space frames", "sequences": S}
+    for route in ("kspace", "frame"):
+        seqs = []
+        for s in range(S):
+            A0 = (torch.randn(n, r, dtype=torch.complex64, device=dev, generator=g) / math.sqrt(n)).contiguous()
+            B0 = (torch.randn(n, r, dtype=torch.complex64, device=dev, generator=g) / math.sqrt(n)).contiguous()
+            seqs.append(tsl.Sequence(n, n, r, lam, A0, B0, seed=7, stream_id=s, route=route))
+        drv = BatchDriver(tsl, torch, seqs, banks, [K] * S, warm, dev)
+        res = time_steps(drv, warm + 2, a.mall_steps, stream, torch, f"beyond-MALL {route}")
+        ph = [0.0] * tsl.N_PHASES
+        t = res["t"]
+        for _ in range(3):
+            ph = tsl.step_many_timed(seqs, drv.frames_for(t), ph, stream)
+            t += 1
+        leg = {"frames_per_s": S * 1000.0 / res["ms_per_step"], "ms_per_step": res["ms_per_step"],
+               "phases_ms": {name: ph[i] / 3 for i, name in enumerate(tsl.PHASES)},
+               "device_status_errors": sum(1 for q in seqs if q.status() != 0)}
+        out[route] = leg
+        for q in seqs:
+            q.close()
+        drv.prepared.clear()
+        torch.cuda.synchronize()
+    out["frame"]["roofline_passes"] = frame_pass_rooflines(out["frame"]["phases_ms"], out["kspace"]["phases_ms"],
+                                                           n, r, K, K, S, f"frame-route passes, {S}-sequence batch")
+    return out
 
 
 def mixed_leg(a, tsl, torch, dev, stream):
@@ -541,24 +613,51 @@ def oracle_leg(a, data, Kd, n, r, lam, K, warm, dev, tsl, torch):
     q.close()
     parity = {"frames": n_par, "max_nrmse_X_vs_oracle": worst,
               "row_draws_bit_exact": f"{agree}/{draws}", "tolerance": 1e-4}
-    # CPU baseline: the oracle alone (its own FP64 draws), bounded time
-    o = oracle.TslOracle(n, n, r, lam, A0, B0)
-    rows_o = np.arange(n, dtype=np.int32)
-    frames = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < a.cpu_seconds:
-        o.push_lines(rows_o, kspace[frames % F][rows_o])
-        Ah_o, _ = o.kspace_factors()
-        frames += 1
-        rows_o = (oracle.draw_lines(Ah_o, n, K, 1609, 0, frames + 1)[0] if frames >= warm
-                  else np.arange(n, dtype=np.int32))
-    el = time.perf_counter() - t0
+    # CPU baseline: the oracle alone (its own FP64 draws), bounded time, with
+    # the BLAS threads it gets by default and again with one thread
+    def oracle_rate(seconds):
+        o = oracle.TslOracle(n, n, r, lam, A0, B0)
+        rows_o = np.arange(n, dtype=np.int32)
+        frames = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            o.push_lines(rows_o, kspace[frames % F][rows_o])
+            Ah_o, _ = o.kspace_factors()
+            frames += 1
+            rows_o = (oracle.draw_lines(Ah_o, n, K, 1609, 0, frames + 1)[0] if frames >= warm
+                      else np.arange(n, dtype=np.int32))
+        return frames, time.perf_counter() - t0
+
+    frames, el = oracle_rate(a.cpu_seconds)
+    f1, el1 = None, None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            f1, el1 = oracle_rate(a.cpu_seconds / 2)
+    except Exception:
+        pass
+    host = {"nproc": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count(),
+            "cpu": cpu_model()}
     cpu = {"value": frames / el, "unit": "frames/s", "cores": threads, "kind": "oracle",
            "sample": f"{frames} frames of sequence 0 ({n}x{n}, R={r}, informative rows) in {el:.1f}s, "
-                     f"FP64 NumPy with dense DFT matrices"}
-    print(f"[bench] oracle {cpu['value']:.1f} frames/s on {threads} threads; parity {parity}",
-          file=sys.stderr, flush=True)
+                     f"FP64 NumPy with dense DFT matrices, {threads} BLAS threads",
+           "value_1thread": (f1 / el1) if f1 else None,
+           "sample_1thread": (f"{f1} frames in {el1:.1f}s with one BLAS thread" if f1 else None),
+           "host": host}
+    print(f"[bench] oracle {cpu['value']:.1f} frames/s on {threads} threads"
+          f"{'' if not f1 else f', {f1 / el1:.1f} on one'}; parity {parity}", file=sys.stderr, flush=True)
     return parity, cpu
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

@@ -351,6 +351,22 @@ int tsl_get_factors(tsl_seq* s, tsl_c32* A, tsl_c32* B, tsl_c32* Ahat, tsl_c32* 
 int tsl_get_state(tsl_seq* s, void* host_blob, size_t* nbytes);
 int tsl_set_state(tsl_seq* s, const void* host_blob, size_t nbytes);
 
+/* Output-synthesis tile tuner.  The output launch of a batched step (X_t =
+   A[t] diag(gamma_t) B[t]^T, FP32 synthesis) has three block tiles that give
+   identical results: 128 x 64 (0, the default), 64 x 64 (1) and 128 x 128 (2).
+   tsl_batch_create times the three on each of the batch's output launches
+   whose (largest n1, largest n2, r <= 32 or not, frame count rounded up to a
+   power of two) has no choice yet -- into scratch frames and scratch row
+   lists, so nothing the caller owns is written -- and keeps the fastest for every later
+   launch of that kind in the process (tsl_step_many included).  TSL_TUNE=0
+   turns the timing off; TSL_TUNE_CACHE names a text file of earlier choices
+   ("n1 n2 one_pass count tile" per line), read at first use and appended to.
+   tsl_output_tile (host) returns the tile such a launch uses now, or TSL_EINVAL. */
+int tsl_output_tile(int n1, int n2, int r, int count);
+/* Fixes the tile of such launches (0, 1 or 2) for the rest of the process, in
+   place of timing (a deployment that wants a known launch shape). */
+int tsl_set_output_tile(int n1, int n2, int r, int count, int tile);
+
 /* Shape queries (host). */
 int tsl_shape(const tsl_seq* s, int* n1, int* n2, int* r);
 

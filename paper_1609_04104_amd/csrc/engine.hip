@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -232,6 +234,7 @@ int launch_phases(const FrameFacts* fa, const FrameArgs* ta, const FrameFacts* f
             b.mode = f[i].mode;
             b.kspace = f[i].kspace != 0;
             b.synth = f[i].synth;
+            b.out_tile = OUT_128x64;
             for (int q = i; q < j; ++q) {
                 b.n1 = std::max(b.n1, f[q].n1);
                 b.n2 = std::max(b.n2, f[q].n2);
@@ -240,12 +243,171 @@ int launch_phases(const FrameFacts* fa, const FrameArgs* ta, const FrameFacts* f
                 b.want_x = b.want_x || f[q].want_x;
                 b.want_sample = b.want_sample || f[q].want_sample;
             }
+            if (p == TSL_N_PHASES - 1 && b.synth == 0) b.out_tile = output_tile(b.n1, b.n2, b.r_max <= 32, b.count);
             hipError_t e = kPhases[p].fn(b, st);
             if (e != hipSuccess) return hip_fail(e, kPhases[p].name);
             i = j;
         }
     }
     if (ev) TSL_HIP(hipEventRecord(ev[TSL_N_PHASES], st));
+    return TSL_OK;
+}
+
+// -------------------------------------------------------------- output-tile tuner
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune;   // (n1, n2, one pass, count bucket) -> OUT_*
+bool g_tune_loaded = false;
+
+int count_bucket(int count) {
+    int b = 1;
+    while (b < count) b *= 2;
+    return b;
+}
+
+const char* tune_cache_path() { return std::getenv("TSL_TUNE_CACHE"); }
+
+// Records "n1 n2 one bucket tile" per line.
+void load_tune_cache_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = tune_cache_path();
+    if (!path || !*path) return;
+    if (FILE* fh = std::fopen(path, "r")) {
+        int a, b, c, d, e;
+        while (std::fscanf(fh, "%d %d %d %d %d", &a, &b, &c, &d, &e) == 5)
+            if (e >= 0 && e < OUT_TILES) g_tune[std::make_tuple(a, b, c, d)] = e;
+        std::fclose(fh);
+    }
+}
+
+}  // namespace
+
+int output_tile(int n1, int n2, bool one_pass, int count) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
+    auto it = g_tune.find(std::make_tuple(n1, n2, one_pass ? 1 : 0, count_bucket(count)));
+    return it == g_tune.end() ? int(OUT_128x64) : it->second;
+}
+
+void set_output_tile(int n1, int n2, bool one_pass, int count, int tile) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
+    g_tune[std::make_tuple(n1, n2, one_pass ? 1 : 0, count_bucket(count))] = tile;
+}
+
+int tune_output_runs(const FrameFacts* fa, const FrameArgs* host, int n) {
+    const char* off = std::getenv("TSL_TUNE");
+    if (off && off[0] == '0') return TSL_OK;
+    constexpr int P7 = TSL_N_PHASES - 1;
+    for (int i = 0; i < n;) {
+        int j = i + 1;
+        while (j < n && same_launch(P7, fa[i], fa[j])) ++j;
+        int n1 = 0, n2 = 0, r_max = 0, rows_max = 0;
+        bool any_x = false;
+        for (int q = i; q < j; ++q) {
+            n1 = std::max(n1, fa[q].n1); n2 = std::max(n2, fa[q].n2); r_max = std::max(r_max, fa[q].r);
+            rows_max = std::max(rows_max, fa[q].cap);
+            any_x = any_x || fa[q].want_x;
+        }
+        const auto key = std::make_tuple(n1, n2, r_max <= 32 ? 1 : 0, count_bucket(j - i));
+        bool known;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            load_tune_cache_locked();
+            known = g_tune.count(key) > 0;
+        }
+        if (known || !any_x || fa[i].synth != 0) { i = j; continue; }
+        // scratch copies of the run's descriptors: X and the drawn rows into
+        // scratch buffers, and a status word that lets the output tiles run
+        const int m = j - i;
+        std::vector<FrameArgs> tmp(host + i, host + j);
+        size_t kall = 0;
+        for (const FrameArgs& fa_ : tmp) kall += size_t(fa_.K_next > 0 ? fa_.K_next : 0) + 1;
+        int* rs = nullptr;
+        float2* xs = nullptr;
+        FrameArgs* table = nullptr;
+        SeqDev* sd = nullptr;
+        hipStream_t ts = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        auto cleanup = [&]() {
+            if (ts) hipStreamSynchronize(ts);
+            if (xs) hipFree(xs);
+            if (rs) hipFree(rs);
+            if (table) hipFree(table);
+            if (sd) hipFree(sd);
+            if (e0) hipEventDestroy(e0);
+            if (e1) hipEventDestroy(e1);
+            if (ts) hipStreamDestroy(ts);
+        };
+        hipError_t e = hipMalloc(&xs, size_t(m) * n1 * n2 * sizeof(float2));
+        if (e == hipSuccess) e = hipMalloc(&rs, kall * sizeof(int));
+        if (e == hipSuccess) e = hipMalloc(&table, size_t(m) * sizeof(FrameArgs));
+        if (e == hipSuccess) e = hipMalloc(&sd, sizeof(SeqDev));
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&ts, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e != hipSuccess) { cleanup(); return hip_fail(e, "output tuner"); }
+        SeqDev ok{};
+        ok.frame_ok = 1;
+        bool any_draw = false;
+        size_t ko = 0;
+        for (int q = 0; q < m; ++q) {
+            tmp[q].X_out = xs + size_t(q) * n1 * n2;
+            if (tmp[q].K_next > 0) {
+                any_draw = true;
+                tmp[q].rows_next = rs + ko;
+                ko += size_t(tmp[q].K_next);
+                tmp[q].n_next = rs + ko;
+                ko += 1;
+            }
+            tmp[q].draws_next = nullptr;
+            tmp[q].prefix_next = nullptr;
+            tmp[q].info_out = nullptr;
+            tmp[q].dev = sd;
+        }
+        e = hipMemcpy(table, tmp.data(), size_t(m) * sizeof(FrameArgs), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(sd, &ok, sizeof(ok), hipMemcpyHostToDevice);
+        Batch b{};
+        b.table = table; b.count = m; b.n1 = n1; b.n2 = n2; b.r_max = r_max; b.rows_max = rows_max;
+        b.mode = fa[i].mode;
+        b.want_x = true; b.want_sample = any_draw; b.synth = 0;
+        // three rounds over the tiles (interleaved, so drift hits all alike),
+        // each tile's best round kept
+        float tile_ms[OUT_TILES];
+        for (float& x : tile_ms) x = 1e30f;
+        for (int round = 0; round < 3 && e == hipSuccess; ++round)
+            for (int v = 0; v < OUT_TILES && e == hipSuccess; ++v) {
+                b.out_tile = v;
+                e = launch_synth_out(b, ts);                 // warm-up
+                if (e == hipSuccess) e = hipEventRecord(e0, ts);
+                constexpr int kReps = 5;
+                for (int k = 0; k < kReps && e == hipSuccess; ++k) e = launch_synth_out(b, ts);
+                if (e == hipSuccess) e = hipEventRecord(e1, ts);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess) tile_ms[v] = std::min(tile_ms[v], ms);
+            }
+        int best = OUT_128x64;
+        for (int v = 0; v < OUT_TILES; ++v)
+            if (tile_ms[v] < tile_ms[best]) best = v;
+        cleanup();
+        if (e != hipSuccess) return hip_fail(e, "output tuner");
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[key] = best;
+            const char* path = tune_cache_path();
+            if (path && *path)
+                if (FILE* fh = std::fopen(path, "a")) {
+                    std::fprintf(fh, "%d %d %d %d %d\n", std::get<0>(key), std::get<1>(key), std::get<2>(key),
+                                 std::get<3>(key), best);
+                    std::fclose(fh);
+                }
+        }
+        i = j;
+    }
     return TSL_OK;
 }
 
@@ -869,6 +1031,7 @@ int tsl_batch_create(tsl_seq* const* seqs, int n, const tsl_frame* frames, int f
     const size_t m = size_t(c.entries());
     std::vector<tsl::FrameArgs> host(m);
     fill_descriptors(c, seqs, frames, host.data());
+    if ((rc = tsl::eng::tune_output_runs(c.fa.data(), host.data(), n)) != TSL_OK) return rc;
     TSL_HIP(hipMalloc(&b->table, m * sizeof(tsl::FrameArgs)));
     TSL_HIP(hipMemcpy(b->table, host.data(), m * sizeof(tsl::FrameArgs), hipMemcpyHostToDevice));
     b->comp = c;
@@ -1032,6 +1195,18 @@ int tsl_set_state(tsl_seq* s, const void* host_blob, size_t nbytes) {
                 if (q == s) bt->dead = true;
     }
     return TSL_OK;
+}
+
+int tsl_set_output_tile(int n1, int n2, int r, int count, int tile) {
+    if (n1 < 1 || n2 < 1 || r < 1 || count < 1 || tile < 0 || tile >= tsl::OUT_TILES)
+        return fail(TSL_EINVAL, "bad output-tile setting");
+    tsl::eng::set_output_tile(n1, n2, r <= 32, count, tile);
+    return TSL_OK;
+}
+
+int tsl_output_tile(int n1, int n2, int r, int count) {
+    if (n1 < 1 || n2 < 1 || r < 1 || count < 1) return fail(TSL_EINVAL, "bad output-tile query");
+    return tsl::eng::output_tile(n1, n2, r <= 32, count);
 }
 
 int tsl_shape(const tsl_seq* s, int* n1, int* n2, int* r) {

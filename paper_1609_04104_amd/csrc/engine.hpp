@@ -92,5 +92,17 @@ bool table_orders(const FrameFacts* facts, int n, int* order_a, int* order_b);
 int launch_phases(const FrameFacts* fa, const FrameArgs* ta, const FrameFacts* fb, const FrameArgs* tb, int n,
                   hipStream_t st, hipEvent_t* ev = nullptr);
 
+// Output-tile tuner: the block tile of the output synthesis for a launch of
+// `count` frames of at most n1 x n2 (one pass of ranks or several): the
+// measured fastest (tune_output_runs, or a TSL_TUNE_CACHE record), else the
+// default 128 x 64.
+int output_tile(int n1, int n2, bool one_pass, int count);
+void set_output_tile(int n1, int n2, bool one_pass, int count, int tile);
+// Times every output tile on the output launches of a batch whose descriptors
+// (order A) are `host` (facts fa) and records the fastest for each launch not
+// yet known; nothing the caller owns is written (the timed launches write
+// their frames and drawn rows to scratch).  Off when TSL_TUNE=0.
+int tune_output_runs(const FrameFacts* fa, const FrameArgs* host, int n);
+
 }  // namespace eng
 }  // namespace tsl

@@ -1074,23 +1074,29 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
 // so a rank pair costs three steps instead of four.  A block owns a 128 x 64 tile of
 // X (eight 32 x 32 wavefront tiles); the rows of AG and of B it needs are
 // staged in LDS with coalesced loads, kOutRC ranks at a time.
-constexpr int kOutTM = 128;                  // block tile rows (i)
-constexpr int kOutTN = 64;                   // block tile columns (j)
-constexpr int kOutThreads = 512;             // eight wavefronts, a 32 x 32 tile each
+// The block tile (TM x TN of X, one wavefront per 32 x 32 sub-tile) is a
+// launch choice (OutTile): 128 x 64 by default, 64 x 64 or 128 x 128 where the
+// tuner measured them faster; every output entry is computed the same way in
+// each, so the choice changes no result.
 constexpr int kOutRC = 32;                   // ranks staged per pass
 constexpr int kOutPitch = kOutRC + 1;        // LDS row pitch (float2): conflict-free column reads
 
 // With ds = 1, block 0 of each frame draws the frame's next rows (Algorithm 4,
 // which needs only F_l A of the new A) beside the output tiles; the two roles
 // share one LDS area.
-constexpr size_t kOutLds = size_t(kOutTM + kOutTN) * kOutPitch * sizeof(float2);
+template <int TM, int TN> struct OutShape {
+    static constexpr int THREADS = (TM / 32) * (TN / 32) * 64;
+    static constexpr size_t LDS = size_t(TM + TN) * kOutPitch * sizeof(float2);
+    static constexpr size_t RAW = LDS > sizeof(SampleLds) ? LDS : sizeof(SampleLds);
+};
 // ONE: every rank fits one pass (R <= kOutRC), so no staging load is in
 // flight beside the accumulators and the kernel needs fewer registers.
 // BF: SYN_FP32 (FP32 steps, two ranks each), SYN_BF16 or SYN_BF16X3 (BF16
 // steps, sixteen ranks each: lane half h takes ranks c0 + 8h + j, j < 8).
-template <bool ONE, int BF, class Src>
-__global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
-    __shared__ __align__(16) unsigned char s_raw[kOutLds > sizeof(SampleLds) ? kOutLds : sizeof(SampleLds)];
+template <bool ONE, int BF, int TM, int TN, class Src>
+__global__ void __launch_bounds__((TM / 32) * (TN / 32) * 64) k_synth_out(Src src, int ds) {
+    constexpr int kOutTM = TM, kOutTN = TN, kOutThreads = OutShape<TM, TN>::THREADS;
+    __shared__ __align__(16) unsigned char s_raw[OutShape<TM, TN>::RAW];
     if (!src.live()) return;
     const DevFrame f = src.get();
     if (src.bx() < ds) {
@@ -1107,7 +1113,7 @@ __global__ void __launch_bounds__(kOutThreads) k_synth_out(Src src, int ds) {
     const int tiles_x = cdiv(n2, kOutTN);
     const int bi = (tile / tiles_x) * kOutTM, bj = (tile % tiles_x) * kOutTN;
     if (bi >= n1) return;                   // a launch sized for a larger frame of the run
-    const int wi = 32 * (w / 2), wj = 32 * (w % 2);    // wavefront tile inside the block tile
+    const int wi = 32 * (w / (TN / 32)), wj = 32 * (w % (TN / 32));    // wavefront tile inside the block tile
     const int m = lane % 32, h = lane / 32;
     // A, gamma and B of a rank pass, all loads in flight together; the first
     // pass goes out before the status check (it reads the frame's own factors)
@@ -1313,20 +1319,25 @@ hipError_t launch_solve(const Batch& b, hipStream_t st) {
 
 hipError_t launch_synth_out(const Batch& b, hipStream_t st) {
     const int ds = b.want_sample ? 1 : 0;
-    const int gx = ds + (b.want_x ? cdiv(b.n1, kOutTM) * cdiv(b.n2, kOutTN) : 0);
-    if (gx == 0) return hipSuccess;
-    const dim3 grid = frame_grid(b, gx);
-    auto go = [&](auto one, auto bf) {
+    auto go = [&](auto one, auto bf, auto tm, auto tn) {
         constexpr bool ONE = decltype(one)::value;
-        constexpr int BF = decltype(bf)::value;
+        constexpr int BF = decltype(bf)::value, TM = decltype(tm)::value, TN = decltype(tn)::value;
+        constexpr int NT = OutShape<TM, TN>::THREADS;
+        const int gx = ds + (b.want_x ? cdiv(b.n1, TM) * cdiv(b.n2, TN) : 0);
+        if (gx == 0) return;
+        const dim3 grid = frame_grid(b, gx);
         if (b.table)
-            k_synth_out<ONE, BF, FrameTable><<<grid, kOutThreads, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
-        else k_synth_out<ONE, BF, OneFrame><<<grid, kOutThreads, 0, st>>>(OneFrame{*b.one}, ds);
+            k_synth_out<ONE, BF, TM, TN, FrameTable><<<grid, NT, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
+        else k_synth_out<ONE, BF, TM, TN, OneFrame><<<grid, NT, 0, st>>>(OneFrame{*b.one}, ds);
     };
+    using I128 = std::integral_constant<int, 128>;
+    using I64 = std::integral_constant<int, 64>;
     auto with_bf = [&](auto one) {
-        if (b.synth == SYN_BF16) go(one, std::integral_constant<int, SYN_BF16>{});
-        else if (b.synth == SYN_BF16X3) go(one, std::integral_constant<int, SYN_BF16X3>{});
-        else go(one, std::integral_constant<int, SYN_FP32>{});
+        if (b.synth == SYN_BF16) go(one, std::integral_constant<int, SYN_BF16>{}, I128{}, I64{});
+        else if (b.synth == SYN_BF16X3) go(one, std::integral_constant<int, SYN_BF16X3>{}, I128{}, I64{});
+        else if (b.out_tile == OUT_64x64) go(one, std::integral_constant<int, SYN_FP32>{}, I64{}, I64{});
+        else if (b.out_tile == OUT_128x128) go(one, std::integral_constant<int, SYN_FP32>{}, I128{}, I128{});
+        else go(one, std::integral_constant<int, SYN_FP32>{}, I128{}, I64{});
     };
     if (b.r_max <= kOutRC) with_bf(std::true_type{});
     else with_bf(std::false_type{});

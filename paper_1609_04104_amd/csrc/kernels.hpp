@@ -19,7 +19,11 @@ struct Batch {
     bool want_x;                 // some frame asks for X_t
     bool want_sample;            // some frame draws its next rows
     int synth;                   // synthesis operands (SYN_*), shared by the frames of an output launch
+    int out_tile;                // output block tile (OUT_*; FP32 synthesis), chosen by the tuner
 };
+
+// Block tiles of the output synthesis (X_t = A diag(gamma) B^T): identical results.
+enum : int { OUT_128x64 = 0, OUT_64x64 = 1, OUT_128x128 = 2, OUT_TILES = 3 };
 
 // Threads per block of the kernels that are not templated on a length.
 constexpr int kBlock = 256;

@@ -24,6 +24,7 @@ EXPORTS = [
     "tsl_opts_default", "tsl_size_supported", "tsl_footprint", "tsl_open", "tsl_close",
     "tsl_push_lines", "tsl_push_points", "tsl_push_frame", "tsl_sample_lines", "tsl_step_many",
     "tsl_step_many_noalloc", "tsl_epochs", "tsl_sample_points", "tsl_open_coils", "tsl_push_coils",
+    "tsl_output_tile", "tsl_set_output_tile",
     "tsl_step_many_timed", "tsl_batch_create", "tsl_batch_launch", "tsl_batch_destroy", "tsl_status",
     "tsl_get_factors", "tsl_get_state", "tsl_set_state", "tsl_shape", "tsl_fft2",
     "tsl_pool_create", "tsl_pool_destroy", "tsl_pool_used", "tsl_open_in_pool",
@@ -84,6 +85,8 @@ def lib():
             "tsl_epochs": (i, [vp, i, P(Frame), i, vp, vp]),
             "tsl_sample_points": (i, [vp, i, vp, vp, vp, vp]),
             "tsl_open_coils": (i, [P(vp), i, i, i, i, d, P(Opts), vp, vp, vp, vp]),
+            "tsl_output_tile": (i, [i, i, i, i]),
+            "tsl_set_output_tile": (i, [i, i, i, i, i]),
             "tsl_push_coils": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
             "tsl_step_many": (i, [P(vp), i, P(Frame), vp]),
             "tsl_step_many_noalloc": (i, [P(vp), i, P(Frame), vp]),
@@ -147,6 +150,20 @@ def footprint(n1, n2, r):
     b = ctypes.c_size_t(0)
     _check(lib().tsl_footprint(n1, n2, r, ctypes.byref(b)))
     return b.value
+
+
+OUT_TILES = {0: "128x64", 1: "64x64", 2: "128x128"}
+
+
+def output_tile(n1, n2, r, count):
+    """The output-synthesis block tile a launch of `count` frames uses now."""
+    return OUT_TILES[_check(lib().tsl_output_tile(int(n1), int(n2), int(r), int(count)))]
+
+
+def set_output_tile(n1, n2, r, count, tile):
+    """Fixes the output-synthesis tile ("128x64", "64x64" or "128x128") of such launches."""
+    code = {v: k for k, v in OUT_TILES.items()}[tile]
+    _check(lib().tsl_set_output_tile(int(n1), int(n2), int(r), int(count), code))
 
 
 def selftest_codelets():
