@@ -114,6 +114,10 @@ def counters(fetch_csv, write_csv, copy_mib, out):
     with open(out, "w") as f:
         json.dump(rec, f, indent=1, sort_keys=True)
     print(f"fetch scale {fscale:.3f}, write scale {wscale:.3f}, {len(rec['kernels'])} kernels -> {out}")
+    print("\n| kernel | dispatches | read MiB | written MiB |\n|---|---|---|---|")
+    for k, v in rec["kernels"].items():
+        if k.startswith("void k_"):
+            print(f"| {k} | {v['dispatches']} | {v['fetch_bytes'] / 2**20:.1f} | {v['write_bytes'] / 2**20:.1f} |")
 
 
 if __name__ == "__main__":
