@@ -96,21 +96,24 @@ def phase_work(n1, n2, r, rows, K, kspace=True):
     FFT = 5 N log2 N flop).  Bytes are the phase's inputs and outputs, not the
     implementation's partial sums; kinds: fp64 (FP64 vector), mfma (FP32 matrix
     cores, with the transforms' FP32 vector work counted in), fp32 (FP32 vector).
-    On the k-space route the A update also applies F_l^H to E conj(Bhat)."""
+    On the k-space route the statistics also write the data terms Y_S conj(Bhat)
+    and Y_S^T conj(Ahat_S) and copy Bhat and Ahat_S, and the update adds the model
+    terms (Ahat_S T_B and Bhat T_AS, T from the Grams) to form the residual's two
+    gradient contractions before applying F_l^H and F_r^H."""
     P, c = n1 * n2, 8
     f1, f2 = 5 * P * math.log2(n1), 5 * P * math.log2(n2)
     a, b = n1 * r, n2 * r
+    ks = 1 if kspace else 0
     return {
-        "partial Grams": (c * (a + b + rows * n2) + 4 * rows + 16 * (r * r + r),
-                          8 * (n1 + n2 + rows) * r * (r + 1) / 2 + 8 * rows * n2 * r, "fp64"),
+        "partial Grams": (c * (a + b + rows * n2) + 4 * rows + 16 * (r * r + r) + ks * 2 * c * (rows * r + b),
+                          8 * (n1 + n2 + rows) * r * (r + 1) / 2 + (1 + ks) * 8 * rows * n2 * r, "fp64"),
         "ridge solve + step size": (16 * 3 * r * r + 16 * r, 8 * r ** 3 / 3 + 6 * r * r, "fp64"),
         "synthesis + row pass": (c * (P + a + b), 8 * P * r + f2, "mfma"),
         "column pass + residual": (c * (2 * P + rows * n2 + a + b) + 4 * rows, 2 * f1 + 8 * P * r, "mfma"),
         "row inverse + A grad": (c * (P + a + b), f2 + 8 * P * r, "mfma"),
-        "k-space residual + gradients": (c * (rows * n2 + 2 * rows * r + 2 * b) + 4 * rows,
-                                         3 * 8 * rows * n2 * r, "mfma"),
-        "factor updates + F_l A, F_r B": (c * 4 * (a + b), (10 if kspace else 5) * a * math.log2(n1) + 8 * a
-                                          + 10 * b * math.log2(n2) + 8 * b, "fp32"),
+        "factor updates + F_l A, F_r B": (c * 4 * (a + b) + ks * (2 * c * (rows * r + b) + 16 * 2 * r * r),
+                                          (10 if kspace else 5) * a * math.log2(n1) + 8 * a
+                                          + 10 * b * math.log2(n2) + 8 * b + ks * 8 * (rows + n2) * r * r, "fp32"),
         "output synthesis + row draw": (c * (P + a + b) + c * a + 4 * K, 8 * P * r + 6 * a, "mfma"),
     }
 
@@ -124,7 +127,6 @@ PHASE_KERNELS = {   # kernel of each phase in a table launch of n x n frames
     "synthesis + row pass": "void k_synth_rowfft<{n}, FrameTable>",
     "column pass + residual": "void k_col_resid<{n}, FrameTable>",
     "row inverse + A grad": "void k_row_inv_grad<{n}, FrameTable>",
-    "k-space residual + gradients": "void k_kres<",
     "factor updates + F_l A, F_r B": "void k_update_ab<{n}, FrameTable>",
     "output synthesis + row draw": "void k_synth_out<",
 }
@@ -144,7 +146,7 @@ def counter_traffic(phase, n, grid=None):
     if rec.get("source_sha") != source_sha():
         return None
     want = PHASE_KERNELS[phase].format(n=n)
-    hits = [v for k, v in rec.get("kernels", {}).items() if k.startswith(want) and "FrameTable" in k]
+    hits = [v for k, v in rec.get("kernels", {}).items() if k.startswith(want) and ("FrameTable" in k or "OutTable" in k)]
     hits = [v for v in hits if v.get("dispatches", 0) > 0]
     if not hits:
         return None

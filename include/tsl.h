@@ -109,7 +109,7 @@ typedef struct {
 enum { TSL_SYNTH_FP32 = 0, TSL_SYNTH_BF16 = 1, TSL_SYNTH_BF16X3 = 2 };
 
 /* Number of timed phases reported by tsl_step_many_timed. */
-#define TSL_N_PHASES 8
+#define TSL_N_PHASES 7
 
 /* One frame of one sequence, for tsl_push_frame and tsl_step_many.  `mask`
    non-NULL selects a point mask (see tsl_push_points); otherwise the sample
@@ -294,9 +294,9 @@ int tsl_step_many_noalloc(tsl_seq* const* seqs, int n, const tsl_frame* frames, 
 /* Profiling form of tsl_step_many: runs the same kernels without a graph,
    brackets each of the TSL_N_PHASES phases (partial Grams; solve and step
    size; synthesis + row transform; column transform + residual + column
-   inverse; row inverse + A gradient [these three: frame route]; k-space
-   residual + gradient contractions [k-space route]; factor updates with
-   F_l A and F_r B of the new factors; output synthesis beside the row draw)
+   inverse; row inverse + A gradient [these three: frame route]; factor
+   updates with F_l A and F_r B of the new factors [on the k-space route also
+   the residual's gradient contractions]; output synthesis beside the row draw)
    with HIP events on `stream`, waits, and
    ADDS each phase's elapsed milliseconds to phase_ms[TSL_N_PHASES] (host). */
 int tsl_step_many_timed(tsl_seq* const* seqs, int n, const tsl_frame* frames, double* phase_ms,

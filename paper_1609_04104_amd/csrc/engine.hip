@@ -49,8 +49,10 @@ Layout layout_for(int n1, int n2, int r, int C) {
     L.frame = take(size_t(n1) * n2 * sizeof(float2));
     L.Wb = take(size_t(n2) * r * sizeof(float2));
     L.GA = take(size_t(n1) * r * sizeof(float2));
-    L.wpart = take(size_t(tsl::n_qparts(n1)) * n2 * r * sizeof(float2));
-    L.mpart = take(size_t(tsl::n_cparts(n2)) * n1 * r * sizeof(float2));
+    L.zm = take(size_t(tsl::n_sparts(n1)) * tsl::n_jparts(n2) * tsl::kSRows * r * sizeof(float2));
+    L.zw = take(size_t(tsl::n_sparts(n1)) * n2 * r * sizeof(float2));
+    L.bcopy = take(size_t(n2) * r * sizeof(float2));
+    L.acopy = take(size_t(n1) * r * sizeof(float2));
     L.part = take(size_t(tsl::n_parts(n1, n2)) * r * r * sizeof(double2));
     L.hpart = take(size_t(tsl::n_hparts(n1, n2)) * r * sizeof(double2));
     L.wq = take(size_t(tsl::cdiv(r, 16)) * n1 * sizeof(double));
@@ -81,8 +83,10 @@ tsl::FrameArgs frame_args(const tsl_seq* s, const tsl_frame& fr) {
     a.dev = s->at<tsl::SeqDev>(s->lay.dev);
     a.gamma64 = s->at<double2>(s->lay.g64); a.gamma32 = s->at<float2>(s->lay.g32);
     a.frame = s->at<float2>(s->lay.frame); a.Wb = s->at<float2>(s->lay.Wb); a.GA = s->at<float2>(s->lay.GA);
-    a.wpart = s->at<float2>(s->lay.wpart);
-    a.mpart = s->at<float2>(s->lay.mpart);
+    a.zm = s->at<float2>(s->lay.zm);
+    a.zw = s->at<float2>(s->lay.zw);
+    a.bcopy = s->at<float2>(s->lay.bcopy);
+    a.acopy = s->at<float2>(s->lay.acopy);
     a.part = s->at<double2>(s->lay.part); a.hpart = s->at<double2>(s->lay.hpart);
     a.rows = fr.rows; a.n_rows_dev = fr.mask ? nullptr : fr.n_rows_dev; a.y_full = fr.y_full ? 1 : 0;
     a.mask = fr.mask; a.y = reinterpret_cast<const float2*>(fr.y);
@@ -104,8 +108,10 @@ hipError_t launch_updates(const tsl::Batch& b, hipStream_t st) {
 }
 
 // The phases of one step (Algorithm 3 with one coil; Algorithm 4's draw of the
-// next rows runs inside the output launch, beside the output tiles).  A group runs either the three
-// frame-route phases or the k-space one; the other launchers return at once.
+// next rows runs inside the output launch, beside the output tiles).  A group
+// runs the three frame-route phases, or none of them on the k-space route,
+// whose residual contractions the statistics and update launches take over;
+// the launchers of phases a group does not run return at once.
 using PhaseFn = hipError_t (*)(const tsl::Batch&, hipStream_t);
 struct Phase {
     PhaseFn fn;
@@ -117,8 +123,7 @@ const Phase kPhases[TSL_N_PHASES] = {
     {tsl::launch_synth_rowfft, "synthesis + row pass"},    // a4, a5 (rows)
     {tsl::launch_col_resid, "column pass + residual"},     // a5 (columns), a6, a7 (columns)
     {tsl::launch_row_inv_grad, "row inverse + A grad"},    // a7 (rows), a9
-    {tsl::launch_kres, "k-space residual + gradients"},    // a4-a7 and a9's contractions on the samples
-    {launch_updates, "factor updates + F_l A, F_r B"},     // a9, a1 (one launch when n1 == n2)
+    {launch_updates, "factor updates + F_l A, F_r B"},     // a9, a1 (one launch when n1 == n2); k-space: a6, a7
     {tsl::launch_synth_out, "output synthesis + row draw"},  // a10; a11 in one more block per frame
 };
 
@@ -175,7 +180,7 @@ int acc_tier(int r) { return r <= 32 ? 2 : r <= 64 ? 4 : 8; }
 bool on_frame_route(const FrameFacts& a) { return a.mode == MODE_POINTS || !a.kspace; }
 
 // The phases in launch order (see kPhases) and the table order each reads.
-bool phase_reads_b(int p) { return p == 2 || p == 3 || p == 4 || p == 6; }
+bool phase_reads_b(int p) { return p == 2 || p == 3 || p == 4 || p == 5; }
 
 // True if frames a and b (adjacent in the phase's table order) share one launch
 // of phase p: the same kernel instantiation and launch-wide arguments.
@@ -185,8 +190,7 @@ bool same_launch(int p, const FrameFacts& a, const FrameFacts& b) {
         case 1: return rank_tier(a.r) == rank_tier(b.r);
         case 2: case 3: case 4:
             return on_frame_route(a) == on_frame_route(b) && (!on_frame_route(a) || (a.n1 == b.n1 && a.n2 == b.n2));
-        case 5: return a.kspace == b.kspace && (!a.kspace || acc_tier(a.r) == acc_tier(b.r));
-        case 6: return a.n1 == b.n1 && a.n2 == b.n2;
+        case 5: return a.n1 == b.n1 && a.n2 == b.n2 && a.kspace == b.kspace;
         default: return (a.r <= 32) == (b.r <= 32) && a.synth == b.synth;
     }
 }

@@ -12,7 +12,7 @@
 
 // Byte offsets of a sequence's arrays inside its one device arena.
 struct Layout {
-    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, wpart, mpart, part, hpart, wq;
+    size_t A, B, Ahat, Bhat, dev, g64, g32, frame, Wb, GA, zm, zw, bcopy, acopy, part, hpart, wq;
     // several coils (0 for a single-coil sequence)
     size_t H, P, Q, gslot, hslot, gain;
     size_t total;

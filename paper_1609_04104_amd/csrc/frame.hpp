@@ -60,7 +60,7 @@ template <class T> using GlobalPtr = T*;
 template <template <class> class P>
 struct FrameArgsT {
     int n1, n2, r, mode;
-    int kspace;           // line mask on the k-space route (GA holds E conj(Bhat) on the sampled rows, W in wpart)
+    int kspace;           // line mask on the k-space route (the update forms the gradients from zm, zw, the copies and the Grams)
     double lambda, mu_const;
     int step_mode, n_rows;
     int synth_bf16;       // SYN_FP32, SYN_BF16 or SYN_BF16X3 (mfma.hpp): operands of the syntheses
@@ -72,10 +72,13 @@ struct FrameArgsT {
     // workspace
     P<float2> frame;      // [n1][n2]: row-transformed synthesis, then the column-back-projected residual
     P<float2> Wb;         // [n2][r]: Z^T conj(A), Z the column-back-projected residual (= E^T conj(Ahat_S))
-    P<float2> GA;         // [n1][r]: Theta conj(B) (frame route); E conj(Bhat) on the sampled rows, else 0 (k-space route)
-    P<float2> wpart;      // [n_qparts(n1)][n2][r]: E^T conj(Ahat_S) per chunk of kKQ sampled rows (k-space route)
-    P<float2> mpart;      // [n_cparts(n2)][n1][r]: slab p >= 1 holds the part of E conj(Bhat) over samples
-                          // [kKCols p, kKCols (p + 1)) on the sampled rows, 0 elsewhere; GA holds part 0 (k-space route)
+    P<float2> GA;         // [n1][r]: Theta conj(B) (frame route)
+    // k-space route, written by the statistics launch for the update (which overwrites Ahat, Bhat):
+    P<float2> zm;         // [n_sparts(n1)][n_jparts(n2)][kSRows][r]: Y_S conj(Bhat) per chunk of sampled
+                          // rows and of readout samples (rows of a chunk in list order)
+    P<float2> zw;         // [n_sparts(n1)][n2][r]: Y_S^T conj(Ahat_S) per chunk of sampled rows
+    P<float2> bcopy;      // [n2][r]: Bhat of frame t - 1
+    P<float2> acopy;      // [n1][r]: the sampled rows of Ahat of frame t - 1, in list order
     P<double2> part;      // [n_parts][r][r] partial Grams
     P<double2> hpart;     // [n_hparts][r] partial right-hand sides
     // inputs of the frame

@@ -188,17 +188,19 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
     }
     // v[m2] = Z[s + Q*m2][col] for threads s < Q.  W[col][r] = sum_i Z[i][col] conj(A[i][r])
     // on the matrix cores: M = the block's kTW columns (lane % 16), N = 16 ranks
-    // per tile, and the K index runs over (row, re/im), each lane feeding its own
-    // rows.  With Re W = sum Zr Ar + Zi Ai and Im W = sum Zi Ar - Zr Ai, a row
-    // costs four 16x16x4 steps per rank tile.  The wavefronts' partial sums over
-    // their rows meet in LDS and are added in wavefront order.
+    // per tile, and the K index runs over rows, each lane feeding its own rows.
+    // Gauss's three-multiplication form with the conjugate's sign on the factor:
+    // P1 = sum Zr Ar, P2 = sum Zi (-Ai), P3 = sum (Zr + Zi)(Ar - Ai), so that
+    // Re W = P1 - P2 and Im W = P3 - P1 - P2: three 16x16x4 steps per four rows
+    // and rank tile.  The wavefronts' partial sums over their rows meet in LDS and
+    // are added in wavefront order.
     static_assert(kTW == 16, "one MFMA row per column of the tile");
     float2* s_w = s_u;                                   // [wave][c][WNT * 16]
     bool bad = false;
     for (int n0 = 0; n0 < R; n0 += WNT * 16) {
-        f32x4 accr[WNT], acci[WNT];
+        f32x4 p1[WNT], p2[WNT], p3[WNT];
 #pragma unroll
-        for (int u = 0; u < WNT; ++u) accr[u] = acci[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int u = 0; u < WNT; ++u) p1[u] = p2[u] = p3[u] = f32x4{0.f, 0.f, 0.f, 0.f};
         if (n0 > 0) load_a(n0);                          // all factor operands in flight at once
         sfor<P>([&](auto mc) {
             constexpr int m2 = decltype(mc)::value;
@@ -206,10 +208,9 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
 #pragma unroll
             for (int u = 0; u < WNT; ++u) {
                 const float2 a = av[m2][u];
-                accr[u] = mfma_16x16x4(z.x, a.x, accr[u]);
-                accr[u] = mfma_16x16x4(z.y, a.y, accr[u]);
-                acci[u] = mfma_16x16x4(z.y, a.x, acci[u]);
-                acci[u] = mfma_16x16x4(-z.x, a.y, acci[u]);
+                p1[u] = mfma_16x16x4(z.x, a.x, p1[u]);
+                p2[u] = mfma_16x16x4(z.y, -a.y, p2[u]);
+                p3[u] = mfma_16x16x4(z.x + z.y, a.x - a.y, p3[u]);
             }
         });
         __syncthreads();
@@ -218,7 +219,8 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int cc = 4 * (lane / 16) + e;                // column of the tile
-                s_w[(wave * kTW + cc) * (WNT * 16) + 16 * u + n] = float2{accr[u][e], acci[u][e]};
+                s_w[(wave * kTW + cc) * (WNT * 16) + 16 * u + n] =
+                    float2{p1[u][e] - p2[u][e], p3[u][e] - p1[u][e] - p2[u][e]};
             }
         __syncthreads();
         for (int e = tid; e < kTW * WNT * 16; e += blockDim.x) {
@@ -281,11 +283,176 @@ __device__ __forceinline__ void row_weight_parts(const DevFrame& f, int bx, cons
     }
 }
 
+// ---------------------------------------------------------------- k-space gradients
+// On the k-space route (line masks) the residual E = Y_S - Ahat_S diag(gamma) Bhat^T
+// of Algorithm 3 on the samples is not formed.  Its two contractions with the
+// factors split into a data term and a model term,
+//     M = E conj(Bhat)     = Y_S conj(Bhat)     + Ahat_S T_B,  T_B[s][r] = -gamma_s G_B[r][s],
+//     W = E^T conj(Ahat_S) = Y_S^T conj(Ahat_S) + Bhat T_AS,   T_AS[s][r] = -gamma_s G_AS[r][s],
+// with G_B = Bhat^H Bhat and G_AS = Ahat_S^H Ahat_S the Grams that the statistics
+// launch already sums for the solve (sum_j Bhat_js conj(Bhat_jr) = G_B[r][s]).
+// The statistics launch leaves the data terms (partials per chunk) and copies
+// of Bhat and of the sampled rows of Ahat of frame t - 1 (this launch
+// overwrites both); the update block of ranks [r0, r0 + kTW) adds the partials
+// of its columns and the model term, K = R, on the matrix cores.
+
+// Entry (r, s) of a Hermitian Gram summed over `ns` partial slots in slot order
+// (a slot holds the entries on and above the diagonal, [R][R]); eight slots'
+// loads go out before their adds (indices clamped, values past ns selected away).
+__device__ __forceinline__ double2 gram_entry(GlobalPtr<const double2> slots, int ns, int R, int r, int s) {
+    const bool up = r <= s;
+    const size_t at = up ? size_t(r) * R + s : size_t(s) * R + r;
+    double2 acc{0.0, 0.0};
+    for (int k0 = 0; k0 < ns; k0 += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double2 x = slots[size_t(k0 + u < ns ? k0 + u : k0) * R * R + at];
+            v[u] = k0 + u < ns ? x : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            acc.x += v[u].x;
+            acc.y += v[u].y;
+        }
+    }
+    return up ? acc : double2{acc.x, -acc.y};
+}
+
+// s_T[s][c] = -gamma_s G[r0 + c][s] (FP64 product, stored as complex64; 0 past
+// the rank): the model term's factor with its sign.
+__device__ __forceinline__ void fill_model_t(const DevFrame& f, GlobalPtr<const double2> slots, int ns, int r0,
+                                             float2* s_T) {
+    const int R = f.r;
+    for (int e = threadIdx.x; e < R * kTW; e += blockDim.x) {
+        const int sr = e / kTW, r = r0 + e % kTW;
+        float2 t{0.f, 0.f};
+        if (r < R) {
+            const double2 gm = gram_entry(slots, ns, R, r, sr);
+            const double2 gs = f.gamma64[sr];
+            t = float2{float(-(gs.x * gm.x - gs.y * gm.y)), float(-(gs.x * gm.y + gs.y * gm.x))};
+        }
+        s_T[e] = t;
+    }
+}
+
+// store(e, sum over k < np of at(e, k)) for every e < n (thread-strided), the
+// sums in part order in FP64; E elements per thread and C parts at a time have
+// their loads in flight together (indices clamped, values past the ends
+// selected away).
+template <int E, int C, class At, class Store>
+__device__ __forceinline__ void sum_fill(int n, int np, At at, Store store) {
+    const int nt = int(blockDim.x);
+    for (int e0 = int(threadIdx.x); e0 < n; e0 += E * nt) {
+        double2 acc[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) acc[u] = double2{0.0, 0.0};
+        for (int k0 = 0; k0 < np; k0 += C) {
+            float2 v[E][C];
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+#pragma unroll
+                for (int w = 0; w < C; ++w) {
+                    const int e = e0 + u * nt, k = k0 + w;
+                    const float2 x = at(min(e, n - 1), min(k, np - 1));
+                    v[u][w] = (e < n && k < np) ? x : float2{0.f, 0.f};
+                }
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+#pragma unroll
+                for (int w = 0; w < C; ++w) {
+                    acc[u].x += v[u][w].x;
+                    acc[u].y += v[u][w].y;
+                }
+        }
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int e = e0 + u * nt;
+            if (e < n) store(e, float2{float(acc[u].x), float(acc[u].y)});
+        }
+    }
+}
+
+// s_out[row_of(q)][c] += sum_{s < R} X[q][s] s_T[s][c] for q < nrows, c < kTW
+// (X: [nrows][R] complex64) on the FP32 matrix cores in Gauss's three-product
+// form (M = 16 rows, N = kTW ranks, K = four ranks per step).  A wavefront takes
+// kMI row tiles per round; the K loop is the outer one, so that one group of
+// operand loads serves all of them, and the next group's loads go out before
+// the current group's products.  Every thread of the block calls it.
+constexpr int kMI = 4;   // row tiles per wavefront and round
+constexpr int kMC = 2;   // K steps per operand group
+template <class RowOf>
+__device__ __forceinline__ void model_add(GlobalPtr<const float2> X, int nrows, int R, const float2* s_T,
+                                          float2* s_out, RowOf row_of) {
+    static_assert(kTW == 16, "one matrix-core column tile of ranks per block");
+    const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int nw = int(blockDim.x) / 64, m = lane % 16, g = lane / 16;
+    const int ntile = cdiv(nrows, 16), nst = cdiv(R, 4);
+    for (int base = wave; base < ntile; base += kMI * nw) {
+        f32x4 p1[kMI], p2[kMI], p3[kMI];
+#pragma unroll
+        for (int u = 0; u < kMI; ++u) p1[u] = p2[u] = p3[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        float2 xa0[kMI][kMC], tb0[kMC], xa1[kMI][kMC], tb1[kMC];
+        auto load = [&](int st0, float2 (&xa)[kMI][kMC], float2 (&tb)[kMC]) {
+#pragma unroll
+            for (int v = 0; v < kMC; ++v) {
+                const int k = 4 * (st0 + v) + g, kc = min(k, R - 1);
+                const bool ok = st0 + v < nst && k < R;
+                const float2 t0 = s_T[kc * kTW + m];
+                tb[v] = ok ? t0 : float2{0.f, 0.f};
+#pragma unroll
+                for (int u = 0; u < kMI; ++u) {
+                    const int q = 16 * (base + nw * u) + m;
+                    const float2 x = X[size_t(min(q, nrows - 1)) * R + kc];
+                    xa[u][v] = (ok && q < nrows) ? x : float2{0.f, 0.f};
+                }
+            }
+        };
+        auto products = [&](const float2 (&xa)[kMI][kMC], const float2 (&tb)[kMC]) {
+#pragma unroll
+            for (int v = 0; v < kMC; ++v)
+#pragma unroll
+                for (int u = 0; u < kMI; ++u) {
+                    const float2 x = xa[u][v], y = tb[v];
+                    p1[u] = mfma_16x16x4(x.x, y.x, p1[u]);
+                    p2[u] = mfma_16x16x4(x.y, y.y, p2[u]);
+                    p3[u] = mfma_16x16x4(x.x + x.y, y.x + y.y, p3[u]);
+                }
+        };
+        load(0, xa0, tb0);
+        for (int st0 = 0; st0 < nst; st0 += 2 * kMC) {
+            if (st0 + kMC < nst) load(st0 + kMC, xa1, tb1);
+            products(xa0, tb0);
+            if (st0 + kMC >= nst) break;
+            if (st0 + 2 * kMC < nst) load(st0 + 2 * kMC, xa0, tb0);
+            products(xa1, tb1);
+        }
+        // D[4 g + i][m] of tile base + nw u: row 16 tile + 4 g + i, column m
+#pragma unroll
+        for (int u = 0; u < kMI; ++u)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q = 16 * (base + nw * u) + 4 * g + i;
+                if (q < nrows) {
+                    float2& o = s_out[row_of(q) * kTW + m];
+                    o = float2{o.x + (p1[u][i] - p2[u][i]), o.y + (p3[u][i] - p1[u][i] - p2[u][i])};
+                }
+            }
+    }
+}
+
+// Sampled-row count of a k-space frame (clamped as the statistics launch clamps it).
+__device__ __forceinline__ int kspace_rows(const DevFrame& f) { return frame_rows(f); }
+
+// Dynamic LDS of a k-space update block: s_T [R][kTW], s_rows [n1].
+__host__ __device__ constexpr size_t grad_lds(int R, int n1) { return size_t(R) * kTW * 8 + size_t(n1) * 4; }
+
 // ---------------------------------------------------------------- K4 (A)
 // Block bx of the A update of one frame (ranks [kTW bx, kTW bx + kTW)); s_tw
 // holds N1 twiddles, s_x the exchange area of ColShape<N1>.
 template <int N1>
-__device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2* s_tw, float2* s_x, double* s_cp) {
+__device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2* s_tw, float2* s_x, double* s_cp,
+                                              float2* s_dyn) {
     using S = ColShape<N1>;
     static_assert(S::XSIZE >= N1 * kTW, "the exchange area holds the energies of the block's columns");
     constexpr int P = S::P, Q = S::Q, T = S::T;
@@ -295,29 +462,14 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
     const int r = bx * kTW + c;
     const bool rv = r < R;
     // Loads that need only the descriptor go out before the status check (inside
-    // the frame's own buffers): twiddles, gamma, GA and A (k-space route: A at
-    // the update's layout after the transform; frame route: both in row order).
+    // the frame's own buffers): twiddles, gamma, and on the frame route A and GA
+    // (both in row order; the k-space route loads A later).
     load_tw<N1>(s_tw);
     const double2 g = rv ? f.gamma64[r] : double2{0.0, 0.0};
-    float2 v[T], apre[T], w1[P];
+    float2 v[T], apre[T];
     zero(v);
     zero(apre);
-    const int ncp = f.kspace ? n_cparts(f.n2) : 1;   // slabs of E conj(Bhat): GA, then mpart 1..
-    if (f.kspace) {
-        if (s < Q && rv) {
-            sfor<P>([&](auto qc) {
-                constexpr int n1c = decltype(qc)::value;
-                v[n1c] = f.GA[size_t(Q * n1c + s) * R + r];
-                w1[n1c] = ncp > 1 ? float2(f.mpart[(size_t(N1) + Q * n1c + s) * R + r]) : float2{0.f, 0.f};
-            });
-        }
-        if (s < P && rv) {
-            sfor<Q>([&](auto k) {
-                constexpr int k2 = decltype(k)::value;
-                apre[k2] = f.A[size_t(s + P * k2) * R + r];
-            });
-        }
-    } else if (s < Q && rv) {
+    if (!f.kspace && s < Q && rv) {
         sfor<P>([&](auto q) {
             constexpr int n1c = decltype(q)::value;
             const size_t at = size_t(Q * n1c + s) * R + r;
@@ -333,22 +485,42 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
         d->t = d->t_new;
     }
     if (f.kspace) {
-        // M = the slabs added in order (the first two were loaded above)
-        if (s < Q && rv) {
+        // Theta conj(B) = F_l^H M with M = E conj(Bhat) on the sampled rows and
+        // zero elsewhere (above), built in s_x as [N1][kTW] with row i of the
+        // frame at i kTW: the data term's partials over the readout chunks, then
+        // the model term added.
+        const int nS = kspace_rows(f), r0 = bx * kTW, nJ = n_jparts(f.n2);
+        float2* s_T = s_dyn;
+        int* s_rows = reinterpret_cast<int*>(s_T + R * kTW);
+        for (int e = tid; e < N1 * kTW; e += blockDim.x) s_x[e] = float2{0.f, 0.f};
+        for (int q = tid; q < nS; q += blockDim.x) s_rows[q] = f.rows[q];
+        fill_model_t(f, f.part + size_t(n_gparts(N1)) * R * R, n_gparts(f.n2), r0, s_T);
+        __syncthreads();
+        GlobalPtr<const float2> Zm = f.zm;
+        sum_fill<4, 4>(
+            nS * kTW, nJ,
+            [&](int e, int j) {
+                const int q = e / kTW, rr = min(r0 + e % kTW, R - 1);
+                return float2(Zm[((size_t(q / kSRows) * nJ + j) * kSRows + q % kSRows) * R + rr]);
+            },
+            [&](int e, float2 z) { s_x[s_rows[e / kTW] * kTW + e % kTW] = r0 + e % kTW < R ? z : float2{0.f, 0.f}; });
+        __syncthreads();
+        model_add(f.acopy, nS, R, s_T, s_x, [&](int q) { return s_rows[q]; });
+        // A at the update's layout after the transform (loaded here, where the
+        // model term no longer holds registers; it arrives during the transform)
+        if (s < P && rv)
+            sfor<Q>([&](auto k) {
+                constexpr int k2 = decltype(k)::value;
+                apre[k2] = f.A[size_t(s + P * k2) * R + r];
+            });
+        __syncthreads();
+        if (s < Q && rv)
             sfor<P>([&](auto qc) {
                 constexpr int n1c = decltype(qc)::value;
-                if (ncp > 1) v[n1c] = cadd(v[n1c], w1[n1c]);
+                v[n1c] = s_x[(Q * n1c + s) * kTW + c];
             });
-            for (int p = 2; p < ncp; ++p)
-                sfor<P>([&](auto qc) {
-                    constexpr int n1c = decltype(qc)::value;
-                    v[n1c] = cadd(v[n1c], float2(f.mpart[(size_t(p) * N1 + Q * n1c + s) * R + r]));
-                });
-        }
-        // k-space route: Theta conj(B) = F_l^H M with M = E conj(Bhat) on the
-        // sampled rows and zero elsewhere (as the k-space residual kernel left the slabs);
-        // then the update in the transform's output layout and F_l A of the new
-        // A, as in the B update.
+        // then the update in the transform's output layout and F_l A of the
+        // new A, as in the B update
         __syncthreads();
         if (s < Q) dft_twiddle<N1, P, true>(v, s, s_tw);
         col_swap_nk<N1>(v, s_x, c, s);
@@ -427,20 +599,23 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
     row_weight_parts<N1>(f, bx, s_e, s_cp);
 }
 
+// Dynamic LDS of the update launches: the k-space gradients' areas (grad_lds).
 template <int N1, class Src>
 __global__ void __launch_bounds__(512) k_update_a(Src src) {
+    extern __shared__ float2 s_dyn[];
     __shared__ float2 s_tw[N1];
     __shared__ float2 s_x[ColShape<N1>::XSIZE];
     __shared__ double s_cp[kWeightParts];
     if (!src.live()) return;
-    update_a_body<N1>(src.get(), src.bx(), s_tw, s_x, s_cp);
+    update_a_body<N1>(src.get(), src.bx(), s_tw, s_x, s_cp, s_dyn);
 }
 
 // ---------------------------------------------------------------- K4 (B)
 // Block bx of the B update of one frame, as the A update above.
 template <int N2>
-__device__ __forceinline__ void update_b_body(const DevFrame& f, int bx, float2* s_tw, float2* s_x) {
+__device__ __forceinline__ void update_b_body(const DevFrame& f, int bx, float2* s_tw, float2* s_x, float2* s_dyn) {
     using S = ColShape<N2>;
+    static_assert(S::XSIZE >= N2 * kTW, "the exchange area holds the block's columns of W");
     constexpr int P = S::P, Q = S::Q, T = S::T;
     const int R = f.r;
     if (bx * kTW >= R) return;
@@ -448,48 +623,50 @@ __device__ __forceinline__ void update_b_body(const DevFrame& f, int bx, float2*
     const int r = bx * kTW + c;
     const bool rv = r < R;
     // Loads that need only the descriptor go out before the status check (inside
-    // the frame's own buffers): twiddles, gamma, W (on the k-space route the
-    // first chunk's partial), B at the update's layout and the row count.
+    // the frame's own buffers): twiddles, gamma, and on the frame route W and B
+    // at the update's layout (the k-space route loads B later).
     load_tw<N2>(s_tw);
     const double2 g = rv ? f.gamma64[r] : double2{0.0, 0.0};
     float2 v[T];
     zero(v);
-    if (s < Q && rv) {
+    if (!f.kspace && s < Q && rv) {
         sfor<P>([&](auto q) {
             constexpr int n1c = decltype(q)::value;
-            const size_t at = size_t(Q * n1c + s) * R + r;
-            v[n1c] = f.kspace ? f.wpart[at] : f.Wb[at];
+            v[n1c] = f.Wb[size_t(Q * n1c + s) * R + r];
         });
     }
     float2 bpre[Q];
-    sfor<Q>([&](auto k) {
-        constexpr int k2 = decltype(k)::value;
-        bpre[k2] = (s < P && rv) ? float2(f.B[size_t(s + P * k2) * R + r]) : float2{0.f, 0.f};
-    });
-    const int cap = frame_rows_cap(f);
-    const int nd = (f.kspace && f.n_rows_dev) ? *f.n_rows_dev : cap;
+    auto load_bpre = [&]() {
+        sfor<Q>([&](auto k) {
+            constexpr int k2 = decltype(k)::value;
+            bpre[k2] = (s < P && rv) ? float2(f.B[size_t(s + P * k2) * R + r]) : float2{0.f, 0.f};
+        });
+    };
+    if (!f.kspace) load_bpre();
     if (!block_frame_ok(f.dev, true)) return;
     const SeqDev* d = f.dev;
     const double mu = d->mu, sh = d->shrink;
-    if (f.kspace && s < Q && rv) {
-        // W = sum over the chunks of sampled rows of E^T conj(Ahat_S), in chunk
-        // order (the first is already in v), two chunks' loads in flight at a time
-        const int nqc = cdiv(nd < 0 ? 0 : (nd > cap ? cap : nd), kKQ);
-        if (nqc == 0) zero(v);
-        for (int c0 = 1; c0 < nqc; c0 += 2) {
-            float2 w0[P], w1[P];
+    if (f.kspace) {
+        // W = E^T conj(Ahat_S) (above), built in s_x as [N2][kTW]: the data
+        // term's partials over the chunks of sampled rows, then the model term
+        const int nsc = cdiv(kspace_rows(f), kSRows), r0 = bx * kTW;
+        float2* s_T = s_dyn;
+        const int gAB = n_gparts(f.n1) + n_gparts(N2);
+        GlobalPtr<const float2> Zw = f.zw;
+        sum_fill<8, 1>(
+            N2 * kTW, nsc,
+            [&](int e, int k) { return float2(Zw[(size_t(k) * N2 + e / kTW) * R + min(r0 + e % kTW, R - 1)]); },
+            [&](int e, float2 z) { s_x[e] = r0 + e % kTW < R ? z : float2{0.f, 0.f}; });
+        fill_model_t(f, f.part + size_t(gAB) * R * R, nsc, r0, s_T);
+        __syncthreads();
+        model_add(f.bcopy, N2, R, s_T, s_x, [](int j) { return j; });
+        load_bpre();                          // B at the update's layout, arriving during the transform
+        __syncthreads();
+        if (s < Q && rv)
             sfor<P>([&](auto q) {
                 constexpr int n1c = decltype(q)::value;
-                const size_t at = size_t(Q * n1c + s) * R + r;
-                w0[n1c] = f.wpart[size_t(c0) * N2 * R + at];
-                w1[n1c] = c0 + 1 < nqc ? float2(f.wpart[size_t(c0 + 1) * N2 * R + at]) : float2{0.f, 0.f};
+                v[n1c] = s_x[(Q * n1c + s) * kTW + c];
             });
-            sfor<P>([&](auto q) {
-                constexpr int n1c = decltype(q)::value;
-                v[n1c] = cadd(v[n1c], w0[n1c]);
-                if (c0 + 1 < nqc) v[n1c] = cadd(v[n1c], w1[n1c]);
-            });
-        }
     }
     __syncthreads();
     // Theta^T conj(A) = F_r^H W: inverse transform along the row index of W.
@@ -529,23 +706,25 @@ __device__ __forceinline__ void update_b_body(const DevFrame& f, int bx, float2*
 
 template <int N2, class Src>
 __global__ void __launch_bounds__(512) k_update_b(Src src) {
+    extern __shared__ float2 s_dyn[];
     __shared__ float2 s_tw[N2];
     __shared__ float2 s_x[ColShape<N2>::XSIZE];
     if (!src.live()) return;
-    update_b_body<N2>(src.get(), src.bx(), s_tw, s_x);
+    update_b_body<N2>(src.get(), src.bx(), s_tw, s_x, s_dyn);
 }
 
 // Both updates in one launch for square frames (they are independent: each
 // uses the factors of frame t - 1): blocks [0, ga) update A, the rest B.
 template <int N, class Src>
 __global__ void __launch_bounds__(512) k_update_ab(Src src, int ga) {
+    extern __shared__ float2 s_dyn[];
     __shared__ float2 s_tw[N];
     __shared__ float2 s_x[ColShape<N>::XSIZE];
     __shared__ double s_cp[kWeightParts];
     if (!src.live()) return;
     const DevFrame f = src.get();
-    if (src.bx() < ga) update_a_body<N>(f, src.bx(), s_tw, s_x, s_cp);
-    else update_b_body<N>(f, src.bx() - ga, s_tw, s_x);
+    if (src.bx() < ga) update_a_body<N>(f, src.bx(), s_tw, s_x, s_cp, s_dyn);
+    else update_b_body<N>(f, src.bx() - ga, s_tw, s_x, s_dyn);
 }
 
 // ---------------------------------------------------------------- standalone column pass
@@ -593,27 +772,32 @@ template <int N1> hipError_t launch_k2_n(const Batch& b, hipStream_t st) {
     else k_col_resid<N1, OneFrame><<<grid, S::THREADS64, 0, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
+// The update launches take whole wavefronts (the k-space gradients run on the
+// matrix cores) and, on the k-space route, s_T in dynamic LDS.
+inline size_t update_lds(const Batch& b) { return b.kspace ? grad_lds(b.r_max, b.n1) : 0; }
 template <int N1> hipError_t launch_k4a_n(const Batch& b, hipStream_t st) {
     using S = ColShape<N1>;
     const int ga = cdiv(b.r_max, kTW);
+    const size_t lds = update_lds(b);
     if (b.n1 == b.n2) {                       // both updates in one launch
         const int gx = 2 * ga;
         const dim3 grid = frame_grid(b, gx);
-        if (b.table) k_update_ab<N1, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table, gx, b.count}, ga);
-        else k_update_ab<N1, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one}, ga);
+        if (b.table) k_update_ab<N1, FrameTable><<<grid, S::THREADS64, lds, st>>>(FrameTable{b.table, gx, b.count}, ga);
+        else k_update_ab<N1, OneFrame><<<grid, S::THREADS64, lds, st>>>(OneFrame{*b.one}, ga);
         return hipGetLastError();
     }
     const dim3 grid = frame_grid(b, ga);
-    if (b.table) k_update_a<N1, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table, ga, b.count});
-    else k_update_a<N1, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one});
+    if (b.table) k_update_a<N1, FrameTable><<<grid, S::THREADS64, lds, st>>>(FrameTable{b.table, ga, b.count});
+    else k_update_a<N1, OneFrame><<<grid, S::THREADS64, lds, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 template <int N2> hipError_t launch_k4b_n(const Batch& b, hipStream_t st) {
     using S = ColShape<N2>;
     const int gb = cdiv(b.r_max, kTW);
     const dim3 grid = frame_grid(b, gb);
-    if (b.table) k_update_b<N2, FrameTable><<<grid, S::THREADS, 0, st>>>(FrameTable{b.table, gb, b.count});
-    else k_update_b<N2, OneFrame><<<grid, S::THREADS, 0, st>>>(OneFrame{*b.one});
+    const size_t lds = update_lds(b);
+    if (b.table) k_update_b<N2, FrameTable><<<grid, S::THREADS64, lds, st>>>(FrameTable{b.table, gb, b.count});
+    else k_update_b<N2, OneFrame><<<grid, S::THREADS64, lds, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 template <int N1>

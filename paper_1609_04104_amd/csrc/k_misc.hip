@@ -6,7 +6,12 @@
 //               Hadamard product (Ahat_S^H Ahat_S) .* (Bhat^H Bhat) and
 //               Phi^H y = sum_{i in S} conj(Ahat_i) .* (y_i conj(Bhat)); with a
 //               point mask both are summed entry by entry.  Partials cover row
-//               chunks and are reduced in a fixed order by the solve.
+//               chunks and are reduced in a fixed order by the solve.  On the
+//               k-space route the same launch also leaves the data terms of the
+//               residual's two gradient contractions, Y_S conj(Bhat) and
+//               Y_S^T conj(Ahat_S) (partials per chunk, from the operands it has
+//               staged anyway), and copies of Bhat and of the sampled rows of
+//               Ahat for the update (k_col.hip), which overwrites both.
 //  k_solve      G = Phi^H Phi + lambda I, Cholesky, gamma_t = G^{-1} Phi^H y (the
 //               closed form of the ridge problem), the step size alpha_t of the
 //               majorizer (Sec. III-A; Gershgorin bound of diag(g)^H A^H A diag(g)
@@ -116,10 +121,14 @@ __device__ void factor_gram_block(const DevFrame& f, int b, float2* s_x, bool ch
         for (int u = 0; u < kFL; ++u)     // clamped index: no branch between the loads
             v[u] = float2(X[min(e0 + int(threadIdx.x) + u * kSB, ne - 1)]);
         if (e0 == 0 && check && !block_frame_ok(f.dev, false)) return;   // uniform
+        const bool keep = !isA && f.kspace;      // the k-space update reads Bhat of frame t - 1 from the copy
 #pragma unroll
         for (int u = 0; u < kFL; ++u) {
             const int e = e0 + int(threadIdx.x) + u * kSB;
-            if (e < ne) s_x[e] = v[u];
+            if (e < ne) {
+                s_x[e] = v[u];
+                if (keep) f.bcopy[size_t(q0) * R + e] = v[u];
+            }
         }
     }
     __syncthreads();
@@ -227,7 +236,11 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             const int e = e0 + tid + u * kSB;
-            if (e < nx) s_x[e] = xr[u] >= 0 ? xv[u] : float2{0.f, 0.f};
+            if (e < nx) {
+                const float2 x = xr[u] >= 0 ? xv[u] : float2{0.f, 0.f};
+                s_x[e] = x;
+                if (gram_role && f.kspace) f.acopy[size_t(q0) * R + e] = x;   // Ahat_S of frame t - 1
+            }
             if (e < ny) {
                 const bool live = yr[u] >= 0 && e % kJCH < nj;
                 const float2 y = live ? yv[u] : float2{0.f, 0.f};
@@ -266,6 +279,32 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
             zp3[u] = mfma_16x16x4_f64(yv.x + yv.y, bv.x - bv.y, zp3[u]);
         }
     }
+    if (f.kspace) {
+        // k-space route: zw[j][r] = sum_q y_qj conj(Ahat_{row_q, r}) over the
+        // block's rows and samples, the chunk's share of Y_S^T conj(Ahat_S), on
+        // the FP32 matrix cores (M = samples, N = ranks, K = four rows per step;
+        // three-product form with the conjugate's sign on the factor)
+        const int TMj = (nj + 15) / 16, nwt = TMj * TMr;
+        for (int tile = wave; tile < nwt; tile += kSB / 64) {
+            const int tj = tile / TMr, tr = tile % TMr, jj = 16 * tj + m, rr = 16 * tr + m;
+            f32x4 w1{0.f, 0.f, 0.f, 0.f}, w2{0.f, 0.f, 0.f, 0.f}, w3{0.f, 0.f, 0.f, 0.f};
+            for (int q4 = 0; q4 < nq; q4 += 4) {
+                const int q = q4 + g, qc = min(q, nq - 1);
+                const float2 yf = s_y[qc * kJCH + min(jj, kJCH - 1)], af = s_x[qc * R + min(rr, R - 1)];
+                const bool yok = q < nq && jj < nj, aok = q < nq && rr < R;
+                const float yr = yok ? yf.x : 0.f, yi = yok ? yf.y : 0.f;
+                const float ar = aok ? af.x : 0.f, ai = aok ? -af.y : 0.f;
+                w1 = mfma_16x16x4(yr, ar, w1);
+                w2 = mfma_16x16x4(yi, ai, w2);
+                w3 = mfma_16x16x4(yr + yi, ar + ai, w3);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = 16 * tj + 4 * g + i, r = 16 * tr + m;
+                if (j < nj && r < R) f.zw[(size_t(k) * n2 + j0 + j) * R + r] = float2{w1[i] - w2[i], w3[i] - w1[i] - w2[i]};
+            }
+        }
+    }
     __syncthreads();                          // s_b and s_y are reused for the products below
     double2* s_p = reinterpret_cast<double2*>(s_b);   // [nq][R]: z[q][r] conj(Ahat_{row_q, r})
 #pragma unroll
@@ -276,7 +315,10 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
         for (int i = 0; i < 4; ++i) {
             const int q = 16 * (tile / TMr) + 4 * i + g, r = 16 * (tile % TMr) + m;
             const double2 z{zp1[u][i] - zp2[u][i], zp3[u][i] - zp1[u][i] - zp2[u][i]};
-            if (q < nq && r < R) s_p[q * R + r] = dcmulc(z, widen(s_x[q * R + r]));
+            if (q < nq && r < R) {
+                s_p[q * R + r] = dcmulc(z, widen(s_x[q * R + r]));
+                if (f.kspace) f.zm[((size_t(k) * nJ + c) * kSRows + q) * R + r] = float2{float(z.x), float(z.y)};
+            }
         }
     }
     __syncthreads();
@@ -707,8 +749,12 @@ template <int RB, class Src>
 __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     static_assert(RB <= 64 && kRegBlk % RB == 0 && (kRegBlk / RB) <= 64, "row groups must sit inside a wavefront");
     constexpr int TPR = kRegBlk / RB;                       // threads per row in the Gershgorin sums
-    __shared__ double2 s_g[RB * RB];       // G row-major, then L below the diagonal
-    __shared__ double s_m[2][RB * RB];     // |(F_l A)^H F_l A|, |(F_r B)^H F_r B|
+    // Row pitch of the LDS matrices: one element more than a row, so that a
+    // column read or written across lanes (row i in lane i) spreads over the
+    // banks instead of landing every lane on the same ones.
+    constexpr int GP = RB + 1;
+    __shared__ double2 s_g[RB * GP];       // G row-major, then L below the diagonal
+    __shared__ double s_m[2][RB * GP];     // |(F_l A)^H F_l A|, |(F_r B)^H F_r B|
     __shared__ double2 s_h[RB];            // gamma
     __shared__ double2 s_hp[kRegBlk];      // the first kRegBlk right-hand-side partial entries
     __shared__ double2 s_c[2][RB];         // column k of the partly reduced G during step k (two buffers)
@@ -733,6 +779,10 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     const double2* pb = f.part + gA * RR;     // slots of (F_r B)^H F_r B
     const double2* ps = f.part + gAB * RR;    // slots of the sampled part
     const double lam = f.lambda;
+    // the step size's inputs (unchanged until this frame commits), read now so
+    // that the epilogue does not wait for them
+    const long long t_prev = d->t;
+    const double abar_prev = d->abar;
 
     // Gather.  A slot holds the upper triangle: entry (r, c), r <= c, is G_rc.
     // Each thread takes upper entries (packed by rows) and writes both (i, j)
@@ -813,13 +863,13 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
             v = double2{1.0, 0.0};                    // identity padding
         }
         const double am = dabs(ma[u]), bm = dabs(mb[u]);
-        s_g[i * RB + j] = v;
-        s_m[0][i * RB + j] = am;
-        s_m[1][i * RB + j] = bm;
+        s_g[i * GP + j] = v;
+        s_m[0][i * GP + j] = am;
+        s_m[1][i * GP + j] = bm;
         if (i != j) {
-            s_g[j * RB + i] = double2{v.x, -v.y};
-            s_m[0][j * RB + i] = am;
-            s_m[1][j * RB + i] = bm;
+            s_g[j * GP + i] = double2{v.x, -v.y};
+            s_m[0][j * GP + i] = am;
+            s_m[1][j * GP + i] = bm;
         }
     }
     __syncthreads();
@@ -856,7 +906,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
         double2 gr[CPL];
         sfor<CPL>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            gr[m] = s_g[i * RB + NG * m + g];
+            gr[m] = s_g[i * GP + NG * m + g];
         });
         if (wave == 0) gather_h(i);
         if (g == 0) s_c[0][i] = gr[0];
@@ -875,7 +925,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
             const double2 li{ci.x * ik, ci.y * ik};             // L_ik
             if (wave == 0) {
                 if (i == k) dinv = ik;
-                if (lane < RB && i > k) s_g[i * RB + k] = li;
+                if (lane < RB && i > k) s_g[i * GP + k] = li;
                 const double2 zk = readlane_d2(hv, k);          // z_k
                 if (i > k) {
                     hv.x = fma(-li.x, zk.x, fma(li.y, zk.y, hv.x));
@@ -924,7 +974,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
         const int i = lane % RB, h = lane / RB;
         sfor<CPL>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            gr[m] = s_g[i * RB + NG * m + h];
+            gr[m] = s_g[i * GP + NG * m + h];
         });
         gather_h(i);
         if (h == 0) s_c[0][i] = gr[0];
@@ -941,7 +991,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
             if (i == k) dinv = ik;
             const double2 ci = s_c[k % 2][i];                   // G_ik
             const double2 li{ci.x * ik, ci.y * ik};             // L_ik
-            if (h == 0 && i > k) s_g[i * RB + k] = li;
+            if (h == 0 && i > k) s_g[i * GP + k] = li;
             const double2 zk = readlane_d2(hv, k);              // z_k
             if (i > k) {
                 hv.x = fma(-li.x, zk.x, fma(li.y, zk.y, hv.x));
@@ -987,7 +1037,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
             double2 lcol[kBS];
             sfor<kBS>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
-                lcol[k] = lane < RB ? s_g[(k0 + k) * RB + lane] : double2{0.0, 0.0};
+                lcol[k] = lane < RB ? s_g[(k0 + k) * GP + lane] : double2{0.0, 0.0};
             });
             sfor<kBS>([&](auto kc) {
                 constexpr int kk = kBS - 1 - decltype(kc)::value, k = k0 + kk;
@@ -1021,8 +1071,8 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
         double ra = 0.0, rb = 0.0;
         if (r < R)
             for (int c = p; c < R; c += TPR) {
-                ra += s_m[0][r * RB + c] * s_ag[c];
-                rb += s_m[1][r * RB + c] * s_ag[c];
+                ra += s_m[0][r * GP + c] * s_ag[c];
+                rb += s_m[1][r * GP + c] * s_ag[c];
             }
 #pragma unroll
         for (int m = 1; m < TPR; m <<= 1) {
@@ -1046,9 +1096,9 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
         double best = 0.0;
 #pragma unroll
         for (int w = 0; w < kRegBlk / 64; ++w) best = fmax(best, s_best[w]);
-        const long long tn = d->t + 1;
+        const long long tn = t_prev + 1;
         const double alpha = lam / double(tn) + best;
-        const double abar = d->abar + alpha;
+        const double abar = abar_prev + alpha;
         const double mu = f.step_mode == TSL_STEP_MM ? 1.0 / abar : f.mu_const;
         d->t_new = tn;
         d->alpha = alpha;
@@ -1089,6 +1139,32 @@ template <int TM, int TN> struct OutShape {
     static constexpr size_t LDS = size_t(TM + TN) * kOutPitch * sizeof(float2);
     static constexpr size_t RAW = LDS > sizeof(SampleLds) ? LDS : sizeof(SampleLds);
 };
+// Block order of a table launch of the output synthesis: first the output
+// tiles of every frame (X per frame, numbered as in FrameTable so that a
+// frame's tiles share an XCD), then the draw blocks (ds per frame, frame y's at
+// a position with the residue of its tiles).  The tiles carry the matrix-core
+// work; dealt out first, they spread evenly over the compute units (two per
+// unit in a launch of 64 frames of 256 x 256), and the light draw blocks fill
+// in after them instead of stacking a third tile block on some units.
+struct OutTable {
+    const FrameArgs* __restrict__ t;
+    int X, count, ds;
+    __device__ __forceinline__ int tile_blocks() const { return (count + kXcds - 1) / kXcds * kXcds * X; }
+    __device__ __forceinline__ int y() const {
+        const int L = int(blockIdx.x), T = tile_blocks();
+        if (L >= T) return (L - T) / ds;
+        const int span = kXcds * X;
+        return kXcds * (L / span) + (L % span) % kXcds;
+    }
+    __device__ __forceinline__ int bx() const {
+        const int L = int(blockIdx.x), T = tile_blocks();
+        if (L >= T) return (L - T) % ds;
+        return ds + (L % (kXcds * X)) / kXcds;
+    }
+    __device__ __forceinline__ bool live() const { return y() < count; }
+    __device__ __forceinline__ DevFrame get() const { return dev_frame(t[y()]); }
+};
+
 // ONE: every rank fits one pass (R <= kOutRC), so no staging load is in
 // flight beside the accumulators and the kernel needs fewer registers.
 // BF: SYN_FP32 (FP32 steps, two ranks each), SYN_BF16 or SYN_BF16X3 (BF16
@@ -1250,7 +1326,6 @@ size_t solve_lds(int R) { return size_t(R * (R + 1) / 2 + R) * sizeof(double2) +
 void init_kernel_attributes() {
     static std::once_flag once;
     std::call_once(once, [] {
-        kres_attributes();
         const int ms = int(size_t(kPStage) * TSL_MAX_R * sizeof(double2));
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pstats<FrameTable>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, ms);
@@ -1327,7 +1402,7 @@ hipError_t launch_synth_out(const Batch& b, hipStream_t st) {
         if (gx == 0) return;
         const dim3 grid = frame_grid(b, gx);
         if (b.table)
-            k_synth_out<ONE, BF, TM, TN, FrameTable><<<grid, NT, 0, st>>>(FrameTable{b.table, gx, b.count}, ds);
+            k_synth_out<ONE, BF, TM, TN, OutTable><<<grid, NT, 0, st>>>(OutTable{b.table, gx - ds, b.count, ds}, ds);
         else k_synth_out<ONE, BF, TM, TN, OneFrame><<<grid, NT, 0, st>>>(OneFrame{*b.one}, ds);
     };
     using I128 = std::integral_constant<int, 128>;

@@ -55,10 +55,6 @@ hipError_t launch_stats(const Batch& b, hipStream_t st);
 hipError_t launch_solve(const Batch& b, hipStream_t st);
 hipError_t launch_synth_out(const Batch& b, hipStream_t st);
 
-// k-space route of line masks: residual at the sampled rows and its two
-// gradient contractions (csrc/k_kspace.hip).
-hipError_t launch_kres(const Batch& b, hipStream_t st);
-void kres_attributes();   // dynamic-LDS limit of the k-space residual kernel
 hipError_t launch_sample(const Batch& b, hipStream_t st);
 // Algorithm 4 on entries (eq. 13) for one frame's sequence: mask [n1][n2], count, trial entries.
 hipError_t launch_sample_points(const FrameArgs& a, int K, unsigned char* mask, int* n_out, int* draws,

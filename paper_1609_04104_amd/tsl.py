@@ -44,9 +44,9 @@ class Opts(ctypes.Structure):
                 ("synth_bf16", ctypes.c_int)]
 
 
-N_PHASES = 8
+N_PHASES = 7
 PHASES = ["partial Grams", "ridge solve + step size", "synthesis + row pass", "column pass + residual",
-          "row inverse + A grad", "k-space residual + gradients", "factor updates + F_l A, F_r B",
+          "row inverse + A grad", "factor updates + F_l A, F_r B",
           "output synthesis + row draw"]
 ROUTE_KSPACE, ROUTE_FRAME = 0, 1
 BATCH_GRAPH = 1

@@ -98,7 +98,7 @@ int tier(int r) { return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : r <= 64 ? 64
 int acc_tier(int r) { return r <= 32 ? 2 : r <= 64 ? 4 : 8; }
 
 // Which launcher a group reaches (the invariants a launch relies on differ).
-enum Phase { P_STATS, P_SOLVE, P_FRAME, P_KRES, P_UPDATE, P_OUT, P_SAMPLE };
+enum Phase { P_STATS, P_SOLVE, P_FRAME, P_UPDATE, P_OUT, P_SAMPLE };
 
 // What a kernel of the launch reads of one descriptor, and the launch-wide
 // arguments it relies on: the grid covers the descriptor's shape, rank and
@@ -123,12 +123,9 @@ void check_frame(const tsl::Batch& b, const tsl::FrameArgs& a, Phase ph) {
             if (a.n1 != b.n1 || a.n2 != b.n2) report("frame-route launch mixes shapes");
             if (!frame_route) report("k-space frame in a frame-route launch");
             break;
-        case P_KRES:
-            if (a.mode != tsl::MODE_LINES || !a.kspace) report("frame-route frame in a k-space residual launch");
-            if (b.table && acc_tier(a.r) != acc_tier(b.r_max)) report("k-space residual launch mixes tiers");
-            break;
         case P_UPDATE:
             if (a.n1 != b.n1 || a.n2 != b.n2) report("update launch mixes shapes");
+            if (a.kspace != (b.kspace ? 1 : 0)) report("update launch mixes routes");
             break;
         case P_OUT:
             if ((a.r <= 32) != (b.r_max <= 32)) report("output launch mixes single- and multi-pass ranks");
@@ -142,8 +139,10 @@ void check_frame(const tsl::Batch& b, const tsl::FrameArgs& a, Phase ph) {
     touch(a.A, n1 * r); touch(a.B, n2 * r); touch(a.Ahat, n1 * r); touch(a.Bhat, n2 * r);
     touch(a.dev, 1); touch(a.gamma64, r); touch(a.gamma32, r);
     touch(a.frame, n1 * n2); touch(a.Wb, n2 * r); touch(a.GA, n1 * r);
-    touch(a.wpart, size_t(tsl::n_qparts(a.n1)) * n2 * r);
-    touch(a.mpart, size_t(tsl::n_cparts(a.n2)) * n1 * r);
+    touch(a.zm, size_t(tsl::n_sparts(a.n1)) * tsl::n_jparts(a.n2) * tsl::kSRows * r);
+    touch(a.zw, size_t(tsl::n_sparts(a.n1)) * n2 * r);
+    touch(a.bcopy, n2 * r);
+    touch(a.acopy, n1 * r);
     touch(a.part, size_t(tsl::n_parts(a.n1, a.n2)) * r * r);
     touch(a.hpart, size_t(tsl::n_hparts(a.n1, a.n2)) * r);
     touch(a.wq, size_t(tsl::cdiv(a.r, 16)) * n1);
@@ -184,7 +183,6 @@ namespace tsl {
 hipError_t launch_synth_rowfft(const Batch& b, hipStream_t st) { return b.mode == MODE_POINTS || !b.kspace ? run_group(b, st, P_FRAME) : hipSuccess; }
 hipError_t launch_row_inv_grad(const Batch& b, hipStream_t st) { return b.mode == MODE_POINTS || !b.kspace ? run_group(b, st, P_FRAME) : hipSuccess; }
 hipError_t launch_col_resid(const Batch& b, hipStream_t st) { return b.mode == MODE_POINTS || !b.kspace ? run_group(b, st, P_FRAME) : hipSuccess; }
-hipError_t launch_kres(const Batch& b, hipStream_t st) { return b.mode == MODE_LINES && b.kspace ? run_group(b, st, P_KRES) : hipSuccess; }
 hipError_t launch_update_a(const Batch& b, hipStream_t st) { return run_group(b, st, P_UPDATE); }
 hipError_t launch_update_b(const Batch& b, hipStream_t st) { return run_group(b, st, P_UPDATE); }
 hipError_t launch_stats(const Batch& b, hipStream_t st) { return run_group(b, st, P_STATS); }
