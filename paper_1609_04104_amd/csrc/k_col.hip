@@ -377,11 +377,11 @@ __device__ __forceinline__ void sum_fill(int n, int np, At at, Store store) {
 // (X: [nrows][R] complex64) on the FP32 matrix cores in Gauss's three-product
 // form (M = 16 rows, N = kTW ranks, K = four ranks per step).  A wavefront takes
 // kMI row tiles per round; the K loop is the outer one, so that one group of
-// operand loads serves all of them, and the next group's loads go out before
-// the current group's products.  Every thread of the block calls it.
-constexpr int kMI = 4;   // row tiles per wavefront and round
-constexpr int kMC = 2;   // K steps per operand group
-template <class RowOf>
+// kMC steps' operand loads serves all of them, and the next group's loads go
+// out before the current group's products (few tiles: one tile and long
+// groups; many tiles: several tiles and short groups, for the registers).
+// Every thread of the block calls it.
+template <int kMI, int kMC, class RowOf>
 __device__ __forceinline__ void model_add(GlobalPtr<const float2> X, int nrows, int R, const float2* s_T,
                                           float2* s_out, RowOf row_of) {
     static_assert(kTW == 16, "one matrix-core column tile of ranks per block");
@@ -497,7 +497,7 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
         fill_model_t(f, f.part + size_t(n_gparts(N1)) * R * R, n_gparts(f.n2), r0, s_T);
         __syncthreads();
         GlobalPtr<const float2> Zm = f.zm;
-        sum_fill<4, 4>(
+        sum_fill<2, 8>(
             nS * kTW, nJ,
             [&](int e, int j) {
                 const int q = e / kTW, rr = min(r0 + e % kTW, R - 1);
@@ -505,7 +505,7 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
             },
             [&](int e, float2 z) { s_x[s_rows[e / kTW] * kTW + e % kTW] = r0 + e % kTW < R ? z : float2{0.f, 0.f}; });
         __syncthreads();
-        model_add(f.acopy, nS, R, s_T, s_x, [&](int q) { return s_rows[q]; });
+        model_add<1, 8>(f.acopy, nS, R, s_T, s_x, [&](int q) { return s_rows[q]; });
         // A at the update's layout after the transform (loaded here, where the
         // model term no longer holds registers; it arrives during the transform)
         if (s < P && rv)
@@ -653,13 +653,23 @@ __device__ __forceinline__ void update_b_body(const DevFrame& f, int bx, float2*
         float2* s_T = s_dyn;
         const int gAB = n_gparts(f.n1) + n_gparts(N2);
         GlobalPtr<const float2> Zw = f.zw;
-        sum_fill<8, 1>(
-            N2 * kTW, nsc,
-            [&](int e, int k) { return float2(Zw[(size_t(k) * N2 + e / kTW) * R + min(r0 + e % kTW, R - 1)]); },
-            [&](int e, float2 z) { s_x[e] = r0 + e % kTW < R ? z : float2{0.f, 0.f}; });
+        auto zw_at = [&](int e, int k) { return float2(Zw[(size_t(k) * N2 + e / kTW) * R + min(r0 + e % kTW, R - 1)]); };
+        auto zw_put = [&](int e, float2 z) { s_x[e] = r0 + e % kTW < R ? z : float2{0.f, 0.f}; };
+        if (nsc == 1) {
+            // one chunk of sampled rows: a copy, all of a thread's loads in flight together
+            constexpr int E = cdiv(N2 * kTW, S::THREADS64);
+            float2 zv[E];
+#pragma unroll
+            for (int u = 0; u < E; ++u) zv[u] = zw_at(min(tid + u * int(blockDim.x), N2 * kTW - 1), 0);
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+                if (tid + u * int(blockDim.x) < N2 * kTW) zw_put(tid + u * int(blockDim.x), zv[u]);
+        } else {
+            sum_fill<8, 1>(N2 * kTW, nsc, zw_at, zw_put);
+        }
         fill_model_t(f, f.part + size_t(gAB) * R * R, nsc, r0, s_T);
         __syncthreads();
-        model_add(f.bcopy, N2, R, s_T, s_x, [](int j) { return j; });
+        model_add<4, 2>(f.bcopy, N2, R, s_T, s_x, [](int j) { return j; });
         load_bpre();                          // B at the update's layout, arriving during the transform
         __syncthreads();
         if (s < Q && rv)
