@@ -1297,7 +1297,11 @@ __global__ void __launch_bounds__((TM / 32) * (TN / 32) * 64) k_synth_out(Src sr
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int row = i0 + mfma32_row(v, lane);
-        if (row < n1) f.X_out[size_t(row) * n2 + j] = float2{p1[v] - p2[v], p3[v] - p1[v] - p2[v]};
+        // X_t is the caller's: no later kernel of the step reads it, so it is
+        // stored past the cache (the end of the launch then has less to write back)
+        if (row < n1)
+            __builtin_nontemporal_store(f32x2{p1[v] - p2[v], p3[v] - p1[v] - p2[v]},
+                                        reinterpret_cast<GlobalPtr<f32x2>>(f.X_out + size_t(row) * n2 + j));
     }
 }
 

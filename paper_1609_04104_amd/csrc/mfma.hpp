@@ -5,6 +5,7 @@
 namespace tsl {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // One 16x16x4 FP32 step, D += A B with A 16x4 and B 4x16.  Lane l supplies
