@@ -53,7 +53,7 @@ Layout layout_for(int n1, int n2, int r, int C) {
     L.zw = take(size_t(tsl::n_sparts(n1)) * n2 * r * sizeof(float2));
     L.bcopy = take(size_t(n2) * r * sizeof(float2));
     L.acopy = take(size_t(n1) * r * sizeof(float2));
-    L.part = take(size_t(tsl::n_parts(n1, n2)) * r * r * sizeof(double2));
+    L.part = take(size_t(tsl::n_parts(n1, n2)) * tsl::slot_size(r) * sizeof(double2));
     L.hpart = take(size_t(tsl::n_hparts(n1, n2)) * r * sizeof(double2));
     L.wq = take(size_t(tsl::cdiv(r, 16)) * n1 * sizeof(double));
     if (C > 0) {

@@ -22,7 +22,9 @@ struct SeqDev {
 
 enum : int { MODE_LINES = 0, MODE_POINTS = 1 };
 
-// Slots of the Gram statistics, each [r][r] (upper entries): first the partials
+// Slots of the Gram statistics, each the entries on and above the diagonal of
+// an r x r Hermitian matrix packed by rows (slot_size(r) entries, entry (i, j),
+// i <= j, at upk(i, j, r)): first the partials
 // of (F_l A)^H F_l A over kGRows rows of F_l A each, then those of
 // (F_r B)^H F_r B, then the partials of the sampled part (kSRows sampled rows
 // per slot for line masks, kPRows mask rows per slot for point masks).  The
@@ -36,6 +38,8 @@ constexpr int kKQ = 16;         // sampled rows per block of the k-space residua
 constexpr int kKCols = 128;     // readout samples per block of the k-space residual (partials of E conj(Bhat))
 
 __host__ __device__ constexpr inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ constexpr inline int slot_size(int r) { return r * (r + 1) / 2; }
+__host__ __device__ constexpr inline int upk(int i, int j, int r) { return i * r - i * (i - 1) / 2 + (j - i); }
 __host__ __device__ inline int n_gparts(int n) { return cdiv(n, kGRows); }
 __host__ __device__ inline int n_sparts(int n1) { return cdiv(n1, kPRows); }   // >= cdiv(n1, kSRows)
 __host__ __device__ inline int n_jparts(int n2) { return cdiv(n2, kJCH); }

@@ -297,17 +297,17 @@ __device__ __forceinline__ void row_weight_parts(const DevFrame& f, int bx, cons
 // of its columns and the model term, K = R, on the matrix cores.
 
 // Entry (r, s) of a Hermitian Gram summed over `ns` partial slots in slot order
-// (a slot holds the entries on and above the diagonal, [R][R]); eight slots'
+// (a slot holds the entries on and above the diagonal, packed by rows); eight slots'
 // loads go out before their adds (indices clamped, values past ns selected away).
 __device__ __forceinline__ double2 gram_entry(GlobalPtr<const double2> slots, int ns, int R, int r, int s) {
     const bool up = r <= s;
-    const size_t at = up ? size_t(r) * R + s : size_t(s) * R + r;
+    const size_t at = size_t(up ? upk(r, s, R) : upk(s, r, R));
     double2 acc{0.0, 0.0};
     for (int k0 = 0; k0 < ns; k0 += 8) {
         double2 v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const double2 x = slots[size_t(k0 + u < ns ? k0 + u : k0) * R * R + at];
+            const double2 x = slots[size_t(k0 + u < ns ? k0 + u : k0) * slot_size(R) + at];
             v[u] = k0 + u < ns ? x : double2{0.0, 0.0};
         }
 #pragma unroll
@@ -494,7 +494,7 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
         int* s_rows = reinterpret_cast<int*>(s_T + R * kTW);
         for (int e = tid; e < N1 * kTW; e += blockDim.x) s_x[e] = float2{0.f, 0.f};
         for (int q = tid; q < nS; q += blockDim.x) s_rows[q] = f.rows[q];
-        fill_model_t(f, f.part + size_t(n_gparts(N1)) * R * R, n_gparts(f.n2), r0, s_T);
+        fill_model_t(f, f.part + size_t(n_gparts(N1)) * slot_size(R), n_gparts(f.n2), r0, s_T);
         __syncthreads();
         GlobalPtr<const float2> Zm = f.zm;
         sum_fill<2, 8>(
@@ -667,7 +667,7 @@ __device__ __forceinline__ void update_b_body(const DevFrame& f, int bx, float2*
         } else {
             sum_fill<8, 1>(N2 * kTW, nsc, zw_at, zw_put);
         }
-        fill_model_t(f, f.part + size_t(gAB) * R * R, nsc, r0, s_T);
+        fill_model_t(f, f.part + size_t(gAB) * slot_size(R), nsc, r0, s_T);
         __syncthreads();
         model_add<4, 2>(f.bcopy, N2, R, s_T, s_x, [](int j) { return j; });
         load_bpre();                          // B at the update's layout, arriving during the transform

@@ -99,7 +99,7 @@ __device__ void gram_staged(const T* s_x, int nq, int R, double2* out) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int rr = 16 * mi + 4 * i + g, ss = 16 * ni + m;
-            if (rr < R && ss < R && rr <= ss) out[size_t(rr) * R + ss] = double2{p1[i] - p2[i], p3[i] - p1[i] - p2[i]};
+            if (rr < R && ss < R && rr <= ss) out[upk(rr, ss, R)] = double2{p1[i] - p2[i], p3[i] - p1[i] - p2[i]};
         }
     }
 }
@@ -132,7 +132,7 @@ __device__ void factor_gram_block(const DevFrame& f, int b, float2* s_x, bool ch
         }
     }
     __syncthreads();
-    gram_staged(s_x, nq, R, f.part + size_t(b) * R * R);
+    gram_staged(s_x, nq, R, f.part + size_t(b) * slot_size(R));
 }
 
 // Line masks, one launch for all of S1's statistics.  Blocks [0, gAB) are the
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
     }
     __syncthreads();
     if (gram_role) {
-        gram_staged(s_x, nq, R, f.part + size_t(gAB + k) * R * R);
+        gram_staged(s_x, nq, R, f.part + size_t(gAB + k) * slot_size(R));
     } else {
     // z[q][r] = sum_j y_qj conj(Bhat_jr) over the chunk on FP64 matrix cores
     // (M = the sampled rows, N = ranks, K = four samples per step) in Gauss's
@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(kSB) k_pstats(Src src) {
         return;
     }
     const int k = src.bx() - gAB;
-    double2* out = f.part + size_t(gAB + k) * R * R;
+    double2* out = f.part + size_t(gAB + k) * slot_size(R);
     if (tid == 0) s_err = 0;
     __syncthreads();
     // The sampled entries of rows [i0, i1) taken in windows of kPW candidates;
@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(kSB) k_pstats(Src src) {
 #pragma unroll
         for (int u = 0; u < kMaxAcc; ++u) {
             const int e = tid + (pass * kMaxAcc + u) * kSB;
-            if (e < RR && (e / R) <= (e % R)) out[e] = acc[u];
+            if (e < RR && (e / R) <= (e % R)) out[upk(e / R, e % R, R)] = acc[u];
         }
         if (pass == 0 && tid < R) f.hpart[size_t(k) * R + tid] = hacc;
     }
@@ -508,7 +508,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
     const int ns = lines ? cdiv(frame_rows(f), kSRows) : cdiv(n1, kPRows);
     const int gA = n_gparts(n1), gB = n_gparts(f.n2), gAB = gA + gB;
     const int nh = ns * (lines ? n_jparts(f.n2) : 1);
-    const size_t RR = size_t(R) * R;
+    const size_t RR = size_t(slot_size(R));   // entries per slot
     const double2* pa = f.part;               // slots of (F_l A)^H F_l A
     const double2* pb = f.part + gA * RR;     // slots of (F_r B)^H F_r B
     const double2* ps = f.part + gAB * RR;    // slots of the sampled part
@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
             ok[u] = e < npairs;
             ii[u] = i;
             jj[u] = e - i * (i + 1) / 2;
-            up[u] = ok[u] ? size_t(jj[u]) * R + i : 0;
+            up[u] = ok[u] ? size_t(upk(jj[u], i, R)) : 0;
         }
         double2 g[kSolveU], gb[kSolveU];
         slot_sums<kSolveU>(ps, RR, ns, up, ok, g);
@@ -652,7 +652,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve(Src src) {
                 const int e = e0 + tid + kSolveThreads * u;
                 const int r = e / R, c = e % R;
                 ok[u] = e < R * R;
-                up[u] = !ok[u] ? 0 : (r <= c ? size_t(r) * R + c : size_t(c) * R + r);
+                up[u] = !ok[u] ? 0 : size_t(r <= c ? upk(r, c, R) : upk(c, r, R));
             }
             double2 v[kSolveU];
             slot_sums<kSolveU>(pm, RR, nm, up, ok, v);
@@ -774,7 +774,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     const int gA = n_gparts(f.n1), gB = n_gparts(f.n2), gAB = gA + gB;
     const int hper = lines ? n_jparts(f.n2) : 1;
     const int nh_cap = ns_cap * hper, nh = ns * hper;
-    const size_t RR = size_t(R) * R;
+    const size_t RR = size_t(slot_size(R));   // entries per slot
     const double2* pa = f.part;               // slots of (F_l A)^H F_l A
     const double2* pb = f.part + gA * RR;     // slots of (F_r B)^H F_r B
     const double2* ps = f.part + gAB * RR;    // slots of the sampled part
@@ -784,9 +784,10 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     const long long t_prev = d->t;
     const double abar_prev = d->abar;
 
-    // Gather.  A slot holds the upper triangle: entry (r, c), r <= c, is G_rc.
-    // Each thread takes upper entries (packed by rows) and writes both (i, j)
-    // and its conjugate mirror (j, i).
+    // Gather.  A slot holds the upper triangle packed by rows: entry (r, c),
+    // r <= c, is G_rc at upk(r, c, R).  Each thread takes upper entries (in the
+    // same packed order, so a wavefront's loads are contiguous) and writes both
+    // (i, j) and its conjugate mirror (j, i).
     constexpr int NU = RB * (RB + 1) / 2;
     constexpr int U = (NU + kRegBlk - 1) / kRegBlk;   // upper entries per thread
     size_t up[U];
@@ -800,7 +801,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
         ui[u] = i;
         uj[u] = i + e;
         ok[u] = tid + u * kRegBlk < NU && uj[u] < R;
-        up[u] = ok[u] ? size_t(ui[u]) * R + uj[u] : 0;
+        up[u] = ok[u] ? size_t(upk(ui[u], uj[u], R)) : 0;
     }
     // one right-hand-side partial entry per thread (entry q R + r is slot q of
     // h_r) and the first kGatherPF slots of all three statistics are in flight

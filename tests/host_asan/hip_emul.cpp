@@ -143,7 +143,7 @@ void check_frame(const tsl::Batch& b, const tsl::FrameArgs& a, Phase ph) {
     touch(a.zw, size_t(tsl::n_sparts(a.n1)) * n2 * r);
     touch(a.bcopy, n2 * r);
     touch(a.acopy, n1 * r);
-    touch(a.part, size_t(tsl::n_parts(a.n1, a.n2)) * r * r);
+    touch(a.part, size_t(tsl::n_parts(a.n1, a.n2)) * tsl::slot_size(a.r));
     touch(a.hpart, size_t(tsl::n_hparts(a.n1, a.n2)) * r);
     touch(a.wq, size_t(tsl::cdiv(a.r, 16)) * n1);
     if (a.mode == tsl::MODE_LINES) {
