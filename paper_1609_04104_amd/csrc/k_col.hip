@@ -84,7 +84,8 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // ---------------------------------------------------------------- K2
 template <int N1, class Src>
-__global__ void __launch_bounds__(512) k_col_resid(Src src) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(ColShape<N1>::THREADS64 <= 256 ? 4 : 1)))
+k_col_resid(Src src) {
     using S = ColShape<N1>;
     constexpr int P = S::P, Q = S::Q, T = S::T;
     constexpr int kWaves = S::THREADS64 / 64;
@@ -161,22 +162,18 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
         });
         dft_twiddle<N1, Q, true>(v, s, s_tw);
     }
-    // The factor rows of the W contraction below, issued before the inverse
-    // transform so that they arrive while it runs (first rank pass).
+    // The factor values of the W contraction below, one 16-rank tile at a time:
+    // few registers, so that four blocks share a compute unit and one block's
+    // loads wait while the others compute.
     const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64), n = lane % 16;
-    float2 av[P][WNT];
-    auto load_a = [&](int n0) {
+    float2 av0[P];
+    auto load_a = [&](int t, float2 (&av)[P]) {
         sfor<P>([&](auto mc) {
             constexpr int m2 = decltype(mc)::value;
-            const int i = s + Q * m2;
-#pragma unroll
-            for (int u = 0; u < WNT; ++u) {
-                const int r = n0 + 16 * u + n;
-                av[m2][u] = (s < Q && r < R) ? float2(f.A[size_t(i) * R + r]) : float2{0.f, 0.f};
-            }
+            const int i = s + Q * m2, r = 16 * t + n;
+            av[m2] = (s < Q && r < R) ? float2(f.A[size_t(i) * R + r]) : float2{0.f, 0.f};
         });
     };
-    load_a(0);
     col_swap_kn<N1>(v, s_u, c, s);
     if (s < Q) {
         dft_only<P, true>(v);
@@ -192,27 +189,37 @@ __global__ void __launch_bounds__(512) k_col_resid(Src src) {
     // Gauss's three-multiplication form with the conjugate's sign on the factor:
     // P1 = sum Zr Ar, P2 = sum Zi (-Ai), P3 = sum (Zr + Zi)(Ar - Ai), so that
     // Re W = P1 - P2 and Im W = P3 - P1 - P2: three 16x16x4 steps per four rows
-    // and rank tile.  The wavefronts' partial sums over their rows meet in LDS and
-    // are added in wavefront order.
+    // and rank tile.  A pass takes WNT rank tiles; the wavefronts' partial sums
+    // over their rows meet in LDS and are added in wavefront order.
+    load_a(0, av0);
     static_assert(kTW == 16, "one MFMA row per column of the tile");
     float2* s_w = s_u;                                   // [wave][c][WNT * 16]
     bool bad = false;
+    const int ntr = cdiv(R, 16);                         // rank tiles
     for (int n0 = 0; n0 < R; n0 += WNT * 16) {
         f32x4 p1[WNT], p2[WNT], p3[WNT];
 #pragma unroll
         for (int u = 0; u < WNT; ++u) p1[u] = p2[u] = p3[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-        if (n0 > 0) load_a(n0);                          // all factor operands in flight at once
-        sfor<P>([&](auto mc) {
-            constexpr int m2 = decltype(mc)::value;
-            const float2 z = (s < Q) ? v[m2] : float2{0.f, 0.f};
-#pragma unroll
-            for (int u = 0; u < WNT; ++u) {
-                const float2 a = av[m2][u];
+        auto products = [&](int u, const float2 (&av)[P]) {
+            sfor<P>([&](auto mc) {
+                constexpr int m2 = decltype(mc)::value;
+                const float2 z = (s < Q) ? v[m2] : float2{0.f, 0.f};
+                const float2 a = av[m2];
                 p1[u] = mfma_16x16x4(z.x, a.x, p1[u]);
                 p2[u] = mfma_16x16x4(z.y, -a.y, p2[u]);
                 p3[u] = mfma_16x16x4(z.x + z.y, a.x - a.y, p3[u]);
+            });
+        };
+        // tiles t0 = n0 / 16 and t0 + 1, one register set reused
+        const int t0 = n0 / 16;
+        products(0, av0);
+        if constexpr (WNT > 1) {
+            if (t0 + 1 < ntr) {
+                load_a(t0 + 1, av0);
+                products(1, av0);
             }
-        });
+        }
+        if (t0 + WNT < ntr) load_a(t0 + WNT, av0);      // the next pass's first tile
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < WNT; ++u)

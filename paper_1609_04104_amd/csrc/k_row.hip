@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(kRowBlock) k_synth_rowfft(Src src) {
 // K range, and partial sums over K ranges are added in a fixed order.
 constexpr int kGNT = 2;   // 16-rank tiles per pass
 template <int N2, class Src>
-__global__ void __launch_bounds__(kRowBlock) k_row_inv_grad(Src src) {
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(3))) k_row_inv_grad(Src src) {
     using S = RowShape<N2>;
     using RT = RowTiles<N2>;
     constexpr int P = S::P, Q = S::Q, T = S::T, ROWS = S::ROWS, PITCH = RT::PITCH, MT = RT::MT;
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(kRowBlock) k_row_inv_grad(Src src) {
 #pragma unroll
             for (int u = 0; u < kGNT; ++u) accr[a][u] = acci[a][u] = f32x4{0.f, 0.f, 0.f, 0.f};
         if (ks < KS) {
-            constexpr int KB = 16;                        // steps whose B operands load together
+            constexpr int KB = 8;                         // steps whose B operands load together
             const int t0 = ks * KPW, t1 = min(KSTEPS, t0 + KPW);
             for (int tb = t0; tb < t1; tb += KB) {
                 float bv[KB][kGNT];
