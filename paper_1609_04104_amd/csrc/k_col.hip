@@ -16,6 +16,8 @@
 //  k_update_b    Theta^T conj(A) = F_r^H W, then the B update and F_r B.
 //  k_colfft      plain column pass of the standalone 2-D transform.
 //  k_factor_fft  column transform of an [n][r] factor (start-up transforms).
+#include <atomic>
+
 #include "fft_engine.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -31,6 +33,10 @@ template <int N> struct ColShape {
     static constexpr int P = Plan<N>::P, Q = Plan<N>::Q, T = Plan<N>::T;
     static constexpr int THREADS = kTW * T;
     static constexpr int THREADS64 = (THREADS + 63) / 64 * 64;   // whole wavefronts (matrix-core passes)
+    // k-space factor updates whose grid fits the device in one round: at least
+    // eight wavefronts (the ones past the transform's rows take part in the
+    // gradient terms only, which halves their dependent load groups)
+    static constexpr int KS_THREADS = THREADS64 < 512 ? 512 : THREADS64;
     static constexpr int PITCH_NK = odd_pitch(Q, kTW);   // entry (k1, n2, c) at k1*PITCH_NK + n2*kTW + c
     static constexpr int PITCH_KN = odd_pitch(P, kTW);   // entry (m1, k1, c) at m1*PITCH_KN + k1*kTW + c
     static constexpr int XSIZE = (P * PITCH_NK > Q * PITCH_KN) ? P * PITCH_NK : Q * PITCH_KN;
@@ -664,7 +670,7 @@ __device__ __forceinline__ void update_b_body(const DevFrame& f, int bx, float2*
         auto zw_put = [&](int e, float2 z) { s_x[e] = r0 + e % kTW < R ? z : float2{0.f, 0.f}; };
         if (nsc == 1) {
             // one chunk of sampled rows: a copy, all of a thread's loads in flight together
-            constexpr int E = cdiv(N2 * kTW, S::THREADS64);
+            constexpr int E = cdiv(N2 * kTW, S::THREADS64);   // covers the smallest launch
             float2 zv[E];
 #pragma unroll
             for (int u = 0; u < E; ++u) zv[u] = zw_at(min(tid + u * int(blockDim.x), N2 * kTW - 1), 0);
@@ -676,7 +682,7 @@ __device__ __forceinline__ void update_b_body(const DevFrame& f, int bx, float2*
         }
         fill_model_t(f, f.part + size_t(gAB) * slot_size(R), nsc, r0, s_T);
         __syncthreads();
-        model_add<4, 2>(f.bcopy, N2, R, s_T, s_x, [](int j) { return j; });
+        model_add<2, 4>(f.bcopy, N2, R, s_T, s_x, [](int j) { return j; });
         load_bpre();                          // B at the update's layout, arriving during the transform
         __syncthreads();
         if (s < Q && rv)
@@ -790,31 +796,51 @@ template <int N1> hipError_t launch_k2_n(const Batch& b, hipStream_t st) {
     return hipGetLastError();
 }
 // The update launches take whole wavefronts (the k-space gradients run on the
-// matrix cores) and, on the k-space route, s_T in dynamic LDS.
+// matrix cores; on the k-space route at least eight of them, ColShape::KS_THREADS)
+// and, on the k-space route, the gradient areas in dynamic LDS.
 inline size_t update_lds(const Batch& b) { return b.kspace ? grad_lds(b.r_max, b.n1) : 0; }
+// compute units of the current device (looked up once per device)
+inline int device_cus() {
+    static std::atomic<int> cus[16];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
+    int v = cus[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        cus[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+// More wavefronts per block only while the launch is one round of blocks (the
+// step is then latency-bound); a larger launch keeps the smaller blocks, of
+// which more share a compute unit.
+template <int N> inline int update_threads(const Batch& b, const dim3& grid) {
+    return b.kspace && int(grid.x) <= device_cus() ? ColShape<N>::KS_THREADS : ColShape<N>::THREADS64;
+}
 template <int N1> hipError_t launch_k4a_n(const Batch& b, hipStream_t st) {
-    using S = ColShape<N1>;
     const int ga = cdiv(b.r_max, kTW);
     const size_t lds = update_lds(b);
     if (b.n1 == b.n2) {                       // both updates in one launch
         const int gx = 2 * ga;
         const dim3 grid = frame_grid(b, gx);
-        if (b.table) k_update_ab<N1, FrameTable><<<grid, S::THREADS64, lds, st>>>(FrameTable{b.table, gx, b.count}, ga);
-        else k_update_ab<N1, OneFrame><<<grid, S::THREADS64, lds, st>>>(OneFrame{*b.one}, ga);
+        const int nt = update_threads<N1>(b, grid);
+        if (b.table) k_update_ab<N1, FrameTable><<<grid, nt, lds, st>>>(FrameTable{b.table, gx, b.count}, ga);
+        else k_update_ab<N1, OneFrame><<<grid, nt, lds, st>>>(OneFrame{*b.one}, ga);
         return hipGetLastError();
     }
     const dim3 grid = frame_grid(b, ga);
-    if (b.table) k_update_a<N1, FrameTable><<<grid, S::THREADS64, lds, st>>>(FrameTable{b.table, ga, b.count});
-    else k_update_a<N1, OneFrame><<<grid, S::THREADS64, lds, st>>>(OneFrame{*b.one});
+    const int nt = update_threads<N1>(b, grid);
+    if (b.table) k_update_a<N1, FrameTable><<<grid, nt, lds, st>>>(FrameTable{b.table, ga, b.count});
+    else k_update_a<N1, OneFrame><<<grid, nt, lds, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 template <int N2> hipError_t launch_k4b_n(const Batch& b, hipStream_t st) {
-    using S = ColShape<N2>;
     const int gb = cdiv(b.r_max, kTW);
     const dim3 grid = frame_grid(b, gb);
+    const int nt = update_threads<N2>(b, grid);
     const size_t lds = update_lds(b);
-    if (b.table) k_update_b<N2, FrameTable><<<grid, S::THREADS64, lds, st>>>(FrameTable{b.table, gb, b.count});
-    else k_update_b<N2, OneFrame><<<grid, S::THREADS64, lds, st>>>(OneFrame{*b.one});
+    if (b.table) k_update_b<N2, FrameTable><<<grid, nt, lds, st>>>(FrameTable{b.table, gb, b.count});
+    else k_update_b<N2, OneFrame><<<grid, nt, lds, st>>>(OneFrame{*b.one});
     return hipGetLastError();
 }
 template <int N1>
