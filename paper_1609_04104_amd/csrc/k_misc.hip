@@ -758,7 +758,8 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
     __shared__ double2 s_h[RB];            // gamma
     __shared__ double2 s_hp[kRegBlk];      // the first kRegBlk right-hand-side partial entries
     __shared__ double2 s_c[2][RB];         // column k of the partly reduced G during step k (two buffers)
-    __shared__ double s_piv[2];            // its pivot D_k (two buffers; four-wavefront sweep)
+    __shared__ double s_ik[2];             // 1 / D_k (two buffers; four-wavefront sweep)
+    __shared__ double s_dk[RB];            // the pivots D_k (four-wavefront sweep)
     __shared__ double s_ag[RB];            // |gamma|
     __shared__ double s_best[kRegBlk / 64];
     __shared__ double s_kappa;
@@ -893,15 +894,15 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
         // g = t / RB (NG = 8 column groups of four columns at RB = 32: lane l of
         // wavefront w in group 2 w + l / 32; NG = 4 groups of sixteen columns at
         // RB = 64: wavefront w is group w).  Step k reads the unscaled column
-        // c = G[:, k] and its pivot D_k from LDS (every wavefront forms 1/D_k)
-        // and applies G_ij -= c_i conj(c_j) / D_k to its columns; the lane group
-        // that holds column k+1 reduces it first and puts it and its pivot in
-        // the other LDS buffer for the next step.  Wavefront 0 also keeps L
+        // c = G[:, k] and 1/D_k from LDS and applies G_ij -= c_i conj(c_j) / D_k
+        // to its columns; the lane group that holds column k+1 reduces it first
+        // and puts it and its pivot's reciprocal in the other LDS buffers for
+        // the next step.  Wavefront 0 also keeps L
         // (into s_g), 1/D and the forward substitution L z = h.  Entries above
         // the diagonal and of finished columns receive updates too (never
         // read).  No branches on the pivots: one that is not positive and
-        // finite sets `fail` (read from LDS, so the same everywhere) and is
-        // replaced by 1; the frame is then rejected.
+        // finite is replaced by 1 in its reciprocal, and the check after the
+        // sweep rejects the frame.
         constexpr int NG = kRegBlk / RB, CPL = RB / NG;   // column groups in the block, columns per lane
         const int i = tid % RB, g = tid / RB;
         double2 gr[CPL];
@@ -910,18 +911,19 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
             gr[m] = s_g[i * GP + NG * m + g];
         });
         if (wave == 0) gather_h(i);
+        // the thread that holds a pivot records it and its reciprocal (of 1 in
+        // place of a pivot that is not positive and finite); the checks on the
+        // recorded pivots run once after the sweep
+        auto put_pivot = [&](int k, double dn) {
+            s_dk[k] = dn;
+            s_ik[k % 2] = recip((dn > 0.0 && isfinite(dn)) ? dn : 1.0);
+        };
         if (g == 0) s_c[0][i] = gr[0];
-        if (g == 0 && i == 0) s_piv[0] = gr[0].x;
+        if (g == 0 && i == 0) put_pivot(0, gr[0].x);
         __syncthreads();
-        bool fail = false;
-        double d_lo = 1e308, d_hi = 0.0;
         sfor<RB>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const double dk = s_piv[k % 2];
-            const bool fk = !(dk > 0.0) || !isfinite(dk);
-            fail = fail || fk;
-            const double ik = recip(fk ? 1.0 : dk);
-            if (k < R) { d_lo = fmin(d_lo, dk); d_hi = fmax(d_hi, dk); }
+            const double ik = s_ik[k % 2];
             const double2 ci = s_c[k % 2][i];                   // G_ik
             const double2 li{ci.x * ik, ci.y * ik};             // L_ik
             if (wave == 0) {
@@ -943,7 +945,7 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
                 if (own) {
                     upd(gr[m1], s_c[k % 2][k1]);
                     s_c[k1 % 2][i] = gr[m1];
-                    if (i == k1) s_piv[k1 % 2] = gr[m1].x;
+                    if (i == k1) put_pivot(k1, gr[m1].x);
                 }
                 sfor<CPL>([&](auto mc) {
                     constexpr int m = decltype(mc)::value;
@@ -953,9 +955,25 @@ __global__ void __launch_bounds__(kRegBlk) k_solve_reg(Src src) {
                 __syncthreads();
             }
         });
-        if (wave == 0 && lane == 0) {
-            s_fail = fail ? ST_ENOTPD : 0;
-            s_kappa = d_hi / d_lo;
+        if (wave == 0) {
+            // pivot checks and the conditioning figure over the recorded pivots
+            bool bad = false;
+            double lo = 1e308, hi = 0.0;
+            for (int k = lane; k < RB; k += 64) {
+                const double dk = s_dk[k];
+                bad = bad || !(dk > 0.0) || !isfinite(dk);
+                if (k < R) { lo = fmin(lo, dk); hi = fmax(hi, dk); }
+            }
+#pragma unroll
+            for (int m = 32; m > 0; m >>= 1) {
+                lo = fmin(lo, __shfl_xor(lo, m, 64));
+                hi = fmax(hi, __shfl_xor(hi, m, 64));
+            }
+            const bool any_bad = __any(bad);
+            if (lane == 0) {
+                s_fail = any_bad ? ST_ENOTPD : 0;
+                s_kappa = hi / lo;
+            }
         }
     } else {
     // Wavefront 0: right-looking L D L^H, one column ahead.  Lane l holds row
