@@ -129,6 +129,23 @@ __device__ __forceinline__ int frame_rows(const DevFrame& f) {
     return n < 0 ? 0 : (n > cap ? cap : n);
 }
 
+// A masked load that puts the mask into the address: a lane whose operand is
+// masked off reads a zero constant instead.  No select on the loaded value
+// follows (such a select has to wait for the load where it is written, and the
+// compiler may turn it into a branch around the load), so the wait moves to the
+// value's first real use and a batch of these loads goes out back to back.
+__device__ __align__(16) const float g_zero_f4[4] = {0.f, 0.f, 0.f, 0.f};
+template <class T> __device__ __forceinline__ T load_or_zero(bool ok, GlobalPtr<const T> p) {
+    static_assert(sizeof(T) <= 16, "the zero constant holds 16 bytes");
+    const GlobalPtr<const T> z = (GlobalPtr<const T>)(const void*)g_zero_f4;
+    GlobalPtr<const T> a = ok ? p : z;
+    // an empty statement that claims to change the address (it holds no
+    // instruction): the compiler cannot split the load back into two loads
+    // under branches
+    asm("" : "+v"(a));
+    return *a;
+}
+
 // Samples of row `row`, listed at position q of the row set (lines).
 __device__ __forceinline__ GlobalPtr<const float2> line_samples(const DevFrame& f, int q, int row) {
     return f.y + size_t(f.y_full ? row : q) * f.n2;

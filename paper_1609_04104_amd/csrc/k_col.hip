@@ -138,25 +138,37 @@ k_col_resid(Src src) {
     __syncthreads();
     // The samples this thread's residual entries need (k = s + P k2 after the
     // forward transform), loaded now so that they arrive during the transform.
+    // Masked lanes read a zero constant instead (the mask is in the address):
+    // no select waits for these loads here, so they stay in flight through
+    // the forward transform.
     float2 ys[Q];
     unsigned on = 0;                               // bit k2: entry k2 is sampled
-    sfor<Q>([&](auto kk) {
-        constexpr int k2 = decltype(kk)::value;
-        const int k = s + P * k2;
-        ys[k2] = float2{0.f, 0.f};
-        if (s < P && cv) {
-            if (lines) {
-                const int q = s_map[k];
-                if (q >= 0) {
-                    on |= 1u << k2;
-                    ys[k2] = line_samples(f, q, k)[col];
-                }
-            } else {
-                if (f.mask[size_t(k) * n2 + col]) on |= 1u << k2;
-                ys[k2] = f.y[size_t(k) * n2 + col];
-            }
-        }
-    });
+    if (!lines) {
+        // the mask bytes first: the bits below wait for them, not for the samples
+        const bool ok = s < P && cv;
+        unsigned char mk[Q];
+        sfor<Q>([&](auto kk) {
+            constexpr int k2 = decltype(kk)::value;
+            mk[k2] = load_or_zero<unsigned char>(ok, f.mask + size_t(s + P * k2) * n2 + col);
+        });
+        sfor<Q>([&](auto kk) {
+            constexpr int k2 = decltype(kk)::value;
+            ys[k2] = load_or_zero<float2>(ok, f.y + size_t(s + P * k2) * n2 + col);
+        });
+        sfor<Q>([&](auto kk) {
+            constexpr int k2 = decltype(kk)::value;
+            if (mk[k2]) on |= 1u << k2;
+        });
+    } else {
+        sfor<Q>([&](auto kk) {
+            constexpr int k2 = decltype(kk)::value;
+            const int k = s + P * k2;
+            const int q = (s < P && cv) ? s_map[k] : -1;
+            const bool ok = q >= 0;
+            if (ok) on |= 1u << k2;
+            ys[k2] = load_or_zero<float2>(ok, line_samples(f, ok ? q : 0, k) + col);
+        });
+    }
     if (s < Q) dft_twiddle<N1, P, false>(v, s, s_tw);
     col_swap_nk<N1>(v, s_u, c, s);
     if (s < P) {
@@ -173,11 +185,12 @@ k_col_resid(Src src) {
     // loads wait while the others compute.
     const int lane = tid % 64, wave = __builtin_amdgcn_readfirstlane(tid / 64), n = lane % 16;
     float2 av0[P];
+    // masked lanes read the zero constant, as for the samples above
     auto load_a = [&](int t, float2 (&av)[P]) {
         sfor<P>([&](auto mc) {
             constexpr int m2 = decltype(mc)::value;
             const int i = s + Q * m2, r = 16 * t + n;
-            av[m2] = (s < Q && r < R) ? float2(f.A[size_t(i) * R + r]) : float2{0.f, 0.f};
+            av[m2] = load_or_zero<float2>(s < Q && r < R, f.A + size_t(i) * R + r);
         });
     };
     col_swap_kn<N1>(v, s_u, c, s);

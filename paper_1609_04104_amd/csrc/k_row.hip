@@ -93,48 +93,106 @@ __global__ void __launch_bounds__(kRowBlock) k_synth_rowfft(Src src) {
     load_tw<N2>(s_tw);
 
     {
-        float2* s_b = s_x;                  // [j][c] = B[j][r0 + c]
-        float2* s_ag = s_x + SB;            // [row][c] = A[i0 + row][r0 + c] gamma[r0 + c]
+        float2* s_b = s_x;                  // [j][c] = B[j][r0 + c] (BF16 passes)
+        float2* s_ag = s_x + SB;            // [row][c] = A[i0 + row][r0 + c] gamma[r0 + c] (BF16 passes)
         f32x4 accr[RT::TPW], acci[RT::TPW];
 #pragma unroll
         for (int u = 0; u < RT::TPW; ++u) accr[u] = acci[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const bool im = g & 1;
         const int bf = __builtin_amdgcn_readfirstlane(f.synth_bf16);   // uniform: scalar branch
         static_assert(kSynRC == 8, "a BF16 step covers the 16 K entries of one pass");
-        for (int r0 = 0; r0 < R; r0 += kSynRC) {
-            const int nr = min(kSynRC, R - r0);
-            __syncthreads();
-            stage_copy<8, float2>(
-                N2 * kSynRC,
-                [&](int e) {
-                    const int j = e / kSynRC, c = e % kSynRC;
-                    return c < nr ? float2(f.B[size_t(j) * R + r0 + c]) : float2{0.f, 0.f};
-                },
-                [&](int e, float2 v) { s_b[(e / kSynRC) * kSynBP + e % kSynRC] = v; });
-            for (int e = tid; e < RT::MT * 16 * kSynRC; e += blockDim.x) {
-                const int row = e / kSynRC, c = e % kSynRC, ia = i0 + row;
-                s_ag[row * kSynBP + c] = (c < nr && row < ROWS && ia < n1)
-                                             ? cmul(float2(f.A[size_t(ia) * R + r0 + c]), float2(f.gamma32[r0 + c]))
-                                             : float2{0.f, 0.f};
-            }
-            __syncthreads();
-            if (bf == SYN_FP32) {
+        if (bf == SYN_FP32) {
+            // Operands straight from global memory, no staging and no barrier:
+            // lane (m, g) of tile (mt, nt) feeds AG[i0 + 16 mt + m][r] and
+            // B[16 nt + m][r], r = r0 + 4 s + g, to the K step s.  Gauss's
+            // three-multiplication form, P1 = sum Re AG Re B, P2 = sum Im AG Im B,
+            // P3 = sum (Re AG + Im AG)(Re B + Im B): Re X = P1 - P2 and
+            // Im X = P3 - P1 - P2, three 16x16x4 steps per four ranks and tile.
+            // A chunk's loads go out together and the steps wait for them in
+            // order; the other blocks on the compute unit cover the latency.
+            constexpr int KC = 4;                                      // K steps per chunk
+            constexpr int AT = RT::MT == 1 ? 1 : RT::TPW;             // A operands per K step
+            f32x4 p3[RT::TPW];
 #pragma unroll
-                for (int k = 0; k < kSynRC / 2; ++k) {
-                    const int c = 2 * k + g / 2;
+            for (int u = 0; u < RT::TPW; ++u) p3[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+            struct Ops {
+                float2 a[KC][AT], b[KC][RT::TPW], gm[KC];
+            };
+            // raw loads only (masked lanes read a zero constant): nothing waits
+            // for a load before the chunk's steps
+            auto load = [&](int r0, Ops& o) {
+#pragma unroll
+                for (int q = 0; q < KC; ++q) {
+                    const int r = r0 + 4 * q + g;
+                    const bool rv = r < R;
+                    o.gm[q] = float2(f.gamma32[rv ? r : R - 1]);
+#pragma unroll
+                    for (int a = 0; a < AT; ++a) {
+                        const int tile = wave + kRowWaves * a, row = 16 * (tile / RT::NT) + m;
+                        const bool ok = rv && tile < RT::MT * RT::NT && row < ROWS && i0 + row < n1;
+                        o.a[q][a] = load_or_zero<float2>(ok, f.A + size_t(i0 + row) * R + r);
+                    }
 #pragma unroll
                     for (int u = 0; u < RT::TPW; ++u) {
-                        const int tile = wave + kRowWaves * u;
-                        if (tile >= RT::MT * RT::NT) break;
-                        const int mt = tile / RT::NT, nt = tile % RT::NT, j = 16 * nt + m;
-                        const float2 a = s_ag[(16 * mt + m) * kSynBP + c];
-                        const float2 b = s_b[(j < N2 ? j : N2 - 1) * kSynBP + c];   // clamped, then masked
-                        const float bv = j < N2 ? (im ? b.y : b.x) : 0.f;
-                        accr[u] = mfma_16x16x4(im ? -a.y : a.x, bv, accr[u]);
-                        acci[u] = mfma_16x16x4(im ? a.x : a.y, bv, acci[u]);
+                        const int tile = wave + kRowWaves * u, j = 16 * (tile % RT::NT) + m;
+                        const bool ok = rv && tile < RT::MT * RT::NT && j < N2;
+                        o.b[q][u] = load_or_zero<float2>(ok, f.B + size_t(j) * R + r);
                     }
                 }
-            } else {
+            };
+            // no branch on the tile here (tiles past the last one have zero
+            // operands), so that no load sinks into one
+            auto steps = [&](const Ops& o) {
+#pragma unroll
+                for (int q = 0; q < KC; ++q) {
+                    float2 xa[AT];
+#pragma unroll
+                    for (int a = 0; a < AT; ++a) xa[a] = cmul(o.a[q][a], o.gm[q]);   // AG = A gamma
+#pragma unroll
+                    for (int u = 0; u < RT::TPW; ++u) {
+                        const float2 x = xa[AT == 1 ? 0 : u], y = o.b[q][u];
+                        accr[u] = mfma_16x16x4(x.x, y.x, accr[u]);
+                        acci[u] = mfma_16x16x4(x.y, y.y, acci[u]);
+                        p3[u] = mfma_16x16x4(x.x + x.y, y.x + y.y, p3[u]);
+                    }
+                }
+            };
+            // A chunk's loads all go out before its first step.  (A second
+            // register set that prefetches the next chunk during the steps
+            // measured slower at 256: it spills and adds load instructions,
+            // and the loads, not the steps, set the pace.)
+            constexpr int RC = 4 * KC;                                 // ranks per chunk
+            for (int r0 = 0; r0 < R; r0 += RC) {
+                Ops o;
+                load(r0, o);
+                __builtin_amdgcn_sched_barrier(0);
+                steps(o);
+            }
+#pragma unroll
+            for (int u = 0; u < RT::TPW; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float q1 = accr[u][e], q2 = acci[u][e];
+                    accr[u][e] = q1 - q2;
+                    acci[u][e] = p3[u][e] - q1 - q2;
+                }
+        } else {
+            for (int r0 = 0; r0 < R; r0 += kSynRC) {
+                const int nr = min(kSynRC, R - r0);
+                __syncthreads();
+                stage_copy<8, float2>(
+                    N2 * kSynRC,
+                    [&](int e) {
+                        const int j = e / kSynRC, c = e % kSynRC;
+                        return c < nr ? float2(f.B[size_t(j) * R + r0 + c]) : float2{0.f, 0.f};
+                    },
+                    [&](int e, float2 v) { s_b[(e / kSynRC) * kSynBP + e % kSynRC] = v; });
+                for (int e = tid; e < RT::MT * 16 * kSynRC; e += blockDim.x) {
+                    const int row = e / kSynRC, c = e % kSynRC, ia = i0 + row;
+                    s_ag[row * kSynBP + c] = (c < nr && row < ROWS && ia < n1)
+                                                 ? cmul(float2(f.A[size_t(ia) * R + r0 + c]), float2(f.gamma32[r0 + c]))
+                                                 : float2{0.f, 0.f};
+                }
+                __syncthreads();
                 // one 16x16x16 BF16 step per pass: lane (m, g) supplies K entries
                 // 4 g + e, e < 4, i.e. rank 2 g + e / 2, real part if e is even
 #pragma unroll
