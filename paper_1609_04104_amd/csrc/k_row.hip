@@ -276,7 +276,8 @@ __global__ void __launch_bounds__(kRowBlock) k_synth_rowfft(Src src) {
 // K range, and partial sums over K ranges are added in a fixed order.
 constexpr int kGNT = 2;   // 16-rank tiles per pass
 template <int N2, class Src>
-__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(3))) k_row_inv_grad(Src src) {
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(RowTiles<N2>::MT == 1 ? 4 : 3)))
+k_row_inv_grad(Src src) {
     using S = RowShape<N2>;
     using RT = RowTiles<N2>;
     constexpr int P = S::P, Q = S::Q, T = S::T, ROWS = S::ROWS, PITCH = RT::PITCH, MT = RT::MT;
@@ -285,11 +286,18 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
     constexpr int MPW = (MT + MW - 1) / MW;                   // M tiles per wavefront
     constexpr int KSTEPS = (N2 + 1) / 2;                      // two columns per 16x16x4 step
     constexpr int KPW = (KSTEPS + KS - 1) / KS;
-    constexpr int SP = KS * MT * 16 * kGNT * 16;              // partials [ks][row][rank]
-    __shared__ float2 s_tw[N2];
+    // Partial sums: [ks][row][rank] over four K ranges with several M tiles;
+    // with one M tile the wavefronts take (rank tile, K half) and one half's
+    // 16 x 16 tiles pass through LDS.  With one M tile the partials share the
+    // twiddles' array (the transform is over before the contraction starts),
+    // which keeps a block within a quarter of the compute unit's LDS.
+    constexpr int SP = MT == 1 ? kGNT * 16 * 16 : KS * MT * 16 * kGNT * 16;
+    constexpr int AUX = MT == 1 ? cmax2(N2, SP) : N2 + SP;
+    __shared__ float2 s_aux[AUX];
     __shared__ float2 s_x[cmax2(S::XSIZE, ROWS * PITCH)];
-    __shared__ float2 s_p[SP];
     __shared__ int s_bad;
+    float2* s_tw = s_aux;
+    float2* s_p = MT == 1 ? s_aux : s_aux + N2;
 
     if (!src.live()) return;
     const DevFrame f = src.get();
@@ -327,6 +335,54 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
     const int mw = wave % MW, ks = wave / MW;
     const bool im = g & 1;
     bool bad = false;
+    if constexpr (MT == 1) {
+        // wavefront (rank tile rs of the pass, K half kh); lane (m, g) feeds
+        // Theta row m and B[j][r], j = 2 t + g / 2 (real part for even g), to
+        // the K step t
+        static_assert(kGNT == 2 && kRowWaves == 4, "two rank tiles by two K halves");
+        const int rs = __builtin_amdgcn_readfirstlane(wave % 2), kh = __builtin_amdgcn_readfirstlane(wave / 2);
+        constexpr int KH = (KSTEPS + 1) / 2, KB = 16;             // K steps per half, per load group
+        const int t0 = kh * KH, t1 = min(KSTEPS, t0 + KH);
+        for (int n0 = 0; n0 < R; n0 += kGNT * 16) {
+            f32x4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+            const int r = n0 + 16 * rs + m;
+            for (int tb = t0; tb < t1; tb += KB) {
+                float bv[KB];
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    const int j = 2 * (tb + k) + g / 2;
+                    const bool ok = tb + k < t1 && j < N2 && r < R;
+                    bv[k] = load_or_zero<float>(ok, reinterpret_cast<GlobalPtr<const float>>(f.B + size_t(j) * R + r) + (im ? 1 : 0));
+                }
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    const int j = 2 * (tb + k) + g / 2;
+                    const float2 th = (tb + k < t1 && m < ROWS && j < N2) ? s_x[m * PITCH + j] : float2{0.f, 0.f};
+                    const float pr = im ? th.y : th.x, pi = im ? -th.x : th.y;
+                    accr = mfma_16x16x4(pr, bv[k], accr);
+                    acci = mfma_16x16x4(pi, bv[k], acci);
+                }
+            }
+            // D[4 g + e][m] = (row 4 g + e, rank r): the second half's tiles go
+            // through LDS and are added to the first half's, in that order
+            if (kh == 1)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s_p[(rs * 16 + 4 * g + e) * 16 + m] = float2{accr[e], acci[e]};
+            __syncthreads();
+            if (kh == 0)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 4 * g + e, ii = src.bx() * ROWS + row;
+                    const float2 q = s_p[(rs * 16 + row) * 16 + m];
+                    const float2 gsum{accr[e] + q.x, acci[e] + q.y};
+                    if (row < ROWS && ii < n1 && r < R) {
+                        bad |= !finite2(gsum);
+                        f.GA[size_t(ii) * R + r] = gsum;
+                    }
+                }
+            __syncthreads();
+        }
+    } else
     for (int n0 = 0; n0 < R; n0 += kGNT * 16) {
         f32x4 accr[MPW][kGNT], acci[MPW][kGNT];
 #pragma unroll
