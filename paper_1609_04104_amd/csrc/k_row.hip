@@ -336,45 +336,49 @@ k_row_inv_grad(Src src) {
     const bool im = g & 1;
     bool bad = false;
     if constexpr (MT == 1) {
-        // wavefront (rank tile rs of the pass, K half kh); lane (m, g) feeds
-        // Theta row m and B[j][r], j = 2 t + g / 2 (real part for even g), to
-        // the K step t
+        // Wavefront (rank tile rs of the pass, K half kh); lane (m, g) feeds
+        // Theta[m][j] and B[j][r], j = 4 t + g, to the K step t.  Gauss's
+        // three-multiplication form with the conjugate's sign on B:
+        // P1 = sum Re Th Re B, P2 = sum Im Th (-Im B),
+        // P3 = sum (Re Th + Im Th)(Re B - Im B), so that Re G_A = P1 - P2 and
+        // Im G_A = P3 - P1 - P2: three 16x16x4 steps per four columns.
         static_assert(kGNT == 2 && kRowWaves == 4, "two rank tiles by two K halves");
         const int rs = __builtin_amdgcn_readfirstlane(wave % 2), kh = __builtin_amdgcn_readfirstlane(wave / 2);
-        constexpr int KH = (KSTEPS + 1) / 2, KB = 16;             // K steps per half, per load group
-        const int t0 = kh * KH, t1 = min(KSTEPS, t0 + KH);
+        constexpr int KS4 = (N2 + 3) / 4, KH = (KS4 + 1) / 2, KB = 8;   // K steps, per half, per load group
+        const int t0 = kh * KH, t1 = min(KS4, t0 + KH);
         for (int n0 = 0; n0 < R; n0 += kGNT * 16) {
-            f32x4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+            f32x4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
             const int r = n0 + 16 * rs + m;
             for (int tb = t0; tb < t1; tb += KB) {
-                float bv[KB];
+                float2 bv[KB];
 #pragma unroll
                 for (int k = 0; k < KB; ++k) {
-                    const int j = 2 * (tb + k) + g / 2;
-                    const bool ok = tb + k < t1 && j < N2 && r < R;
-                    bv[k] = load_or_zero<float>(ok, reinterpret_cast<GlobalPtr<const float>>(f.B + size_t(j) * R + r) + (im ? 1 : 0));
+                    const int j = 4 * (tb + k) + g;
+                    bv[k] = load_or_zero<float2>(tb + k < t1 && j < N2 && r < R, f.B + size_t(j) * R + r);
                 }
 #pragma unroll
                 for (int k = 0; k < KB; ++k) {
-                    const int j = 2 * (tb + k) + g / 2;
+                    const int j = 4 * (tb + k) + g;
                     const float2 th = (tb + k < t1 && m < ROWS && j < N2) ? s_x[m * PITCH + j] : float2{0.f, 0.f};
-                    const float pr = im ? th.y : th.x, pi = im ? -th.x : th.y;
-                    accr = mfma_16x16x4(pr, bv[k], accr);
-                    acci = mfma_16x16x4(pi, bv[k], acci);
+                    const float2 b = bv[k];
+                    p1 = mfma_16x16x4(th.x, b.x, p1);
+                    p2 = mfma_16x16x4(th.y, -b.y, p2);
+                    p3 = mfma_16x16x4(th.x + th.y, b.x - b.y, p3);
                 }
             }
             // D[4 g + e][m] = (row 4 g + e, rank r): the second half's tiles go
             // through LDS and are added to the first half's, in that order
             if (kh == 1)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) s_p[(rs * 16 + 4 * g + e) * 16 + m] = float2{accr[e], acci[e]};
+                for (int e = 0; e < 4; ++e)
+                    s_p[(rs * 16 + 4 * g + e) * 16 + m] = float2{p1[e] - p2[e], p3[e] - p1[e] - p2[e]};
             __syncthreads();
             if (kh == 0)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int row = 4 * g + e, ii = src.bx() * ROWS + row;
                     const float2 q = s_p[(rs * 16 + row) * 16 + m];
-                    const float2 gsum{accr[e] + q.x, acci[e] + q.y};
+                    const float2 gsum{(p1[e] - p2[e]) + q.x, (p3[e] - p1[e] - p2[e]) + q.y};
                     if (row < ROWS && ii < n1 && r < R) {
                         bad |= !finite2(gsum);
                         f.GA[size_t(ii) * R + r] = gsum;
