@@ -68,16 +68,20 @@ constexpr int cmax2(int a, int b) { return a > b ? a : b; }
 // (the block's rows) are staged in LDS per pass with coalesced loads; the
 // operands of the 16x16x4 steps are read from there.  The tiles land in LDS as
 // [row][col] and the row transform reads its natural-layout inputs from there.
-constexpr int kSynRC = 8;                  // ranks staged per pass (four K steps)
+constexpr int kSynRC = 8;                  // ranks staged per pass (BF16 steps)
 constexpr int kSynBP = kSynRC + 1;         // LDS pitch (float2) of a staged row
+// ranks staged per pass of the FP32 steps: 16 (8 past 256 columns, so that the
+// staging area stays within a quarter of the compute unit's LDS)
+template <int N2> constexpr int syn_rc32() { return N2 <= 256 ? 16 : 8; }
 template <int N2, class Src>
-__global__ void __launch_bounds__(kRowBlock) k_synth_rowfft(Src src) {
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) k_synth_rowfft(Src src) {
     using S = RowShape<N2>;
     using RT = RowTiles<N2>;
     constexpr int P = S::P, Q = S::Q, T = S::T, ROWS = S::ROWS, PITCH = RT::PITCH;
-    constexpr int SB = N2 * kSynBP, SA = RT::MT * 16 * kSynBP;      // staged B rows, staged AG rows
+    constexpr int SB = N2 * kSynBP, SA = RT::MT * 16 * kSynBP;      // staged B rows, staged AG rows (BF16)
+    constexpr int SB32 = N2 * (syn_rc32<N2>() + 1), SA32 = RT::MT * 16 * (syn_rc32<N2>() + 1);   // FP32 passes
     __shared__ float2 s_tw[N2];
-    __shared__ float2 s_x[cmax2(cmax2(S::XSIZE, ROWS * PITCH), SB + SA)];
+    __shared__ float2 s_x[cmax2(cmax2(S::XSIZE, ROWS * PITCH), cmax2(SB + SA, SB32 + SA32))];
 
     if (!src.live()) return;
     const DevFrame f = src.get();
@@ -101,71 +105,88 @@ __global__ void __launch_bounds__(kRowBlock) k_synth_rowfft(Src src) {
         const int bf = __builtin_amdgcn_readfirstlane(f.synth_bf16);   // uniform: scalar branch
         static_assert(kSynRC == 8, "a BF16 step covers the 16 K entries of one pass");
         if (bf == SYN_FP32) {
-            // Operands straight from global memory, no staging and no barrier:
-            // lane (m, g) of tile (mt, nt) feeds AG[i0 + 16 mt + m][r] and
-            // B[16 nt + m][r], r = r0 + 4 s + g, to the K step s.  Gauss's
-            // three-multiplication form, P1 = sum Re AG Re B, P2 = sum Im AG Im B,
-            // P3 = sum (Re AG + Im AG)(Re B + Im B): Re X = P1 - P2 and
-            // Im X = P3 - P1 - P2, three 16x16x4 steps per four ranks and tile.
-            // A chunk's loads go out together and the steps wait for them in
-            // order; the other blocks on the compute unit cover the latency.
-            constexpr int KC = 4;                                      // K steps per chunk
-            constexpr int AT = RT::MT == 1 ? 1 : RT::TPW;             // A operands per K step
+            // RC ranks of B (all n2 rows) and of AG (the block's rows) are
+            // staged in LDS per pass: consecutive lanes load consecutive ranks
+            // of a row, so that the loads of RC lanes share one row segment (in
+            // the matrix-core layout, neighbouring lanes read different rows
+            // and every lane costs the L1 a tag lookup of its own; that lookup
+            // rate, not the latency, bounded the direct loads).  The other
+            // blocks on the compute unit cover a pass's load latency.
+            // Lane (m, g) of tile (mt, nt) feeds
+            // AG[16 mt + m][r] and B[16 nt + m][r], r = r0 + 4 q + g, to the
+            // K step q, in Gauss's three-multiplication form:
+            // P1 = sum Re AG Re B, P2 = sum Im AG Im B,
+            // P3 = sum (Re AG + Im AG)(Re B + Im B), Re X = P1 - P2 and
+            // Im X = P3 - P1 - P2.
+            constexpr int RC = syn_rc32<N2>(), BP = RC + 1;
+            constexpr int NB = cdiv(N2 * RC, kRowBlock), NA = cdiv(RT::MT * 16 * RC, kRowBlock);
+            float2* s_b32 = s_x;                                     // [j][c] = B[j][r0 + c]
+            float2* s_ag32 = s_x + N2 * BP;                          // [row][c] = AG[i0 + row][r0 + c]
             f32x4 p3[RT::TPW];
 #pragma unroll
             for (int u = 0; u < RT::TPW; ++u) p3[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-            struct Ops {
-                float2 a[KC][AT], b[KC][RT::TPW], gm[KC];
-            };
-            // raw loads only (masked lanes read a zero constant): nothing waits
-            // for a load before the chunk's steps
-            auto load = [&](int r0, Ops& o) {
+            float2 rb[NB < 8 ? NB : 8], ra[NA], rg[NA];
+            // B in groups of at most eight loads per thread (the registers that
+            // hold a group stay few), then AG
+            constexpr int GB = NB < 8 ? NB : 8;
+            auto fetch_b = [&](int r0, int k0) {
 #pragma unroll
-                for (int q = 0; q < KC; ++q) {
-                    const int r = r0 + 4 * q + g;
-                    const bool rv = r < R;
-                    o.gm[q] = float2(f.gamma32[rv ? r : R - 1]);
-#pragma unroll
-                    for (int a = 0; a < AT; ++a) {
-                        const int tile = wave + kRowWaves * a, row = 16 * (tile / RT::NT) + m;
-                        const bool ok = rv && tile < RT::MT * RT::NT && row < ROWS && i0 + row < n1;
-                        o.a[q][a] = load_or_zero<float2>(ok, f.A + size_t(i0 + row) * R + r);
-                    }
-#pragma unroll
-                    for (int u = 0; u < RT::TPW; ++u) {
-                        const int tile = wave + kRowWaves * u, j = 16 * (tile % RT::NT) + m;
-                        const bool ok = rv && tile < RT::MT * RT::NT && j < N2;
-                        o.b[q][u] = load_or_zero<float2>(ok, f.B + size_t(j) * R + r);
-                    }
+                for (int k = 0; k < GB; ++k) {
+                    const int e = tid + (k0 + k) * kRowBlock, j = e / RC, c = e % RC;
+                    rb[k] = load_or_zero<float2>(k0 + k < NB && j < N2 && r0 + c < R, f.B + size_t(j) * R + r0 + c);
                 }
             };
-            // no branch on the tile here (tiles past the last one have zero
-            // operands), so that no load sinks into one
-            auto steps = [&](const Ops& o) {
+            auto stage_b = [&](int k0) {
 #pragma unroll
-                for (int q = 0; q < KC; ++q) {
-                    float2 xa[AT];
+                for (int k = 0; k < GB; ++k) {
+                    const int e = tid + (k0 + k) * kRowBlock;
+                    if (k0 + k < NB && e < N2 * RC) s_b32[(e / RC) * BP + e % RC] = rb[k];
+                }
+            };
+            auto fetch = [&](int r0) {                               // AG: global -> registers
 #pragma unroll
-                    for (int a = 0; a < AT; ++a) xa[a] = cmul(o.a[q][a], o.gm[q]);   // AG = A gamma
+                for (int k = 0; k < NA; ++k) {
+                    const int e = tid + k * kRowBlock, row = e / RC, c = e % RC;
+                    const bool ok = row < ROWS && i0 + row < n1 && r0 + c < R;
+                    ra[k] = load_or_zero<float2>(ok, f.A + size_t(i0 + row) * R + r0 + c);
+                    rg[k] = load_or_zero<float2>(ok, f.gamma32 + r0 + c);
+                }
+            };
+            auto stage = [&]() {                                     // AG: registers -> LDS
+#pragma unroll
+                for (int k = 0; k < NA; ++k) {
+                    const int e = tid + k * kRowBlock;
+                    if (e < RT::MT * 16 * RC) s_ag32[(e / RC) * BP + e % RC] = cmul(ra[k], rg[k]);
+                }
+            };
+            auto steps = [&]() {
+#pragma unroll
+                for (int q = 0; q < RC / 4; ++q)
 #pragma unroll
                     for (int u = 0; u < RT::TPW; ++u) {
-                        const float2 x = xa[AT == 1 ? 0 : u], y = o.b[q][u];
+                        const int tile = wave + kRowWaves * u;
+                        if (tile >= RT::MT * RT::NT) break;
+                        const int mt = tile / RT::NT, nt = tile % RT::NT, j = 16 * nt + m;
+                        const float2 x = s_ag32[(16 * mt + m) * BP + 4 * q + g];
+                        const float2 yb = s_b32[(j < N2 ? j : N2 - 1) * BP + 4 * q + g];   // clamped, then masked
+                        const float2 y = j < N2 ? yb : float2{0.f, 0.f};
                         accr[u] = mfma_16x16x4(x.x, y.x, accr[u]);
                         acci[u] = mfma_16x16x4(x.y, y.y, acci[u]);
                         p3[u] = mfma_16x16x4(x.x + x.y, y.x + y.y, p3[u]);
                     }
-                }
             };
-            // A chunk's loads all go out before its first step.  (A second
-            // register set that prefetches the next chunk during the steps
-            // measured slower at 256: it spills and adds load instructions,
-            // and the loads, not the steps, set the pace.)
-            constexpr int RC = 4 * KC;                                 // ranks per chunk
             for (int r0 = 0; r0 < R; r0 += RC) {
-                Ops o;
-                load(r0, o);
-                __builtin_amdgcn_sched_barrier(0);
-                steps(o);
+                fetch(r0);
+                fetch_b(r0, 0);
+                __syncthreads();                                     // the previous pass's steps are done
+                stage();
+                stage_b(0);
+                for (int k0 = GB; k0 < NB; k0 += GB) {
+                    fetch_b(r0, k0);
+                    stage_b(k0);
+                }
+                __syncthreads();
+                steps();
             }
 #pragma unroll
             for (int u = 0; u < RT::TPW; ++u)
