@@ -125,10 +125,10 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
             f32x4 p3[RT::TPW];
 #pragma unroll
             for (int u = 0; u < RT::TPW; ++u) p3[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-            float2 rb[NB < 8 ? NB : 8], ra[NA], rg[NA];
+            float2 rb[NB < 4 ? NB : 4], ra[NA], rg[NA];
             // B in groups of at most eight loads per thread (the registers that
             // hold a group stay few), then AG
-            constexpr int GB = NB < 8 ? NB : 8;
+            constexpr int GB = NB < 4 ? NB : 4;
             auto fetch_b = [&](int r0, int k0) {
 #pragma unroll
                 for (int k = 0; k < GB; ++k) {
