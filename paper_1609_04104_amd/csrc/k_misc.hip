@@ -70,6 +70,11 @@ static_assert(kJCH >= kSRows, "the rhs products reuse the readout-chunk staging 
 // 16x16x4 steps per four rows (below); the wavefronts take the 16 x 16 tiles on
 // and above the diagonal.
 __device__ __forceinline__ double2 widen(float2 v) { return double2{v.x, v.y}; }
+// A store past the cache, for values that only a later launch reads: the end of
+// this launch then has fewer dirty lines to write back before the next starts.
+__device__ __forceinline__ void store_nt(GlobalPtr<float2> p, float2 v) {
+    __builtin_nontemporal_store(f32x2{v.x, v.y}, reinterpret_cast<GlobalPtr<f32x2>>(p));
+}
 __device__ __forceinline__ double2 widen(double2 v) { return v; }
 template <class T>
 __device__ void gram_staged(const T* s_x, int nq, int R, double2* out) {
@@ -127,7 +132,7 @@ __device__ void factor_gram_block(const DevFrame& f, int b, float2* s_x, bool ch
             const int e = e0 + int(threadIdx.x) + u * kSB;
             if (e < ne) {
                 s_x[e] = v[u];
-                if (keep) f.bcopy[size_t(q0) * R + e] = v[u];
+                if (keep) store_nt(f.bcopy + size_t(q0) * R + e, v[u]);
             }
         }
     }
@@ -239,7 +244,7 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
             if (e < nx) {
                 const float2 x = xr[u] >= 0 ? xv[u] : float2{0.f, 0.f};
                 s_x[e] = x;
-                if (gram_role && f.kspace) f.acopy[size_t(q0) * R + e] = x;   // Ahat_S of frame t - 1
+                if (gram_role && f.kspace) store_nt(f.acopy + size_t(q0) * R + e, x);   // Ahat_S of frame t - 1
             }
             if (e < ny) {
                 const bool live = yr[u] >= 0 && e % kJCH < nj;
@@ -301,7 +306,7 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int j = 16 * tj + 4 * g + i, r = 16 * tr + m;
-                if (j < nj && r < R) f.zw[(size_t(k) * n2 + j0 + j) * R + r] = float2{w1[i] - w2[i], w3[i] - w1[i] - w2[i]};
+                if (j < nj && r < R) store_nt(f.zw + (size_t(k) * n2 + j0 + j) * R + r, float2{w1[i] - w2[i], w3[i] - w1[i] - w2[i]});
             }
         }
     }
@@ -317,7 +322,7 @@ __global__ void __launch_bounds__(kSB) k_lstats(Src src, int nsg) {
             const double2 z{zp1[u][i] - zp2[u][i], zp3[u][i] - zp1[u][i] - zp2[u][i]};
             if (q < nq && r < R) {
                 s_p[q * R + r] = dcmulc(z, widen(s_x[q * R + r]));
-                if (f.kspace) f.zm[((size_t(k) * nJ + c) * kSRows + q) * R + r] = float2{float(z.x), float(z.y)};
+                if (f.kspace) store_nt(f.zm + ((size_t(k) * nJ + c) * kSRows + q) * R + r, float2{float(z.x), float(z.y)});
             }
         }
     }
