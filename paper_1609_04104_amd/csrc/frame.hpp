@@ -146,6 +146,13 @@ template <class T> __device__ __forceinline__ T load_or_zero(bool ok, GlobalPtr<
     return *a;
 }
 
+// A store past the cache, for values that only a later launch reads: the end of
+// this launch then has fewer dirty lines to write back before the next starts.
+__device__ __forceinline__ void store_nt(GlobalPtr<float2> p, float2 v) {
+    typedef float nt2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(nt2{v.x, v.y}, reinterpret_cast<GlobalPtr<nt2>>(p));
+}
+
 // Samples of row `row`, listed at position q of the row set (lines).
 __device__ __forceinline__ GlobalPtr<const float2> line_samples(const DevFrame& f, int q, int row) {
     return f.y + size_t(f.y_full ? row : q) * f.n2;

@@ -575,7 +575,7 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
             sfor<P>([&](auto m) {
                 constexpr int m2 = decltype(m)::value;
                 v[m2] = cscale(v[m2], InvSqrt<N1>::value);
-                if (rv) f.Ahat[size_t(s + Q * m2) * R + r] = v[m2];
+                if (rv) store_nt(f.Ahat + size_t(s + Q * m2) * R + r, v[m2]);   // read by the next step
             });
         }
         __syncthreads();                      // s_x is free: it takes the energies
@@ -611,7 +611,7 @@ __device__ __forceinline__ void update_a_body(const DevFrame& f, int bx, float2*
         sfor<Q>([&](auto k) {
             constexpr int k2 = decltype(k)::value;
             v[k2] = cscale(v[k2], InvSqrt<N1>::value);
-            if (rv) f.Ahat[size_t(s + P * k2) * R + r] = v[k2];
+            if (rv) store_nt(f.Ahat + size_t(s + P * k2) * R + r, v[k2]);   // read by the next step
         });
     }
     __syncthreads();                          // s_x is free: it takes the energies
@@ -734,7 +734,7 @@ __device__ __forceinline__ void update_b_body(const DevFrame& f, int bx, float2*
         if (rv) {
             sfor<P>([&](auto m) {
                 constexpr int m2 = decltype(m)::value;
-                f.Bhat[size_t(s + Q * m2) * R + r] = cscale(v[m2], InvSqrt<N2>::value);
+                store_nt(f.Bhat + size_t(s + Q * m2) * R + r, cscale(v[m2], InvSqrt<N2>::value));   // read by the next step
             });
         }
     }

@@ -70,11 +70,6 @@ static_assert(kJCH >= kSRows, "the rhs products reuse the readout-chunk staging 
 // 16x16x4 steps per four rows (below); the wavefronts take the 16 x 16 tiles on
 // and above the diagonal.
 __device__ __forceinline__ double2 widen(float2 v) { return double2{v.x, v.y}; }
-// A store past the cache, for values that only a later launch reads: the end of
-// this launch then has fewer dirty lines to write back before the next starts.
-__device__ __forceinline__ void store_nt(GlobalPtr<float2> p, float2 v) {
-    __builtin_nontemporal_store(f32x2{v.x, v.y}, reinterpret_cast<GlobalPtr<f32x2>>(p));
-}
 __device__ __forceinline__ double2 widen(double2 v) { return v; }
 template <class T>
 __device__ void gram_staged(const T* s_x, int nq, int R, double2* out) {
