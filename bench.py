@@ -256,7 +256,7 @@ def time_steps(drv, warmup, steps, stream, torch, label):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+        print(json.dumps({"error": "the step runs on one GPU; --gpus must be 1 (sharding across GPUs is "
                           "described, not built)"}))
         return 2
     import torch
